@@ -1,0 +1,492 @@
+/*
+ * Plain CPU oracle for the bootstrap particle filter — TEST INFRASTRUCTURE.
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg may load
+ * it.  FP64, single threaded, sequential.  Build with contraction off
+ * (-ffp-contract=off) so every expression below is evaluated as written.
+ *
+ * Functions whose only pin is agreement with a definition given here (not
+ * by the paper) say so in their comment.
+ */
+#include "pf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11).  The paper's library has a pseudorandom number
+ * generator but does not name it (Sec. 4); this counter-based generator is
+ * our reading, chosen so that every draw is a pure function of its position.
+ * One round: the two 32x32->64 products M0*c0 and M1*c2 are split into
+ * high/low words and mixed with c1, c3 and the round key; the key is bumped
+ * by the Weyl constants between rounds.
+ * ---------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on (0,1): the centre of the w-th of 2^32 equal cells (exact). */
+double orc_u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+/* Natural log of a positive normal double, from IEEE +,-,*,/ only:
+ * x = f*2^e with f in [sqrt(1/2), sqrt(2)), ln f = 2 atanh(s), s=(f-1)/(f+1),
+ * atanh summed as its odd power series through s^21 (|s| <= 0.1716, so the
+ * first dropped term is below 2^-56 relative).  Written out, rather than
+ * taken from libm, so that the normal transform is one fixed function of the
+ * generator's words (a reading; the paper fixes no transform).  Pinned
+ * against libm log in the tests. */
+double orc_ln(double x) {
+  uint64_t bits;
+  memcpy(&bits, &x, sizeof bits);
+  int e = (int)((bits >> 52) & 0x7ff) - 1022;
+  bits = (bits & 0x000fffffffffffffULL) | 0x3fe0000000000000ULL; /* f in [0.5, 1) */
+  double f;
+  memcpy(&f, &bits, sizeof f);
+  if (f < 0x1.6a09e667f3bcdp-1) { /* sqrt(1/2) */
+    f = f + f;
+    e = e - 1;
+  }
+  double s = (f - 1.0) / (f + 1.0);
+  double s2 = s * s;
+  double p = 1.0 / 21.0;
+  p = p * s2 + 1.0 / 19.0;
+  p = p * s2 + 1.0 / 17.0;
+  p = p * s2 + 1.0 / 15.0;
+  p = p * s2 + 1.0 / 13.0;
+  p = p * s2 + 1.0 / 11.0;
+  p = p * s2 + 1.0 / 9.0;
+  p = p * s2 + 1.0 / 7.0;
+  p = p * s2 + 1.0 / 5.0;
+  p = p * s2 + 1.0 / 3.0;
+  p = p * s2 + 1.0;
+  double lnf = (2.0 * s) * p;
+  double de = (double)e;
+  /* ln 2 split so that de * LN2_HI is exact for |e| < 2^11 */
+  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + lnf);
+}
+
+/* sin(2 pi u) and cos(2 pi u) for u in [0, 1): reduce to the nearest quarter
+ * turn k (exact on the dyadic u), then Taylor series of sin and cos on
+ * |phi| <= pi/4 through phi^19 and phi^18.  Same reading as orc_ln. */
+void orc_sincos2pi(double u, double* s_out, double* c_out) {
+  double v = 4.0 * u;
+  double kf = floor(v + 0.5);
+  double f = v - kf;
+  int k = ((int)kf) & 3;
+  double p = f * 0x1.921fb54442d18p0; /* pi/2 */
+  double p2 = p * p;
+  double sp = -1.0 / 121645100408832000.0;    /* -1/19! */
+  sp = sp * p2 + 1.0 / 355687428096000.0;     /*  1/17! */
+  sp = sp * p2 - 1.0 / 1307674368000.0;       /* -1/15! */
+  sp = sp * p2 + 1.0 / 6227020800.0;          /*  1/13! */
+  sp = sp * p2 - 1.0 / 39916800.0;            /* -1/11! */
+  sp = sp * p2 + 1.0 / 362880.0;              /*  1/9!  */
+  sp = sp * p2 - 1.0 / 5040.0;                /* -1/7!  */
+  sp = sp * p2 + 1.0 / 120.0;                 /*  1/5!  */
+  sp = sp * p2 - 1.0 / 6.0;                   /* -1/3!  */
+  sp = sp * p2 + 1.0;
+  sp = sp * p;
+  double cp = -1.0 / 6402373705728000.0;      /* -1/18! */
+  cp = cp * p2 + 1.0 / 20922789888000.0;      /*  1/16! */
+  cp = cp * p2 - 1.0 / 87178291200.0;         /* -1/14! */
+  cp = cp * p2 + 1.0 / 479001600.0;           /*  1/12! */
+  cp = cp * p2 - 1.0 / 3628800.0;             /* -1/10! */
+  cp = cp * p2 + 1.0 / 40320.0;               /*  1/8!  */
+  cp = cp * p2 - 1.0 / 720.0;                 /* -1/6!  */
+  cp = cp * p2 + 1.0 / 24.0;                  /*  1/4!  */
+  cp = cp * p2 - 1.0 / 2.0;                   /* -1/2!  */
+  cp = cp * p2 + 1.0;
+  double s, c;
+  switch (k) {
+    case 0: s = sp; c = cp; break;
+    case 1: s = cp; c = -sp; break;
+    case 2: s = -sp; c = -cp; break;
+    default: s = -cp; c = sp; break;
+  }
+  *s_out = s;
+  *c_out = c;
+}
+
+/* Four standard normals from one generator call: Box-Muller on the word
+ * pairs (w0, w1) and (w2, w3), radius sqrt(-2 ln u_a), angle 2 pi u_b.
+ * Counter layout: (particle j, substep or time n, tag<<28 | blk<<20 | iter,
+ * filter b); key = the 64-bit seed split low/high.  Component i of a state
+ * uses blk = i/4 and the (i mod 4)-th normal. */
+void orc_normals4(uint64_t seed, uint32_t tag, uint32_t blk, uint32_t iter, uint32_t j,
+                  uint32_t n, uint32_t b, double z[4]) {
+  uint32_t ctr[4] = {j, n, (tag << 28) | (blk << 20) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  for (int p = 0; p < 2; ++p) {
+    double ua = orc_u01(w[2 * p]);
+    double ub = orc_u01(w[2 * p + 1]);
+    double r = sqrt(-2.0 * orc_ln(ua));
+    double s, c;
+    orc_sincos2pi(ub, &s, &c);
+    z[2 * p] = r * c;
+    z[2 * p + 1] = r * s;
+  }
+}
+
+void orc_normals_bulk(uint64_t seed, uint32_t tag, uint32_t iter, uint32_t b, uint32_t n,
+                      int64_t count, double* z) {
+  for (int64_t j = 0; j < count; ++j) orc_normals4(seed, tag, 0, iter, (uint32_t)j, n, b, z + 4 * j);
+}
+
+/* one normal for component i of "particle" j at counter n */
+static double normal_at(uint64_t seed, uint32_t tag, uint32_t iter, uint32_t j, uint32_t n,
+                        uint32_t b, int i) {
+  double z[4];
+  orc_normals4(seed, tag, (uint32_t)(i / 4), iter, j, n, b, z);
+  return z[i % 4];
+}
+
+/* ------------------------------------------------------------------------
+ * Models.
+ * ---------------------------------------------------------------------- */
+
+/* Initial state x(t0) ~ p(X0 | theta) (Alg. 2, initialisation).
+ * Windkessel: P_p(t0) ~ N(m0, s0^2) (Sec. 2.1.1, initial block: mean 90,
+ * sd 15).  Lorenz '96: x_i(t0) ~ N(0, 1) (the workload's initial law). */
+static void init_one(const orc_problem* P, const double* th, uint64_t seed, uint32_t tag,
+                     uint32_t iter, uint32_t j, uint32_t b, double* x /* [d] */) {
+  if (P->model == ORC_MODEL_WK) {
+    double z = normal_at(seed, tag, iter, j, 0, b, 0);
+    x[0] = th[4] + th[5] * z;
+  } else {
+    for (int i = 0; i < P->d; ++i) x[i] = normal_at(seed, tag, iter, j, 0, b, i);
+  }
+}
+
+/* Lorenz '96 drift (eq. lorenz96-ode), cyclic indices:
+ * f_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + F. */
+void orc_l96_drift(int32_t d, const double* x, double F, double* out) {
+  for (int i = 0; i < d; ++i) {
+    int ip1 = (i + 1) % d, im1 = (i + d - 1) % d, im2 = (i + d - 2) % d;
+    out[i] = ((x[ip1] - x[im2]) * x[im1] - x[i]) + F;
+  }
+}
+
+/* One substep n (from t_{n-1} to t_n) of the transition.
+ * Windkessel, exact solution of the two-element ODE over a step with the
+ * flow held at F(t_{n-1}) (eq. 2-windkessel), plus an additive Gaussian
+ * pressure perturbation of sd sigma_p:  p <- (a p + c q_{n-1}) + sigma_p z.
+ * Lorenz '96: one classic RK4 step of size h of the drift, then the
+ * Wiener increment sigma dW_i with dW_i ~ N(0, h) added after the step
+ * (reading of eq. lorenz96-sde; the variance matches the paper's dW). */
+static void substep_one(const orc_problem* P, const double* th, uint64_t seed, uint32_t tag,
+                        uint32_t iter, uint32_t j, uint32_t b, int32_t n, double* x,
+                        double* w /* scratch 5*d */) {
+  if (P->model == ORC_MODEL_WK) {
+    double z = normal_at(seed, tag, iter, j, (uint32_t)n, b, 0);
+    double a = th[0], c = th[1], sp = th[3];
+    x[0] = (a * x[0] + c * P->q[n - 1]) + sp * z;
+    return;
+  }
+  int d = P->d;
+  double F = th[0];
+  double h = P->h, hh = 0.5 * P->h, h6 = P->h / 6.0;
+  double sq = th[1] * sqrt(P->h);
+  double *k1 = w, *k2 = w + d, *k3 = w + 2 * d, *k4 = w + 3 * d, *xt = w + 4 * d;
+  orc_l96_drift(d, x, F, k1);
+  for (int i = 0; i < d; ++i) xt[i] = x[i] + hh * k1[i];
+  orc_l96_drift(d, xt, F, k2);
+  for (int i = 0; i < d; ++i) xt[i] = x[i] + hh * k2[i];
+  orc_l96_drift(d, xt, F, k3);
+  for (int i = 0; i < d; ++i) xt[i] = x[i] + h * k3[i];
+  orc_l96_drift(d, xt, F, k4);
+  for (int i = 0; i < d; ++i) {
+    double xn = x[i] + h6 * ((k1[i] + k4[i]) + 2.0 * (k2[i] + k3[i]));
+    double z = normal_at(seed, tag, iter, j, (uint32_t)n, b, i);
+    x[i] = xn + sq * z;
+  }
+}
+
+/* Observation log-density log p(y(t) | x(t), theta), Gaussian with sd
+ * obs_sd on each observed component; the normalising constant is kept so
+ * the estimator targets the same likelihood as the Kalman filter.
+ * Windkessel (eq. 3-windkessel): mean P_p + Z F(t).  Lorenz '96: mean x_i. */
+static double logdens_one(const orc_problem* P, const double* th, int32_t t, const double* x,
+                          const double* y) {
+  double inv_sd = 1.0 / P->obs_sd;
+  double cst = -(double)P->n_obs * (log(P->obs_sd) + 0.5 * 1.8378770664093454836);
+  double acc = 0.0;
+  for (int o = 0; o < P->n_obs; ++o) {
+    double mu;
+    if (P->model == ORC_MODEL_WK)
+      mu = x[0] + th[2] * P->q[(int64_t)t * P->K];
+    else
+      mu = x[P->obs_idx[o]];
+    double e = (y[o] - mu) * inv_sd;
+    acc = acc + e * e;
+  }
+  return -0.5 * acc + cst;
+}
+
+/* ------------------------------------------------------------------------
+ * Filter pieces.
+ * ---------------------------------------------------------------------- */
+
+void orc_init(const orc_problem* P, const double* theta, int64_t N, uint32_t b, uint32_t iter,
+              double* x) {
+  double* xj = (double*)malloc(sizeof(double) * (size_t)P->d);
+  for (int64_t j = 0; j < N; ++j) {
+    init_one(P, theta, P->seed, ORC_TAG_INIT, iter, (uint32_t)j, b, xj);
+    for (int i = 0; i < P->d; ++i) x[(int64_t)i * N + j] = xj[i];
+  }
+  free(xj);
+}
+
+/* Propagate each particle from t-1 to t: K substeps n = (t-1)K+1 .. tK
+ * (Alg. 2, propagation). */
+void orc_propagate(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                   uint32_t iter, int32_t t, const double* x_in, double* x_out) {
+  int d = P->d;
+  double* xj = (double*)malloc(sizeof(double) * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  for (int64_t j = 0; j < N; ++j) {
+    for (int i = 0; i < d; ++i) xj[i] = x_in[(int64_t)i * N + j];
+    for (int s = 1; s <= P->K; ++s)
+      substep_one(P, theta, P->seed, ORC_TAG_NOISE, iter, (uint32_t)j, b,
+                  (t - 1) * P->K + s, xj, w);
+    for (int i = 0; i < d; ++i) x_out[(int64_t)i * N + j] = xj[i];
+  }
+  free(w);
+  free(xj);
+}
+
+/* Log-weights lw_j = log p(y(t) | x_j(t), theta) (Alg. 2, weighting). */
+void orc_weight(const orc_problem* P, const double* theta, int64_t N, int32_t t,
+                const double* x, double* lw) {
+  double* xj = (double*)malloc(sizeof(double) * (size_t)P->d);
+  for (int64_t j = 0; j < N; ++j) {
+    for (int i = 0; i < P->d; ++i) xj[i] = x[(int64_t)i * N + j];
+    lw[j] = logdens_one(P, theta, t, xj, P->obs + (int64_t)(t - 1) * P->n_obs);
+  }
+  free(xj);
+}
+
+/* The single uniform of systematic resampling at time t for filter b. */
+double orc_resample_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter) {
+  uint32_t ctr[4] = {0u, (uint32_t)t, ((uint32_t)ORC_TAG_RESAMPLE << 28) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return orc_u01(w[0]);
+}
+
+/* Likelihood increment, ESS and systematic resampling of one weight vector.
+ *   M   = max_j lw_j (NaN log-weights count as zero weight)
+ *   w_j = exp(lw_j - M),  W_j = sum_{i<=j} w_i (left to right),  S = W_{N-1}
+ *   ell = M + ln S - ln N    (log of the time-t factor of the likelihood
+ *                             estimate, Alg. 2 "marginal likelihood" line)
+ *   ESS = S^2 / sum_j w_j^2
+ * Systematic resampling (Sec. 3.3 names it among the collective resamplers;
+ * Kitagawa 1996): one uniform u, strata (u+k)/N, k = 0..N-1, and
+ *   a_k = min { j : N W_j > (u + k) S }
+ * i.e. stratum k falls in particle j's half-open cell [W_{j-1}, W_j); a
+ * particle of zero weight has an empty cell.  If rounding leaves no such j,
+ * a_k is the last particle of positive weight.  Returns ORC_NUMERIC (and
+ * ell = -inf, identity ancestors) when no weight is positive and finite. */
+int32_t orc_reduce_resample(int64_t N, const double* lw, double u, double* ell, double* ess,
+                            int32_t* a) {
+  double M = -INFINITY;
+  for (int64_t j = 0; j < N; ++j)
+    if (lw[j] > M) M = lw[j];
+  if (!(M > -INFINITY) || !(M < INFINITY)) {
+    *ell = -INFINITY;
+    *ess = 0.0;
+    for (int64_t k = 0; k < N; ++k) a[k] = (int32_t)k;
+    return ORC_NUMERIC;
+  }
+  double* W = (double*)malloc(sizeof(double) * (size_t)N);
+  double acc = 0.0, acc2 = 0.0;
+  int64_t jstar = -1;
+  for (int64_t j = 0; j < N; ++j) {
+    double w = (lw[j] == lw[j]) ? exp(lw[j] - M) : 0.0;
+    acc = acc + w;
+    acc2 = acc2 + w * w;
+    W[j] = acc;
+    if (w > 0.0) jstar = j;
+  }
+  double S = acc;
+  *ell = (M + log(S)) - log((double)N);
+  *ess = (S * S) / acc2;
+  double Nd = (double)N;
+  int64_t j = 0;
+  for (int64_t k = 0; k < N; ++k) {
+    double thr = (u + (double)k) * S;
+    while (j < N && !(Nd * W[j] > thr)) ++j;
+    a[k] = (int32_t)(j < N ? j : jstar);
+  }
+  free(W);
+  return ORC_OK;
+}
+
+/* x'_k = x_{a_k}: offspring take their ancestor's state. */
+void orc_gather(int32_t d, int64_t N, const double* x, const int32_t* a, double* x_out) {
+  for (int i = 0; i < d; ++i)
+    for (int64_t k = 0; k < N; ++k) x_out[(int64_t)i * N + k] = x[(int64_t)i * N + a[k]];
+}
+
+/* Alg. 2 over t = 1..T_run from a fresh initialisation.  Order within each
+ * time: propagate, weight, accumulate the likelihood factor, resample and
+ * gather (the paper draws ancestors at the top of the next iteration; the
+ * draw at t = 1 from uniform initial weights is skipped as it changes
+ * nothing in law — a reading).  The marginal log-likelihood is the running
+ * sum of ell_t. */
+int32_t orc_pf_run(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                   uint32_t iter, int32_t T_run, double* ell, double* ess, double* loglik,
+                   int32_t* anc_trace, double* lw_trace, double* x_final,
+                   const double* u_override) {
+  int d = P->d;
+  double* x = (double*)malloc(sizeof(double) * (size_t)d * (size_t)N);
+  double* xp = (double*)malloc(sizeof(double) * (size_t)d * (size_t)N);
+  double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+  int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t status = ORC_OK;
+  double ll = 0.0;
+  orc_init(P, theta, N, b, iter, x);
+  for (int32_t t = 1; t <= T_run; ++t) {
+    orc_propagate(P, theta, N, b, iter, t, x, xp);
+    orc_weight(P, theta, N, t, xp, lw);
+    if (lw_trace) memcpy(lw_trace + (int64_t)(t - 1) * N, lw, sizeof(double) * (size_t)N);
+    double u = u_override ? u_override[t - 1] : orc_resample_u(P->seed, t, b, iter);
+    double e, s;
+    int32_t st = orc_reduce_resample(N, lw, u, &e, &s, a);
+    if (st != ORC_OK) status = st;
+    ll = ll + e;
+    ell[t - 1] = e;
+    ess[t - 1] = s;
+    if (anc_trace) memcpy(anc_trace + (int64_t)(t - 1) * N, a, sizeof(int32_t) * (size_t)N);
+    orc_gather(d, N, xp, a, x);
+  }
+  *loglik = (status == ORC_OK) ? ll : -INFINITY;
+  if (x_final) memcpy(x_final, x, sizeof(double) * (size_t)d * (size_t)N);
+  free(a);
+  free(lw);
+  free(xp);
+  free(x);
+  return status;
+}
+
+/* Exact marginal likelihood of the windkessel by the Kalman filter (Alg. 1
+ * with N_x = N_y = 1, where every Cholesky factor is a square root): per
+ * substep, mean m <- a m + c q_{n-1} and variance V <- a^2 V + sigma_p^2;
+ * at each observation, innovation v = y - (m + Z q), innovation variance
+ * S = V + obs_sd^2, ell = -(ln(2 pi S) + v^2 / S)/2, then condition. */
+double orc_kf_wk(const orc_problem* P, const double* theta, double* ell) {
+  double a = theta[0], c = theta[1], Z = theta[2], sp = theta[3];
+  double m = theta[4], V = theta[5] * theta[5];
+  double R = P->obs_sd * P->obs_sd;
+  double ll = 0.0;
+  for (int32_t t = 1; t <= P->T; ++t) {
+    for (int s = 1; s <= P->K; ++s) {
+      int64_t n = (int64_t)(t - 1) * P->K + s;
+      m = a * m + c * P->q[n - 1];
+      V = a * a * V + sp * sp;
+    }
+    double qn = P->q[(int64_t)t * P->K];
+    double v = P->obs[t - 1] - (m + Z * qn);
+    double S = V + R;
+    double e = -0.5 * (log(2.0 * 3.14159265358979323846 * S) + v * v / S);
+    double Kg = V / S;
+    m = m + Kg * v;
+    V = (1.0 - Kg) * V;
+    ell[t - 1] = e;
+    ll += e;
+  }
+  return ll;
+}
+
+/* Synthetic truth and observations from the same model with the data seed:
+ * initial state and state noise under tag DATA (particle 0, filter 0),
+ * observation noise under tag OBS at counter n = t, blk = o/4. */
+void orc_simulate(const orc_problem* P, const double* theta, uint64_t data_seed,
+                  double* x_traj, double* obs) {
+  int d = P->d;
+  double* x = (double*)malloc(sizeof(double) * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  init_one(P, theta, data_seed, ORC_TAG_DATA, 0, 0, 0, x);
+  memcpy(x_traj, x, sizeof(double) * (size_t)d);
+  for (int32_t t = 1; t <= P->T; ++t) {
+    for (int s = 1; s <= P->K; ++s)
+      substep_one(P, theta, data_seed, ORC_TAG_DATA, 0, 0, 0, (t - 1) * P->K + s, x, w);
+    memcpy(x_traj + (int64_t)t * d, x, sizeof(double) * (size_t)d);
+    for (int o = 0; o < P->n_obs; ++o) {
+      double mu = (P->model == ORC_MODEL_WK) ? x[0] + theta[2] * P->q[(int64_t)t * P->K]
+                                             : x[P->obs_idx[o]];
+      double z = normal_at(data_seed, ORC_TAG_OBS, 0, 0, (uint32_t)t, 0, o);
+      obs[(int64_t)(t - 1) * P->n_obs + o] = mu + P->obs_sd * z;
+    }
+  }
+  free(w);
+  free(x);
+}
+
+/* Marginal Metropolis-Hastings (Alg. 3, eq. mh) on theta = log F of the
+ * Lorenz '96 model with sigma fixed, one chain per filter index b.
+ * Proposal: symmetric Gaussian random walk theta' = theta + step_sd z.
+ * Prior: F ~ U(f_lo, f_hi); in log F coordinates its density carries the
+ * Jacobian F, so the acceptance ratio is
+ *     l' F' 1[f_lo <= F' <= f_hi] / (l F),
+ * and a move is accepted iff ln(alpha) <= (ll' - ll) + (theta' - theta)
+ * (ties accept, as in Alg. 3).  Iteration i (1-based) runs its filter with
+ * generator iteration field i; the initial filter uses 0.  The random
+ * numbers of this layer (z, alpha, the initial theta) are inputs. */
+int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chains,
+                 int32_t n_chains_total, int32_t iters, const double* log_f0,
+                 const double* z, const double* alpha, double step_sd, double f_lo,
+                 double f_hi, double sigma, double* log_f_trace, double* ll_trace,
+                 int32_t* accepts) {
+  double* ell = (double*)malloc(sizeof(double) * (size_t)P->T);
+  double* ess = (double*)malloc(sizeof(double) * (size_t)P->T);
+  for (int32_t cc = 0; cc < n_chains; ++cc) {
+    int32_t c = chain0 + cc;
+    double th = log_f0[c];
+    double theta[2] = {exp(th), sigma};
+    double ll;
+    orc_pf_run(P, theta, N, (uint32_t)c, 0, P->T, ell, ess, &ll, NULL, NULL, NULL, NULL);
+    int32_t acc = 0;
+    for (int32_t i = 0; i < iters; ++i) {
+      double thp = th + step_sd * z[(int64_t)i * n_chains_total + c];
+      double Fp = exp(thp);
+      if (Fp >= f_lo && Fp <= f_hi) {
+        double thetap[2] = {Fp, sigma};
+        double llp;
+        orc_pf_run(P, thetap, N, (uint32_t)c, (uint32_t)(i + 1), P->T, ell, ess, &llp, NULL,
+                   NULL, NULL, NULL);
+        double lhs = log(alpha[(int64_t)i * n_chains_total + c]);
+        if (lhs <= (llp - ll) + (thp - th)) {
+          th = thp;
+          ll = llp;
+          ++acc;
+        }
+      }
+      log_f_trace[(int64_t)i * n_chains + cc] = th;
+      ll_trace[(int64_t)i * n_chains + cc] = ll;
+    }
+    accepts[cc] = acc;
+  }
+  free(ess);
+  free(ell);
+  return ORC_OK;
+}

@@ -1,0 +1,95 @@
+/*
+ * Plain CPU oracle for the bootstrap particle filter — TEST INFRASTRUCTURE.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The product (the HIP library and its Python
+ * binding) never calls it, and it shares no code with the product.
+ *
+ * Everything is FP64, single threaded, sequential and unblocked, following
+ * the paper's statement of the methods:
+ *   - bootstrap particle filter: Sec. 3.1.2, Alg. 2 (Particle-Filter);
+ *   - Kalman filter likelihood: Sec. 3.1.1, Alg. 1 (scalar case);
+ *   - marginal Metropolis-Hastings: Sec. 3.2.1, eq. (mh), Alg. 3;
+ *   - models: Sec. 2.1.1 eqs. (2-windkessel), (3-windkessel) and Sec. 2.1.2
+ *     eq. (lorenz96-sde) with classic fixed-step RK4.
+ *
+ * Readings where the paper is silent are stated beside each function.
+ * Particle state is structure-of-arrays: x[i*N + j] is component i of
+ * particle j.
+ */
+#ifndef PF_ORACLE_H
+#define PF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_MODEL_WK = 1, ORC_MODEL_L96 = 2 };
+enum { ORC_TAG_INIT = 1, ORC_TAG_NOISE = 2, ORC_TAG_RESAMPLE = 3, ORC_TAG_DATA = 4,
+       ORC_TAG_OBS = 8 };
+enum { ORC_OK = 0, ORC_NUMERIC = 4 };
+
+typedef struct orc_problem {
+  int32_t model;          /* ORC_MODEL_WK or ORC_MODEL_L96 */
+  int32_t d;              /* state dimension */
+  int32_t K;              /* substeps per observation interval */
+  int32_t T;              /* number of observations */
+  double h;               /* substep length */
+  int32_t n_obs;          /* observed components per time */
+  const int32_t* obs_idx; /* [n_obs] */
+  double obs_sd;          /* observation noise sd */
+  const double* obs;      /* [T][n_obs] (may be NULL for simulation) */
+  const double* q;        /* windkessel flow series [T*K+1], NULL for L96 */
+  uint64_t seed;          /* Philox key */
+} orc_problem;
+
+/* counter-based generator */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_u01(uint32_t w);
+double orc_ln(double x);
+void orc_sincos2pi(double u, double* s, double* c);
+void orc_normals4(uint64_t seed, uint32_t tag, uint32_t blk, uint32_t iter, uint32_t j,
+                  uint32_t n, uint32_t b, double z[4]);
+void orc_normals_bulk(uint64_t seed, uint32_t tag, uint32_t iter, uint32_t b, uint32_t n,
+                      int64_t count, double* z /* [count][4] for j = 0..count-1, blk 0 */);
+
+/* models */
+void orc_l96_drift(int32_t d, const double* x, double F, double* out);
+
+/* filter pieces (step level) */
+void orc_init(const orc_problem* P, const double* theta, int64_t N, uint32_t b, uint32_t iter,
+              double* x);
+void orc_propagate(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                   uint32_t iter, int32_t t, const double* x_in, double* x_out);
+void orc_weight(const orc_problem* P, const double* theta, int64_t N, int32_t t,
+                const double* x, double* lw);
+double orc_resample_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter);
+int32_t orc_reduce_resample(int64_t N, const double* lw, double u, double* ell, double* ess,
+                            int32_t* a);
+void orc_gather(int32_t d, int64_t N, const double* x, const int32_t* a, double* x_out);
+
+/* whole filter over t = 1..T; traces are optional (NULL) */
+int32_t orc_pf_run(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                   uint32_t iter, int32_t T_run, double* ell, double* ess, double* loglik,
+                   int32_t* anc_trace, double* lw_trace, double* x_final,
+                   const double* u_override);
+
+/* exact Kalman filter on the windkessel (scalar linear-Gaussian) */
+double orc_kf_wk(const orc_problem* P, const double* theta, double* ell);
+
+/* synthetic truth and observations */
+void orc_simulate(const orc_problem* P, const double* theta, uint64_t data_seed,
+                  double* x_traj /* [T+1][d] */, double* obs /* [T][n_obs] */);
+
+/* marginal Metropolis-Hastings chains on Lorenz '96 log F */
+int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chains,
+                 int32_t n_chains_total, int32_t iters, const double* log_f0,
+                 const double* z, const double* alpha, double step_sd, double f_lo,
+                 double f_hi, double sigma, double* log_f_trace /* [iters][n_chains] */,
+                 double* ll_trace /* [iters][n_chains] */, int32_t* accepts /* [n_chains] */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,199 @@
+"""Seeded synthetic workloads for the bootstrap particle filter.
+
+This module only builds inputs: model constants, per-filter parameter
+vectors, particle counts and the windkessel flow series.  It holds none of
+the filter's arithmetic (no propagation, weighting, reduction or
+resampling) and imports neither the oracle nor the HIP library, so both
+sides can be fed from it.  Observations are *not* made here: simulating
+the model is model arithmetic, so each side has its own simulator.
+
+The five workloads follow the paper's two examples:
+
+* windkessel (Sec. 2.1.1, eqs. 2-windkessel / 3-windkessel): a scalar
+  linear-Gaussian state with an exact Kalman likelihood;
+* Lorenz '96 (Sec. 2.1.2, eq. lorenz96-sde): a chaotic cyclic system
+  integrated with fixed-step RK4.
+
+Parameter layouts (one row of ``theta`` per filter):
+
+* windkessel: ``(a, c, Z, sigma_p, m0, s0)`` with ``a = exp(-h/(R C))``
+  and ``c = R (1 - a)``, so the exponential of the exact step
+  (eq. 2-windkessel) is evaluated once, here, and passed as data;
+* Lorenz '96: ``(F, sigma)``; the per-substep noise sd is ``sigma*sqrt(h)``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+MODEL_WK = 1
+MODEL_L96 = 2
+FP64 = 0
+FP32_MIXED = 1
+
+N_THETA = {MODEL_WK: 6, MODEL_L96: 2}
+
+
+@dataclasses.dataclass
+class Problem:
+    """One filtering problem: model, sizes, parameters and seeds.
+
+    ``theta`` has shape ``[B, n_theta]``; ``n_particles`` has shape ``[B]``.
+    ``data_theta`` is the parameter vector the synthetic truth is simulated
+    with; ``obs`` is filled in by whichever simulator the caller uses.
+    """
+    name: str
+    model: int
+    d: int
+    K: int
+    h: float
+    obs_idx: np.ndarray
+    obs_sd: float
+    T: int
+    theta: np.ndarray
+    n_particles: np.ndarray
+    q: Optional[np.ndarray]
+    seed: int
+    data_seed: int
+    data_theta: np.ndarray
+    precision: int = FP64
+    obs: Optional[np.ndarray] = None
+
+    @property
+    def B(self) -> int:
+        return int(self.theta.shape[0])
+
+    @property
+    def n_obs(self) -> int:
+        return int(self.obs_idx.shape[0])
+
+    @property
+    def n_theta(self) -> int:
+        return int(self.theta.shape[1])
+
+    def with_obs(self, obs: np.ndarray) -> "Problem":
+        obs = np.ascontiguousarray(obs, dtype=np.float64).reshape(self.T, self.n_obs)
+        return dataclasses.replace(self, obs=obs)
+
+
+# ---------------------------------------------------------------- windkessel
+
+def wk_flow(n_steps: int, h: float, peak: float = 400.0, period: float = 0.8) -> np.ndarray:
+    """Flow input F(t_n) = peak*max(0, sin(2*pi*t_n/period))^2, t_n = n*h.
+
+    A periodic pulse standing in for the paper's prescribed flow (eq. flow),
+    held constant over each step [t_n, t_n + h).  Returns n_steps + 1
+    values, n = 0..n_steps.
+    """
+    t = np.arange(n_steps + 1, dtype=np.float64) * h
+    s = np.sin(2.0 * np.pi * t / period)
+    return peak * np.maximum(0.0, s) ** 2
+
+
+def wk_theta(R: float, C: float, Z: float, sigma_p: float, m0: float, s0: float,
+             h: float) -> np.ndarray:
+    a = math.exp(-h / (R * C))
+    return np.array([a, R * (1.0 - a), Z, sigma_p, m0, s0], dtype=np.float64)
+
+
+def windkessel(N: int = 1024, T: int = 100, K: int = 10, seed: int = 0, data_seed: int = 1,
+               precision: int = FP64, B: int = 1) -> Problem:
+    """Linear-Gaussian windkessel workload: R=1, C=1.5, h=0.01, Z=0.03,
+    process sd 0.5 on the pressure, observation sd 1, initial N(90, 15^2)
+    (the paper's initial block gives mean 90, sd 15)."""
+    h = 0.01
+    th = wk_theta(1.0, 1.5, 0.03, 0.5, 90.0, 15.0, h)
+    return Problem(
+        name=f"windkessel_N{N}_T{T}", model=MODEL_WK, d=1, K=K, h=h,
+        obs_idx=np.zeros(1, dtype=np.int32), obs_sd=1.0, T=T,
+        theta=np.tile(th, (B, 1)), n_particles=np.full(B, N, dtype=np.int64),
+        q=wk_flow(T * K, h), seed=seed, data_seed=data_seed, data_theta=th.copy(),
+        precision=precision)
+
+
+# ---------------------------------------------------------------- Lorenz '96
+
+def lorenz96(d: int = 8, N: int = 65536, T: int = 200, K: int = 8, F: float = 8.0,
+             sigma: float = 0.1, obs_every: int = 1, seed: int = 0, data_seed: int = 1,
+             precision: int = FP64, B: int = 1) -> Problem:
+    """Stochastic Lorenz '96 with RK4 step h=0.05, K substeps between
+    observations, observation sd 0.5 on components 0, obs_every, 2*obs_every..."""
+    th = np.array([F, sigma], dtype=np.float64)
+    idx = np.arange(0, d, obs_every, dtype=np.int32)
+    return Problem(
+        name=f"lorenz96_d{d}_N{N}_T{T}", model=MODEL_L96, d=d, K=K, h=0.05,
+        obs_idx=idx, obs_sd=0.5, T=T, theta=np.tile(th, (B, 1)),
+        n_particles=np.full(B, N, dtype=np.int64), q=None, seed=seed,
+        data_seed=data_seed, data_theta=th.copy(), precision=precision)
+
+
+def batched_thetas(B: int, seed: int = 2, f_lo: float = 6.0, f_hi: float = 10.0,
+                   s_lo: float = 0.05, s_hi: float = 0.3,
+                   counts=(256, 512, 1024, 2048, 4096, 8192)):
+    """Parameter particles for the batched (SMC^2-style) workload:
+    F ~ U(f_lo, f_hi), sigma ~ U(s_lo, s_hi), N_b uniform over ``counts``."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    F = rng.uniform(f_lo, f_hi, size=B)
+    s = rng.uniform(s_lo, s_hi, size=B)
+    n = rng.choice(np.asarray(counts, dtype=np.int64), size=B)
+    return np.stack([F, s], axis=1).astype(np.float64), n.astype(np.int64)
+
+
+def lorenz96_batched(B: int = 512, T: int = 200, seed: int = 0, data_seed: int = 1,
+                     theta_seed: int = 2, precision: int = FP32_MIXED,
+                     counts=(256, 512, 1024, 2048, 4096, 8192)) -> Problem:
+    """B filters, each with its own (F_b, sigma_b) and N_b, all on the
+    d=8 Lorenz '96 data set (truth F=8, sigma=0.1)."""
+    base = lorenz96(d=8, N=1, T=T, seed=seed, data_seed=data_seed, precision=precision)
+    th, n = batched_thetas(B, theta_seed, counts=counts)
+    return dataclasses.replace(base, name=f"lorenz96_batched_B{B}_T{T}", theta=th,
+                               n_particles=n)
+
+
+@dataclasses.dataclass
+class PmmhInputs:
+    """Random numbers the marginal Metropolis-Hastings layer draws, passed in
+    as inputs: initial log F per chain, proposal normals and acceptance
+    uniforms per (iteration, chain)."""
+    log_f0: np.ndarray        # [chains]
+    z: np.ndarray             # [iters, chains]
+    alpha: np.ndarray         # [iters, chains], in (0, 1)
+    step_sd: float
+    f_lo: float
+    f_hi: float
+    sigma: float
+
+
+def pmmh_inputs(chains: int = 64, iters: int = 2000, seed: int = 3, step_sd: float = 0.05,
+                f_lo: float = 6.0, f_hi: float = 10.0, sigma: float = 0.1) -> PmmhInputs:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f0 = rng.uniform(f_lo, f_hi, size=chains)
+    z = rng.standard_normal(size=(iters, chains))
+    # strictly inside (0, 1): log(alpha) is finite
+    alpha = (rng.integers(0, 2 ** 32, size=(iters, chains), dtype=np.uint64).astype(np.float64)
+             + 0.5) * 2.0 ** -32
+    return PmmhInputs(np.log(f0), z, alpha, step_sd, f_lo, f_hi, sigma)
+
+
+# ---------------------------------------------------------------- named configs
+
+def config(name: str, **kw) -> Problem:
+    """The five headline workloads (c1..c5) plus small variants via kwargs."""
+    if name == "c1":
+        return windkessel(**kw)
+    if name == "c2":
+        return lorenz96(d=8, N=kw.pop("N", 65536), T=kw.pop("T", 200), **kw)
+    if name == "c3":
+        return lorenz96(d=40, N=kw.pop("N", 1 << 20), T=kw.pop("T", 500), obs_every=2,
+                        precision=kw.pop("precision", FP32_MIXED), **kw)
+    if name == "c4":
+        return lorenz96_batched(**kw)
+    if name == "c5":
+        chains = kw.pop("chains", 64)
+        N = kw.pop("N", 4096)
+        return lorenz96(d=8, N=N, T=kw.pop("T", 200), B=chains,
+                        precision=kw.pop("precision", FP32_MIXED), **kw)
+    raise KeyError(name)

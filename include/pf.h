@@ -1,0 +1,240 @@
+/*
+ * pf.h — C ABI of the MI355X (gfx950) bootstrap particle filter.
+ *
+ * The filter is Alg. 2 (Particle-Filter) of Murray, "Bayesian state-space
+ * modelling on high-performance hardware using LibBi" (Sec. 3.1.2): particles
+ * are propagated through the state-space model's transition, weighted by the
+ * observation density, the marginal likelihood estimate is accumulated as the
+ * product over time of the mean weight, and particles are resampled with
+ * replacement in proportion to their weights.  The paper states the filter
+ * over an interval t_{r:s} so that callers (marginal Metropolis-Hastings,
+ * Alg. 3; SMC over parameters, Alg. 4) can run it piecewise; pf_step and
+ * pf_resample are that unit for one observation interval.  Resampling is
+ * systematic (one of the collective resamplers named in Sec. 3.3).
+ *
+ * Conventions (all entry points):
+ *  - Device memory is owned by the caller: pf_workspace_bytes() says how
+ *    much, pf_init() carves it.  The library allocates no device memory.
+ *    Host arrays referenced by pf_config are copied during pf_init(); the
+ *    caller may free them when it returns.
+ *  - Every call is asynchronous on the HIP stream given to pf_init() (NULL =
+ *    the null stream), except pf_loglik(), pf_get_*() and pf_timing_get(),
+ *    which synchronise that stream.
+ *  - Status codes: PF_OK; PF_E_INVAL for an argument rejected on the host
+ *    before any HIP call; PF_E_DEVICE for a HIP runtime error; PF_E_STATE for
+ *    a call out of order (pf_step twice without pf_resample, a step past T,
+ *    any call on a destroyed handle); PF_E_NUMERIC from pf_loglik() when some
+ *    filter met a time at which no weight was positive and finite (that
+ *    filter's log-likelihood is then -infinity, and the flag is sticky until
+ *    pf_reset).  pf_last_error() returns a message for the last failing call
+ *    on the calling thread.
+ *  - A handle is not thread safe; distinct handles are independent.
+ *  - No call falls back to the CPU: without a gfx950 device every call that
+ *    needs one returns PF_E_DEVICE.
+ *
+ * Particle state is structure-of-arrays: component i of particle k of filter
+ * b is at x[i * N_total + offset_b + k], with offset_b the sum of the
+ * particle counts of filters before b.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pf_status {
+  PF_OK = 0,
+  PF_E_INVAL = 1,
+  PF_E_DEVICE = 2,
+  PF_E_STATE = 3,
+  PF_E_NUMERIC = 4
+} pf_status;
+
+/* State-space models (Sec. 2.1).
+ * PF_MODEL_WK: windkessel pressure, d = 1; exact step of the two-element
+ *   windkessel ODE with the flow held constant over a substep (eq.
+ *   2-windkessel), plus Gaussian noise on the pressure; observation of the
+ *   three-element aortal pressure P_p + Z F (eq. 3-windkessel) with Gaussian
+ *   noise.  theta = (a, c, Z, sigma_p, m0, s0): a = exp(-h/(RC)),
+ *   c = R(1-a), initial P_p ~ N(m0, s0^2).  Requires cfg.q.
+ * PF_MODEL_L96: Lorenz '96 (eq. lorenz96-sde), d in {4, 8, 16, 32, 40};
+ *   classic RK4 substeps of length h on the drift, then the increment
+ *   sigma dW with dW ~ N(0, h) per component; initial x ~ N(0, I);
+ *   observation of components obs_idx with Gaussian noise.
+ *   theta = (F, sigma). */
+enum { PF_MODEL_WK = 1, PF_MODEL_L96 = 2 };
+
+/* Arithmetic of the hot path.
+ * PF_FP64: everything in FP64.
+ * PF_FP32_MIXED: particle state, propagation and log-weights in FP32; the
+ *   max-shifted sums, the weight prefix scan, the likelihood increment, its
+ *   running sum and the ESS in FP64. */
+enum { PF_FP64 = 0, PF_FP32_MIXED = 1 };
+
+/* Kernel organisation.
+ * PF_LAYOUT_PLAIN: each filter is stepped by its own kernels (propagate +
+ *   weight, block combine, scan + stratum counts, merge-path resample +
+ *   gather); any particle count up to 2^31 - 1.
+ * PF_LAYOUT_BATCHED: all filters are stepped by one persistent kernel per
+ *   observation interval (work queue over particle chunks, then one
+ *   workgroup per filter for the collective part); every filter's particle
+ *   count must be <= PF_BATCHED_MAX_PARTICLES. */
+enum { PF_LAYOUT_PLAIN = 0, PF_LAYOUT_BATCHED = 1 };
+#define PF_BATCHED_MAX_PARTICLES 8192
+
+typedef struct pf_config {
+  int32_t model;              /* PF_MODEL_* */
+  int32_t precision;          /* PF_FP64 or PF_FP32_MIXED */
+  int32_t layout;             /* PF_LAYOUT_* */
+  int32_t d;                  /* state dimension */
+  int32_t K;                  /* substeps per observation interval, >= 1 */
+  int32_t T;                  /* number of observation times, >= 1 */
+  double h;                   /* substep length, > 0 */
+  int32_t n_obs;              /* observed components per time, >= 1 */
+  const int32_t* obs_idx;     /* host [n_obs], each in [0, d) */
+  double obs_sd;              /* observation noise sd, > 0 */
+  const double* obs;          /* host [T][n_obs], finite */
+  const double* q;            /* host [T*K + 1] windkessel flow F(n h); NULL for L96 */
+  int32_t B;                  /* number of filters, >= 1 */
+  int32_t n_theta;            /* 6 for WK, 2 for L96 */
+  const int64_t* n_particles; /* host [B], each >= 1 */
+  const double* theta;        /* host [B][n_theta] */
+  uint64_t seed;              /* key of the counter-based generator */
+} pf_config;
+
+typedef struct pf_handle pf_handle;
+
+/* Device bytes pf_init() needs for cfg, or 0 if cfg is invalid (the reason
+ * is then in pf_last_error()). */
+size_t pf_workspace_bytes(const pf_config* cfg);
+
+/* Validate cfg, carve d_workspace (device memory of ws_bytes >= the size
+ * query, 256-byte aligned), copy cfg's host arrays to it and draw the initial
+ * particles x(t0) ~ p(X0 | theta) with uniform weights (Alg. 2,
+ * initialisation).  Sets t = 0 and every log-likelihood to 0.  hip_stream is
+ * a hipStream_t or NULL.  On PF_OK *out receives a new handle. */
+pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                  pf_handle** out);
+
+/* One observation interval for every filter (Alg. 2, propagation and
+ * weighting, time t -> t+1): K substeps of the transition from the current
+ * equally weighted particles, log-weights log p(y(t+1) | x), then in FP64
+ * M = max lw, S = sum exp(lw - M), ell = M + ln S - ln N (the log of the
+ * time-(t+1) factor of the likelihood estimate), loglik += ell and
+ * ESS = S^2 / sum exp(2(lw - M)).  Requires t < T and the previous interval
+ * resampled. */
+pf_status pf_step(pf_handle* h);
+
+/* Systematic resampling of every filter after pf_step (Sec. 3.3): one
+ * uniform u from the generator, strata (u + k)/N, ancestor
+ * a_k = min{ j : N W_j > (u + k) S } with W the FP64 prefix sum of
+ * exp(lw - M), then the gather x_k <- x_{a_k}.  Ancestors are sorted. */
+pf_status pf_resample(pf_handle* h);
+
+/* Synchronise the stream and copy out per-filter results: loglik_out[B]
+ * (running marginal log-likelihood), ess_out[B] (ESS of the last step; may be
+ * NULL), *t_out (observations processed; may be NULL).  Returns
+ * PF_E_NUMERIC if any filter is flagged (its loglik is -infinity). */
+pf_status pf_loglik(pf_handle* h, double* loglik_out, double* ess_out, int32_t* t_out);
+
+/* Per-step traces, synchronous: ell_out[B][T] and ess_out[B][T] (entries
+ * after the current t are 0).  Either pointer may be NULL. */
+pf_status pf_get_trace(pf_handle* h, double* ell_out, double* ess_out);
+
+/* Release the handle and its HIP graph objects (not the workspace). */
+pf_status pf_destroy(pf_handle* h);
+
+/* Run n_steps observation intervals (pf_step + pf_resample each) by replaying
+ * a HIP graph captured on the first call.  Same results as the eager calls. */
+pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
+
+/* Replace every filter's parameters (host [B][n_theta]) and re-initialise
+ * (t = 0, loglik = 0, fresh x(t0)) with generator iteration field
+ * `iteration` (< 2^20), so that successive restarts draw independent
+ * particles — the unit marginal Metropolis-Hastings needs (Alg. 3).
+ * pf_reset keeps theta. */
+pf_status pf_set_theta(pf_handle* h, const double* theta, uint32_t iteration);
+pf_status pf_reset(pf_handle* h, uint32_t iteration);
+
+/* ---- parameter inference drivers ---------------------------------------- */
+/* Marginal Metropolis-Hastings chains (Sec. 3.2.1, eq. mh, Alg. 3) on the
+ * Lorenz '96 forcing F with sigma fixed, one chain per filter of the handle
+ * (all chains' filters are stepped together each iteration; the batched
+ * layout is the intended one).  The chain state is theta = log F; proposal
+ * theta' = theta + step_sd z; prior F ~ U(f_lo, f_hi), whose density in log F
+ * carries the Jacobian F; a move is accepted iff F' lies in [f_lo, f_hi] and
+ * ln(alpha) <= (ll' - ll) + (theta' - theta) (ties accept, as in Alg. 3).
+ * Iteration i (0-based) runs its filters with generator iteration field
+ * i + 1; the initial estimate uses 0.  The chain layer's random numbers are
+ * inputs (host): log_f0[B], z[iters][B], alpha[iters][B] in (0, 1).  Outputs
+ * (host): log_f_trace[iters][B], ll_trace[iters][B], accepts[B].
+ * Synchronous; leaves the handle holding the last proposal's run. */
+pf_status pf_pmmh(pf_handle* h, int32_t iters, const double* log_f0, const double* z,
+                  const double* alpha, double step_sd, double f_lo, double f_hi, double sigma,
+                  double* log_f_trace, double* ll_trace, int32_t* accepts);
+
+/* Autotuner for the batched layout: times each candidate workgroup size of
+ * the per-filter collective kernel (256, 512, 1024 lanes) over `steps`
+ * intervals of this handle's own workload, keeps the fastest for later
+ * calls, and re-initialises the filters (t = 0).  ms_out[3] (may be NULL)
+ * receives each candidate's mean interval time in ms, *choice_out (may be
+ * NULL) the chosen size.  Plain layout: nothing to tune, *choice_out = 0. */
+pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* choice_out, double* ms_out);
+
+/* ---- inspection and teacher forcing (synchronous; same kernels) -------- */
+/* Current particle set, FP64 host [d][N_total]: after pf_resample (or init)
+ * the equally weighted set; after pf_step the propagated, weighted set. */
+pf_status pf_get_state(pf_handle* h, double* x_out);
+/* Overwrite the current equally weighted set (only between intervals);
+ * values are rounded to the path's precision. */
+pf_status pf_set_state(pf_handle* h, const double* x_in);
+/* Log-weights of the last pf_step, FP64 host [N_total]. */
+pf_status pf_get_logweights(pf_handle* h, double* lw_out);
+/* Ancestors of the last pf_resample, host [N_total], indices local to each
+ * filter. */
+pf_status pf_get_ancestors(pf_handle* h, int32_t* a_out);
+/* pf_resample with caller-given uniforms u[B] in [0, 1) instead of the
+ * generator's (brute-force checks of the resampler). */
+pf_status pf_resample_u(pf_handle* h, const double* u);
+
+/* ---- synthetic data ----------------------------------------------------- */
+/* Simulate the model from theta (host [n_theta]) with generator key
+ * data_seed, in FP64 on the device (the same transition and observation
+ * arithmetic as the filter, with the particle index fixed to 0).  d_out is a
+ * caller-owned device buffer of out_doubles >= pf_simulate_doubles(cfg)
+ * doubles; it receives the truth x(t_0..t_T) as [T+1][d] followed by the
+ * observations as [T][n_obs]; the rest is scratch.  cfg.obs, cfg.B,
+ * cfg.n_particles and cfg.theta are ignored.  Synchronous. */
+size_t pf_simulate_doubles(const pf_config* cfg);
+pf_status pf_simulate(const pf_config* cfg, const double* theta, uint64_t data_seed,
+                      double* d_out, size_t out_doubles, void* hip_stream);
+
+/* ---- measurement -------------------------------------------------------- */
+typedef struct pf_timing {
+  double propagate_ms;   /* propagate + weight kernels */
+  double combine_ms;     /* block-combine kernels (likelihood increment, offsets) */
+  double scan_ms;        /* weight scan + stratum count kernels */
+  double gather_ms;      /* merge-path resample + ancestor gather kernels */
+  double batched_ms;     /* persistent batched step kernel */
+  int64_t propagate_launches, combine_launches, scan_launches, gather_launches,
+      batched_launches;
+} pf_timing;
+/* When on, eager pf_step/pf_resample bracket each kernel with HIP events on
+ * the handle's stream; pf_timing_get() synchronises and sums them.  Turning
+ * it on clears the sums. */
+pf_status pf_timing_enable(pf_handle* h, int32_t on);
+pf_status pf_timing_get(pf_handle* h, pf_timing* out);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* pf_last_error(void);
+/* Library version string. */
+const char* pf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -73,6 +73,10 @@ def lib():
             "orc_init": (None, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, _D]),
             "orc_propagate": (None, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32, _D,
                                      _D]),
+            "orc_init_idx": (None, [P, _D, C.c_int64, C.POINTER(C.c_int64), C.c_uint32,
+                                    C.c_uint32, _D]),
+            "orc_propagate_idx": (None, [P, _D, C.c_int64, C.POINTER(C.c_int64), C.c_uint32,
+                                         C.c_uint32, C.c_int32, _D, _D]),
             "orc_weight": (None, [P, _D, C.c_int64, C.c_int32, _D, _D]),
             "orc_resample_u": (C.c_double, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32]),
             "orc_reduce_resample": (C.c_int32, [C.c_int64, _D, C.c_double, _D, _D, _I]),
@@ -177,6 +181,29 @@ def propagate(pb, theta, x, t, b=0, it=0) -> np.ndarray:
     N = x.shape[1]
     out = np.zeros_like(x)
     lib().orc_propagate(P.ref, _dp(th), N, b, it, t, _dp(x), _dp(out))
+    return out
+
+
+def init_idx(pb, theta, idx, b=0, it=0) -> np.ndarray:
+    """Initial states of particles idx (columns) of filter b."""
+    P = _Prob(pb)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    x = np.zeros((pb.d, idx.size))
+    lib().orc_init_idx(P.ref, _dp(th), idx.size, idx.ctypes.data_as(C.POINTER(C.c_int64)), b, it,
+                       _dp(x))
+    return x
+
+
+def propagate_idx(pb, theta, x, idx, t, b=0, it=0) -> np.ndarray:
+    """Propagate columns of x, column c being particle idx[c], from t-1 to t."""
+    P = _Prob(pb)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    lib().orc_propagate_idx(P.ref, _dp(th), idx.size, idx.ctypes.data_as(C.POINTER(C.c_int64)),
+                            b, it, t, _dp(x), _dp(out))
     return out
 
 

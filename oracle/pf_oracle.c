@@ -273,6 +273,35 @@ void orc_propagate(const orc_problem* P, const double* theta, int64_t N, uint32_
   free(xj);
 }
 
+/* The same two steps for a subset of particles: column c of x holds
+ * particle idx[c] of a filter, so it draws that particle's numbers.  Lets
+ * the tests check single outputs of runs too large for the whole oracle. */
+void orc_init_idx(const orc_problem* P, const double* theta, int64_t n, const int64_t* idx,
+                  uint32_t b, uint32_t iter, double* x) {
+  double* xj = (double*)malloc(sizeof(double) * (size_t)P->d);
+  for (int64_t c = 0; c < n; ++c) {
+    init_one(P, theta, P->seed, ORC_TAG_INIT, iter, (uint32_t)idx[c], b, xj);
+    for (int i = 0; i < P->d; ++i) x[(int64_t)i * n + c] = xj[i];
+  }
+  free(xj);
+}
+
+void orc_propagate_idx(const orc_problem* P, const double* theta, int64_t n, const int64_t* idx,
+                       uint32_t b, uint32_t iter, int32_t t, const double* x_in, double* x_out) {
+  int d = P->d;
+  double* xj = (double*)malloc(sizeof(double) * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  for (int64_t c = 0; c < n; ++c) {
+    for (int i = 0; i < d; ++i) xj[i] = x_in[(int64_t)i * n + c];
+    for (int s = 1; s <= P->K; ++s)
+      substep_one(P, theta, P->seed, ORC_TAG_NOISE, iter, (uint32_t)idx[c], b,
+                  (t - 1) * P->K + s, xj, w);
+    for (int i = 0; i < d; ++i) x_out[(int64_t)i * n + c] = xj[i];
+  }
+  free(w);
+  free(xj);
+}
+
 /* Log-weights lw_j = log p(y(t) | x_j(t), theta) (Alg. 2, weighting). */
 void orc_weight(const orc_problem* P, const double* theta, int64_t N, int32_t t,
                 const double* x, double* lw) {

@@ -62,6 +62,10 @@ void orc_init(const orc_problem* P, const double* theta, int64_t N, uint32_t b, 
               double* x);
 void orc_propagate(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
                    uint32_t iter, int32_t t, const double* x_in, double* x_out);
+void orc_init_idx(const orc_problem* P, const double* theta, int64_t n, const int64_t* idx,
+                  uint32_t b, uint32_t iter, double* x);
+void orc_propagate_idx(const orc_problem* P, const double* theta, int64_t n, const int64_t* idx,
+                       uint32_t b, uint32_t iter, int32_t t, const double* x_in, double* x_out);
 void orc_weight(const orc_problem* P, const double* theta, int64_t N, int32_t t,
                 const double* x, double* lw);
 double orc_resample_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter);

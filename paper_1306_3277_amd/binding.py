@@ -1,0 +1,295 @@
+"""ctypes binding of the C ABI in include/pf.h — argument marshalling only.
+
+Every step of the filter runs in the HIP library; PyTorch provides the device
+workspace and the stream.  If the library is missing or no gfx950 device is
+present, the calls raise: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf_mi355x.so")
+
+PF_OK, PF_E_INVAL, PF_E_DEVICE, PF_E_STATE, PF_E_NUMERIC = 0, 1, 2, 3, 4
+PF_MODEL_WK, PF_MODEL_L96 = 1, 2
+PF_FP64, PF_FP32_MIXED = 0, 1
+PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
+PF_BATCHED_MAX_PARTICLES = 8192
+
+_STATUS = {1: "PF_E_INVAL", 2: "PF_E_DEVICE", 3: "PF_E_STATE", 4: "PF_E_NUMERIC"}
+
+
+class PfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PfConfig(C.Structure):
+    _fields_ = [
+        ("model", C.c_int32), ("precision", C.c_int32), ("layout", C.c_int32),
+        ("d", C.c_int32), ("K", C.c_int32), ("T", C.c_int32), ("h", C.c_double),
+        ("n_obs", C.c_int32), ("obs_idx", C.POINTER(C.c_int32)), ("obs_sd", C.c_double),
+        ("obs", C.POINTER(C.c_double)), ("q", C.POINTER(C.c_double)),
+        ("B", C.c_int32), ("n_theta", C.c_int32), ("n_particles", C.POINTER(C.c_int64)),
+        ("theta", C.POINTER(C.c_double)), ("seed", C.c_uint64),
+    ]
+
+
+class PfTiming(C.Structure):
+    _fields_ = [
+        ("propagate_ms", C.c_double), ("combine_ms", C.c_double), ("scan_ms", C.c_double),
+        ("gather_ms", C.c_double), ("batched_ms", C.c_double),
+        ("propagate_launches", C.c_int64), ("combine_launches", C.c_int64),
+        ("scan_launches", C.c_int64), ("gather_launches", C.c_int64),
+        ("batched_launches", C.c_int64),
+    ]
+
+
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int32)
+_H = C.c_void_p
+
+# exported symbols and their signatures (also checked by the CPU tests)
+SIGNATURES = {
+    "pf_workspace_bytes": (C.c_size_t, [C.POINTER(PfConfig)]),
+    "pf_init": (C.c_int, [C.POINTER(PfConfig), C.c_void_p, C.c_size_t, C.c_void_p,
+                          C.POINTER(_H)]),
+    "pf_step": (C.c_int, [_H]),
+    "pf_resample": (C.c_int, [_H]),
+    "pf_loglik": (C.c_int, [_H, _D, _D, _I]),
+    "pf_get_trace": (C.c_int, [_H, _D, _D]),
+    "pf_destroy": (C.c_int, [_H]),
+    "pf_graph_run": (C.c_int, [_H, C.c_int32]),
+    "pf_set_theta": (C.c_int, [_H, _D, C.c_uint32]),
+    "pf_reset": (C.c_int, [_H, C.c_uint32]),
+    "pf_get_state": (C.c_int, [_H, _D]),
+    "pf_set_state": (C.c_int, [_H, _D]),
+    "pf_get_logweights": (C.c_int, [_H, _D]),
+    "pf_get_ancestors": (C.c_int, [_H, _I]),
+    "pf_resample_u": (C.c_int, [_H, _D]),
+    "pf_simulate_doubles": (C.c_size_t, [C.POINTER(PfConfig)]),
+    "pf_simulate": (C.c_int, [C.POINTER(PfConfig), _D, C.c_uint64, C.c_void_p, C.c_size_t,
+                              C.c_void_p]),
+    "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
+                          C.c_double, _D, _D, _I]),
+    "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _D]),
+    "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
+    "pf_timing_get": (C.c_int, [_H, C.POINTER(PfTiming)]),
+    "pf_last_error": (C.c_char_p, []),
+    "pf_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (built by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build()")
+        L = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != PF_OK:
+        raise PfError(st, load().pf_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _ip(a):
+    return a.ctypes.data_as(_I)
+
+
+class _HostCfg:
+    """A pf_config plus the numpy arrays it points into."""
+
+    def __init__(self, pb, precision: Optional[int] = None, layout: int = PF_LAYOUT_PLAIN,
+                 theta=None, n_particles=None, seed: Optional[int] = None):
+        self.obs_idx = np.ascontiguousarray(pb.obs_idx, dtype=np.int32)
+        obs = pb.obs if pb.obs is not None else np.zeros((pb.T, len(self.obs_idx)))
+        self.obs = np.ascontiguousarray(obs, dtype=np.float64)
+        self.q = None if pb.q is None else np.ascontiguousarray(pb.q, dtype=np.float64)
+        th = pb.theta if theta is None else theta
+        self.theta = np.ascontiguousarray(np.atleast_2d(th), dtype=np.float64)
+        npart = pb.n_particles if n_particles is None else n_particles
+        self.n_particles = np.ascontiguousarray(np.atleast_1d(npart), dtype=np.int64)
+        prec = pb.precision if precision is None else precision
+        self.cfg = PfConfig(
+            pb.model, prec, layout, pb.d, pb.K, pb.T, pb.h, len(self.obs_idx),
+            _ip(self.obs_idx), pb.obs_sd, _dp(self.obs),
+            _dp(self.q) if self.q is not None else None,
+            self.theta.shape[0], self.theta.shape[1], self.n_particles.ctypes.data_as(
+                C.POINTER(C.c_int64)), _dp(self.theta), int(pb.seed if seed is None else seed))
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Filter:
+    """One handle over B filters (Alg. 2) on the current HIP device."""
+
+    def __init__(self, pb, precision: Optional[int] = None, layout: int = PF_LAYOUT_PLAIN,
+                 stream=None, seed: Optional[int] = None, device: str = "cuda"):
+        import torch
+        L = load()
+        self.pb = pb
+        self.hc = _HostCfg(pb, precision, layout, seed=seed)
+        self.precision = self.hc.cfg.precision
+        self.layout = layout
+        self.B = self.hc.cfg.B
+        self.d = pb.d
+        self.T = pb.T
+        self.n_total = int(self.hc.n_particles.sum())
+        self.offsets = np.concatenate([[0], np.cumsum(self.hc.n_particles)])
+        nbytes = L.pf_workspace_bytes(C.byref(self.hc.cfg))
+        if nbytes == 0:
+            _check(PF_E_INVAL)
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream
+        self._sh = _stream_handle(stream)
+        h = _H()
+        _check(L.pf_init(C.byref(self.hc.cfg), C.c_void_p(aligned), C.c_size_t(nbytes),
+                         C.c_void_p(self._sh), C.byref(h)))
+        self.h = h
+
+    # -- the filter
+    def step(self):
+        _check(load().pf_step(self.h))
+
+    def resample(self):
+        _check(load().pf_resample(self.h))
+
+    def resample_u(self, u):
+        u = np.ascontiguousarray(np.atleast_1d(u), dtype=np.float64)
+        _check(load().pf_resample_u(self.h, _dp(u)))
+
+    def advance(self, n: int = 1):
+        for _ in range(n):
+            self.step()
+            self.resample()
+
+    def graph_run(self, n: int):
+        _check(load().pf_graph_run(self.h, int(n)))
+
+    def loglik(self, allow_numeric: bool = False):
+        ll = np.zeros(self.B)
+        ess = np.zeros(self.B)
+        t = C.c_int32()
+        st = load().pf_loglik(self.h, _dp(ll), _dp(ess), C.byref(t))
+        if not (allow_numeric and st == PF_E_NUMERIC):
+            _check(st)
+        return ll, ess, t.value
+
+    def trace(self):
+        ell = np.zeros((self.B, self.T))
+        ess = np.zeros((self.B, self.T))
+        _check(load().pf_get_trace(self.h, _dp(ell), _dp(ess)))
+        return ell, ess
+
+    def set_theta(self, theta, iteration: int = 0):
+        th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+        _check(load().pf_set_theta(self.h, _dp(th), int(iteration)))
+
+    def reset(self, iteration: int = 0):
+        _check(load().pf_reset(self.h, int(iteration)))
+
+    # -- parameter inference / tuning
+    def pmmh(self, inputs, iters: Optional[int] = None):
+        """Alg. 3 chains, one per filter; ``inputs`` is a workloads.PmmhInputs."""
+        iters = inputs.z.shape[0] if iters is None else iters
+        lf0 = np.ascontiguousarray(inputs.log_f0[:self.B], dtype=np.float64)
+        z = np.ascontiguousarray(inputs.z[:iters, :self.B], dtype=np.float64)
+        al = np.ascontiguousarray(inputs.alpha[:iters, :self.B], dtype=np.float64)
+        lft = np.zeros((iters, self.B))
+        llt = np.zeros((iters, self.B))
+        acc = np.zeros(self.B, dtype=np.int32)
+        _check(load().pf_pmmh(self.h, int(iters), _dp(lf0), _dp(z), _dp(al), inputs.step_sd,
+                              inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
+                              _ip(acc)))
+        return dict(log_f=lft, ll=llt, accepts=acc)
+
+    def autotune(self, steps: int = 8):
+        choice = C.c_int32()
+        ms = np.zeros(3)
+        _check(load().pf_autotune(self.h, int(steps), C.byref(choice), _dp(ms)))
+        return choice.value, ms
+
+    # -- inspection / teacher forcing
+    def get_state(self) -> np.ndarray:
+        x = np.zeros((self.d, self.n_total))
+        _check(load().pf_get_state(self.h, _dp(x)))
+        return x
+
+    def set_state(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.d, self.n_total)
+        _check(load().pf_set_state(self.h, _dp(x)))
+
+    def logweights(self) -> np.ndarray:
+        lw = np.zeros(self.n_total)
+        _check(load().pf_get_logweights(self.h, _dp(lw)))
+        return lw
+
+    def ancestors(self) -> np.ndarray:
+        a = np.zeros(self.n_total, dtype=np.int32)
+        _check(load().pf_get_ancestors(self.h, _ip(a)))
+        return a
+
+    # -- measurement
+    def timing(self, on: bool = True):
+        _check(load().pf_timing_enable(self.h, 1 if on else 0))
+
+    def timing_get(self) -> dict:
+        t = PfTiming()
+        _check(load().pf_timing_get(self.h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in PfTiming._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().pf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate(pb, theta=None, data_seed: Optional[int] = None, stream=None, device: str = "cuda"):
+    """Synthetic truth [T+1, d] and observations [T, n_obs], simulated on the GPU."""
+    import torch
+    L = load()
+    th = np.ascontiguousarray(pb.data_theta if theta is None else theta, dtype=np.float64)
+    hc = _HostCfg(pb, theta=th[None, :], n_particles=[1])
+    n = L.pf_simulate_doubles(C.byref(hc.cfg))
+    buf = torch.zeros(int(n), dtype=torch.float64, device=device)
+    sh = _stream_handle(stream)
+    _check(L.pf_simulate(C.byref(hc.cfg), _dp(th), int(pb.data_seed if data_seed is None
+                                                         else data_seed),
+                         C.c_void_p(buf.data_ptr()), C.c_size_t(int(n)), C.c_void_p(sh)))
+    out = buf.cpu().numpy()
+    nx = (pb.T + 1) * pb.d
+    xt = out[:nx].reshape(pb.T + 1, pb.d)
+    y = out[nx:nx + pb.T * len(pb.obs_idx)].reshape(pb.T, len(pb.obs_idx))
+    return xt.copy(), y.copy()

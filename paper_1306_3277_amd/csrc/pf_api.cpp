@@ -1,0 +1,942 @@
+// Host runtime of the gfx950 particle filter: validates configurations,
+// carves the caller's workspace, launches the kernels, captures and replays
+// HIP graphs, and implements the inspection and timing calls of pf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_internal.hpp"
+
+using pfk::FilterState;
+using pfk::PlainArgs;
+using pfk::BatchArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+pf_status fail(pf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(PF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+bool l96_dim_ok(int d) { return d == 4 || d == 8 || d == 16 || d == 32 || d == 40; }
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+  int64_t n_total = 0;
+  std::vector<int64_t> off;     // [B+1]
+  std::vector<int64_t> boff0;   // [B] first block slot
+  std::vector<int32_t> nblk;    // [B]
+  std::vector<int64_t> bst0;    // [B] first merge-path boundary slot
+  int64_t bst_total = 0;
+  std::vector<int64_t> bj0;     // [B] first scan-block slot
+  int64_t bj_total = 0;
+  int64_t nblk_total = 0;
+  // byte offsets into the workspace
+  size_t x_cur, x_tmp, lw, counts, anc, part, boff, bstate, bjs, fs, ell, ess, theta, obs, obs_pos, obs_idx,
+      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, total;
+  int32_t n_chunks = 0;
+};
+
+pf_status validate(const pf_config* c) {
+  if (!c) return fail(PF_E_INVAL, "cfg is NULL");
+  if (c->model != PF_MODEL_WK && c->model != PF_MODEL_L96)
+    return fail(PF_E_INVAL, "model %d unknown", c->model);
+  if (c->precision != PF_FP64 && c->precision != PF_FP32_MIXED)
+    return fail(PF_E_INVAL, "precision %d unknown", c->precision);
+  if (c->layout != PF_LAYOUT_PLAIN && c->layout != PF_LAYOUT_BATCHED)
+    return fail(PF_E_INVAL, "layout %d unknown", c->layout);
+  if (c->model == PF_MODEL_WK) {
+    if (c->d != 1) return fail(PF_E_INVAL, "windkessel needs d = 1 (got %d)", c->d);
+    if (c->n_obs != 1) return fail(PF_E_INVAL, "windkessel needs n_obs = 1");
+    if (c->n_theta != 6) return fail(PF_E_INVAL, "windkessel needs n_theta = 6");
+  } else {
+    if (!l96_dim_ok(c->d))
+      return fail(PF_E_INVAL, "Lorenz '96 d must be one of 4, 8, 16, 32, 40 (got %d)", c->d);
+    if (c->n_theta != 2) return fail(PF_E_INVAL, "Lorenz '96 needs n_theta = 2");
+  }
+  if (c->K < 1) return fail(PF_E_INVAL, "K must be >= 1");
+  if (c->T < 1) return fail(PF_E_INVAL, "T must be >= 1");
+  if ((int64_t)c->T * c->K >= (1LL << 31)) return fail(PF_E_INVAL, "T*K too large");
+  if (!(c->h > 0.0) || !std::isfinite(c->h)) return fail(PF_E_INVAL, "h must be positive");
+  if (c->n_obs < 1 || c->n_obs > c->d) return fail(PF_E_INVAL, "n_obs out of range");
+  if (!c->obs_idx) return fail(PF_E_INVAL, "obs_idx is NULL");
+  for (int o = 0; o < c->n_obs; ++o) {
+    if (c->obs_idx[o] < 0 || c->obs_idx[o] >= c->d)
+      return fail(PF_E_INVAL, "obs_idx[%d] = %d out of range", o, c->obs_idx[o]);
+    if (o > 0 && c->obs_idx[o] <= c->obs_idx[o - 1])
+      return fail(PF_E_INVAL, "obs_idx must be strictly increasing");
+  }
+  if (!(c->obs_sd > 0.0) || !std::isfinite(c->obs_sd))
+    return fail(PF_E_INVAL, "obs_sd must be positive");
+  if (!c->obs) return fail(PF_E_INVAL, "obs is NULL");
+  for (int64_t i = 0; i < (int64_t)c->T * c->n_obs; ++i)
+    if (!std::isfinite(c->obs[i])) return fail(PF_E_INVAL, "obs[%lld] is not finite", (long long)i);
+  if (c->model == PF_MODEL_WK) {
+    if (!c->q) return fail(PF_E_INVAL, "windkessel needs the flow series q");
+    for (int64_t i = 0; i <= (int64_t)c->T * c->K; ++i)
+      if (!std::isfinite(c->q[i])) return fail(PF_E_INVAL, "q[%lld] is not finite", (long long)i);
+  }
+  if (c->B < 1) return fail(PF_E_INVAL, "B must be >= 1");
+  if (!c->n_particles || !c->theta) return fail(PF_E_INVAL, "n_particles or theta is NULL");
+  int64_t tot = 0;
+  for (int b = 0; b < c->B; ++b) {
+    const int64_t n = c->n_particles[b];
+    if (n < 1) return fail(PF_E_INVAL, "n_particles[%d] = %lld must be >= 1", b, (long long)n);
+    if (n > 2147483647LL) return fail(PF_E_INVAL, "n_particles[%d] too large", b);
+    if (c->layout == PF_LAYOUT_BATCHED && n > PF_BATCHED_MAX_PARTICLES)
+      return fail(PF_E_INVAL, "batched layout needs n_particles <= %d (filter %d has %lld)",
+                  PF_BATCHED_MAX_PARTICLES, b, (long long)n);
+    tot += n;
+    for (int i = 0; i < c->n_theta; ++i)
+      if (!std::isfinite(c->theta[(int64_t)b * c->n_theta + i]))
+        return fail(PF_E_INVAL, "theta[%d][%d] is not finite", b, i);
+  }
+  if (tot > 2147483647LL) return fail(PF_E_INVAL, "total particles exceed 2^31 - 1");
+  if (c->model == PF_MODEL_WK) {
+    for (int b = 0; b < c->B; ++b)
+      if (c->theta[(int64_t)b * 6 + 3] < 0 || c->theta[(int64_t)b * 6 + 5] < 0)
+        return fail(PF_E_INVAL, "windkessel sds must be >= 0");
+  } else {
+    for (int b = 0; b < c->B; ++b)
+      if (c->theta[(int64_t)b * 2 + 1] < 0) return fail(PF_E_INVAL, "sigma must be >= 0");
+  }
+  return PF_OK;
+}
+
+Layout make_layout(const pf_config* c) {
+  Layout L;
+  const size_t sx = c->precision == PF_FP64 ? 8 : 4;
+  L.off.assign(c->B + 1, 0);
+  L.boff0.assign(c->B, 0);
+  L.nblk.assign(c->B, 0);
+  L.bst0.assign(c->B, 0);
+  L.bj0.assign(c->B, 0);
+  for (int b = 0; b < c->B; ++b) {
+    L.bj0[b] = L.bj_total;
+    L.bj_total += (c->n_particles[b] + pfk::K3_SPAN - 1) / pfk::K3_SPAN;
+    L.bst0[b] = L.bst_total;
+    L.bst_total += (2 * c->n_particles[b] + pfk::K4_DB - 1) / pfk::K4_DB + 1;
+    L.off[b + 1] = L.off[b] + c->n_particles[b];
+    L.nblk[b] = (int32_t)((c->n_particles[b] + pfk::K1_NT - 1) / pfk::K1_NT);
+    L.boff0[b] = L.nblk_total;
+    L.nblk_total += L.nblk[b];
+  }
+  L.n_total = L.off[c->B];
+  {
+    int64_t nc = 0;
+    for (int b = 0; b < c->B; ++b) nc += (c->n_particles[b] + pfk::BATCH_NT - 1) / pfk::BATCH_NT;
+    L.n_chunks = (int32_t)nc;
+  }
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = p;
+    p = align256(p + bytes);
+    return at;
+  };
+  const int64_t N = L.n_total;
+  L.x_cur = take(sx * c->d * N);
+  L.x_tmp = take(sx * c->d * N);
+  L.lw = take(8 * N);  // log-weights are FP64 in both precisions
+  L.counts = take(4 * N);
+  L.anc = take(4 * N);
+  L.part = take(24 * L.nblk_total);
+  L.boff = take(8 * (L.nblk_total + c->B));  // nblk + 1 offsets per filter
+  L.bstate = take(4 * L.bst_total);
+  L.bjs = take(4 * L.bj_total);
+  L.fs = take(sizeof(FilterState) * c->B);
+  L.ell = take(8 * (size_t)c->B * c->T);
+  L.ess = take(8 * (size_t)c->B * c->T);
+  L.theta = take(8 * 8 * (size_t)c->B);
+  L.obs = take(8 * (size_t)c->T * c->n_obs);
+  L.obs_pos = take(4 * (size_t)c->d);
+  L.obs_idx = take(4 * (size_t)c->n_obs);
+  L.q = take(c->model == PF_MODEL_WK ? 8 * ((size_t)c->T * c->K + 1) : 8);
+  L.b_off = take(8 * (size_t)(c->B + 1));
+  L.b_order = take(4 * (size_t)c->B);
+  L.b_chunk_f = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
+  L.b_chunk_k = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
+  L.b_u = take(8 * (size_t)c->B);
+  L.total = p;
+  return L;
+}
+
+// derived parameters: WK as given; L96 (F, sigma*sqrt(h))
+void derive_theta(const pf_config* c, const double* theta_in, std::vector<double>& out) {
+  out.assign((size_t)c->B * 8, 0.0);
+  for (int b = 0; b < c->B; ++b) {
+    const double* t = theta_in + (size_t)b * c->n_theta;
+    double* o = out.data() + (size_t)b * 8;
+    if (c->model == PF_MODEL_WK) {
+      for (int i = 0; i < 6; ++i) o[i] = t[i];
+    } else {
+      o[0] = t[0];
+      o[1] = t[1] * std::sqrt(c->h);
+    }
+  }
+}
+
+}  // namespace
+
+struct pf_handle {
+  pf_config cfg{};           // host pointers cleared after init
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int phase = 0;             // 0: equally weighted (ready to step), 1: weighted
+  int32_t t = 0;
+  uint32_t iter = 0;
+  bool resampled_once = false;
+  bool stepped_once = false;
+  std::vector<int64_t> np;
+  std::vector<double> theta_host;  // [B][n_theta]
+  int batch_nt = 256;              // K5b workgroup size (autotuned)
+  // timing
+  bool timing = false;
+  struct Ev {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Ev> events;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool alive = true;
+
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+namespace {
+
+PlainArgs plain_args(const pf_handle* H, int b) {
+  const pf_config& c = H->cfg;
+  PlainArgs a{};
+  a.N = H->np[b];
+  a.ld = H->L.n_total;
+  a.off = H->L.off[b];
+  a.boff0 = H->L.boff0[b];
+  a.bst0 = H->L.bst0[b];
+  a.bj0 = H->L.bj0[b];
+  a.nblk = H->L.nblk[b];
+  a.K = c.K;
+  a.T = c.T;
+  a.d = c.d;
+  a.n_obs = c.n_obs;
+  a.b = (uint32_t)b;
+  a.key.lo = (uint32_t)(c.seed & 0xffffffffu);
+  a.key.hi = (uint32_t)(c.seed >> 32);
+  a.h = c.h;
+  a.hh = 0.5 * c.h;
+  a.h6 = c.h / 6.0;
+  a.inv_sd = 1.0 / c.obs_sd;
+  a.lw_cst = -(double)c.n_obs * (std::log(c.obs_sd) + 0.5 * 1.8378770664093454836);
+  a.theta = H->at<double>(H->L.theta) + (size_t)b * 8;
+  a.obs = H->at<double>(H->L.obs);
+  a.obs_pos = H->at<int32_t>(H->L.obs_pos);
+  a.obs_idx = H->at<int32_t>(H->L.obs_idx);
+  a.q = c.model == PF_MODEL_WK ? H->at<double>(H->L.q) : nullptr;
+  a.fs = H->at<FilterState>(H->L.fs) + b;
+  a.ell_tr = H->at<double>(H->L.ell) + (size_t)b * c.T;
+  a.ess_tr = H->at<double>(H->L.ess) + (size_t)b * c.T;
+  return a;
+}
+
+BatchArgs batch_args(const pf_handle* H) {
+  const pf_config& c = H->cfg;
+  BatchArgs a{};
+  a.B = c.B;
+  a.K = c.K;
+  a.T = c.T;
+  a.d = c.d;
+  a.n_obs = c.n_obs;
+  a.key.lo = (uint32_t)(c.seed & 0xffffffffu);
+  a.key.hi = (uint32_t)(c.seed >> 32);
+  a.ld = H->L.n_total;
+  a.n_chunks = H->L.n_chunks;
+  a.h = c.h;
+  a.hh = 0.5 * c.h;
+  a.h6 = c.h / 6.0;
+  a.inv_sd = 1.0 / c.obs_sd;
+  a.lw_cst = -(double)c.n_obs * (std::log(c.obs_sd) + 0.5 * 1.8378770664093454836);
+  a.theta = H->at<double>(H->L.theta);
+  a.obs = H->at<double>(H->L.obs);
+  a.obs_pos = H->at<int32_t>(H->L.obs_pos);
+  a.q = c.model == PF_MODEL_WK ? H->at<double>(H->L.q) : nullptr;
+  a.off = H->at<int64_t>(H->L.b_off);
+  a.order = H->at<int32_t>(H->L.b_order);
+  a.chunk_f = H->at<int32_t>(H->L.b_chunk_f);
+  a.chunk_k = H->at<int32_t>(H->L.b_chunk_k);
+  a.fs = H->at<FilterState>(H->L.fs);
+  a.ell_tr = H->at<double>(H->L.ell);
+  a.ess_tr = H->at<double>(H->L.ess);
+  a.u_override = H->at<double>(H->L.b_u);
+  a.mode = 0;
+  return a;
+}
+
+pf_status ev_begin(pf_handle* H, hipEvent_t* e) {
+  if (!H->timing) return PF_OK;
+  HIP_TRY(hipEventCreate(e));
+  HIP_TRY(hipEventRecord(*e, H->stream));
+  return PF_OK;
+}
+pf_status ev_end(pf_handle* H, hipEvent_t a, int kind) {
+  if (!H->timing) return PF_OK;
+  hipEvent_t b;
+  HIP_TRY(hipEventCreate(&b));
+  HIP_TRY(hipEventRecord(b, H->stream));
+  H->events.push_back({a, b, kind});
+  return PF_OK;
+}
+
+pf_status check_handle(pf_handle* H) {
+  if (!H) return fail(PF_E_INVAL, "handle is NULL");
+  if (!H->alive) return fail(PF_E_STATE, "handle was destroyed");
+  return PF_OK;
+}
+
+// init kernels for every filter (fresh x(t0), scalars and traces cleared)
+pf_status do_init(pf_handle* H, hipStream_t s) {
+  const pf_config& c = H->cfg;
+  HIP_TRY(pfk::launch_reset(H->at<FilterState>(H->L.fs), H->at<double>(H->L.ell),
+                            H->at<double>(H->L.ess), c.B, c.T, H->iter, s));
+  if (c.layout == PF_LAYOUT_PLAIN) {
+    for (int b = 0; b < c.B; ++b) {
+      PlainArgs a = plain_args(H, b);
+      HIP_TRY(pfk::launch_init(c.model, c.d, c.precision, H->ws + H->L.x_cur, a, s));
+    }
+  } else {
+    BatchArgs a = batch_args(H);
+    HIP_TRY(pfk::launch_batched_init(c.model, c.d, c.precision, H->ws + H->L.x_cur,
+                                     H->at<int32_t>(H->L.anc), a, s));
+  }
+  H->t = 0;
+  H->phase = 0;
+  return PF_OK;
+}
+
+pf_status enqueue_step(pf_handle* H, hipStream_t s) {
+  const pf_config& c = H->cfg;
+  if (c.layout == PF_LAYOUT_BATCHED) {
+    BatchArgs a = batch_args(H);
+    hipEvent_t e0{};
+    pf_status st = ev_begin(H, &e0);
+    if (st) return st;
+    HIP_TRY(pfk::launch_batched_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
+                                          H->ws + H->L.x_tmp, H->at<double>(H->L.lw),
+                                          H->at<int32_t>(H->L.anc), a, s));
+    if ((st = ev_end(H, e0, 0))) return st;
+    if ((st = ev_begin(H, &e0))) return st;
+    HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
+                                         H->at<int32_t>(H->L.anc), a, s));
+    if ((st = ev_end(H, e0, 4))) return st;
+    return PF_OK;
+  }
+  for (int b = 0; b < c.B; ++b) {
+    PlainArgs a = plain_args(H, b);
+    hipEvent_t e0{};
+    pf_status st = ev_begin(H, &e0);
+    if (st) return st;
+    HIP_TRY(pfk::launch_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
+                                  H->ws + H->L.x_tmp, H->ws + H->L.lw,
+                                  H->at<double>(H->L.part), a, s));
+    if ((st = ev_end(H, e0, 0))) return st;
+    if ((st = ev_begin(H, &e0))) return st;
+    HIP_TRY(pfk::launch_combine(H->at<double>(H->L.part), H->at<double>(H->L.boff), a, s));
+    if ((st = ev_end(H, e0, 1))) return st;
+  }
+  return PF_OK;
+}
+
+pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
+  const pf_config& c = H->cfg;
+  if (c.layout == PF_LAYOUT_BATCHED) {
+    // the ancestors were drawn with the step; the gather happens in the next
+    // step's state load.  Given uniforms redraw them without touching the
+    // likelihood.
+    if (!u) return PF_OK;
+    HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_u, u, 8 * (size_t)c.B, hipMemcpyHostToDevice, s));
+    BatchArgs a = batch_args(H);
+    a.mode = 1;
+    HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
+                                         H->at<int32_t>(H->L.anc), a, s));
+    HIP_TRY(hipStreamSynchronize(s));  // u is a host array
+    return PF_OK;
+  }
+  for (int b = 0; b < c.B; ++b) {
+    PlainArgs a = plain_args(H, b);
+    if (u) HIP_TRY(pfk::launch_set_u(a.fs, u[b], s));
+    hipEvent_t e0{};
+    pf_status st = ev_begin(H, &e0);
+    if (st) return st;
+    HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
+                                   H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
+                                   H->at<int32_t>(H->L.bjs), a, s));
+    if ((st = ev_end(H, e0, 2))) return st;
+    if ((st = ev_begin(H, &e0))) return st;
+    HIP_TRY(pfk::launch_merge_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.counts),
+                                     H->at<int32_t>(H->L.bstate), H->at<int32_t>(H->L.bjs),
+                                     H->ws + H->L.x_tmp,
+                                     H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
+    if ((st = ev_end(H, e0, 3))) return st;
+  }
+  return PF_OK;
+}
+
+pf_status upload_theta(pf_handle* H, const double* theta) {
+  std::vector<double> th;
+  derive_theta(&H->cfg, theta, th);
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.theta, th.data(), th.size() * 8, hipMemcpyHostToDevice,
+                         H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  H->theta_host.assign(theta, theta + (size_t)H->cfg.B * H->cfg.n_theta);
+  return PF_OK;
+}
+
+pf_status require_device() {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(PF_E_DEVICE, "device %d is %s; this library is built for gfx950", dev,
+                prop.gcnArchName);
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+const char* pf_version(void) { return "pfmi-gfx950 0.1"; }
+
+size_t pf_workspace_bytes(const pf_config* cfg) {
+  if (validate(cfg) != PF_OK) return 0;
+  return make_layout(cfg).total;
+}
+
+pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                  pf_handle** out) {
+  g_err.clear();
+  if (!out) return fail(PF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  pf_status st = validate(cfg);
+  if (st) return st;
+  Layout L = make_layout(cfg);
+  if (!d_workspace) return fail(PF_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_E_INVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(PF_E_INVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  if ((st = require_device())) return st;
+
+  pf_handle* H = new pf_handle();
+  H->cfg = *cfg;
+  H->L = L;
+  H->stream = (hipStream_t)hip_stream;
+  H->ws = (char*)d_workspace;
+  H->np.assign(cfg->n_particles, cfg->n_particles + cfg->B);
+  const pf_config& c = *cfg;
+  hipStream_t s = H->stream;
+  // host arrays -> device
+  std::vector<int32_t> pos(c.d, -1);
+  for (int o = 0; o < c.n_obs; ++o) pos[c.obs_idx[o]] = o;
+  auto cp = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    return hipMemcpyAsync(H->ws + off, src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = cp(L.obs, c.obs, 8 * (size_t)c.T * c.n_obs);
+  if (e == hipSuccess) e = cp(L.obs_pos, pos.data(), 4 * (size_t)c.d);
+  if (e == hipSuccess) e = cp(L.obs_idx, c.obs_idx, 4 * (size_t)c.n_obs);
+  if (e == hipSuccess && c.model == PF_MODEL_WK) e = cp(L.q, c.q, 8 * ((size_t)c.T * c.K + 1));
+  // filters largest first (longest-processing-time order) and their chunks
+  std::vector<int32_t> order(c.B);
+  for (int b = 0; b < c.B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return c.n_particles[x] > c.n_particles[y];
+  });
+  std::vector<int32_t> chf, chk;
+  chf.reserve(L.n_chunks);
+  chk.reserve(L.n_chunks);
+  for (int32_t b : order)
+    for (int64_t k = 0; k < c.n_particles[b]; k += pfk::BATCH_NT) {
+      chf.push_back(b);
+      chk.push_back((int32_t)k);
+    }
+  if (e == hipSuccess) e = cp(L.b_off, L.off.data(), 8 * (size_t)(c.B + 1));
+  if (e == hipSuccess) e = cp(L.b_order, order.data(), 4 * (size_t)c.B);
+  if (e == hipSuccess) e = cp(L.b_chunk_f, chf.data(), 4 * chf.size());
+  if (e == hipSuccess) e = cp(L.b_chunk_k, chk.data(), 4 * chk.size());
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete H;
+    return fail(PF_E_DEVICE, "copying the configuration failed: %s", hipGetErrorString(e));
+  }
+  if ((st = upload_theta(H, c.theta))) {
+    delete H;
+    return st;
+  }
+  H->cfg.obs = nullptr;
+  H->cfg.obs_idx = nullptr;
+  H->cfg.q = nullptr;
+  H->cfg.n_particles = nullptr;
+  H->cfg.theta = nullptr;
+  if ((st = do_init(H, s))) {
+    delete H;
+    return st;
+  }
+  *out = H;
+  return PF_OK;
+}
+
+pf_status pf_step(pf_handle* H) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (H->phase != 0) return fail(PF_E_STATE, "pf_step called twice without pf_resample");
+  if (H->t >= H->cfg.T) return fail(PF_E_STATE, "all %d observations already processed", H->cfg.T);
+  if ((st = enqueue_step(H, H->stream))) return st;
+  H->t += 1;
+  H->phase = 1;
+  return PF_OK;
+}
+
+pf_status pf_resample(pf_handle* H) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (H->phase != 1) return fail(PF_E_STATE, "pf_resample needs a preceding pf_step");
+  if ((st = enqueue_resample(H, H->stream, nullptr))) return st;
+  H->phase = 0;
+  return PF_OK;
+}
+
+pf_status pf_resample_u(pf_handle* H, const double* u) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!u) return fail(PF_E_INVAL, "u is NULL");
+  for (int b = 0; b < H->cfg.B; ++b)
+    if (!(u[b] >= 0.0 && u[b] < 1.0)) return fail(PF_E_INVAL, "u[%d] must lie in [0, 1)", b);
+  if (H->phase != 1) return fail(PF_E_STATE, "pf_resample_u needs a preceding pf_step");
+  if ((st = enqueue_resample(H, H->stream, u))) return st;
+  H->phase = 0;
+  return PF_OK;
+}
+
+pf_status pf_loglik(pf_handle* H, double* loglik_out, double* ess_out, int32_t* t_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!loglik_out) return fail(PF_E_INVAL, "loglik_out is NULL");
+  std::vector<FilterState> fs(H->cfg.B);
+  HIP_TRY(hipMemcpyAsync(fs.data(), H->ws + H->L.fs, sizeof(FilterState) * fs.size(),
+                         hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  bool numeric = false;
+  for (int b = 0; b < H->cfg.B; ++b)
+    if (fs[b].pad != 0)
+      return fail(PF_E_DEVICE, "internal resampling inconsistency flagged on filter %d", b);
+  for (int b = 0; b < H->cfg.B; ++b) {
+    loglik_out[b] = fs[b].status ? -INFINITY : fs[b].loglik;
+    if (ess_out) ess_out[b] = fs[b].ess;
+    numeric |= fs[b].status != 0;
+  }
+  if (t_out) *t_out = H->t;
+  if (numeric) return fail(PF_E_NUMERIC, "a filter met a step with no positive finite weight");
+  return PF_OK;
+}
+
+pf_status pf_get_trace(pf_handle* H, double* ell_out, double* ess_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  const size_t n = (size_t)H->cfg.B * H->cfg.T;
+  if (ell_out)
+    HIP_TRY(hipMemcpyAsync(ell_out, H->ws + H->L.ell, 8 * n, hipMemcpyDeviceToHost, H->stream));
+  if (ess_out)
+    HIP_TRY(hipMemcpyAsync(ess_out, H->ws + H->L.ess, 8 * n, hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  return PF_OK;
+}
+
+pf_status pf_destroy(pf_handle* H) {
+  if (!H) return fail(PF_E_INVAL, "handle is NULL");
+  if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
+  if (H->graph) (void)hipGraphDestroy(H->graph);
+  if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
+  for (auto& ev : H->events) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  H->alive = false;
+  delete H;
+  return PF_OK;
+}
+
+pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (n_steps < 0) return fail(PF_E_INVAL, "n_steps must be >= 0");
+  if (H->phase != 0) return fail(PF_E_STATE, "pf_graph_run needs a resampled particle set");
+  if (H->t + n_steps > H->cfg.T)
+    return fail(PF_E_STATE, "%d steps from t = %d exceed T = %d", n_steps, H->t, H->cfg.T);
+  if (n_steps == 0) return PF_OK;
+  if (!H->gexec) {
+    // capture on the caller's stream, or on a blocking stream of our own when
+    // the caller uses the null stream (which cannot be captured)
+    hipStream_t cs = H->stream;
+    if (!cs) {
+      HIP_TRY(hipStreamCreate(&H->cap_stream));
+      cs = H->cap_stream;
+    }
+    const bool tm = H->timing;
+    H->timing = false;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    pf_status s1 = enqueue_step(H, cs);
+    if (!s1) s1 = enqueue_resample(H, cs, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    H->timing = tm;
+    if (s1) return s1;
+    if (e != hipSuccess) return fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    H->graph = g;
+    HIP_TRY(hipGraphInstantiate(&H->gexec, H->graph, nullptr, nullptr, 0));
+  }
+  hipStream_t ls = H->cap_stream ? H->cap_stream : H->stream;
+  for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(H->gexec, ls));
+  H->t += n_steps;
+  return PF_OK;
+}
+
+pf_status pf_set_theta(pf_handle* H, const double* theta, uint32_t iteration) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!theta) return fail(PF_E_INVAL, "theta is NULL");
+  if (iteration >= (1u << 20)) return fail(PF_E_INVAL, "iteration must be < 2^20");
+  for (int64_t i = 0; i < (int64_t)H->cfg.B * H->cfg.n_theta; ++i)
+    if (!std::isfinite(theta[i])) return fail(PF_E_INVAL, "theta[%lld] not finite", (long long)i);
+  if ((st = upload_theta(H, theta))) return st;
+  H->iter = iteration;
+  return do_init(H, H->stream);
+}
+
+pf_status pf_reset(pf_handle* H, uint32_t iteration) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (iteration >= (1u << 20)) return fail(PF_E_INVAL, "iteration must be < 2^20");
+  H->iter = iteration;
+  return do_init(H, H->stream);
+}
+
+// Buffer holding the propagated state of the last step (batched layout: the
+// step-s state lives in buffer s % 2; buffer 0 holds x(t0)).
+static size_t batched_buf(const pf_handle* H, int32_t t) {
+  return (t & 1) ? H->L.x_tmp : H->L.x_cur;
+}
+
+pf_status pf_get_state(pf_handle* H, double* x_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!x_out) return fail(PF_E_INVAL, "x_out is NULL");
+  const size_t n = (size_t)H->cfg.d * H->L.n_total;
+  size_t src = H->phase == 0 ? H->L.x_cur : H->L.x_tmp;
+  if (H->cfg.layout == PF_LAYOUT_BATCHED) {
+    src = batched_buf(H, H->t);
+    if (H->phase == 0) {  // equally weighted set = propagated[ancestors]
+      const size_t spare = batched_buf(H, H->t + 1);
+      BatchArgs a = batch_args(H);
+      HIP_TRY(pfk::launch_batched_gather(H->cfg.precision, H->ws + src, H->at<int32_t>(H->L.anc),
+                                         H->ws + spare, a, H->stream));
+      src = spare;
+    }
+  }
+  if (H->cfg.precision == PF_FP64) {
+    HIP_TRY(hipMemcpyAsync(x_out, H->ws + src, 8 * n, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+  } else {
+    std::vector<float> tmp(n);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), H->ws + src, 4 * n, hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    for (size_t i = 0; i < n; ++i) x_out[i] = tmp[i];
+  }
+  return PF_OK;
+}
+
+pf_status pf_set_state(pf_handle* H, const double* x_in) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!x_in) return fail(PF_E_INVAL, "x_in is NULL");
+  if (H->phase != 0) return fail(PF_E_STATE, "pf_set_state only between intervals");
+  const size_t n = (size_t)H->cfg.d * H->L.n_total;
+  const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
+  const size_t dst = batched ? batched_buf(H, H->t) : H->L.x_cur;
+  if (H->cfg.precision == PF_FP64) {
+    HIP_TRY(hipMemcpyAsync(H->ws + dst, x_in, 8 * n, hipMemcpyHostToDevice, H->stream));
+  } else {
+    std::vector<float> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (float)x_in[i];
+    HIP_TRY(hipMemcpyAsync(H->ws + dst, tmp.data(), 4 * n, hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+  }
+  if (batched) {  // the next step reads the given particles as they are
+    std::vector<int32_t> ident((size_t)H->L.n_total);
+    for (int b = 0; b < H->cfg.B; ++b)
+      for (int64_t k = 0; k < H->np[b]; ++k) ident[(size_t)(H->L.off[b] + k)] = (int32_t)k;
+    HIP_TRY(hipMemcpyAsync(H->ws + H->L.anc, ident.data(), 4 * ident.size(),
+                           hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  return PF_OK;
+}
+
+pf_status pf_get_logweights(pf_handle* H, double* lw_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!lw_out) return fail(PF_E_INVAL, "lw_out is NULL");
+  if (H->t == 0) return fail(PF_E_STATE, "no step taken yet");
+  HIP_TRY(hipMemcpyAsync(lw_out, H->ws + H->L.lw, 8 * (size_t)H->L.n_total,
+                         hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  return PF_OK;
+}
+
+pf_status pf_get_ancestors(pf_handle* H, int32_t* a_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!a_out) return fail(PF_E_INVAL, "a_out is NULL");
+  HIP_TRY(hipMemcpyAsync(a_out, H->ws + H->L.anc, 4 * (size_t)H->L.n_total,
+                         hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  return PF_OK;
+}
+
+static size_t sim_out_doubles(const pf_config* c) {
+  return (size_t)(c->T + 1) * c->d + (size_t)c->T * c->n_obs;
+}
+static size_t sim_scratch_doubles(const pf_config* c) {
+  const size_t nq = c->model == PF_MODEL_WK ? ((size_t)c->T * c->K + 1) : 0;
+  return 8 + nq + ((size_t)c->n_obs + 1) / 2;
+}
+
+size_t pf_simulate_doubles(const pf_config* cfg) {
+  if (!cfg) return 0;
+  return sim_out_doubles(cfg) + sim_scratch_doubles(cfg) + 32;
+}
+
+pf_status pf_simulate(const pf_config* cfg, const double* theta, uint64_t data_seed,
+                      double* d_out, size_t out_doubles, void* hip_stream) {
+  g_err.clear();
+  if (!cfg || !theta || !d_out) return fail(PF_E_INVAL, "NULL argument");
+  pf_config c = *cfg;
+  // the filter-only fields are not needed here
+  std::vector<double> dummy_obs((size_t)c.T * c.n_obs, 0.0);
+  int64_t one = 1;
+  c.obs = dummy_obs.data();
+  c.B = 1;
+  c.n_particles = &one;
+  c.theta = theta;
+  c.layout = PF_LAYOUT_PLAIN;
+  pf_status st = validate(&c);
+  if (st) return st;
+  if (out_doubles < pf_simulate_doubles(&c))
+    return fail(PF_E_INVAL, "output buffer has %zu doubles, needs %zu", out_doubles,
+                pf_simulate_doubles(&c));
+  if ((st = require_device())) return st;
+  hipStream_t s = (hipStream_t)hip_stream;
+  std::vector<double> th;
+  derive_theta(&c, theta, th);
+  const size_t nq = c.model == PF_MODEL_WK ? ((size_t)c.T * c.K + 1) : 0;
+  // scratch after the outputs, 256-byte aligned
+  const size_t base = (sim_out_doubles(&c) + 31) & ~(size_t)31;
+  double* dth = d_out + base;
+  double* dq = dth + 8;
+  int32_t* didx = (int32_t*)(dq + nq);
+  HIP_TRY(hipMemcpyAsync(dth, th.data(), 64, hipMemcpyHostToDevice, s));
+  if (nq) HIP_TRY(hipMemcpyAsync(dq, c.q, 8 * nq, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(didx, c.obs_idx, 4 * (size_t)c.n_obs, hipMemcpyHostToDevice, s));
+  PlainArgs a{};
+  a.K = c.K;
+  a.T = c.T;
+  a.d = c.d;
+  a.n_obs = c.n_obs;
+  a.key.lo = (uint32_t)(data_seed & 0xffffffffu);
+  a.key.hi = (uint32_t)(data_seed >> 32);
+  a.h = c.h;
+  a.hh = 0.5 * c.h;
+  a.h6 = c.h / 6.0;
+  a.theta = dth;
+  a.q = nq ? dq : nullptr;
+  a.obs_idx = didx;
+  HIP_TRY(pfk::launch_simulate(c.model, c.d, d_out, a, c.obs_sd, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+// Advance every filter through all T intervals from a fresh start, through
+// the captured graph.
+static pf_status run_full(pf_handle* H) {
+  pf_status st = pf_graph_run(H, H->cfg.T - H->t);
+  if (st) return st;
+  H->phase = 0;
+  return PF_OK;
+}
+
+pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const double* z,
+                  const double* alpha, double step_sd, double f_lo, double f_hi, double sigma,
+                  double* log_f_trace, double* ll_trace, int32_t* accepts) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  const pf_config& c = H->cfg;
+  if (c.model != PF_MODEL_L96) return fail(PF_E_INVAL, "pf_pmmh needs the Lorenz '96 model");
+  if (iters < 0 || iters + 1 >= (1 << 20)) return fail(PF_E_INVAL, "iters out of range");
+  if (!log_f0 || (iters > 0 && (!z || !alpha || !log_f_trace || !ll_trace)) || !accepts)
+    return fail(PF_E_INVAL, "NULL argument");
+  if (!(step_sd >= 0.0) || !(f_lo < f_hi) || !(sigma >= 0.0))
+    return fail(PF_E_INVAL, "step_sd, prior bounds or sigma invalid");
+  const int B = c.B;
+  std::vector<double> th(B), thp(B), ll(B), llp(B), theta(2 * (size_t)B), ess(B);
+  for (int b = 0; b < B; ++b) {
+    th[b] = log_f0[b];
+    theta[2 * b] = std::exp(th[b]);
+    theta[2 * b + 1] = sigma;
+    accepts[b] = 0;
+  }
+  // initial estimate with iteration field 0
+  if ((st = pf_set_theta(H, theta.data(), 0))) return st;
+  if ((st = run_full(H))) return st;
+  st = pf_loglik(H, ll.data(), ess.data(), nullptr);
+  if (st && st != PF_E_NUMERIC) return st;
+  std::vector<char> inside(B);
+  for (int32_t i = 0; i < iters; ++i) {
+    for (int b = 0; b < B; ++b) {
+      thp[b] = th[b] + step_sd * z[(size_t)i * B + b];
+      const double Fp = std::exp(thp[b]);
+      inside[b] = (Fp >= f_lo && Fp <= f_hi);
+      // a proposal outside the prior's support is rejected without a filter
+      // estimate; its filter slot reruns the current value meanwhile
+      theta[2 * b] = inside[b] ? Fp : std::exp(th[b]);
+    }
+    if ((st = pf_set_theta(H, theta.data(), (uint32_t)(i + 1)))) return st;
+    if ((st = run_full(H))) return st;
+    st = pf_loglik(H, llp.data(), ess.data(), nullptr);
+    if (st && st != PF_E_NUMERIC) return st;
+    for (int b = 0; b < B; ++b) {
+      if (inside[b] && std::log(alpha[(size_t)i * B + b]) <= (llp[b] - ll[b]) + (thp[b] - th[b])) {
+        th[b] = thp[b];
+        ll[b] = llp[b];
+        accepts[b] += 1;
+      }
+      log_f_trace[(size_t)i * B + b] = th[b];
+      ll_trace[(size_t)i * B + b] = ll[b];
+    }
+  }
+  g_err.clear();
+  return PF_OK;
+}
+
+pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* choice_out, double* ms_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (steps < 1) return fail(PF_E_INVAL, "steps must be >= 1");
+  if (H->cfg.layout != PF_LAYOUT_BATCHED) {
+    if (choice_out) *choice_out = 0;
+    return pf_reset(H, H->iter);
+  }
+  const int cand[3] = {256, 512, 1024};
+  double best = 1e300;
+  int best_nt = H->batch_nt;
+  const bool tm = H->timing;
+  H->timing = false;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int n = steps < H->cfg.T ? steps : H->cfg.T;
+  for (int ci = 0; ci < 3; ++ci) {
+    H->batch_nt = cand[ci];
+    if ((st = pf_reset(H, H->iter))) break;
+    // one untimed interval, then n timed
+    if ((st = enqueue_step(H, H->stream))) break;
+    HIP_TRY(hipEventRecord(e0, H->stream));
+    for (int i = 1; i < n && !st; ++i) st = enqueue_step(H, H->stream);
+    if (st) break;
+    HIP_TRY(hipEventRecord(e1, H->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    const double per = n > 1 ? ms / (n - 1) : ms;
+    if (ms_out) ms_out[ci] = per;
+    if (per < best) {
+      best = per;
+      best_nt = cand[ci];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  H->timing = tm;
+  if (st) return st;
+  H->batch_nt = best_nt;
+  if (H->gexec) {  // the captured graph holds the old launch shape
+    (void)hipGraphExecDestroy(H->gexec);
+    (void)hipGraphDestroy(H->graph);
+    H->gexec = nullptr;
+    H->graph = nullptr;
+  }
+  if (choice_out) *choice_out = best_nt;
+  return pf_reset(H, H->iter);
+}
+
+pf_status pf_timing_enable(pf_handle* H, int32_t on) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  for (auto& ev : H->events) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  H->events.clear();
+  H->timing = on != 0;
+  return PF_OK;
+}
+
+pf_status pf_timing_get(pf_handle* H, pf_timing* out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!out) return fail(PF_E_INVAL, "out is NULL");
+  std::memset(out, 0, sizeof *out);
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  for (auto& ev : H->events) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+    switch (ev.kind) {
+      case 0: out->propagate_ms += ms; out->propagate_launches++; break;
+      case 1: out->combine_ms += ms; out->combine_launches++; break;
+      case 2: out->scan_ms += ms; out->scan_launches++; break;
+      case 3: out->gather_ms += ms; out->gather_launches++; break;
+      default: out->batched_ms += ms; out->batched_launches++; break;
+    }
+  }
+  return PF_OK;
+}
+
+}  // extern "C"

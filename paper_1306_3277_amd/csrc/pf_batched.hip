@@ -1,0 +1,392 @@
+// Batched layout: many filters with uneven particle counts (parameter
+// particles of SMC over parameters, Alg. 4, or parallel marginal
+// Metropolis-Hastings chains, Alg. 3), stepped together.
+//
+//   K5a  propagate + weight over a flat grid of 256-particle chunks of all
+//        filters; each particle loads its ancestor's state (the gather of
+//        the previous resampling is fused into this load), so the state is
+//        read and written once per interval.
+//   K5b  one workgroup per filter, largest filters dispatched first: the
+//        filter's FP64 weights live in LDS (at most 8192), block max, sums,
+//        scan, stratum counts and a merge-path walk all run in LDS, and the
+//        ancestors go to global memory for the next K5a.
+// Both kernels read the filter's step counter from device memory and pick
+// the state buffers by its parity, so one captured graph replays every step.
+#include <math.h>
+
+#include "pf_device.hpp"
+#include "pf_internal.hpp"
+
+namespace pfk {
+
+__device__ __forceinline__ Key bkey(const KeyArg& k) { return Key{k.lo, k.hi}; }
+
+// ---------------------------------------------------------------- init
+template <int MODEL, int D, typename Real>
+__global__ __launch_bounds__(BATCH_NT) void k_batch_init(Real* __restrict__ x,
+                                                         int32_t* __restrict__ anc,
+                                                         BatchArgs A) {
+  const int f = A.chunk_f[blockIdx.x];
+  const int64_t off = A.off[f];
+  const int64_t N = A.off[f + 1] - off;
+  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  if (k >= N) return;
+  const Key key = bkey(A.key);
+  const uint32_t iter = A.fs[f].iter;
+  const double* th = A.theta + (size_t)f * 8;
+  anc[off + k] = (int32_t)k;
+  if (MODEL == 1) {
+    double z0, z1;
+    const uint4 w = draw(key, TAG_INIT, 0, iter, (uint32_t)k, 0, (uint32_t)f);
+    bm_pair_f64(w.x, w.y, z0, z1);
+    x[off + k] = (Real)(th[4] + th[5] * z0);
+  } else {
+#pragma unroll
+    for (int blk = 0; blk < D / 4; ++blk) {
+      double z[4];
+      normals4_f64(draw(key, TAG_INIT, blk, iter, (uint32_t)k, 0, (uint32_t)f), z);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) x[(int64_t)(4 * blk + m) * A.ld + off + k] = (Real)z[m];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- K5a
+template <int D, typename Real>
+__device__ __forceinline__ double batch_logdens(const Real (&x)[D], const double* yrow,
+                                                const int32_t* obs_pos, double inv_sd,
+                                                double cst) {
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int o = obs_pos[i];
+    if (o >= 0) {
+      const double e = (yrow[o] - (double)x[i]) * inv_sd;
+      acc = acc + e * e;
+    }
+  }
+  return -0.5 * acc + cst;
+}
+
+template <int MODEL, int D, typename Real>
+__global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__ xa,
+                                                              Real* __restrict__ xb,
+                                                              double* __restrict__ lw,
+                                                              const int32_t* __restrict__ anc,
+                                                              BatchArgs A) {
+  const int f = A.chunk_f[blockIdx.x];
+  const int64_t off = A.off[f];
+  const int64_t N = A.off[f + 1] - off;
+  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  if (k >= N) return;
+  const int t = A.fs[f].t + 1;
+  const uint32_t iter = A.fs[f].iter;
+  // state written by step s lives in buffer s % 2
+  const Real* xp = ((t - 1) & 1) ? xb : xa;
+  Real* xn = (t & 1) ? xb : xa;
+  const Key key = bkey(A.key);
+  const double* th = A.theta + (size_t)f * 8;
+  const double* yrow = A.obs + (int64_t)(t - 1) * A.n_obs;
+  const int n0 = (t - 1) * A.K;
+  const int64_t src = off + anc[off + k];
+  const int64_t dst = off + k;
+  double l;
+  if constexpr (MODEL == 1) {
+    if constexpr (sizeof(Real) == 8) {
+      double p = xp[src];
+      for (int s = 1; s <= A.K; ++s) {
+        const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)k, (uint32_t)(n0 + s), (uint32_t)f);
+        double z0, z1;
+        bm_pair_f64(w.x, w.y, z0, z1);
+        p = wk_substep_f64(p, th, A.q[n0 + s - 1], z0);
+      }
+      xn[dst] = p;
+      const double e = (yrow[0] - (p + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+      l = -0.5 * (e * e) + A.lw_cst;
+    } else {
+      float p = xp[src];
+      const float a = (float)th[0], c = (float)th[1], sp = (float)th[3];
+      for (int s = 1; s <= A.K; ++s) {
+        const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)k, (uint32_t)(n0 + s), (uint32_t)f);
+        float z0, z1;
+        bm_pair_f32(w.x, w.y, z0, z1);
+        p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
+      }
+      xn[dst] = p;
+      const double e = (yrow[0] - ((double)p + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+      l = -0.5 * (e * e) + A.lw_cst;
+    }
+  } else {
+    Real x[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) x[i] = xp[(int64_t)i * A.ld + src];
+    if constexpr (sizeof(Real) == 8) {
+      ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
+      for (int s = 1; s <= A.K; ++s)
+        l96_substep_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
+                           (uint32_t)(n0 + s), (uint32_t)f);
+    } else {
+      const float F = (float)th[0], sq = (float)th[1];
+      const float h = (float)A.h, hh = (float)A.hh, h6 = (float)A.h6;
+      const float h3 = (float)(A.h / 3.0);
+      for (int s = 1; s <= A.K; ++s)
+        l96_substep_f32<D>(x, F, sq, h, hh, h3, h6, key, TAG_NOISE, iter, (uint32_t)k,
+                           (uint32_t)(n0 + s), (uint32_t)f);
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) xn[(int64_t)i * A.ld + dst] = x[i];
+    l = batch_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+  }
+  lw[dst] = l;
+}
+
+// ---------------------------------------------------------------- K5b
+// One workgroup per filter.  Lane t owns the P = ceil(N/NT) consecutive
+// particles [tP, tP + P): their weights are summed sequentially in the lane
+// (exact monotone prefix), the lanes' totals are scanned across the block,
+// and an exact running maximum over earlier lanes keeps the cumulative
+// weights non-decreasing at lane edges.  Counts then feed a merge-path walk of
+// 2N/NT diagonals per lane, entirely in LDS.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict__ lw,
+                                                       int32_t* __restrict__ anc,
+                                                       BatchArgs A) {
+  constexpr int MAXP = BATCH_MAXN / NT;
+  __shared__ double sw[BATCH_MAXN];
+  __shared__ double red[NT / WAVE];
+  __shared__ double wmax[NT / WAVE];
+  __shared__ int redi[NT / WAVE];
+  __shared__ double bc[3];
+  const int f = A.order[blockIdx.x];
+  const int64_t off = A.off[f];
+  const int N = (int)(A.off[f + 1] - off);
+  FilterState* fs = A.fs + f;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const bool resample_only = A.mode != 0;
+  const int t = resample_only ? fs->t : fs->t + 1;
+  for (int i = threadIdx.x; i < N; i += NT) sw[i] = lw[off + i];
+  __syncthreads();
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < N; i += NT) {
+    const double l = sw[i];
+    if (l == l) m = fmax(m, l);
+  }
+  const double M = block_max<NT>(m, red);
+  const bool finite = (M > -INFINITY) && (M < INFINITY);
+  const int P = (N + NT - 1) / NT;
+  const int i0 = min(N, (int)threadIdx.x * P), i1 = min(N, i0 + P);
+  double run = 0.0, run2 = 0.0;
+  int cand = -1;
+  double loc[MAXP];
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) {
+    const int i = i0 + e;
+    double w = 0.0;
+    if (e < P && i < i1) {
+      const double l = sw[i];
+      w = (finite && l == l) ? exp(l - M) : 0.0;
+      if (w > 0.0) cand = i;
+    }
+    run += w;
+    run2 += w * w;
+    loc[e] = run;
+  }
+  double tot;
+  const double pre = block_incl_scan<NT>(run, red, tot) - run;
+  const double S2 = block_sum<NT>(run2, red);
+  const int jstar = block_max_i<NT>(cand, redi);
+  // exclusive running maximum of the lanes' last cumulative weights
+  const double vlast = (i1 > i0) ? pre + loc[MAXP - 1] : -INFINITY;
+  const double vmax = block_incl_max_scan<NT>(vlast, red);
+  double vprev = __shfl_up(vmax, 1, WAVE);
+  if (lane == WAVE - 1) wmax[wv] = vmax;
+  __syncthreads();
+  if (lane == 0) vprev = wv > 0 ? wmax[wv - 1] : -INFINITY;
+  const double S = fmax(tot, wmax[NT / WAVE - 1]);
+  if (threadIdx.x == 0) {
+    double u;
+    if (resample_only) {
+      u = A.u_override[f];
+    } else {
+      double ell, ess;
+      if (finite && S > 0.0) {
+        ell = (M + log(S)) - log((double)N);
+        ess = (S * S) / S2;
+      } else {
+        ell = -INFINITY;
+        ess = 0.0;
+        fs->status = 4;
+      }
+      fs->loglik = fs->loglik + ell;
+      fs->M = finite ? M : -INFINITY;
+      fs->S = S;
+      fs->ell = ell;
+      fs->ess = ess;
+      A.ell_tr[(size_t)f * A.T + t - 1] = ell;
+      A.ess_tr[(size_t)f * A.T + t - 1] = ess;
+      const uint4 w = draw(bkey(A.key), TAG_RESAMPLE, 0, fs->iter, 0, (uint32_t)t, (uint32_t)f);
+      u = u01_f64(w.x);
+      fs->u = u;
+      fs->t = t;
+    }
+    bc[0] = u;
+  }
+  __syncthreads();
+  const double u = bc[0];
+  // stratum counts of this lane's particles (registers), then to LDS
+  int32_t cnt[MAXP];
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) {
+    const int i = i0 + e;
+    int32_t c = 0;
+    if (e < P && i < i1) {
+      const double W = fmin(fmax(pre + loc[e], vprev), S);
+      c = finite ? (int32_t)stratum_count(W, S, u, N) : i + 1;
+    }
+    cnt[e] = c;
+  }
+  __syncthreads();
+  int32_t* sc = reinterpret_cast<int32_t*>(sw);
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e)
+    if (e < P && i0 + e < i1) sc[i0 + e] = cnt[e];
+  __syncthreads();
+  // merge path: lane walks diagonals [dt, dt + L)
+  const int L = (2 * N + NT - 1) / NT;
+  const int dt = (int)threadIdx.x * L;
+  if (dt < 2 * N) {
+    int lo = max(0, dt - N), hi = min(dt, N);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sc[mid] <= dt - 1 - mid)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int j = lo, k = dt - lo;
+    const int dend = min(dt + L, 2 * N);
+    for (int s = dt; s < dend; ++s) {
+      if (j < N && (k >= N || sc[j] <= k)) {
+        ++j;
+      } else {
+        int32_t aj = j < N ? j : jstar;
+        if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
+          aj = 0;
+          atomicOr(&fs->pad, 1);
+        }
+        anc[off + k] = aj;
+        ++k;
+      }
+    }
+  }
+}
+
+// x_out = x_prop[ancestors]: materialises the equally weighted set for
+// inspection (the stepping kernels never need it).
+template <typename Real>
+__global__ __launch_bounds__(BATCH_NT) void k_batch_gather(const Real* __restrict__ xprop,
+                                                           const int32_t* __restrict__ anc,
+                                                           Real* __restrict__ xout,
+                                                           BatchArgs A) {
+  const int f = A.chunk_f[blockIdx.x];
+  const int64_t off = A.off[f];
+  const int64_t N = A.off[f + 1] - off;
+  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  if (k >= N) return;
+  const int64_t src = off + anc[off + k];
+  for (int i = 0; i < A.d; ++i) xout[(int64_t)i * A.ld + off + k] = xprop[(int64_t)i * A.ld + src];
+}
+
+// ---------------------------------------------------------------- launchers
+#define PF_L96_DIMS_B(X) X(4) X(8) X(16) X(32) X(40)
+
+hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc,
+                               const BatchArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)a.n_chunks;
+  if (model == 1) {
+    if (prec == 0)
+      hipLaunchKernelGGL((k_batch_init<1, 1, double>), g, BATCH_NT, 0, s, (double*)x, anc, a);
+    else
+      hipLaunchKernelGGL((k_batch_init<1, 1, float>), g, BATCH_NT, 0, s, (float*)x, anc, a);
+    return hipGetLastError();
+  }
+  switch (d) {
+#define X(DD)                                                                              \
+  case DD:                                                                                 \
+    if (prec == 0)                                                                         \
+      hipLaunchKernelGGL((k_batch_init<2, DD, double>), g, BATCH_NT, 0, s, (double*)x,     \
+                         anc, a);                                                          \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_batch_init<2, DD, float>), g, BATCH_NT, 0, s, (float*)x, anc,  \
+                         a);                                                               \
+    break;
+    PF_L96_DIMS_B(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
+                                    const int32_t* anc, const BatchArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)a.n_chunks;
+  if (model == 1) {
+    if (prec == 0)
+      hipLaunchKernelGGL((k_batch_propagate<1, 1, double>), g, BATCH_NT, 0, s, (double*)xa,
+                         (double*)xb, lw, anc, a);
+    else
+      hipLaunchKernelGGL((k_batch_propagate<1, 1, float>), g, BATCH_NT, 0, s, (float*)xa,
+                         (float*)xb, lw, anc, a);
+    return hipGetLastError();
+  }
+  switch (d) {
+#define X(DD)                                                                              \
+  case DD:                                                                                 \
+    if (prec == 0)                                                                         \
+      hipLaunchKernelGGL((k_batch_propagate<2, DD, double>), g, BATCH_NT, 0, s,            \
+                         (double*)xa, (double*)xb, lw, anc, a);                            \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_batch_propagate<2, DD, float>), g, BATCH_NT, 0, s, (float*)xa, \
+                         (float*)xb, lw, anc, a);                                          \
+    break;
+    PF_L96_DIMS_B(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
+                                   hipStream_t s) {
+  const unsigned g = (unsigned)a.B;
+  switch (nt) {
+    case 256:
+      hipLaunchKernelGGL((k_batch_resample<256>), g, 256, 0, s, lw, anc, a);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_batch_resample<512>), g, 512, 0, s, lw, anc, a);
+      break;
+    case 1024:
+      hipLaunchKernelGGL((k_batch_resample<1024>), g, 1024, 0, s, lw, anc, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_gather(int prec, const void* xprop, const int32_t* anc, void* xout,
+                                 const BatchArgs& a, hipStream_t s) {
+  const unsigned g = (unsigned)a.n_chunks;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_batch_gather<double>), g, BATCH_NT, 0, s, (const double*)xprop, anc,
+                       (double*)xout, a);
+  else
+    hipLaunchKernelGGL((k_batch_gather<float>), g, BATCH_NT, 0, s, (const float*)xprop, anc,
+                       (float*)xout, a);
+  return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -1,0 +1,399 @@
+// Device-side building blocks of the gfx950 particle filter: the
+// counter-based generator, the normal transforms, the two models'
+// transitions and observation densities, and wave/block reductions.
+//
+// Compiled with -ffp-contract=off: every FP64 expression is evaluated as
+// written, which makes the FP64 path reproduce the generator's normals and
+// the model arithmetic bit for bit.  The FP32 path asks for fused
+// multiply-adds explicitly (fmaf).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+enum : uint32_t { TAG_INIT = 1, TAG_NOISE = 2, TAG_RESAMPLE = 3, TAG_DATA = 4, TAG_OBS = 8 };
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- generator
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplies mixed with the round key; the key schedule is uniform across a
+// wave, so it lives in scalar registers.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+// Counter word 2: tag (4 bits) | component block (8 bits) | iteration (20 bits).
+__device__ __forceinline__ uint32_t ctr_word2(uint32_t tag, uint32_t blk, uint32_t iter) {
+  return (tag << 28) | (blk << 20) | iter;
+}
+
+struct Key {
+  uint32_t lo, hi;
+};
+
+__device__ __forceinline__ uint4 draw(Key key, uint32_t tag, uint32_t blk, uint32_t iter,
+                                      uint32_t j, uint32_t n, uint32_t b) {
+  return philox(j, n, ctr_word2(tag, blk, iter), b, key.lo, key.hi);
+}
+
+// ---------------------------------------------------------------- FP64 normals
+// u = (w + 1/2) 2^-32; ln from the atanh series on [sqrt(1/2), sqrt(2));
+// sin/cos of 2 pi u by quarter-turn reduction and Taylor series; radius
+// sqrt(-2 ln u_a).  IEEE +, -, *, / and sqrt only, so the host and the device
+// produce the same bits.
+__device__ __forceinline__ double u01_f64(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+
+__device__ __forceinline__ double ln_f64(double x) {
+  uint64_t bits = (uint64_t)__double_as_longlong(x);
+  int e = (int)((bits >> 52) & 0x7ff) - 1022;
+  double f = __longlong_as_double((long long)((bits & 0x000fffffffffffffULL) | 0x3fe0000000000000ULL));
+  if (f < 0x1.6a09e667f3bcdp-1) {
+    f = f + f;
+    e = e - 1;
+  }
+  const double s = (f - 1.0) / (f + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 21.0;
+  p = p * s2 + 1.0 / 19.0;
+  p = p * s2 + 1.0 / 17.0;
+  p = p * s2 + 1.0 / 15.0;
+  p = p * s2 + 1.0 / 13.0;
+  p = p * s2 + 1.0 / 11.0;
+  p = p * s2 + 1.0 / 9.0;
+  p = p * s2 + 1.0 / 7.0;
+  p = p * s2 + 1.0 / 5.0;
+  p = p * s2 + 1.0 / 3.0;
+  p = p * s2 + 1.0;
+  const double lnf = (2.0 * s) * p;
+  const double de = (double)e;
+  return de * 0x1.62e42feep-1 + (de * 0x1.a39ef35793c76p-33 + lnf);
+}
+
+__device__ __forceinline__ void sincos2pi_f64(double u, double& s_out, double& c_out) {
+  const double v = 4.0 * u;
+  const double kf = __builtin_floor(v + 0.5);
+  const double f = v - kf;
+  const int k = ((int)kf) & 3;
+  const double p = f * 0x1.921fb54442d18p0;
+  const double p2 = p * p;
+  double sp = -1.0 / 121645100408832000.0;
+  sp = sp * p2 + 1.0 / 355687428096000.0;
+  sp = sp * p2 - 1.0 / 1307674368000.0;
+  sp = sp * p2 + 1.0 / 6227020800.0;
+  sp = sp * p2 - 1.0 / 39916800.0;
+  sp = sp * p2 + 1.0 / 362880.0;
+  sp = sp * p2 - 1.0 / 5040.0;
+  sp = sp * p2 + 1.0 / 120.0;
+  sp = sp * p2 - 1.0 / 6.0;
+  sp = sp * p2 + 1.0;
+  sp = sp * p;
+  double cp = -1.0 / 6402373705728000.0;
+  cp = cp * p2 + 1.0 / 20922789888000.0;
+  cp = cp * p2 - 1.0 / 87178291200.0;
+  cp = cp * p2 + 1.0 / 479001600.0;
+  cp = cp * p2 - 1.0 / 3628800.0;
+  cp = cp * p2 + 1.0 / 40320.0;
+  cp = cp * p2 - 1.0 / 720.0;
+  cp = cp * p2 + 1.0 / 24.0;
+  cp = cp * p2 - 1.0 / 2.0;
+  cp = cp * p2 + 1.0;
+  const bool odd = (k & 1) != 0;
+  const double s0 = odd ? cp : sp;
+  const double c0 = odd ? -sp : cp;
+  const bool neg = (k & 2) != 0;
+  s_out = neg ? -s0 : s0;
+  c_out = neg ? -c0 : c0;
+}
+
+__device__ __forceinline__ void bm_pair_f64(uint32_t wa, uint32_t wb, double& z0, double& z1) {
+  const double r = __builtin_sqrt(-2.0 * ln_f64(u01_f64(wa)));
+  double s, c;
+  sincos2pi_f64(u01_f64(wb), s, c);
+  z0 = r * c;
+  z1 = r * s;
+}
+
+__device__ __forceinline__ void normals4_f64(uint4 w, double z[4]) {
+  bm_pair_f64(w.x, w.y, z[0], z[1]);
+  bm_pair_f64(w.z, w.w, z[2], z[3]);
+}
+
+// ---------------------------------------------------------------- FP32 normals
+// 23-bit uniforms (exact in FP32), hardware log2 / sqrt / sin / cos; the
+// sin and cos instructions take their argument in revolutions, so
+// cos(2 pi u) is one instruction.
+__device__ __forceinline__ float u01_f32(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+}
+
+__device__ __forceinline__ void bm_pair_f32(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+  const float ua = u01_f32(wa);
+  const float ub = u01_f32(wb);
+  // -2 ln u = -2 ln(2) log2(u)
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+  z0 = r * __builtin_amdgcn_cosf(ub);
+  z1 = r * __builtin_amdgcn_sinf(ub);
+}
+
+__device__ __forceinline__ void normals4_f32(uint4 w, float z[4]) {
+  bm_pair_f32(w.x, w.y, z[0], z[1]);
+  bm_pair_f32(w.z, w.w, z[2], z[3]);
+}
+
+// ---------------------------------------------------------------- models
+// Per-filter constants, derived on the host in FP64.
+struct ModelConsts {
+  double h, hh, h6;        // substep, h/2, h/6 (Lorenz '96 RK4)
+  double inv_sd, lw_cst;   // 1/obs_sd and -n_obs (ln obs_sd + ln(2 pi)/2)
+};
+
+// Windkessel substep n (t_{n-1} -> t_n), exact two-element step with the
+// flow held at q_{n-1}, plus pressure noise:  p <- (a p + c q_{n-1}) + sp z.
+__device__ __forceinline__ double wk_substep_f64(double p, const double* th, double q_prev,
+                                                 double z) {
+  return (th[0] * p + th[1] * q_prev) + th[3] * z;
+}
+
+__device__ __forceinline__ float wk_substep_f32(float p, float a, float c, float sp,
+                                                float q_prev, float z) {
+  return fmaf(sp, z, fmaf(a, p, c * q_prev));
+}
+
+// Lorenz '96 drift, written as the oracle writes it:
+//   f_i = ((x_{i+1} - x_{i-2}) x_{i-1} - x_i) + F.
+template <int D>
+__device__ __forceinline__ void l96_drift_f64(const double (&x)[D], double F, double (&k)[D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    k[i] = ((x[(i + 1) % D] - x[(i + D - 2) % D]) * x[(i + D - 1) % D] - x[i]) + F;
+}
+
+// One RK4 substep of the drift plus the Wiener increment, FP64, with the
+// same expression tree as the oracle:
+//   x <- (x + h6 ((k1 + k4) + 2 (k2 + k3))) + sq z.
+template <int D>
+__device__ __forceinline__ void l96_substep_f64(double (&x)[D], double F, double sq,
+                                                const ModelConsts& mc, Key key, uint32_t tag,
+                                                uint32_t iter, uint32_t j, uint32_t n,
+                                                uint32_t b) {
+  double k[D], xt[D], s14[D], s23[D];
+  l96_drift_f64<D>(x, F, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s14[i] = k[i];
+    xt[i] = x[i] + mc.hh * k[i];
+  }
+  l96_drift_f64<D>(xt, F, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s23[i] = k[i];
+    xt[i] = x[i] + mc.hh * k[i];
+  }
+  l96_drift_f64<D>(xt, F, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s23[i] = s23[i] + k[i];
+    xt[i] = x[i] + mc.h * k[i];
+  }
+  l96_drift_f64<D>(xt, F, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) s14[i] = s14[i] + k[i];
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    double z[4];
+    normals4_f64(draw(key, tag, blk, iter, j, n, b), z);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = 4 * blk + m;
+      const double xn = x[i] + mc.h6 * (s14[i] + 2.0 * s23[i]);
+      x[i] = xn + sq * z[m];
+    }
+  }
+}
+
+// FP32 RK4 substep: accumulator form with fused multiply-adds, and each stage
+// updated in place with a two-value window so only x, acc and the stage
+// input stay live (3D registers).
+template <int D>
+__device__ __forceinline__ void l96_stage_f32(float (&xt)[D], const float (&x)[D], float (&acc)[D],
+                                              float F, float c_acc, float c_xt, bool last) {
+  const float old0 = xt[0];
+  float pm2 = xt[D - 2], pm1 = xt[D - 1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float xi = xt[i];
+    const float xp1 = (i == D - 1) ? old0 : xt[i + 1];
+    const float k = fmaf(xp1 - pm2, pm1, F - xi);
+    pm2 = pm1;
+    pm1 = xi;
+    acc[i] = fmaf(c_acc, k, acc[i]);
+    if (!last) xt[i] = fmaf(c_xt, k, x[i]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void l96_substep_f32(float (&x)[D], float F, float sq, float h,
+                                                float hh, float h3, float h6, Key key,
+                                                uint32_t tag, uint32_t iter, uint32_t j,
+                                                uint32_t n, uint32_t b) {
+  float acc[D], xt[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    acc[i] = x[i];
+    xt[i] = x[i];
+  }
+  l96_stage_f32<D>(xt, x, acc, F, h6, hh, false);
+  l96_stage_f32<D>(xt, x, acc, F, h3, hh, false);
+  l96_stage_f32<D>(xt, x, acc, F, h3, h, false);
+  l96_stage_f32<D>(xt, x, acc, F, h6, 0.0f, true);
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    float z[4];
+    normals4_f32(draw(key, tag, blk, iter, j, n, b), z);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[4 * blk + m] = fmaf(sq, z[m], acc[4 * blk + m]);
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+// inclusive scan across a wave
+__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const double u = __shfl_up(v, o, WAVE);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Block-wide reductions for a block of NT threads (NT/64 waves); `red` is
+// LDS scratch of NT/64 doubles; ends with a barrier so `red` can be reused.
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* red) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_max(v);
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / WAVE; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_sum(v);
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+template <int NT>
+__device__ __forceinline__ int block_max_i(int v, int* red) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_max_i(v);
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  int r = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / WAVE; ++i) r = max(r, red[i]);
+  __syncthreads();
+  return r;
+}
+// inclusive block scan; returns the thread's inclusive prefix and the total
+template <int NT>
+__device__ __forceinline__ double block_incl_scan(double v, double* red, double& total) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_incl_scan(v, lane);
+  if (lane == WAVE - 1) red[w] = v;
+  __syncthreads();
+  double pre = 0.0, tot = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i) {
+    if (i < w) pre += red[i];
+    tot += red[i];
+  }
+  __syncthreads();
+  total = tot;
+  return pre + v;
+}
+
+// inclusive running maximum across a wave and a block (exact: max does not round)
+__device__ __forceinline__ double wave_incl_max_scan(double v, int lane) {
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const double u = __shfl_up(v, o, WAVE);
+    if (lane >= o) v = fmax(v, u);
+  }
+  return v;
+}
+template <int NT>
+__device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_incl_max_scan(v, lane);
+  if (lane == WAVE - 1) red[w] = v;
+  __syncthreads();
+  double pre = -INFINITY;
+#pragma unroll
+  for (int i = 0; i < NT / WAVE; ++i)
+    if (i < w) pre = fmax(pre, red[i]);
+  __syncthreads();
+  return fmax(pre, v);
+}
+
+// Number of strata k in [0, N) with (u + k) S < N W, i.e. the particles up
+// to and including this one own strata 0 .. count-1.  The estimate from one
+// division is corrected with the exact product comparison.
+__device__ __forceinline__ int64_t stratum_count(double W, double S, double u, int64_t N) {
+  const double Nd = (double)N;
+  const double NW = Nd * W;
+  const double xv = NW / S - u;
+  int64_t est;
+  if (!(xv > 0.0))
+    est = 0;
+  else if (xv >= Nd)
+    est = N;
+  else
+    est = (int64_t)__builtin_ceil(xv);
+  while (est > 0 && !((u + (double)(est - 1)) * S < NW)) --est;
+  while (est < N && (u + (double)est) * S < NW) ++est;
+  return est;
+}
+
+}  // namespace pfk

@@ -1,0 +1,108 @@
+// Internal types shared by the kernels (pf_kernels.hip, pf_batched.hip) and
+// the host runtime (pf_api.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// Per-filter scalars kept in device memory.
+struct FilterState {
+  double loglik;  // running marginal log-likelihood
+  double M;       // max log-weight of the last step
+  double S;       // sum exp(lw - M) of the last step
+  double u;       // uniform of the pending systematic resampling
+  double ell;     // last likelihood increment
+  double ess;     // last ESS
+  int32_t t;      // observation intervals completed
+  int32_t status; // 0, or 4 once a step had no positive finite weight (sticky)
+  uint32_t iter;  // generator iteration field of the current run
+  int32_t pad;    // nonzero if the resampler met an inconsistency (never expected)
+};
+
+struct KeyArg {
+  uint32_t lo, hi;
+};
+
+// Arguments of the per-filter (plain layout) kernels.
+struct PlainArgs {
+  int64_t N;              // particles of this filter
+  int64_t ld;             // row stride of the structure-of-arrays state (N_total)
+  int64_t off;            // first particle of this filter
+  int64_t boff0;          // first block-partial slot of this filter
+  int64_t bst0;           // first merge-path boundary slot of this filter
+  int64_t bj0;            // first K3-block slot of this filter
+  int32_t nblk;           // 256-particle blocks of this filter
+  int32_t K, T, d, n_obs;
+  uint32_t b;
+  KeyArg key;
+  double h, hh, h6, inv_sd, lw_cst;
+  const double* theta;    // device, derived parameters of this filter
+  const double* obs;      // device [T][n_obs]
+  const int32_t* obs_pos; // device [d]: position in the observation row, or -1
+  const int32_t* obs_idx; // device [n_obs]
+  const double* q;        // device windkessel flow (or null)
+  FilterState* fs;        // this filter's scalars
+  double* ell_tr;         // this filter's trace rows [T]
+  double* ess_tr;
+};
+
+// Arguments of the batched-layout kernels.
+struct BatchArgs {
+  int32_t B, K, T, d, n_obs;
+  KeyArg key;
+  int64_t ld;
+  int32_t n_chunks;         // 256-particle propagation chunks over all filters
+  double h, hh, h6, inv_sd, lw_cst;
+  const double* theta;      // device [B][8] derived parameters
+  const double* obs;        // device [T][n_obs]
+  const int32_t* obs_pos;   // device [d]
+  const double* q;          // device windkessel flow (or null)
+  const int64_t* off;       // device [B+1] first particle of each filter
+  const int32_t* order;     // device [B] filters, largest first
+  const int32_t* chunk_f;   // device [n_chunks] filter of each chunk
+  const int32_t* chunk_k;   // device [n_chunks] first particle of each chunk
+  FilterState* fs;          // device [B]
+  double* ell_tr;           // device [B][T]
+  double* ess_tr;
+  const double* u_override; // device [B] (resample-only mode)
+  int32_t mode;             // 0: likelihood + ancestors; 1: ancestors only, given u
+};
+
+constexpr int K1_NT = 256;  // particles per propagate / scan block
+constexpr int K2_NT = 1024; // combine kernel threads
+constexpr int K3_NT = 256;  // scan + count threads
+constexpr int K3_PER = 4;   // consecutive particles per scan lane
+constexpr int K3_SPAN = K3_NT * K3_PER;  // particles per scan block (4 K1 blocks)
+constexpr int K4_NT = 256;  // merge-path threads
+constexpr int K4_L = 8;     // merge steps per thread
+constexpr int K4_DB = K4_NT * K4_L;  // merge-path diagonals per K4 block
+constexpr int BATCH_NT = 256;
+constexpr int BATCH_MAXN = 8192;
+
+// ---- launchers (pf_kernels.hip) ----
+hipError_t launch_init(int model, int d, int prec, void* x, const PlainArgs& a, hipStream_t s);
+hipError_t launch_reset(FilterState* fs, double* ell, double* ess, int B, int T, uint32_t iter,
+                        hipStream_t s);
+hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* xprop, void* lw,
+                            double* part, const PlainArgs& a, hipStream_t s);
+hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s);
+hipError_t launch_scan_count(int prec, const void* lw, const double* boff, int32_t* counts,
+                             int32_t* bstate, int32_t* bjs, const PlainArgs& a, hipStream_t s);
+hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts,
+                               const int32_t* bstate, const int32_t* bjs, const void* xprop,
+                               void* xcur, int32_t* anc, const PlainArgs& a, hipStream_t s);
+hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
+hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, double obs_sd,
+                           hipStream_t s);
+// ---- batched (pf_batched.hip) ----
+hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc,
+                               const BatchArgs& a, hipStream_t s);
+hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
+                                    const int32_t* anc, const BatchArgs& a, hipStream_t s);
+hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
+                                   hipStream_t s);
+hipError_t launch_batched_gather(int prec, const void* xprop, const int32_t* anc, void* xout,
+                                 const BatchArgs& a, hipStream_t s);
+
+}  // namespace pfk

@@ -1,0 +1,364 @@
+"""GPU parity of the plain-layout HIP path against the oracle, through the C ABI.
+
+FP64: log-weights equal the oracle's bit for bit; ancestors equal the
+oracle's except where a stratum lies within 1e-9 (normalised) of a
+cumulative weight; each likelihood increment and the running
+log-likelihood within 1e-10 relative.  FP32 mixed: under teacher forcing
+(both sides start each interval from the oracle's state rounded to FP32)
+every likelihood increment within 1e-4 absolute.  Sizes span several 256-particle blocks and
+a ragged tail; the full-size workloads are checked on sampled particles and
+on properties that hold at any size.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BAND = 1e-9
+REL64 = 1e-10
+ABS32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_3277_amd as pfm
+    pfm.load()  # raises if the HIP library is missing: no silent fallback
+    return pfm
+
+
+def _with_data(pb):
+    _, y = oracle.simulate(pb)
+    return pb.with_obs(y)
+
+
+def _band_ok(lw, u, a_gpu, a_ref):
+    """Every ancestor mismatch must sit at a stratum within BAND of a cell edge."""
+    mism = np.flatnonzero(a_gpu != a_ref)
+    if mism.size == 0:
+        return 0
+    w = np.where(np.isnan(lw), 0.0, np.exp(lw - np.nanmax(lw)))
+    cw = np.cumsum(w) / w.sum()
+    N = lw.size
+    for k in mism:
+        gap = np.min(np.abs(cw - (u + k) / N))
+        assert gap < BAND, f"ancestor {k}: gpu {a_gpu[k]} oracle {a_ref[k]} gap {gap}"
+    return mism.size
+
+
+def _free_running_fp64(pfm, pb, check_lw=True):
+    ref = oracle.pf_run(pb, traces=True)
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    flips = 0
+    for t in range(1, pb.T + 1):
+        f.step()
+        lw = f.logweights()
+        if check_lw:
+            np.testing.assert_array_equal(lw, ref["lw"][t - 1], err_msg=f"lw at t={t}")
+        f.resample()
+        a = f.ancestors()
+        u = oracle.resample_u(pb.seed, t)
+        n = _band_ok(ref["lw"][t - 1], u, a, ref["anc"][t - 1])
+        if n:  # resynchronise on the oracle's particles after an in-band flip
+            flips += n
+            x = oracle.init(pb, pb.theta[0], int(pb.n_particles[0]))
+            for s in range(1, t + 1):
+                xp = oracle.propagate(pb, pb.theta[0], x, s)
+                x = oracle.gather(xp, ref["anc"][s - 1])
+            f.set_state(x)
+    ell, ess = f.trace()
+    ll, _, tt = f.loglik()
+    assert tt == pb.T
+    np.testing.assert_array_less(np.abs(ell[0] - ref["ell"]),
+                                 REL64 * np.maximum(1.0, np.abs(ref["ell"])) + 1e-300)
+    np.testing.assert_allclose(ess[0], ref["ess"], rtol=1e-9)
+    assert abs(ll[0] - ref["loglik"]) <= REL64 * max(1.0, abs(ref["loglik"]))
+    if flips == 0:
+        np.testing.assert_array_equal(f.get_state(), ref["x"])
+    f.close()
+    return ref, ll[0], flips
+
+
+def test_simulator_matches_oracle_bitwise(pfm):
+    for pb in (W.config("c1"), W.config("c2", T=200), W.config("c3", T=60)):
+        xt_ref, y_ref = oracle.simulate(pb)
+        xt, y = pfm.simulate(pb)
+        np.testing.assert_array_equal(xt, xt_ref, err_msg=pb.name)
+        np.testing.assert_array_equal(y, y_ref, err_msg=pb.name)
+
+
+def test_windkessel_fp64_full_size_against_oracle_and_kalman(pfm):
+    pb = _with_data(W.config("c1"))  # N = 1024, T = 100
+    ref, ll, flips = _free_running_fp64(pfm, pb)
+    ll_kf, _ = oracle.kf_wk(pb)
+    assert abs(ll - ll_kf) < 5.0, (ll, ll_kf)
+    assert flips == 0
+
+
+@pytest.mark.parametrize("N,T", [(1, 6), (2, 6), (255, 8), (4096 + 77, 25)])
+def test_lorenz96_d8_fp64_free_running(pfm, N, T):
+    pb = _with_data(W.config("c2", N=N, T=T))
+    _free_running_fp64(pfm, pb)
+
+
+def test_lorenz96_d8_fp64_full_particle_count(pfm):
+    pb = _with_data(W.config("c2", T=3))  # N = 65536
+    _free_running_fp64(pfm, pb)
+
+
+def test_lorenz96_d40_fp64_half_observed(pfm):
+    pb = _with_data(W.config("c3", N=1100, T=4, precision=W.FP64))
+    _free_running_fp64(pfm, pb)
+
+
+def _teacher_forced_fp32(pfm, pb, steps):
+    f = pfm.Filter(pb, precision=pfm.PF_FP32_MIXED)
+    th = pb.theta[0]
+    N = int(pb.n_particles[0])
+    x = oracle.init(pb, th, N)
+    worst = 0.0
+    for t in range(1, steps + 1):
+        # both sides start the interval from the oracle's state rounded to FP32
+        x32 = x.astype(np.float32).astype(np.float64)
+        f.set_state(x32)
+        f.step()
+        xp = oracle.propagate(pb, th, x32, t)
+        lw = oracle.weight(pb, th, xp, t)
+        st, ell_ref, ess_ref, a = oracle.reduce_resample(lw, oracle.resample_u(pb.seed, t))
+        f.resample()
+        ell, ess = f.trace()
+        err = abs(ell[0, t - 1] - ell_ref)
+        worst = max(worst, err)
+        assert err <= ABS32, (t, ell[0, t - 1], ell_ref)
+        assert ess[0, t - 1] == pytest.approx(ess_ref, rel=1e-2)
+        x = oracle.gather(xp, a)
+    f.close()
+    return worst
+
+
+def test_fp32_teacher_forced_lorenz96_d8(pfm):
+    pb = _with_data(W.config("c2", N=4096 + 13, T=12, precision=W.FP32_MIXED))
+    _teacher_forced_fp32(pfm, pb, 12)
+
+
+def test_fp32_teacher_forced_lorenz96_d40(pfm):
+    pb = _with_data(W.config("c3", N=2048 + 5, T=6))
+    _teacher_forced_fp32(pfm, pb, 6)
+
+
+def test_fp32_teacher_forced_windkessel(pfm):
+    pb = _with_data(W.config("c1", T=30, precision=W.FP32_MIXED))
+    _teacher_forced_fp32(pfm, pb, 30)
+
+
+def _wk_states_for_weights(pb, th, t, lw_target):
+    """Initial pressures whose noise-free propagation to time t gives
+    log-weights lw_target (the windkessel step is affine in the pressure)."""
+    th0 = th.copy()
+    th0[3] = 0.0
+    base = oracle.propagate(pb, th0, np.array([[0.0, 1.0]]), t)[0]
+    A, c0 = base[1] - base[0], base[0]
+    y = pb.obs[t - 1, 0] - th[2] * pb.q[t * pb.K]
+    cst = -(math.log(pb.obs_sd) + 0.5 * math.log(2 * math.pi))
+    r = np.sqrt(np.maximum(0.0, 2.0 * (cst - np.asarray(lw_target))))
+    sign = np.where(np.arange(len(r)) % 2 == 0, 1.0, -1.0)
+    p_t = y - sign * r * pb.obs_sd
+    return ((p_t - c0) / A)[None, :]
+
+
+BRUTE_WEIGHTS = [
+    [1.0], [0.3, 0.7], [1, 2, 3], [5, 1, 1, 1, 1, 1, 1, 1], [1, 0, 0, 3, 0, 2, 2],
+    [0.25, 0.25, 0.25, 0.25], [1e-9, 1, 1e-9, 1, 1e-9], [0.9, 0.01, 0.01, 0.08], [0, 0, 1],
+]
+
+
+@pytest.mark.parametrize("weights", BRUTE_WEIGHTS)
+def test_resample_brute_force_every_u_interval(pfm, weights):
+    """For each interval of u on which the outcome is constant, the GPU's
+    ancestors (via pf_resample_u at the interval's midpoint) equal the
+    oracle's, and the length-weighted offspring counts are N * wbar."""
+    w = np.asarray(weights, dtype=np.float64)
+    N = w.size
+    pb = _with_data(W.windkessel(N=N, T=1))
+    th = pb.theta[0].copy()
+    th[3] = 0.0  # noise-free transition: weights are set through the state
+    pb = dataclasses.replace(pb, theta=th[None, :])
+    with np.errstate(divide="ignore"):
+        target = np.where(w > 0, np.log(w / w.max()), -1e4) - 0.5
+    x = _wk_states_for_weights(pb, th, 1, target)
+    lw = oracle.weight(pb, th, oracle.propagate(pb, th, x, 1), 1)
+    wb = np.exp(lw - lw.max())
+    wb /= wb.sum()
+    cuts = np.unique(np.concatenate([[0.0, 1.0], np.mod(np.cumsum(wb) * N, 1.0)]))
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    expected = np.zeros(N)
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        if hi - lo < 1e-12:
+            continue
+        u = 0.5 * (lo + hi)
+        f.reset(0)
+        f.set_state(x)
+        f.step()
+        f.resample_u([u])
+        a = f.ancestors()
+        st, _, _, a_ref = oracle.reduce_resample(lw, u)
+        np.testing.assert_array_equal(a, a_ref, err_msg=f"u={u}")
+        expected += (hi - lo) * np.bincount(a, minlength=N)
+    np.testing.assert_allclose(expected, N * wb, atol=1e-9)
+    f.close()
+
+
+def test_numeric_flag_from_nan_state(pfm):
+    pb = _with_data(W.config("c2", N=300, T=3))
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    x = f.get_state()
+    x[:, :] = np.nan
+    f.set_state(x)
+    f.step()
+    f.resample()
+    with pytest.raises(pfm.PfError) as ei:
+        f.loglik()
+    assert ei.value.status == 4
+    ll, _, _ = f.loglik(allow_numeric=True)
+    assert ll[0] == -np.inf
+    st, ell, _, a = oracle.reduce_resample(np.full(300, np.nan), 0.5)
+    assert st == oracle.ORC_NUMERIC and ell == -np.inf
+    np.testing.assert_array_equal(f.ancestors(), a)
+    f.close()
+
+
+def test_partial_nan_counts_as_zero_weight(pfm):
+    pb = _with_data(W.config("c2", N=512, T=2))
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    x = oracle.init(pb, pb.theta[0], 512)
+    x[:, ::3] = np.nan
+    f.set_state(x)
+    f.step()
+    f.resample()
+    xp = oracle.propagate(pb, pb.theta[0], x, 1)
+    lw = oracle.weight(pb, pb.theta[0], xp, 1)
+    st, ell, ess, a = oracle.reduce_resample(lw, oracle.resample_u(pb.seed, 1))
+    assert st == oracle.ORC_OK
+    e, _ = f.trace()
+    assert abs(e[0, 0] - ell) <= REL64 * max(1, abs(ell))
+    _band_ok(lw, oracle.resample_u(pb.seed, 1), f.ancestors(), a)
+    assert np.all(np.isfinite(f.get_state()))
+    f.close()
+
+
+def test_graph_replay_equals_eager(pfm):
+    pb = _with_data(W.config("c2", N=5000, T=10, precision=W.FP32_MIXED))
+    f1 = pfm.Filter(pb)
+    f1.advance(pb.T)
+    f2 = pfm.Filter(pb)
+    f2.graph_run(4)
+    f2.step()
+    f2.resample()
+    f2.graph_run(5)
+    e1, s1 = f1.trace()
+    e2, s2 = f2.trace()
+    np.testing.assert_array_equal(e1, e2)
+    np.testing.assert_array_equal(s1, s2)
+    np.testing.assert_array_equal(f1.get_state(), f2.get_state())
+    f1.close()
+    f2.close()
+
+
+def test_several_filters_in_one_handle(pfm):
+    base = _with_data(W.config("c2", N=1, T=6))
+    th = np.array([[8.0, 0.1], [9.5, 0.25], [6.3, 0.05]])
+    n = np.array([700, 1, 2100])
+    pb = dataclasses.replace(base, theta=th, n_particles=n)
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    f.advance(pb.T)
+    ell, _ = f.trace()
+    ll, _, _ = f.loglik()
+    x = f.get_state()
+    off = np.concatenate([[0], np.cumsum(n)])
+    for b in range(3):
+        ref = oracle.pf_run(pb, theta=th[b], N=int(n[b]), b=b)
+        np.testing.assert_array_less(np.abs(ell[b] - ref["ell"]),
+                                     REL64 * np.maximum(1.0, np.abs(ref["ell"])))
+        assert abs(ll[b] - ref["loglik"]) <= REL64 * max(1.0, abs(ref["loglik"]))
+        np.testing.assert_array_equal(x[:, off[b]:off[b + 1]], ref["x"])
+    f.close()
+
+
+def test_set_theta_and_iteration_field(pfm):
+    pb = _with_data(W.config("c2", N=999, T=5))
+    f = pfm.Filter(pb, precision=pfm.PF_FP64)
+    f.advance(2)
+    th = np.array([[9.1, 0.2]])
+    f.set_theta(th, iteration=7)
+    f.advance(pb.T)
+    ll, _, _ = f.loglik()
+    ref = oracle.pf_run(pb, theta=th[0], it=7)
+    assert abs(ll[0] - ref["loglik"]) <= REL64 * max(1.0, abs(ref["loglik"]))
+    f.reset(0)
+    f.advance(pb.T)
+    ll0, _, _ = f.loglik()
+    ref0 = oracle.pf_run(pb, theta=th[0], it=0)
+    assert abs(ll0[0] - ref0["loglik"]) <= REL64 * max(1.0, abs(ref0["loglik"]))
+    f.close()
+
+
+def test_call_order_errors(pfm):
+    pb = _with_data(W.config("c2", N=64, T=2))
+    f = pfm.Filter(pb)
+    with pytest.raises(pfm.PfError) as ei:
+        f.resample()
+    assert ei.value.status == 3
+    f.step()
+    with pytest.raises(pfm.PfError) as ei:
+        f.step()
+    assert ei.value.status == 3
+    f.resample()
+    f.advance(1)
+    with pytest.raises(pfm.PfError) as ei:
+        f.step()
+    assert ei.value.status == 3
+    f.close()
+
+
+def test_lorenz96_d40_full_size_fp32_sampled(pfm):
+    """N = 2^20, d = 40, the benchmark's launch shapes: sampled particles
+    against the oracle, and resampling properties over all particles."""
+    pb = _with_data(W.config("c3", T=3))
+    N = 1 << 20
+    f = pfm.Filter(pb)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([[0, 1, 255, 256, N // 2, N - 2, N - 1],
+                                    rng.integers(0, N, 57)]))
+    x0 = oracle.init_idx(pb, pb.theta[0], idx)
+    np.testing.assert_allclose(f.get_state()[:, idx], x0, rtol=1e-7, atol=1e-7)
+    f.step()
+    xg = f.get_state()
+    lwg = f.logweights()
+    xr = oracle.propagate_idx(pb, pb.theta[0], x0, idx, 1)
+    lwr = oracle.weight(pb, pb.theta[0], xr, 1)
+    np.testing.assert_allclose(xg[:, idx], xr, rtol=0, atol=2e-4)
+    assert np.max(np.abs(lwg[idx] - lwr)) < 5e-3
+    f.resample()
+    a = f.ancestors()
+    assert np.all(np.diff(a) >= 0) and a[0] >= 0 and a[-1] < N
+    w = np.exp(lwg - lwg.max())
+    wb = w / w.sum()
+    o = np.bincount(a, minlength=N)
+    assert o.sum() == N
+    assert np.all(o >= np.floor(N * wb) - 1) and np.all(o <= np.ceil(N * wb) + 1)
+    ell, ess = f.trace()
+    assert np.isfinite(ell[0, 0]) and 1.0 <= ess[0, 0] <= N
+    m = lwg.max()
+    assert abs(ell[0, 0] - (m + math.log(w.sum()) - math.log(N))) < 1e-4
+    xs = f.get_state()
+    np.testing.assert_array_equal(xs[:, :4096], xg[:, a[:4096]])
+    np.testing.assert_array_equal(xs[:, -4096:], xg[:, a[-4096:]])
+    f.close()

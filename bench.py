@@ -1,21 +1,25 @@
-"""Throughput of the MI355X bootstrap particle filter.
+"""Throughput of the MI355X bootstrap particle filter (one JSON line on stdout).
 
 A step is one observation interval of the whole hot path for every particle
 of the workload: propagate (K substeps) + weight + likelihood increment +
 ESS + systematic resampling + ancestor gather.  Inputs (observations,
 parameters, particles) are resident in HBM before timing starts; the data
-are simulated on the GPU.
+are simulated on the GPU from the model.
 
-Default workload: Lorenz '96, d = 8, N = 65,536, T = 200 (FP32 mixed path),
-with the FP64 plain filter timed on the same workload for comparison, plus
-the resample + gather HBM rate on the large single filter (d = 40,
-N = 2^20).  One JSON line on stdout.
+Headline (``value``): the FP32 batched form on the batched workload — 512
+Lorenz '96 (d = 8) filters with F ~ U(6, 10), sigma ~ U(0.05, 0.3) and
+particle counts uniform over {256, ..., 8192}, T = 200 — in particle-steps/s,
+next to the FP64 plain filter (one filter at a time, per-filter kernels) on
+the same workload, and the FP32 error per step measured at full size by
+teacher forcing against the FP64 path.  Secondary legs: the single filter
+(d = 8, N = 65,536), the large filter (d = 40, N = 2^20: resample + gather
+against HBM, propagation against the VALU issue rate), and marginal
+Metropolis-Hastings chains (64 x N = 4096).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,8 +33,10 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue slots per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU peak in lane-operations/s: the FP32 vector peak of 157.3 TFLOP/s counts
+# an FMA as 2 FLOP, i.e. 78.6 T lane-operations/s (256 CUs x 2.4 GHz x 128);
+# every VALU instruction is counted as one lane-operation.
+VALU_PEAK_TOPS = 157.3 / 2
 
 
 def log(msg):
@@ -57,48 +63,104 @@ def valu_slots_per_particle_step(model: int, d: int, K: int, n_obs: int, fp32: b
 
 
 def resample_gather_bytes(d: int, sx: int, slw: int) -> int:
-    """Algorithmic HBM bytes per particle of one resample + gather: read the
-    log-weight (scan), write and read the stratum count, write the ancestor,
-    read and write the d state components."""
+    """Algorithmic HBM bytes per particle of one plain-layout resample +
+    gather: read the log-weight (scan), write and read the stratum count,
+    write the ancestor, read and write the d state components."""
     return slw + 4 + 4 + 4 + 2 * d * sx
 
 
-def run_steps(f, T: int, n: int, use_graph: bool = True):
-    """n consecutive observation intervals, restarting the filter at T."""
-    done = 0
-    while done < n:
-        if f.t_host >= T:
-            f.reset(0)
-            f.t_host = 0
-        k = min(n - done, T - f.t_host)
-        if use_graph:
-            f.graph_run(k)
-        else:
-            f.advance(k)
-        f.t_host += k
-        done += k
+class Runner:
+    """Drives one handle for n consecutive intervals, restarting at T."""
+
+    def __init__(self, f, T):
+        self.f, self.T, self.t = f, T, 0
+
+    def run(self, n, graph=True):
+        done = 0
+        while done < n:
+            if self.t >= self.T:
+                self.f.reset(0)
+                self.t = 0
+            k = min(n - done, self.T - self.t)
+            if graph:
+                self.f.graph_run(k)
+            else:
+                self.f.advance(k)
+            self.t += k
+            done += k
+
+    def restart(self):
+        self.f.reset(0)
+        self.t = 0
 
 
-def make_filter(pfm, pb, precision, stream):
-    f = pfm.Filter(pb, precision=precision, stream=stream)
-    f.t_host = 0
-    return f
+def timed(torch, runner, steps, warmup):
+    runner.run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runner.run(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def kernel_times(runner, steps):
+    """Per-kernel mean durations (us) from HIP events on the handle's stream."""
+    f = runner.f
+    runner.restart()
+    f.timing(True)
+    runner.run(steps, graph=False)
+    tm = f.timing_get()
+    f.timing(False)
+    out = {}
+    for k in ("propagate", "combine", "scan", "gather", "batched"):
+        n = tm[f"{k}_launches"]
+        out[k] = tm[f"{k}_ms"] / n * 1e3 if n else 0.0
+    out["steps"] = steps
+    return out
+
+
+def teacher_forced_fp32_error(pfm, pb, stream, steps):
+    """Max |ell_t(FP32 batched) - ell_t(FP64 plain)| over all filters, each
+    interval started on both sides from the FP64 path's particles rounded to
+    FP32 (the FP64 path is the one checked bit for bit against the oracle)."""
+    f64 = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_PLAIN, stream=stream)
+    f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    worst = 0.0
+    for t in range(steps):
+        x = f64.get_state().astype(np.float32).astype(np.float64)
+        f64.set_state(x)
+        f32.set_state(x)
+        f64.step()
+        f32.step()
+        e64, _ = f64.trace()
+        e32, _ = f32.trace()
+        worst = max(worst, float(np.max(np.abs(e32[:, t] - e64[:, t]))))
+        f64.resample()
+        f32.resample()
+    f64.close()
+    f32.close()
+    return worst
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=40,
+                    help="intervals timed for the FP64 plain comparison")
+    ap.add_argument("--pmmh-iters", type=int, default=10)
+    ap.add_argument("--tf-steps", type=int, default=4, help="teacher-forced error intervals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the d=40, N=2^20 HBM leg")
+    ap.add_argument("--no-legs", action="store_true", help="headline workload only")
+    ap.add_argument("--profile-headline", action="store_true",
+                    help="run only the timed FP32 batched intervals (for counter runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; the multi-GPU layout is a design "
-              "only (filters shard across GPUs with no per-step exchange). Use --gpus 1.",
-              file=sys.stderr)
+        print("bench.py runs on one GPU: the filters of the batched workload shard across "
+              "GPUs with no per-step exchange, but this build measures one GPU only. "
+              "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -107,131 +169,183 @@ def main():
     pfm.load()
     stream = torch.cuda.Stream()
 
-    pb = W.config(args.workload)
-    if pb.B != 1:
-        raise SystemExit("bench.py: use a single-filter workload (c1, c2 or c3)")
-    with torch.cuda.stream(stream):
-        _, y = pfm.simulate(pb, stream=stream)
+    # ---------------------------------------------------------------- headline
+    pb = W.config("c4")
+    _, y = pfm.simulate(pb, stream=stream)
     pb = pb.with_obs(y)
-    N = int(pb.n_particles[0])
-    log(f"[bench] workload {args.workload}: {pb.name} d={pb.d} N={N} T={pb.T} K={pb.K}")
+    n_tot = int(pb.n_particles.sum())
+    log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
 
-    results = {}
-    for name, prec in (("fp32", W.FP32_MIXED), ("fp64", W.FP64)):
-        f = make_filter(pfm, pb, prec, stream)
-        run_steps(f, pb.T, args.warmup)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_steps(f, pb.T, args.steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        # one full filter run for the log-likelihood
-        f.reset(0)
-        f.t_host = 0
-        run_steps(f, pb.T, pb.T)
-        ll, ess, _ = f.loglik()
-        # per-kernel durations, measured with HIP events on the filter's stream
-        f.reset(0)
-        f.t_host = 0
-        f.timing(True)
-        run_steps(f, pb.T, min(pb.T, args.steps), use_graph=False)
-        tm = f.timing_get()
-        f.timing(False)
-        results[name] = dict(seconds=dt, rate=N * args.steps / dt, loglik=float(ll[0]),
-                             timing=tm)
-        log(f"[bench] {name}: {dt * 1e3 / args.steps:.4f} ms/step "
-            f"{N * args.steps / dt:.4e} particle-steps/s loglik {ll[0]:.6f} "
-            f"K1 {tm['propagate_ms'] / max(1, tm['propagate_launches']) * 1e3:.2f} us "
-            f"K2 {tm['combine_ms'] / max(1, tm['combine_launches']) * 1e3:.2f} us "
-            f"K3 {tm['scan_ms'] / max(1, tm['scan_launches']) * 1e3:.2f} us "
-            f"K4 {tm['gather_ms'] / max(1, tm['gather_launches']) * 1e3:.2f} us")
-        f.close()
+    f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    threads, groups, cand_ms = f32.autotune(steps=8)
+    log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
+        f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
+        f"{np.round(cand_ms * 1e3, 1).tolist()}")
+    r32 = Runner(f32, pb.T)
+    dt32 = timed(torch, r32, args.steps, args.warmup)
+    # per-kernel durations on one stream (no group overlap), for the roofline
+    f32.set_tuning(threads, 1)
+    kt32 = kernel_times(r32, min(args.steps, pb.T))
+    f32.set_tuning(threads, groups)
+    r32.restart()
+    r32.run(pb.T)
+    ll32, _, _ = f32.loglik()
+    f32.close()
+    rate32 = n_tot * args.steps / dt32
+    log(f"[bench] fp32 batched: {dt32 / args.steps * 1e3:.4f} ms/step {rate32:.4e} p-steps/s; "
+        f"propagate {kt32['propagate']:.1f} us, collective {kt32['batched']:.1f} us")
 
-    r32 = results["fp32"]
-    tm = r32["timing"]
-    k1_s = tm["propagate_ms"] / tm["propagate_launches"] / 1e3
+    if args.profile_headline:
+        f32.close()
+        print(json.dumps({"profile_headline": pb.name, "ms_per_step": dt32 / args.steps * 1e3}),
+              flush=True)
+        return
+
+    f64 = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_PLAIN, stream=stream)
+    r64 = Runner(f64, pb.T)
+    dt64 = timed(torch, r64, args.fp64_steps, 2)
+    r64.restart()
+    r64.run(pb.T)
+    ll64, _, _ = f64.loglik()
+    f64.close()
+    rate64 = n_tot * args.fp64_steps / dt64
+    log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.4f} ms/step {rate64:.4e} p-steps/s")
+
+    tf_err = teacher_forced_fp32_error(pfm, pb, stream, args.tf_steps)
+    log(f"[bench] teacher-forced FP32 error: max |d ell_t| = {tf_err:.2e} over {pb.B} filters "
+        f"x {args.tf_steps} intervals")
+
     slots = valu_slots_per_particle_step(pb.model, pb.d, pb.K, pb.n_obs, True)
-    achieved = slots * N / k1_s / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": "k_propagate_weight<fp32>", "kernel_us": k1_s * 1e6,
-                "ops_per_particle_step": slots}
+    k5a_s = kt32["propagate"] / 1e6
+    achieved = slots * n_tot / k5a_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "kernel": "k_batch_propagate<fp32, d=8>", "kernel_us": kt32["propagate"],
+                "ops_per_particle_step": slots, "particles_per_launch": n_tot}
 
     out = {
         "metric": "particle-steps/sec (FP32 batched vs FP64 plain) at stated loglik error; "
                   "% HBM roofline",
-        "value": r32["rate"],
+        "value": rate32,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["seconds"] * 1e3 / args.steps,
+        "ms_per_step": dt32 / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic (simulated on the GPU from the model)",
-        "config": {"workload": pb.name, "model": "lorenz96" if pb.model == 2 else "windkessel",
-                   "d": pb.d, "particles": N, "T": pb.T, "substeps": pb.K,
-                   "precision": "fp32 state/log-weights, fp64 scan/likelihood"},
-        "fp64_plain": {"value": results["fp64"]["rate"], "unit": "particle-steps/s",
-                       "ms_per_step": results["fp64"]["seconds"] * 1e3 / args.steps},
-        "fp32_over_fp64": r32["rate"] / results["fp64"]["rate"],
-        "loglik": {"fp32": r32["loglik"], "fp64": results["fp64"]["loglik"],
-                   "fp32_teacher_forced_bound_per_step": 1e-4},
+        "config": {"workload": pb.name, "model": "lorenz96", "d": pb.d, "filters": pb.B,
+                   "particles": n_tot, "particle_counts": "uniform over 256..8192",
+                   "T": pb.T, "substeps": pb.K, "layout": "batched",
+                   "collective_workgroup": threads, "filter_groups": groups,
+                   "precision": "fp32 state/propagation, fp64 log-weights/scan/likelihood"},
+        "fp64_plain": {"value": rate64, "unit": "particle-steps/s",
+                       "ms_per_step": dt64 / args.fp64_steps * 1e3, "steps": args.fp64_steps},
+        "fp32_batched_over_fp64_plain": rate32 / rate64,
+        "loglik_error": {"fp32_teacher_forced_max_abs_per_step": tf_err, "bound": 1e-4,
+                         "fp64_vs_oracle_rel_bound": 1e-10,
+                         "fp32_free_running_median_abs_diff_vs_fp64":
+                             float(np.median(np.abs(ll32 - ll64)))},
+        "kernels_us": {"fp32_batched": kt32},
         "roofline": roofline,
     }
 
-    if not args.no_large:
+    if not args.no_legs:
+        # ------------------------------------------------------------ single filter
+        pc = W.config("c2")
+        _, yc = pfm.simulate(pc, stream=stream)
+        pc = pc.with_obs(yc)
+        leg = {"workload": pc.name, "particles": int(pc.n_particles[0])}
+        for name, prec in (("fp32", W.FP32_MIXED), ("fp64", W.FP64)):
+            f = pfm.Filter(pc, precision=prec, stream=stream)
+            r = Runner(f, pc.T)
+            dt = timed(torch, r, pc.T, 20)
+            leg[name] = {"particle_steps_per_s": pc.n_particles[0] * pc.T / dt,
+                         "us_per_step": dt / pc.T * 1e6,
+                         "kernels_us": kernel_times(r, 50)}
+            f.close()
+        leg["fp32_over_fp64"] = (leg["fp32"]["particle_steps_per_s"] /
+                                 leg["fp64"]["particle_steps_per_s"])
+        out["single_filter"] = leg
+        log(f"[bench] single filter: fp32 {leg['fp32']['us_per_step']:.1f} us/step, "
+            f"fp64 {leg['fp64']['us_per_step']:.1f} us/step")
+
+        # ------------------------------------------------------------ large filter
         big = W.config("c3")
-        with torch.cuda.stream(stream):
-            _, yb = pfm.simulate(big, stream=stream)
+        _, yb = pfm.simulate(big, stream=stream)
         big = big.with_obs(yb)
-        fb = make_filter(pfm, big, W.FP32_MIXED, stream)
-        run_steps(fb, big.T, 3)
-        fb.timing(True)
-        run_steps(fb, big.T, 10, use_graph=False)
-        tb = fb.timing_get()
+        fb = pfm.Filter(big, stream=stream)
+        rb = Runner(fb, big.T)
+        rb.run(3)
+        kb = kernel_times(rb, 10)
+        dtb = timed(torch, rb, 20, 2)
         fb.close()
         nb = 1 << 20
-        n_st = tb["propagate_launches"]
-        rs = (tb["scan_ms"] + tb["gather_ms"]) / n_st / 1e3
-        k1b = tb["propagate_ms"] / n_st / 1e3
-        step_s = (tb["propagate_ms"] + tb["combine_ms"] + tb["scan_ms"] + tb["gather_ms"]) / n_st / 1e3
+        rs_us = kb["scan"] + kb["gather"]
         byt = resample_gather_bytes(big.d, 4, 8)
-        gbs = byt * nb / rs / 1e9
+        gbs = byt * nb / (rs_us * 1e-6) / 1e9
         slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
+        ach_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
         out["large_filter"] = {
-            "workload": big.name, "particles": nb, "step_us": step_s * 1e6,
-            "particle_steps_per_s": nb / step_s,
+            "workload": big.name, "particles": nb, "us_per_step": dtb / 20 * 1e6,
+            "particle_steps_per_s": nb * 20 / dtb,
             "resample_gather": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                                 "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                                "bytes_per_particle": byt, "us": rs * 1e6,
-                                "scan_us": tb["scan_ms"] / n_st * 1e3,
-                                "gather_us": tb["gather_ms"] / n_st * 1e3},
-            "propagate": {"bound": "alu", "achieved": slots_b * nb / k1b / 1e12,
-                          "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                          "frac": slots_b * nb / k1b / 1e12 / VALU_PEAK_TOPS, "us": k1b * 1e6},
-            "combine_us": tb["combine_ms"] / n_st * 1e3,
+                                "bytes_per_particle": byt, "us": rs_us,
+                                "scan_us": kb["scan"], "gather_us": kb["gather"]},
+            "propagate": {"bound": "alu", "achieved": ach_b, "peak": VALU_PEAK_TOPS,
+                          "unit": "TOP/s", "frac": ach_b / VALU_PEAK_TOPS,
+                          "us": kb["propagate"], "ops_per_particle_step": slots_b},
+            "combine_us": kb["combine"],
         }
-        log(f"[bench] large filter: resample+gather {rs * 1e6:.1f} us = {gbs:.0f} GB/s; "
-            f"propagate {k1b * 1e6:.1f} us")
+        log(f"[bench] large filter: resample+gather {rs_us:.1f} us = {gbs:.0f} GB/s "
+            f"({gbs / HBM_PEAK_GBS:.0%}); propagate {kb['propagate']:.1f} us "
+            f"({ach_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
+
+        # ------------------------------------------------------------ PMMH chains
+        if args.pmmh_iters > 0:
+            pm = W.config("c5")
+            pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
+            inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
+            fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+            fm.autotune(steps=4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fm.pmmh(inp)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            fm.close()
+            nfilt = pm.B * (args.pmmh_iters + 1)
+            out["pmmh"] = {"chains": pm.B, "iterations": args.pmmh_iters,
+                           "particles": int(pm.n_particles[0]), "T": pm.T,
+                           "filters_per_s": nfilt / dtm,
+                           "particle_steps_per_s": nfilt * int(pm.n_particles[0]) * pm.T / dtm,
+                           "accept_rate": float(res["accepts"].sum() /
+                                                (pm.B * args.pmmh_iters))}
+            log(f"[bench] pmmh: {nfilt / dtm:.1f} filters/s, accept "
+                f"{out['pmmh']['accept_rate']:.3f}")
 
     if not args.no_cpu_baseline:
         import oracle
-        # bounded sample of the same workload: all N particles over the first
-        # T' intervals, T' sized for about cpu_seconds of work
-        t_probe = time.perf_counter()
-        oracle.pf_run(pb, T=1)
-        per_step = time.perf_counter() - t_probe
-        Tp = max(1, min(pb.T, int(args.cpu_seconds / max(per_step, 1e-6))))
+        # bounded sample of the headline workload: whole filters of the batch,
+        # taken in order, all T intervals, until about cpu_seconds of work
         t0 = time.perf_counter()
-        oracle.pf_run(pb, T=Tp)
+        done_ps = 0
+        nf = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and nf < pb.B:
+            b = nf
+            oracle.pf_run(pb, theta=pb.theta[b], N=int(pb.n_particles[b]), b=b, T=pb.T // 10)
+            done_ps += int(pb.n_particles[b]) * (pb.T // 10)
+            nf += 1
         dtc = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": N * Tp / dtc, "unit": "particle-steps/s", "cores": 1,
+        out["cpu_baseline"] = {"value": done_ps / dtc, "unit": "particle-steps/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"{pb.name}: all {N} particles, first {Tp} of {pb.T} "
-                                         f"intervals, FP64, one thread ({dtc:.1f} s)"}
+                               "sample": f"{pb.name}: filters 0..{nf - 1} of {pb.B}, first "
+                                         f"{pb.T // 10} of {pb.T} intervals each, FP64, one "
+                                         f"thread ({dtc:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 

@@ -177,13 +177,23 @@ pf_status pf_pmmh(pf_handle* h, int32_t iters, const double* log_f0, const doubl
                   const double* alpha, double step_sd, double f_lo, double f_hi, double sigma,
                   double* log_f_trace, double* ll_trace, int32_t* accepts);
 
-/* Autotuner for the batched layout: times each candidate workgroup size of
- * the per-filter collective kernel (256, 512, 1024 lanes) over `steps`
- * intervals of this handle's own workload, keeps the fastest for later
- * calls, and re-initialises the filters (t = 0).  ms_out[3] (may be NULL)
- * receives each candidate's mean interval time in ms, *choice_out (may be
- * NULL) the chosen size.  Plain layout: nothing to tune, *choice_out = 0. */
-pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* choice_out, double* ms_out);
+/* Autotuner for the batched layout: for each candidate workgroup size of the
+ * per-filter collective kernel (256, 512, 1024 lanes) and each number of
+ * filter groups (1, 2, 4; groups are balanced by particle count and stepped
+ * concurrently on their own streams, so one group's collective overlaps
+ * another's propagation), replays `steps` intervals of this handle's own
+ * workload, keeps the fastest pair and re-initialises the filters (t = 0).
+ * ms_out[9] (may be NULL) receives the mean interval time in ms of candidate
+ * (groups index g, size index s) at [3g + s] (-1 when groups > B);
+ * *threads_out and *groups_out (may be NULL) the choice.  Plain layout:
+ * nothing to tune (both outputs 0). */
+pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* threads_out, int32_t* groups_out,
+                      double* ms_out);
+
+/* Set the batched layout's tuning directly: collective_threads in
+ * {256, 512, 1024}, groups in [1, 8] (capped at B).  Takes effect from the
+ * next interval; the plain layout ignores it. */
+pf_status pf_set_tuning(pf_handle* h, int32_t collective_threads, int32_t groups);
 
 /* ---- inspection and teacher forcing (synchronous; same kernels) -------- */
 /* Current particle set, FP64 host [d][N_total]: after pf_resample (or init)

@@ -78,7 +78,8 @@ SIGNATURES = {
                               C.c_void_p]),
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
-    "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _D]),
+    "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _I, _D]),
+    "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
     "pf_timing_get": (C.c_int, [_H, C.POINTER(PfTiming)]),
     "pf_last_error": (C.c_char_p, []),
@@ -230,10 +231,15 @@ class Filter:
         return dict(log_f=lft, ll=llt, accepts=acc)
 
     def autotune(self, steps: int = 8):
-        choice = C.c_int32()
-        ms = np.zeros(3)
-        _check(load().pf_autotune(self.h, int(steps), C.byref(choice), _dp(ms)))
-        return choice.value, ms
+        """Returns (collective threads, groups, ms per interval [groups x sizes])."""
+        th = C.c_int32()
+        gr = C.c_int32()
+        ms = np.zeros(9)
+        _check(load().pf_autotune(self.h, int(steps), C.byref(th), C.byref(gr), _dp(ms)))
+        return th.value, gr.value, ms.reshape(3, 3)
+
+    def set_tuning(self, threads: int, groups: int):
+        _check(load().pf_set_tuning(self.h, int(threads), int(groups)))
 
     # -- inspection / teacher forcing
     def get_state(self) -> np.ndarray:

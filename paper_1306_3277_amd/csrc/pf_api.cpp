@@ -211,7 +211,14 @@ struct pf_handle {
   bool stepped_once = false;
   std::vector<int64_t> np;
   std::vector<double> theta_host;  // [B][n_theta]
-  int batch_nt = 256;              // K5b workgroup size (autotuned)
+  // batched layout tuning: workgroup size of the per-filter collective, and
+  // the number of filter groups stepped concurrently on their own streams
+  int batch_nt = 256;
+  int groups = 1;
+  std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt;
+  std::vector<hipStream_t> side;     // streams of groups 1..G-1
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join;   // per side stream
   // timing
   bool timing = false;
   struct Ev {
@@ -219,9 +226,9 @@ struct pf_handle {
     int kind;
   };
   std::vector<Ev> events;
-  // graph
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // graphs: one per filter group (plain layout: one)
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> gexecs;
   hipStream_t cap_stream = nullptr;
   bool alive = true;
 
@@ -291,6 +298,8 @@ BatchArgs batch_args(const pf_handle* H) {
   a.order = H->at<int32_t>(H->L.b_order);
   a.chunk_f = H->at<int32_t>(H->L.b_chunk_f);
   a.chunk_k = H->at<int32_t>(H->L.b_chunk_k);
+  a.chunk0 = 0;
+  a.order0 = 0;
   a.fs = H->at<FilterState>(H->L.fs);
   a.ell_tr = H->at<double>(H->L.ell);
   a.ess_tr = H->at<double>(H->L.ess);
@@ -299,20 +308,24 @@ BatchArgs batch_args(const pf_handle* H) {
   return a;
 }
 
-pf_status ev_begin(pf_handle* H, hipEvent_t* e) {
+pf_status ev_begin(pf_handle* H, hipEvent_t* e, hipStream_t s) {
   if (!H->timing) return PF_OK;
   HIP_TRY(hipEventCreate(e));
-  HIP_TRY(hipEventRecord(*e, H->stream));
+  HIP_TRY(hipEventRecord(*e, s));
   return PF_OK;
 }
-pf_status ev_end(pf_handle* H, hipEvent_t a, int kind) {
+pf_status ev_end(pf_handle* H, hipEvent_t a, int kind, hipStream_t s) {
   if (!H->timing) return PF_OK;
   hipEvent_t b;
   HIP_TRY(hipEventCreate(&b));
-  HIP_TRY(hipEventRecord(b, H->stream));
+  HIP_TRY(hipEventRecord(b, s));
   H->events.push_back({a, b, kind});
   return PF_OK;
 }
+
+pf_status build_groups(pf_handle* H, int G);
+void destroy_streams(pf_handle* H);
+void destroy_graphs(pf_handle* H);
 
 pf_status check_handle(pf_handle* H) {
   if (!H) return fail(PF_E_INVAL, "handle is NULL");
@@ -340,35 +353,64 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
   return PF_OK;
 }
 
+// One interval for filter group g of the batched layout, on stream s.
+pf_status enqueue_group_step(pf_handle* H, int g, hipStream_t s) {
+  const pf_config& c = H->cfg;
+  BatchArgs a = batch_args(H);
+  a.chunk0 = H->grp_chunk0[g];
+  a.order0 = H->grp_order0[g];
+  hipEvent_t e0{};
+  pf_status st = ev_begin(H, &e0, s);
+  if (st) return st;
+  HIP_TRY(pfk::launch_batched_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
+                                        H->ws + H->L.x_tmp, H->at<double>(H->L.lw),
+                                        H->at<int32_t>(H->L.anc), a, H->grp_nchunks[g], s));
+  if ((st = ev_end(H, e0, 0, s))) return st;
+  if ((st = ev_begin(H, &e0, s))) return st;
+  HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
+                                       H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
+  if ((st = ev_end(H, e0, 4, s))) return st;
+  return PF_OK;
+}
+
+// The side streams wait for everything issued so far on s ...
+pf_status fork(pf_handle* H, hipStream_t s) {
+  if (H->groups <= 1) return PF_OK;
+  HIP_TRY(hipEventRecord(H->ev_fork, s));
+  for (int g = 1; g < H->groups; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g - 1], H->ev_fork, 0));
+  return PF_OK;
+}
+// ... and s waits for everything issued on the side streams.
+pf_status join(pf_handle* H, hipStream_t s) {
+  if (H->groups <= 1) return PF_OK;
+  for (int g = 1; g < H->groups; ++g) {
+    HIP_TRY(hipEventRecord(H->ev_join[g - 1], H->side[g - 1]));
+    HIP_TRY(hipStreamWaitEvent(s, H->ev_join[g - 1], 0));
+  }
+  return PF_OK;
+}
+
 pf_status enqueue_step(pf_handle* H, hipStream_t s) {
   const pf_config& c = H->cfg;
   if (c.layout == PF_LAYOUT_BATCHED) {
-    BatchArgs a = batch_args(H);
-    hipEvent_t e0{};
-    pf_status st = ev_begin(H, &e0);
+    pf_status st = fork(H, s);
     if (st) return st;
-    HIP_TRY(pfk::launch_batched_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
-                                          H->ws + H->L.x_tmp, H->at<double>(H->L.lw),
-                                          H->at<int32_t>(H->L.anc), a, s));
-    if ((st = ev_end(H, e0, 0))) return st;
-    if ((st = ev_begin(H, &e0))) return st;
-    HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                         H->at<int32_t>(H->L.anc), a, s));
-    if ((st = ev_end(H, e0, 4))) return st;
-    return PF_OK;
+    for (int g = 0; g < H->groups; ++g)
+      if ((st = enqueue_group_step(H, g, g == 0 ? s : H->side[g - 1]))) return st;
+    return join(H, s);
   }
   for (int b = 0; b < c.B; ++b) {
     PlainArgs a = plain_args(H, b);
     hipEvent_t e0{};
-    pf_status st = ev_begin(H, &e0);
+    pf_status st = ev_begin(H, &e0, s);
     if (st) return st;
     HIP_TRY(pfk::launch_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
                                   H->ws + H->L.x_tmp, H->ws + H->L.lw,
                                   H->at<double>(H->L.part), a, s));
-    if ((st = ev_end(H, e0, 0))) return st;
-    if ((st = ev_begin(H, &e0))) return st;
+    if ((st = ev_end(H, e0, 0, s))) return st;
+    if ((st = ev_begin(H, &e0, s))) return st;
     HIP_TRY(pfk::launch_combine(H->at<double>(H->L.part), H->at<double>(H->L.boff), a, s));
-    if ((st = ev_end(H, e0, 1))) return st;
+    if ((st = ev_end(H, e0, 1, s))) return st;
   }
   return PF_OK;
 }
@@ -384,7 +426,7 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     BatchArgs a = batch_args(H);
     a.mode = 1;
     HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                         H->at<int32_t>(H->L.anc), a, s));
+                                         H->at<int32_t>(H->L.anc), a, c.B, s));
     HIP_TRY(hipStreamSynchronize(s));  // u is a host array
     return PF_OK;
   }
@@ -392,18 +434,18 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     PlainArgs a = plain_args(H, b);
     if (u) HIP_TRY(pfk::launch_set_u(a.fs, u[b], s));
     hipEvent_t e0{};
-    pf_status st = ev_begin(H, &e0);
+    pf_status st = ev_begin(H, &e0, s);
     if (st) return st;
     HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
                                    H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
                                    H->at<int32_t>(H->L.bjs), a, s));
-    if ((st = ev_end(H, e0, 2))) return st;
-    if ((st = ev_begin(H, &e0))) return st;
+    if ((st = ev_end(H, e0, 2, s))) return st;
+    if ((st = ev_begin(H, &e0, s))) return st;
     HIP_TRY(pfk::launch_merge_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.counts),
                                      H->at<int32_t>(H->L.bstate), H->at<int32_t>(H->L.bjs),
                                      H->ws + H->L.x_tmp,
                                      H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
-    if ((st = ev_end(H, e0, 3))) return st;
+    if ((st = ev_end(H, e0, 3, s))) return st;
   }
   return PF_OK;
 }
@@ -427,6 +469,136 @@ pf_status require_device() {
     return fail(PF_E_DEVICE, "device %d is %s; this library is built for gfx950", dev,
                 prop.gcnArchName);
   return PF_OK;
+}
+
+// Filters largest first (longest-processing-time order), dealt to G groups
+// by always giving the next filter to the group with the fewest particles;
+// each group's filters and 256-particle chunks are contiguous in the device
+// tables, so a launch covers one group with a base offset.
+pf_status build_groups(pf_handle* H, int G) {
+  const pf_config& c = H->cfg;
+  if (G < 1) G = 1;
+  if (G > c.B) G = c.B;
+  std::vector<int32_t> order(c.B);
+  for (int b = 0; b < c.B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return H->np[x] > H->np[y]; });
+  std::vector<std::vector<int32_t>> members(G);
+  std::vector<int64_t> load(G, 0);
+  for (int32_t b : order) {
+    int gbest = 0;
+    for (int g = 1; g < G; ++g)
+      if (load[g] < load[gbest]) gbest = g;
+    members[gbest].push_back(b);
+    load[gbest] += H->np[b];
+  }
+  std::vector<int32_t> ord, chf, chk;
+  H->grp_chunk0.assign(G, 0);
+  H->grp_nchunks.assign(G, 0);
+  H->grp_order0.assign(G, 0);
+  H->grp_nfilt.assign(G, 0);
+  for (int g = 0; g < G; ++g) {
+    H->grp_order0[g] = (int32_t)ord.size();
+    H->grp_chunk0[g] = (int32_t)chf.size();
+    for (int32_t b : members[g]) {
+      ord.push_back(b);
+      for (int64_t k = 0; k < H->np[b]; k += pfk::BATCH_NT) {
+        chf.push_back(b);
+        chk.push_back((int32_t)k);
+      }
+    }
+    H->grp_nfilt[g] = (int32_t)ord.size() - H->grp_order0[g];
+    H->grp_nchunks[g] = (int32_t)chf.size() - H->grp_chunk0[g];
+  }
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_order, ord.data(), 4 * ord.size(), hipMemcpyHostToDevice,
+                         H->stream));
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_chunk_f, chf.data(), 4 * chf.size(),
+                         hipMemcpyHostToDevice, H->stream));
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_chunk_k, chk.data(), 4 * chk.size(),
+                         hipMemcpyHostToDevice, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  // streams and events for the extra groups (default priority)
+  while ((int)H->side.size() < G - 1) {
+    hipStream_t st;
+    HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    H->side.push_back(st);
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    H->ev_join.push_back(ev);
+  }
+  if (G > 1 && !H->ev_fork) HIP_TRY(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+  H->groups = G;
+  return PF_OK;
+}
+
+void destroy_graphs(pf_handle* H) {
+  for (auto g : H->gexecs) (void)hipGraphExecDestroy(g);
+  for (auto g : H->graphs) (void)hipGraphDestroy(g);
+  H->gexecs.clear();
+  H->graphs.clear();
+}
+
+void destroy_streams(pf_handle* H) {
+  destroy_graphs(H);
+  for (auto s : H->side) (void)hipStreamDestroy(s);
+  for (auto e : H->ev_join) (void)hipEventDestroy(e);
+  if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+  if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
+  H->side.clear();
+  H->ev_join.clear();
+  H->ev_fork = nullptr;
+  H->cap_stream = nullptr;
+}
+
+// The stream graph replays go on: the caller's, or a blocking stream of our
+// own when the caller uses the null stream (which cannot be captured).
+pf_status launch_stream(pf_handle* H, hipStream_t* out) {
+  if (H->stream) {
+    *out = H->stream;
+    return PF_OK;
+  }
+  if (!H->cap_stream) HIP_TRY(hipStreamCreate(&H->cap_stream));
+  *out = H->cap_stream;
+  return PF_OK;
+}
+
+// One graph per filter group (plain layout: one graph for all filters), each
+// holding one whole interval (step + resample).
+pf_status ensure_graphs(pf_handle* H) {
+  if (!H->gexecs.empty()) return PF_OK;
+  hipStream_t cs;
+  pf_status st = launch_stream(H, &cs);
+  if (st) return st;
+  const bool tm = H->timing;
+  H->timing = false;
+  const int ng = H->cfg.layout == PF_LAYOUT_BATCHED ? H->groups : 1;
+  for (int g = 0; g < ng && !st; ++g) {
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    if (H->cfg.layout == PF_LAYOUT_BATCHED) {
+      st = enqueue_group_step(H, g, cs);
+    } else {
+      st = enqueue_step(H, cs);
+      if (!st) st = enqueue_resample(H, cs, nullptr);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (st) break;
+    if (e != hipSuccess) {
+      st = fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+      break;
+    }
+    H->graphs.push_back(graph);
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      st = fail(PF_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+      break;
+    }
+    H->gexecs.push_back(ex);
+  }
+  H->timing = tm;
+  if (st) destroy_graphs(H);
+  return st;
 }
 
 }  // namespace
@@ -474,30 +646,14 @@ pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void
   if (e == hipSuccess) e = cp(L.obs_pos, pos.data(), 4 * (size_t)c.d);
   if (e == hipSuccess) e = cp(L.obs_idx, c.obs_idx, 4 * (size_t)c.n_obs);
   if (e == hipSuccess && c.model == PF_MODEL_WK) e = cp(L.q, c.q, 8 * ((size_t)c.T * c.K + 1));
-  // filters largest first (longest-processing-time order) and their chunks
-  std::vector<int32_t> order(c.B);
-  for (int b = 0; b < c.B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    return c.n_particles[x] > c.n_particles[y];
-  });
-  std::vector<int32_t> chf, chk;
-  chf.reserve(L.n_chunks);
-  chk.reserve(L.n_chunks);
-  for (int32_t b : order)
-    for (int64_t k = 0; k < c.n_particles[b]; k += pfk::BATCH_NT) {
-      chf.push_back(b);
-      chk.push_back((int32_t)k);
-    }
   if (e == hipSuccess) e = cp(L.b_off, L.off.data(), 8 * (size_t)(c.B + 1));
-  if (e == hipSuccess) e = cp(L.b_order, order.data(), 4 * (size_t)c.B);
-  if (e == hipSuccess) e = cp(L.b_chunk_f, chf.data(), 4 * chf.size());
-  if (e == hipSuccess) e = cp(L.b_chunk_k, chk.data(), 4 * chk.size());
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete H;
     return fail(PF_E_DEVICE, "copying the configuration failed: %s", hipGetErrorString(e));
   }
-  if ((st = upload_theta(H, c.theta))) {
+  if ((st = upload_theta(H, c.theta)) || (st = build_groups(H, 1))) {
+    destroy_streams(H);
     delete H;
     return st;
   }
@@ -582,9 +738,7 @@ pf_status pf_get_trace(pf_handle* H, double* ell_out, double* ess_out) {
 
 pf_status pf_destroy(pf_handle* H) {
   if (!H) return fail(PF_E_INVAL, "handle is NULL");
-  if (H->gexec) (void)hipGraphExecDestroy(H->gexec);
-  if (H->graph) (void)hipGraphDestroy(H->graph);
-  if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
+  destroy_streams(H);
   for (auto& ev : H->events) {
     (void)hipEventDestroy(ev.a);
     (void)hipEventDestroy(ev.b);
@@ -602,29 +756,17 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   if (H->t + n_steps > H->cfg.T)
     return fail(PF_E_STATE, "%d steps from t = %d exceed T = %d", n_steps, H->t, H->cfg.T);
   if (n_steps == 0) return PF_OK;
-  if (!H->gexec) {
-    // capture on the caller's stream, or on a blocking stream of our own when
-    // the caller uses the null stream (which cannot be captured)
-    hipStream_t cs = H->stream;
-    if (!cs) {
-      HIP_TRY(hipStreamCreate(&H->cap_stream));
-      cs = H->cap_stream;
-    }
-    const bool tm = H->timing;
-    H->timing = false;
-    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    pf_status s1 = enqueue_step(H, cs);
-    if (!s1) s1 = enqueue_resample(H, cs, nullptr);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &g);
-    H->timing = tm;
-    if (s1) return s1;
-    if (e != hipSuccess) return fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-    H->graph = g;
-    HIP_TRY(hipGraphInstantiate(&H->gexec, H->graph, nullptr, nullptr, 0));
-  }
-  hipStream_t ls = H->cap_stream ? H->cap_stream : H->stream;
-  for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(H->gexec, ls));
+  if ((st = ensure_graphs(H))) return st;
+  hipStream_t ls;
+  if ((st = launch_stream(H, &ls))) return st;
+  const int ng = (int)H->gexecs.size();
+  if (ng > 1 && (st = fork(H, ls))) return st;
+  // each group's filters are independent, so its intervals run back to back
+  // on its own stream while the other groups' run beside them
+  for (int i = 0; i < n_steps; ++i)
+    for (int g = 0; g < ng; ++g)
+      HIP_TRY(hipGraphLaunch(H->gexecs[g], g == 0 ? ls : H->side[g - 1]));
+  if (ng > 1 && (st = join(H, ls))) return st;
   H->t += n_steps;
   return PF_OK;
 }
@@ -856,54 +998,69 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
   return PF_OK;
 }
 
-pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* choice_out, double* ms_out) {
+pf_status pf_set_tuning(pf_handle* H, int32_t collective_threads, int32_t groups) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (collective_threads != 256 && collective_threads != 512 && collective_threads != 1024)
+    return fail(PF_E_INVAL, "collective_threads must be 256, 512 or 1024");
+  if (groups < 1 || groups > 8) return fail(PF_E_INVAL, "groups must be in [1, 8]");
+  if (H->cfg.layout != PF_LAYOUT_BATCHED) return PF_OK;  // nothing to tune
+  destroy_graphs(H);
+  H->batch_nt = collective_threads;
+  if (groups != H->groups) return build_groups(H, groups);
+  return PF_OK;
+}
+
+pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t* groups_out,
+                      double* ms_out) {
   pf_status st = check_handle(H);
   if (st) return st;
   if (steps < 1) return fail(PF_E_INVAL, "steps must be >= 1");
   if (H->cfg.layout != PF_LAYOUT_BATCHED) {
-    if (choice_out) *choice_out = 0;
+    if (threads_out) *threads_out = 0;
+    if (groups_out) *groups_out = 0;
     return pf_reset(H, H->iter);
   }
-  const int cand[3] = {256, 512, 1024};
+  const int cand_nt[3] = {256, 512, 1024};
+  const int cand_g[3] = {1, 2, 4};
   double best = 1e300;
-  int best_nt = H->batch_nt;
-  const bool tm = H->timing;
-  H->timing = false;
+  int best_nt = H->batch_nt, best_g = H->groups;
+  hipStream_t ls;
+  if ((st = launch_stream(H, &ls))) return st;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const int n = steps < H->cfg.T ? steps : H->cfg.T;
-  for (int ci = 0; ci < 3; ++ci) {
-    H->batch_nt = cand[ci];
-    if ((st = pf_reset(H, H->iter))) break;
-    // one untimed interval, then n timed
-    if ((st = enqueue_step(H, H->stream))) break;
-    HIP_TRY(hipEventRecord(e0, H->stream));
-    for (int i = 1; i < n && !st; ++i) st = enqueue_step(H, H->stream);
-    if (st) break;
-    HIP_TRY(hipEventRecord(e1, H->stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    const double per = n > 1 ? ms / (n - 1) : ms;
-    if (ms_out) ms_out[ci] = per;
-    if (per < best) {
-      best = per;
-      best_nt = cand[ci];
+  const int n = steps < H->cfg.T - 1 ? steps : H->cfg.T - 1;
+  for (int gi = 0; gi < 3 && !st; ++gi) {
+    for (int ci = 0; ci < 3 && !st; ++ci) {
+      const int idx = gi * 3 + ci;
+      if (ms_out) ms_out[idx] = -1.0;
+      if (cand_g[gi] > H->cfg.B) continue;
+      if ((st = pf_set_tuning(H, cand_nt[ci], cand_g[gi]))) break;
+      if ((st = pf_reset(H, H->iter))) break;
+      if ((st = pf_graph_run(H, 1))) break;  // capture + one untimed interval
+      if (n < 1) continue;
+      HIP_TRY(hipEventRecord(e0, ls));
+      if ((st = pf_graph_run(H, n))) break;
+      HIP_TRY(hipEventRecord(e1, ls));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / n;
+      if (ms_out) ms_out[idx] = per;
+      if (per < best) {
+        best = per;
+        best_nt = cand_nt[ci];
+        best_g = cand_g[gi];
+      }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  H->timing = tm;
   if (st) return st;
-  H->batch_nt = best_nt;
-  if (H->gexec) {  // the captured graph holds the old launch shape
-    (void)hipGraphExecDestroy(H->gexec);
-    (void)hipGraphDestroy(H->graph);
-    H->gexec = nullptr;
-    H->graph = nullptr;
-  }
-  if (choice_out) *choice_out = best_nt;
+  if ((st = pf_set_tuning(H, best_nt, best_g))) return st;
+  if (threads_out) *threads_out = best_nt;
+  if (groups_out) *groups_out = best_g;
   return pf_reset(H, H->iter);
 }
 

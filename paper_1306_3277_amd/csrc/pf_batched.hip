@@ -26,10 +26,10 @@ template <int MODEL, int D, typename Real>
 __global__ __launch_bounds__(BATCH_NT) void k_batch_init(Real* __restrict__ x,
                                                          int32_t* __restrict__ anc,
                                                          BatchArgs A) {
-  const int f = A.chunk_f[blockIdx.x];
+  const int f = A.chunk_f[A.chunk0 + blockIdx.x];
   const int64_t off = A.off[f];
   const int64_t N = A.off[f + 1] - off;
-  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  const int64_t k = (int64_t)A.chunk_k[A.chunk0 + blockIdx.x] + threadIdx.x;
   if (k >= N) return;
   const Key key = bkey(A.key);
   const uint32_t iter = A.fs[f].iter;
@@ -74,10 +74,10 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
                                                               double* __restrict__ lw,
                                                               const int32_t* __restrict__ anc,
                                                               BatchArgs A) {
-  const int f = A.chunk_f[blockIdx.x];
+  const int f = A.chunk_f[A.chunk0 + blockIdx.x];
   const int64_t off = A.off[f];
   const int64_t N = A.off[f + 1] - off;
-  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  const int64_t k = (int64_t)A.chunk_k[A.chunk0 + blockIdx.x] + threadIdx.x;
   if (k >= N) return;
   const int t = A.fs[f].t + 1;
   const uint32_t iter = A.fs[f].iter;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
       l = -0.5 * (e * e) + A.lw_cst;
     } else {
       float p = xp[src];
-      const float a = (float)th[0], c = (float)th[1], sp = (float)th[3];
+      const float a = (float)(th[0] - 1.0), c = (float)th[1], sp = (float)th[3];
       for (int s = 1; s <= A.K; ++s) {
         const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)k, (uint32_t)(n0 + s), (uint32_t)f);
         float z0, z1;
@@ -142,69 +142,100 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 
 // ---------------------------------------------------------------- K5b
 // One workgroup per filter.  Lane t owns the P = ceil(N/NT) consecutive
-// particles [tP, tP + P): their weights are summed sequentially in the lane
-// (exact monotone prefix), the lanes' totals are scanned across the block,
-// and an exact running maximum over earlier lanes keeps the cumulative
-// weights non-decreasing at lane edges.  Counts then feed a merge-path walk of
-// 2N/NT diagonals per lane, entirely in LDS.
+// particles [tP, tP + P), read straight from global memory into registers:
+// their weights are summed sequentially in the lane (an exact monotone
+// prefix), the lanes' totals are scanned across the block, and an exact
+// running maximum over earlier lanes keeps the cumulative weights
+// non-decreasing at lane edges.  The stratum counts go to LDS (at most 8192
+// int32) for a merge-path walk of 2N/NT diagonals per lane.  Reductions that
+// can share a block exchange do, so the whole collective costs five
+// barriers.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
                                                        BatchArgs A) {
   constexpr int MAXP = BATCH_MAXN / NT;
-  __shared__ double sw[BATCH_MAXN];
-  __shared__ double red[NT / WAVE];
-  __shared__ double wmax[NT / WAVE];
-  __shared__ int redi[NT / WAVE];
-  __shared__ double bc[3];
-  const int f = A.order[blockIdx.x];
+  constexpr int NW = NT / WAVE;
+  __shared__ int32_t sc[BATCH_MAXN];
+  __shared__ double xa[NW], xb[NW], xc[NW];
+  __shared__ int xi[NW];
+  __shared__ double bc;
+  const int f = A.order[A.order0 + blockIdx.x];
   const int64_t off = A.off[f];
   const int N = (int)(A.off[f + 1] - off);
   FilterState* fs = A.fs + f;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const bool resample_only = A.mode != 0;
-  const int t = resample_only ? fs->t : fs->t + 1;
-  for (int i = threadIdx.x; i < N; i += NT) sw[i] = lw[off + i];
-  __syncthreads();
-  double m = -INFINITY;
-  for (int i = threadIdx.x; i < N; i += NT) {
-    const double l = sw[i];
-    if (l == l) m = fmax(m, l);
-  }
-  const double M = block_max<NT>(m, red);
-  const bool finite = (M > -INFINITY) && (M < INFINITY);
   const int P = (N + NT - 1) / NT;
   const int i0 = min(N, (int)threadIdx.x * P), i1 = min(N, i0 + P);
-  double run = 0.0, run2 = 0.0;
-  int cand = -1;
-  double loc[MAXP];
+  // (1) this lane's log-weights and their maximum
+  double l[MAXP];
+  double m = -INFINITY;
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
-    const int i = i0 + e;
-    double w = 0.0;
-    if (e < P && i < i1) {
-      const double l = sw[i];
-      w = (finite && l == l) ? exp(l - M) : 0.0;
-      if (w > 0.0) cand = i;
+    l[e] = -INFINITY;
+    if (e < P && i0 + e < i1) {
+      const double v = lw[off + i0 + e];
+      l[e] = (v == v) ? v : -INFINITY;  // NaN counts as zero weight
+      m = fmax(m, l[e]);
     }
+  }
+  m = wave_max(m);
+  if (lane == 0) xa[wv] = m;
+  __syncthreads();  // 1
+  double M = xa[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) M = fmax(M, xa[w]);
+  const bool finite = (M > -INFINITY) && (M < INFINITY);
+  // (2) weights, in-lane prefix, square sum and last positive particle
+  double loc[MAXP];
+  double run = 0.0, run2 = 0.0;
+  int cand = -1;
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) {
+    const double w = finite ? exp(l[e] - M) : 0.0;  // exp(-inf) = 0
+    if (w > 0.0) cand = i0 + e;
     run += w;
     run2 += w * w;
     loc[e] = run;
   }
-  double tot;
-  const double pre = block_incl_scan<NT>(run, red, tot) - run;
-  const double S2 = block_sum<NT>(run2, red);
-  const int jstar = block_max_i<NT>(cand, redi);
+  // one exchange: scan of the lanes' sums, total of squares, last positive
+  const double incl = wave_incl_scan(run, lane);
+  const double s2w = wave_sum(run2);
+  const int cw = wave_max_i(cand);
+  __syncthreads();  // 2 (xa reused)
+  if (lane == WAVE - 1) xa[wv] = incl;
+  if (lane == 0) {
+    xb[wv] = s2w;
+    xi[wv] = cw;
+  }
+  __syncthreads();  // 3
+  double pre = incl - run, S = 0.0, S2 = 0.0;
+  int jstar = -1;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) pre += xa[w];
+    S += xa[w];
+    S2 += xb[w];
+    jstar = max(jstar, xi[w]);
+  }
   // exclusive running maximum of the lanes' last cumulative weights
-  const double vlast = (i1 > i0) ? pre + loc[MAXP - 1] : -INFINITY;
-  const double vmax = block_incl_max_scan<NT>(vlast, red);
-  double vprev = __shfl_up(vmax, 1, WAVE);
-  if (lane == WAVE - 1) wmax[wv] = vmax;
-  __syncthreads();
-  if (lane == 0) vprev = wv > 0 ? wmax[wv - 1] : -INFINITY;
-  const double S = fmax(tot, wmax[NT / WAVE - 1]);
+  const double vlast = (i1 > i0) ? pre + run : -INFINITY;
+  const double vin = wave_incl_max_scan(vlast, lane);
+  double vprev = __shfl_up(vin, 1, WAVE);
+  if (lane == WAVE - 1) xc[wv] = vin;
+  __syncthreads();  // 4
+  double vw = -INFINITY, vall = -INFINITY;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) vw = fmax(vw, xc[w]);
+    vall = fmax(vall, xc[w]);
+  }
+  vprev = (lane == 0) ? vw : fmax(vprev, vw);
+  S = fmax(S, vall);
   if (threadIdx.x == 0) {
     double u;
+    const int t = resample_only ? fs->t : fs->t + 1;
     if (resample_only) {
       u = A.u_override[f];
     } else {
@@ -229,29 +260,22 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
       fs->u = u;
       fs->t = t;
     }
-    bc[0] = u;
+    bc = u;
   }
-  __syncthreads();
-  const double u = bc[0];
-  // stratum counts of this lane's particles (registers), then to LDS
-  int32_t cnt[MAXP];
+  __syncthreads();  // 5
+  const double u = bc;
+  const double invS = 1.0 / S;
+  // (3) stratum counts of this lane's particles, to LDS
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int i = i0 + e;
-    int32_t c = 0;
     if (e < P && i < i1) {
       const double W = fmin(fmax(pre + loc[e], vprev), S);
-      c = finite ? (int32_t)stratum_count(W, S, u, N) : i + 1;
+      sc[i] = finite ? (int32_t)stratum_count(W, S, invS, u, N) : i + 1;
     }
-    cnt[e] = c;
   }
-  __syncthreads();
-  int32_t* sc = reinterpret_cast<int32_t*>(sw);
-#pragma unroll
-  for (int e = 0; e < MAXP; ++e)
-    if (e < P && i0 + e < i1) sc[i0 + e] = cnt[e];
-  __syncthreads();
-  // merge path: lane walks diagonals [dt, dt + L)
+  __syncthreads();  // 6
+  // (4) merge path: this lane walks diagonals [dt, dt + L)
   const int L = (2 * N + NT - 1) / NT;
   const int dt = (int)threadIdx.x * L;
   if (dt < 2 * N) {
@@ -265,6 +289,7 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
     }
     int j = lo, k = dt - lo;
     const int dend = min(dt + L, 2 * N);
+    bool bad = false;
     for (int s = dt; s < dend; ++s) {
       if (j < N && (k >= N || sc[j] <= k)) {
         ++j;
@@ -272,12 +297,13 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
         int32_t aj = j < N ? j : jstar;
         if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
           aj = 0;
-          atomicOr(&fs->pad, 1);
+          bad = true;
         }
         anc[off + k] = aj;
         ++k;
       }
     }
+    if (bad) atomicOr(&fs->pad, 1);
   }
 }
 
@@ -288,10 +314,10 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_gather(const Real* __restric
                                                            const int32_t* __restrict__ anc,
                                                            Real* __restrict__ xout,
                                                            BatchArgs A) {
-  const int f = A.chunk_f[blockIdx.x];
+  const int f = A.chunk_f[A.chunk0 + blockIdx.x];
   const int64_t off = A.off[f];
   const int64_t N = A.off[f + 1] - off;
-  const int64_t k = (int64_t)A.chunk_k[blockIdx.x] + threadIdx.x;
+  const int64_t k = (int64_t)A.chunk_k[A.chunk0 + blockIdx.x] + threadIdx.x;
   if (k >= N) return;
   const int64_t src = off + anc[off + k];
   for (int i = 0; i < A.d; ++i) xout[(int64_t)i * A.ld + off + k] = xprop[(int64_t)i * A.ld + src];
@@ -329,8 +355,10 @@ hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc
 }
 
 hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
-                                    const int32_t* anc, const BatchArgs& a, hipStream_t s) {
-  const unsigned g = (unsigned)a.n_chunks;
+                                    const int32_t* anc, const BatchArgs& a, int nchunks,
+                                    hipStream_t s) {
+  if (nchunks <= 0) return hipSuccess;
+  const unsigned g = (unsigned)nchunks;
   if (model == 1) {
     if (prec == 0)
       hipLaunchKernelGGL((k_batch_propagate<1, 1, double>), g, BATCH_NT, 0, s, (double*)xa,
@@ -359,8 +387,9 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
 }
 
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   hipStream_t s) {
-  const unsigned g = (unsigned)a.B;
+                                   int nfilters, hipStream_t s) {
+  if (nfilters <= 0) return hipSuccess;
+  const unsigned g = (unsigned)nfilters;
   switch (nt) {
     case 256:
       hipLaunchKernelGGL((k_batch_resample<256>), g, 256, 0, s, lw, anc, a);

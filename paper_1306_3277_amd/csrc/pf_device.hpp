@@ -136,11 +136,14 @@ __device__ __forceinline__ void normals4_f64(uint4 w, double z[4]) {
 }
 
 // ---------------------------------------------------------------- FP32 normals
-// 23-bit uniforms (exact in FP32), hardware log2 / sqrt / sin / cos; the
-// sin and cos instructions take their argument in revolutions, so
-// cos(2 pi u) is one instruction.
+// Uniforms from the whole 32-bit word: float(w) 2^-32 + 2^-33 keeps 24
+// significant bits at every magnitude, so the small u that make the tails
+// of the normal keep their relative precision (a fixed 23-bit grid would
+// lose it there).  u lies in (0, 1]; u = 1 gives a zero radius.  Hardware
+// log2 / sqrt / sin / cos; sin and cos take their argument in revolutions,
+// so cos(2 pi u) is one instruction.
 __device__ __forceinline__ float u01_f32(uint32_t w) {
-  return ((float)(w >> 9) + 0.5f) * 0x1p-23f;
+  return fmaf((float)w, 0x1p-32f, 0x1p-33f);
 }
 
 __device__ __forceinline__ void bm_pair_f32(uint32_t wa, uint32_t wb, float& z0, float& z1) {
@@ -171,9 +174,11 @@ __device__ __forceinline__ double wk_substep_f64(double p, const double* th, dou
   return (th[0] * p + th[1] * q_prev) + th[3] * z;
 }
 
-__device__ __forceinline__ float wk_substep_f32(float p, float a, float c, float sp,
+// FP32 form: the increment (a - 1) p + c q + sp z is formed first and added
+// to the pressure (|p| ~ 90) once.
+__device__ __forceinline__ float wk_substep_f32(float p, float am1, float c, float sp,
                                                 float q_prev, float z) {
-  return fmaf(sp, z, fmaf(a, p, c * q_prev));
+  return p + fmaf(sp, z, fmaf(am1, p, c * q_prev));
 }
 
 // Lorenz '96 drift, written as the oracle writes it:
@@ -228,12 +233,16 @@ __device__ __forceinline__ void l96_substep_f64(double (&x)[D], double F, double
   }
 }
 
-// FP32 RK4 substep: accumulator form with fused multiply-adds, and each stage
-// updated in place with a two-value window so only x, acc and the stage
-// input stay live (3D registers).
+// FP32 RK4 substep: the increment h/6 (k1 + 2k2 + 2k3 + k4) + sq z is
+// accumulated from zero with fused multiply-adds and added to the state once,
+// so the state (|x| ~ 10, ulp ~ 1e-6) is rounded once per substep rather
+// than at every stage; each stage input is updated in place with a
+// two-value window, so only x, the increment and the stage input stay live
+// (3D registers).
 template <int D>
 __device__ __forceinline__ void l96_stage_f32(float (&xt)[D], const float (&x)[D], float (&acc)[D],
-                                              float F, float c_acc, float c_xt, bool last) {
+                                              float F, float c_acc, float c_xt, bool first,
+                                              bool last) {
   const float old0 = xt[0];
   float pm2 = xt[D - 2], pm1 = xt[D - 1];
 #pragma unroll
@@ -243,7 +252,7 @@ __device__ __forceinline__ void l96_stage_f32(float (&xt)[D], const float (&x)[D
     const float k = fmaf(xp1 - pm2, pm1, F - xi);
     pm2 = pm1;
     pm1 = xi;
-    acc[i] = fmaf(c_acc, k, acc[i]);
+    acc[i] = first ? c_acc * k : fmaf(c_acc, k, acc[i]);
     if (!last) xt[i] = fmaf(c_xt, k, x[i]);
   }
 }
@@ -255,20 +264,17 @@ __device__ __forceinline__ void l96_substep_f32(float (&x)[D], float F, float sq
                                                 uint32_t n, uint32_t b) {
   float acc[D], xt[D];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    acc[i] = x[i];
-    xt[i] = x[i];
-  }
-  l96_stage_f32<D>(xt, x, acc, F, h6, hh, false);
-  l96_stage_f32<D>(xt, x, acc, F, h3, hh, false);
-  l96_stage_f32<D>(xt, x, acc, F, h3, h, false);
-  l96_stage_f32<D>(xt, x, acc, F, h6, 0.0f, true);
+  for (int i = 0; i < D; ++i) xt[i] = x[i];
+  l96_stage_f32<D>(xt, x, acc, F, h6, hh, true, false);
+  l96_stage_f32<D>(xt, x, acc, F, h3, hh, false, false);
+  l96_stage_f32<D>(xt, x, acc, F, h3, h, false, false);
+  l96_stage_f32<D>(xt, x, acc, F, h6, 0.0f, false, true);
 #pragma unroll
   for (int blk = 0; blk < D / 4; ++blk) {
     float z[4];
     normals4_f32(draw(key, tag, blk, iter, j, n, b), z);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) x[4 * blk + m] = fmaf(sq, z[m], acc[4 * blk + m]);
+    for (int m = 0; m < 4; ++m) x[4 * blk + m] = x[4 * blk + m] + fmaf(sq, z[m], acc[4 * blk + m]);
   }
 }
 
@@ -379,11 +385,13 @@ __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
 
 // Number of strata k in [0, N) with (u + k) S < N W, i.e. the particles up
 // to and including this one own strata 0 .. count-1.  The estimate from one
-// division is corrected with the exact product comparison.
-__device__ __forceinline__ int64_t stratum_count(double W, double S, double u, int64_t N) {
+// multiplication by invS = 1/S is corrected with the exact product
+// comparison, so the result does not depend on how the estimate rounds.
+__device__ __forceinline__ int64_t stratum_count(double W, double S, double invS, double u,
+                                                 int64_t N) {
   const double Nd = (double)N;
   const double NW = Nd * W;
-  const double xv = NW / S - u;
+  const double xv = NW * invS - u;
   int64_t est;
   if (!(xv > 0.0))
     est = 0;

@@ -62,6 +62,8 @@ struct BatchArgs {
   const int32_t* order;     // device [B] filters, largest first
   const int32_t* chunk_f;   // device [n_chunks] filter of each chunk
   const int32_t* chunk_k;   // device [n_chunks] first particle of each chunk
+  int32_t chunk0;           // first chunk of the launch (its filter group)
+  int32_t order0;           // first filter slot of the launch in `order`
   FilterState* fs;          // device [B]
   double* ell_tr;           // device [B][T]
   double* ess_tr;
@@ -70,7 +72,7 @@ struct BatchArgs {
 };
 
 constexpr int K1_NT = 256;  // particles per propagate / scan block
-constexpr int K2_NT = 1024; // combine kernel threads
+constexpr int K2_NT = 512;  // combine kernel threads
 constexpr int K3_NT = 256;  // scan + count threads
 constexpr int K3_PER = 4;   // consecutive particles per scan lane
 constexpr int K3_SPAN = K3_NT * K3_PER;  // particles per scan block (4 K1 blocks)
@@ -99,9 +101,10 @@ hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, do
 hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc,
                                const BatchArgs& a, hipStream_t s);
 hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
-                                    const int32_t* anc, const BatchArgs& a, hipStream_t s);
+                                    const int32_t* anc, const BatchArgs& a, int nchunks,
+                                    hipStream_t s);
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   hipStream_t s);
+                                   int nfilters, hipStream_t s);
 hipError_t launch_batched_gather(int prec, const void* xprop, const int32_t* anc, void* xout,
                                  const BatchArgs& a, hipStream_t s);
 

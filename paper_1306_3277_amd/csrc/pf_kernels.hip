@@ -118,7 +118,7 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
         l = -0.5 * (e * e) + A.lw_cst;
       } else {
         float p = xcur[col];
-        const float a = (float)A.theta[0], c = (float)A.theta[1], sp = (float)A.theta[3];
+        const float a = (float)(A.theta[0] - 1.0), c = (float)A.theta[1], sp = (float)A.theta[3];
         for (int s = 1; s <= A.K; ++s) {
           const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
           float z0, z1;
@@ -177,53 +177,107 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
 // the stratum counts can be merged.
 __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ part,
                                                    double* __restrict__ boff, PlainArgs A) {
-  __shared__ double red[K2_NT / WAVE];
+  constexpr int NW = K2_NT / WAVE;
+  constexpr int KC = 8;  // block terms cached per lane (nb <= 8192 stays in registers)
+  __shared__ double xm[NW], xs[NW], xs2[NW], xv[NW];
   const int nb = A.nblk;
   const double* P = part + 3 * A.boff0;
   double* bo = boff + A.boff0 + A.b;
-  double m = -INFINITY;
-  for (int i = threadIdx.x; i < nb; i += K2_NT) m = fmax(m, P[3 * i]);
-  const double M = block_max<K2_NT>(m, red);
-  const bool finite = (M > -INFINITY) && (M < INFINITY);
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const int chunk = (nb + K2_NT - 1) / K2_NT;
   const int i0 = min(nb, (int)threadIdx.x * chunk), i1 = min(nb, i0 + chunk);
-  double loc = 0.0, loc2 = 0.0;
-  for (int i = i0; i < i1; ++i) {
+  // exchange 1: the global maximum
+  double m = -INFINITY;
+  for (int i = i0; i < i1; ++i) m = fmax(m, P[3 * i]);
+  m = wave_max(m);
+  if (lane == 0) xm[wv] = m;
+  __syncthreads();
+  double M = xm[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) M = fmax(M, xm[w]);
+  const bool finite = (M > -INFINITY) && (M < INFINITY);
+  // block totals T_i = s_i exp(m_i - M), summed sequentially within the lane;
+  // the first KC of a lane's terms stay in registers (unrolled, fixed
+  // indices), any further ones are recomputed
+  auto term = [&](int i, double& T2) -> double {
     const double mb = P[3 * i];
-    if (finite && mb > -INFINITY) {
-      const double sc = exp(mb - M);
-      loc += P[3 * i + 1] * sc;
-      loc2 += P[3 * i + 2] * (sc * sc);
+    T2 = 0.0;
+    if (!(finite && mb > -INFINITY)) return 0.0;
+    const double sc = exp(mb - M);
+    T2 = P[3 * i + 2] * (sc * sc);
+    return P[3 * i + 1] * sc;
+  };
+  double Tc[KC];
+  double loc = 0.0, loc2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < KC; ++e) {
+    double T = 0.0, T2 = 0.0;
+    if (i0 + e < i1) T = term(i0 + e, T2);
+    Tc[e] = T;
+    loc += T;
+    loc2 += T2;
+  }
+  for (int i = i0 + KC; i < i1; ++i) {
+    double T2;
+    loc += term(i, T2);
+    loc2 += T2;
+  }
+  // exchange 2: scan of the lanes' sums, total of squares
+  const double incl = wave_incl_scan(loc, lane);
+  const double s2w = wave_sum(loc2);
+  if (lane == WAVE - 1) xs[wv] = incl;
+  if (lane == 0) xs2[wv] = s2w;
+  __syncthreads();
+  double pre = incl - loc, S = 0.0, S2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) pre += xs[w];
+    S += xs[w];
+    S2 += xs2[w];
+  }
+  // this lane's last offset; an exact running maximum over earlier lanes
+  // makes the offsets non-decreasing whatever the rounding of the scan
+  double last = -INFINITY;
+  {
+    double run = pre;
+#pragma unroll
+    for (int e = 0; e < KC; ++e)
+      if (i0 + e < i1) {
+        last = run;
+        run += Tc[e];
+      }
+    for (int i = i0 + KC; i < i1; ++i) {
+      double T2;
+      last = run;
+      run += term(i, T2);
     }
   }
-  double S;
-  const double incl = block_incl_scan<K2_NT>(loc, red, S);
-  const double S2 = block_sum<K2_NT>(loc2, red);
-  double run = incl - loc;
-  double last = -INFINITY;
-  for (int i = i0; i < i1; ++i) {
-    bo[i] = run;
-    last = run;
-    const double mb = P[3 * i];
-    if (finite && mb > -INFINITY) run += P[3 * i + 1] * exp(mb - M);
+  const double vin = wave_incl_max_scan(last, lane);
+  const double vup = __shfl_up(vin, 1, WAVE);
+  if (lane == WAVE - 1) xv[wv] = vin;
+  __syncthreads();  // exchange 3
+  double vw = -INFINITY, vall = -INFINITY;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) vw = fmax(vw, xv[w]);
+    vall = fmax(vall, xv[w]);
   }
-  // maximum over the chunks before this one, then over this chunk (which is
-  // already non-decreasing)
-  const double upto = block_incl_max_scan<K2_NT>(last, red);
-  const double before = __shfl_up(upto, 1, WAVE);
-  __syncthreads();
-  __shared__ double wlast[K2_NT / WAVE];
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  if (lane == WAVE - 1) wlast[wv] = upto;
-  __syncthreads();
-  double prev = (lane > 0) ? before : (wv > 0 ? wlast[wv - 1] : -INFINITY);
-  for (int i = i0; i < i1; ++i) {
-    const double v = fmax(bo[i], prev);
-    bo[i] = v;
-    prev = v;
+  const double vprev = (lane == 0) ? vw : fmax(vup, vw);
+  {
+    double run = pre;
+#pragma unroll
+    for (int e = 0; e < KC; ++e)
+      if (i0 + e < i1) {
+        bo[i0 + e] = fmax(run, vprev);
+        run += Tc[e];
+      }
+    for (int i = i0 + KC; i < i1; ++i) {
+      double T2;
+      bo[i] = fmax(run, vprev);
+      run += term(i, T2);
+    }
   }
-  const double tot_max = wlast[K2_NT / WAVE - 1];
-  const double Sf = fmax(S, tot_max);
+  const double Sf = fmax(S, vall);
   if (threadIdx.x == 0) {
     bo[nb] = Sf;
     FilterState* f = A.fs;
@@ -290,6 +344,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   const FilterState* f = A.fs;
   const double M = f->M, S = f->S, u = f->u;
   const bool finite = (M > -INFINITY) && (M < INFINITY) && (S > 0.0);
+  const double invS = 1.0 / S;
   const double* bo = boff + A.boff0 + A.b;
   const int k1b = (int)blockIdx.x * (K3_SPAN / K1_NT);  // first K1 block of this block
   const double lo_off = bo[k1b];
@@ -327,13 +382,13 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   for (int e = 0; e < K3_PER; ++e) {
     const int64_t j = j0 + e;
     const double W = fmin(fmax(V[e], vprev), hi_off);
-    c[e] = (j < N) ? (finite ? stratum_count(W, S, u, N) : j + 1) : 0;
+    c[e] = (j < N) ? (finite ? stratum_count(W, S, invS, u, N) : j + 1) : 0;
     if (j < N) counts[A.off + j] = (int32_t)c[e];
   }
   // merge-path states on the K4 block boundaries (see above)
-  const int64_t g_lo = finite ? stratum_count(lo_off, S, u, N) : jb;
+  const int64_t g_lo = finite ? stratum_count(lo_off, S, invS, u, N) : jb;
   const int64_t jnext = jb + K3_SPAN;
-  const int64_t g_hi = (jnext < N) ? (finite ? stratum_count(hi_off, S, u, N) : jnext) : N;
+  const int64_t g_hi = (jnext < N) ? (finite ? stratum_count(hi_off, S, invS, u, N) : jnext) : N;
   int64_t cprev = __shfl_up(c[K3_PER - 1], 1, WAVE);
   if (lane == WAVE - 1) wlast[wv] = c[K3_PER - 1];
   __syncthreads();

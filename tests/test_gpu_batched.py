@@ -194,9 +194,32 @@ def test_autotune_keeps_results(pfm):
     f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
     f.advance(pb.T)
     e0, _ = f.trace()
-    choice, ms = f.autotune(steps=4)
-    assert choice in (256, 512, 1024) and np.all(ms > 0)
+    threads, groups, ms = f.autotune(steps=3)
+    assert threads in (256, 512, 1024) and groups in (1, 2, 4)
+    assert np.all(ms[ms >= 0] > 0)
     f.advance(pb.T)  # autotune leaves the filters re-initialised
     e1, _ = f.trace()
     np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=1e-12)
     f.close()
+
+
+def test_filter_groups_do_not_change_results(pfm):
+    """Groups only change which stream steps which filters: eager and graph
+    replay, one group or three, give the same bits."""
+    th, n = W.batched_thetas(23, seed=12)
+    pb = _problem(n, th, T=6)
+    outs = []
+    for groups, graph in ((1, False), (3, False), (3, True), (2, True)):
+        f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
+        f.set_tuning(512, groups)
+        if graph:
+            f.graph_run(2)
+            f.advance(1)
+            f.graph_run(pb.T - 3)
+        else:
+            f.advance(pb.T)
+        outs.append((f.trace()[0], f.get_state(), f.ancestors(), f.loglik()[0]))
+        f.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            np.testing.assert_array_equal(a, b)

@@ -362,3 +362,31 @@ def test_lorenz96_d40_full_size_fp32_sampled(pfm):
     np.testing.assert_array_equal(xs[:, :4096], xg[:, a[:4096]])
     np.testing.assert_array_equal(xs[:, -4096:], xg[:, a[-4096:]])
     f.close()
+
+
+def test_plain_layout_very_large_filter_sampled(pfm):
+    """N = 2^23 + 77 (d = 4): more block partials than the combine kernel
+    keeps in registers; sampled particles against the oracle and the
+    resampling properties over all particles."""
+    pb = _with_data(W.lorenz96(d=4, N=(1 << 23) + 77, T=2, precision=W.FP32_MIXED))
+    N = int(pb.n_particles[0])
+    f = pfm.Filter(pb)
+    idx = np.array([0, 1, 4095, 4096, N // 3, N - 78, N - 1])
+    x0 = oracle.init_idx(pb, pb.theta[0], idx)
+    f.step()
+    xg = f.get_state()
+    lwg = f.logweights()
+    xr = oracle.propagate_idx(pb, pb.theta[0], x0, idx, 1)
+    np.testing.assert_allclose(xg[:, idx], xr, rtol=0, atol=2e-4)
+    assert np.max(np.abs(lwg[idx] - oracle.weight(pb, pb.theta[0], xr, 1))) < 5e-3
+    f.resample()
+    a = f.ancestors()
+    assert np.all(np.diff(a) >= 0) and a[0] >= 0 and a[-1] < N
+    w = np.exp(lwg - lwg.max())
+    o = np.bincount(a, minlength=N)
+    assert o.sum() == N
+    wb = w / w.sum()
+    assert np.all(o >= np.floor(N * wb) - 1) and np.all(o <= np.ceil(N * wb) + 1)
+    ell, _ = f.trace()
+    assert abs(ell[0, 0] - (lwg.max() + np.log(w.sum()) - np.log(N))) < 1e-6
+    f.close()

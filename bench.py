@@ -44,20 +44,22 @@ def log(msg):
 
 
 def valu_slots_per_particle_step(model: int, d: int, K: int, n_obs: int, fp32: bool) -> float:
-    """Algorithmic VALU issue slots (lane-instructions) one particle needs for
+    """Algorithmic VALU operations (lane-instructions) one particle needs for
     one observation interval.  Per generator call (4 words): 10 Philox rounds
-    of 2 wide multiplies + 4 xors = 60; FP32 normals: 4 uniforms x 3 + 2
-    Box-Muller pairs x 7 (log, scale, sqrt, cos, sin, 2 products) = 26; FP64
-    normals: 4 uniforms x 2 + 2 pairs x 95 (own log ~32, sincos ~45, sqrt ~12,
-    products) = 198.  Lorenz '96 RK4 per component: drift 3 ops x 4 stages +
-    4 accumulations + 3 stage inputs + the noise = 20 (FP32, fused) or 30
-    (FP64, unfused).  Weight: 3 FP64 ops per observed component."""
-    philox = 60
-    bm_call = 26 if fp32 else 198
+    of 2 wide multiplies + 2 three-input xors = 40; FP32 normals: 4 uniforms
+    x 2 + 2 Box-Muller pairs x 5 (log, scale, sqrt, cos, sin) = 18; FP64
+    normals: 4 uniforms x 2 + 2 pairs x 95 (own log ~32, sincos ~45, sqrt
+    ~12, products) = 198.  Lorenz '96 per component per substep, FP32: 4
+    stages x (drift 2 + increment 1 + stage input 1) - 1 + 2 (x + cF) + the
+    noise (1) and the state update (1) = 19; FP64 (the oracle's expression
+    tree, no fusion): 30.  Weight: 3 FP64 operations per observed component
+    + 4."""
+    philox = 40
+    bm_call = 18 if fp32 else 198
     if model == W.MODEL_WK:
         per_sub = philox + bm_call // 2 + (4 if fp32 else 5)
         return K * per_sub + 8
-    rk4 = 20 if fp32 else 30
+    rk4 = 19 if fp32 else 30
     per_sub = (d // 4) * (philox + bm_call) + rk4 * d
     return K * per_sub + 3 * n_obs + 4
 
@@ -120,26 +122,83 @@ def kernel_times(runner, steps):
 
 
 def teacher_forced_fp32_error(pfm, pb, stream, steps):
-    """Max |ell_t(FP32 batched) - ell_t(FP64 plain)| over all filters, each
-    interval started on both sides from the FP64 path's particles rounded to
-    FP32 (the FP64 path is the one checked bit for bit against the oracle)."""
+    """|ell_t(FP32 batched) - ell_t(FP64 plain)| for every filter and interval,
+    each interval started on both sides from the FP64 path's particles rounded
+    to FP32 (the FP64 path is the one checked bit for bit against the oracle).
+    Returns the errors [steps, B], the FP64 increments and the FP64 ESS."""
     f64 = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_PLAIN, stream=stream)
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    worst = 0.0
+    err, ell, ess = [], [], []
     for t in range(steps):
         x = f64.get_state().astype(np.float32).astype(np.float64)
         f64.set_state(x)
         f32.set_state(x)
         f64.step()
         f32.step()
-        e64, _ = f64.trace()
+        e64, s64 = f64.trace()
         e32, _ = f32.trace()
-        worst = max(worst, float(np.max(np.abs(e32[:, t] - e64[:, t]))))
+        err.append(np.abs(e32[:, t] - e64[:, t]))
+        ell.append(e64[:, t])
+        ess.append(s64[:, t])
         f64.resample()
         f32.resample()
     f64.close()
     f32.close()
-    return worst
+    return np.array(err), np.array(ell), np.array(ess)
+
+
+def tf_summary(err, ell, ess, bound, rel_bound):
+    """Distribution of the teacher-forced errors over (interval, filter) pairs;
+    the combined bound is max(bound, rel_bound |ell_t|)."""
+    comb = np.maximum(bound, rel_bound * np.abs(ell))
+    worst = np.argsort(-(err / comb).ravel())[:3]
+    ok = ess >= 2.0
+    return {"max_abs": float(err.max()), "p99_abs": float(np.quantile(err, 0.99)),
+            "median_abs": float(np.median(err)),
+            "frac_within_abs_bound": float(np.mean(err <= bound)),
+            "max_abs_where_ess_ge_2": float(err[ok].max()) if ok.any() else None,
+            "rel_bound": rel_bound,
+            "frac_within_combined_bound": float(np.mean(err <= comb)),
+            "max_ratio_to_combined_bound": float((err / comb).max()),
+            "worst": [{"err": float(err.ravel()[i]), "ell": float(ell.ravel()[i]),
+                       "ess": float(ess.ravel()[i])} for i in worst],
+            "pairs": int(err.size)}
+
+
+def large_filter_leg(torch, pfm, stream):
+    """One Lorenz '96 (d = 40) filter of 2^20 particles, FP32 mixed: resample +
+    gather priced against HBM, propagation against the VALU issue rate."""
+    big = W.config("c3")
+    _, yb = pfm.simulate(big, stream=stream)
+    big = big.with_obs(yb)
+    fb = pfm.Filter(big, stream=stream)
+    rb = Runner(fb, big.T)
+    rb.run(3)
+    kb = kernel_times(rb, 10)
+    dtb = timed(torch, rb, 20, 2)
+    fb.close()
+    nb = int(big.n_particles[0])
+    rs_us = kb["scan"] + kb["gather"]
+    byt = resample_gather_bytes(big.d, 4, 8)
+    gbs = byt * nb / (rs_us * 1e-6) / 1e9
+    slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
+    ach_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
+    leg = {
+        "workload": big.name, "particles": nb, "us_per_step": dtb / 20 * 1e6,
+        "particle_steps_per_s": nb * 20 / dtb,
+        "resample_gather": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                            "bytes_per_particle": byt, "us": rs_us,
+                            "scan_us": kb["scan"], "gather_us": kb["gather"]},
+        "propagate": {"bound": "alu", "achieved": ach_b, "peak": VALU_PEAK_TOPS,
+                      "unit": "TOP/s", "frac": ach_b / VALU_PEAK_TOPS,
+                      "us": kb["propagate"], "ops_per_particle_step": slots_b},
+        "combine_us": kb["combine"],
+    }
+    log(f"[bench] large filter: resample+gather {rs_us:.1f} us = {gbs:.0f} GB/s "
+        f"({gbs / HBM_PEAK_GBS:.0%}); propagate {kb['propagate']:.1f} us "
+        f"({ach_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
+    return leg
 
 
 def main():
@@ -150,11 +209,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=40,
                     help="intervals timed for the FP64 plain comparison")
     ap.add_argument("--pmmh-iters", type=int, default=10)
-    ap.add_argument("--tf-steps", type=int, default=4, help="teacher-forced error intervals")
+    ap.add_argument("--tf-steps", type=int, default=8, help="teacher-forced error intervals")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline workload only")
     ap.add_argument("--profile-headline", action="store_true",
                     help="run only the timed FP32 batched intervals (for counter runs)")
+    ap.add_argument("--profile-large", action="store_true",
+                    help="run only the large single-filter leg (for counter runs)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -168,6 +229,9 @@ def main():
     torch.cuda.set_device(0)
     pfm.load()
     stream = torch.cuda.Stream()
+    if args.profile_large:
+        print(json.dumps({"profile_large": large_filter_leg(torch, pfm, stream)}), flush=True)
+        return
 
     # ---------------------------------------------------------------- headline
     pb = W.config("c4")
@@ -196,7 +260,6 @@ def main():
         f"propagate {kt32['propagate']:.1f} us, collective {kt32['batched']:.1f} us")
 
     if args.profile_headline:
-        f32.close()
         print(json.dumps({"profile_headline": pb.name, "ms_per_step": dt32 / args.steps * 1e3}),
               flush=True)
         return
@@ -211,9 +274,21 @@ def main():
     rate64 = n_tot * args.fp64_steps / dt64
     log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.4f} ms/step {rate64:.4e} p-steps/s")
 
-    tf_err = teacher_forced_fp32_error(pfm, pb, stream, args.tf_steps)
-    log(f"[bench] teacher-forced FP32 error: max |d ell_t| = {tf_err:.2e} over {pb.B} filters "
-        f"x {args.tf_steps} intervals")
+    tf = tf_summary(*teacher_forced_fp32_error(pfm, pb, stream, args.tf_steps), 1e-4, 1e-6)
+    log(f"[bench] teacher-forced FP32 error over {pb.B} filters x {args.tf_steps} intervals: "
+        f"max {tf['max_abs']:.2e}, p99 {tf['p99_abs']:.2e}, median {tf['median_abs']:.2e}, "
+        f"within 1e-4: {tf['frac_within_abs_bound']:.4f}; within max(1e-4, 1e-6 |ell|): "
+        f"{tf['frac_within_combined_bound']:.4f} (worst ratio {tf['max_ratio_to_combined_bound']:.2f}); "
+        f"max where ESS >= 2: {tf['max_abs_where_ess_ge_2']:.2e}; worst {tf['worst']}")
+
+    # FP64 batched (same kernels as the headline, FP64 state and own-math normals)
+    f64b = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    f64b.autotune(steps=4)
+    r64b = Runner(f64b, pb.T)
+    dt64b = timed(torch, r64b, args.fp64_steps, 4)
+    f64b.close()
+    rate64b = n_tot * args.fp64_steps / dt64b
+    log(f"[bench] fp64 batched: {dt64b / args.fp64_steps * 1e3:.4f} ms/step {rate64b:.4e} p-steps/s")
 
     slots = valu_slots_per_particle_step(pb.model, pb.d, pb.K, pb.n_obs, True)
     k5a_s = kt32["propagate"] / 1e6
@@ -244,8 +319,11 @@ def main():
                    "precision": "fp32 state/propagation, fp64 log-weights/scan/likelihood"},
         "fp64_plain": {"value": rate64, "unit": "particle-steps/s",
                        "ms_per_step": dt64 / args.fp64_steps * 1e3, "steps": args.fp64_steps},
+        "fp64_batched": {"value": rate64b, "unit": "particle-steps/s",
+                         "ms_per_step": dt64b / args.fp64_steps * 1e3, "steps": args.fp64_steps},
         "fp32_batched_over_fp64_plain": rate32 / rate64,
-        "loglik_error": {"fp32_teacher_forced_max_abs_per_step": tf_err, "bound": 1e-4,
+        "fp32_batched_over_fp64_batched": rate32 / rate64b,
+        "loglik_error": {"fp32_teacher_forced_per_step": tf, "bound": 1e-4,
                          "fp64_vs_oracle_rel_bound": 1e-10,
                          "fp32_free_running_median_abs_diff_vs_fp64":
                              float(np.median(np.abs(ll32 - ll64)))},
@@ -274,36 +352,7 @@ def main():
             f"fp64 {leg['fp64']['us_per_step']:.1f} us/step")
 
         # ------------------------------------------------------------ large filter
-        big = W.config("c3")
-        _, yb = pfm.simulate(big, stream=stream)
-        big = big.with_obs(yb)
-        fb = pfm.Filter(big, stream=stream)
-        rb = Runner(fb, big.T)
-        rb.run(3)
-        kb = kernel_times(rb, 10)
-        dtb = timed(torch, rb, 20, 2)
-        fb.close()
-        nb = 1 << 20
-        rs_us = kb["scan"] + kb["gather"]
-        byt = resample_gather_bytes(big.d, 4, 8)
-        gbs = byt * nb / (rs_us * 1e-6) / 1e9
-        slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
-        ach_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
-        out["large_filter"] = {
-            "workload": big.name, "particles": nb, "us_per_step": dtb / 20 * 1e6,
-            "particle_steps_per_s": nb * 20 / dtb,
-            "resample_gather": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                                "bytes_per_particle": byt, "us": rs_us,
-                                "scan_us": kb["scan"], "gather_us": kb["gather"]},
-            "propagate": {"bound": "alu", "achieved": ach_b, "peak": VALU_PEAK_TOPS,
-                          "unit": "TOP/s", "frac": ach_b / VALU_PEAK_TOPS,
-                          "us": kb["propagate"], "ops_per_particle_step": slots_b},
-            "combine_us": kb["combine"],
-        }
-        log(f"[bench] large filter: resample+gather {rs_us:.1f} us = {gbs:.0f} GB/s "
-            f"({gbs / HBM_PEAK_GBS:.0%}); propagate {kb['propagate']:.1f} us "
-            f"({ach_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
+        out["large_filter"] = large_filter_leg(torch, pfm, stream)
 
         # ------------------------------------------------------------ PMMH chains
         if args.pmmh_iters > 0:

@@ -126,12 +126,10 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
         l96_substep_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
                            (uint32_t)(n0 + s), (uint32_t)f);
     } else {
-      const float F = (float)th[0], sq = (float)th[1];
-      const float h = (float)A.h, hh = (float)A.hh, h6 = (float)A.h6;
-      const float h3 = (float)(A.h / 3.0);
+      const L96F32 c = l96_f32_consts(th[0], th[1], A.h);
       for (int s = 1; s <= A.K; ++s)
-        l96_substep_f32<D>(x, F, sq, h, hh, h3, h6, key, TAG_NOISE, iter, (uint32_t)k,
-                           (uint32_t)(n0 + s), (uint32_t)f);
+        l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)k, (uint32_t)(n0 + s),
+                           (uint32_t)f);
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) xn[(int64_t)i * A.ld + dst] = x[i];

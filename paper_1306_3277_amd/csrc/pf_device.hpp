@@ -29,8 +29,18 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     }
     const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    // From the third round on every operand varies per lane, and the
+    // three-input exclusive or takes one instruction (truth table 0x96); in
+    // the first two rounds some words are uniform across the wave and the
+    // compiler keeps that part on the scalar unit.
+    uint32_t n0, n2;
+    if (r < 2) {
+      n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+      n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    } else {
+      n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+      n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+    }
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -233,48 +243,101 @@ __device__ __forceinline__ void l96_substep_f64(double (&x)[D], double F, double
   }
 }
 
-// FP32 RK4 substep: the increment h/6 (k1 + 2k2 + 2k3 + k4) + sq z is
-// accumulated from zero with fused multiply-adds and added to the state once,
-// so the state (|x| ~ 10, ulp ~ 1e-6) is rounded once per substep rather
-// than at every stage; each stage input is updated in place with a
-// two-value window, so only x, the increment and the stage input stay live
-// (3D registers).
+// FP32 Lorenz '96 substep.  With g_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i the
+// drift is g_i + F, and since the RK4 weights sum to h the increment is
+//   F h + (h/6) g1 + (h/3) g2 + (h/3) g3 + (h/6) g4 + sq z,
+// accumulated from F h with fused multiply-adds and added to the state once
+// (|x| ~ 10 with ulp ~ 1e-6: the state is rounded once per substep).  Stage
+// inputs are (x + c F) + c g with x + c F formed once per substep for c = h/2
+// and once for c = h and kept (4D live registers) when D <= 16; for larger D
+// they are x + c (g + F), so only 3D registers stay live and occupancy holds.  The
+// Wiener increment sq z is formed as sqrt(-2 ln(2) sq^2 log2 u_a)
+// cos(2 pi u_b): the noise scale rides in the radius.
+struct L96F32 {
+  float F, Fh;      // F and F h
+  float hF, hF2;    // (h/2) F and h F
+  float h, hh, h3, h6;
+  float nc2;        // -2 ln(2) sq^2
+};
+
+__device__ __forceinline__ L96F32 l96_f32_consts(double F, double sq, double h) {
+  L96F32 c;
+  c.F = (float)F;
+  c.Fh = (float)(F * h);
+  c.hF = (float)(0.5 * h * F);
+  c.hF2 = (float)(h * F);
+  c.h = (float)h;
+  c.hh = (float)(0.5 * h);
+  c.h3 = (float)(h / 3.0);
+  c.h6 = (float)(h / 6.0);
+  c.nc2 = (float)(-1.3862943611198906 * sq * sq);
+  return c;
+}
+
+// radius sqrt(nc2 log2 u_a) and the angle 2 pi u_b of one Box-Muller pair
+__device__ __forceinline__ void noise_pair_f32(uint32_t wa, uint32_t wb, float nc2, float& r,
+                                               float& cs, float& sn) {
+  r = __builtin_amdgcn_sqrtf(nc2 * __builtin_amdgcn_logf(u01_f32(wa)));
+  const float ub = u01_f32(wb);
+  cs = __builtin_amdgcn_cosf(ub);
+  sn = __builtin_amdgcn_sinf(ub);
+}
+
+constexpr bool l96_keep_xc(int D) { return D <= 16; }
+
+// one RK4 stage; xc holds x + c_xt F when kept, else x
 template <int D>
-__device__ __forceinline__ void l96_stage_f32(float (&xt)[D], const float (&x)[D], float (&acc)[D],
-                                              float F, float c_acc, float c_xt, bool first,
-                                              bool last) {
+__device__ __forceinline__ void l96_stage_f32(float (&xt)[D], const float (&xc)[D],
+                                              float (&acc)[D], float Fh, float F, float c_acc,
+                                              float c_xt, bool first, bool last) {
   const float old0 = xt[0];
   float pm2 = xt[D - 2], pm1 = xt[D - 1];
 #pragma unroll
   for (int i = 0; i < D; ++i) {
     const float xi = xt[i];
     const float xp1 = (i == D - 1) ? old0 : xt[i + 1];
-    const float k = fmaf(xp1 - pm2, pm1, F - xi);
+    const float g = fmaf(xp1 - pm2, pm1, -xi);
     pm2 = pm1;
     pm1 = xi;
-    acc[i] = first ? c_acc * k : fmaf(c_acc, k, acc[i]);
-    if (!last) xt[i] = fmaf(c_xt, k, x[i]);
+    acc[i] = fmaf(c_acc, g, first ? Fh : acc[i]);
+    if (!last) xt[i] = l96_keep_xc(D) ? fmaf(c_xt, g, xc[i]) : fmaf(c_xt, g + F, xc[i]);
   }
 }
 
 template <int D>
-__device__ __forceinline__ void l96_substep_f32(float (&x)[D], float F, float sq, float h,
-                                                float hh, float h3, float h6, Key key,
+__device__ __forceinline__ void l96_substep_f32(float (&x)[D], const L96F32& c, Key key,
                                                 uint32_t tag, uint32_t iter, uint32_t j,
                                                 uint32_t n, uint32_t b) {
   float acc[D], xt[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) xt[i] = x[i];
-  l96_stage_f32<D>(xt, x, acc, F, h6, hh, true, false);
-  l96_stage_f32<D>(xt, x, acc, F, h3, hh, false, false);
-  l96_stage_f32<D>(xt, x, acc, F, h3, h, false, false);
-  l96_stage_f32<D>(xt, x, acc, F, h6, 0.0f, false, true);
+  if constexpr (l96_keep_xc(D)) {
+    float xc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) xc[i] = x[i] + c.hF;
+    l96_stage_f32<D>(xt, xc, acc, c.Fh, 0.0f, c.h6, c.hh, true, false);
+    l96_stage_f32<D>(xt, xc, acc, c.Fh, 0.0f, c.h3, c.hh, false, false);
+#pragma unroll
+    for (int i = 0; i < D; ++i) xc[i] = x[i] + c.hF2;
+    l96_stage_f32<D>(xt, xc, acc, c.Fh, 0.0f, c.h3, c.h, false, false);
+    l96_stage_f32<D>(xt, xc, acc, c.Fh, 0.0f, c.h6, 0.0f, false, true);
+  } else {
+    l96_stage_f32<D>(xt, x, acc, c.Fh, c.F, c.h6, c.hh, true, false);
+    l96_stage_f32<D>(xt, x, acc, c.Fh, c.F, c.h3, c.hh, false, false);
+    l96_stage_f32<D>(xt, x, acc, c.Fh, c.F, c.h3, c.h, false, false);
+    l96_stage_f32<D>(xt, x, acc, c.Fh, c.F, c.h6, 0.0f, false, true);
+  }
 #pragma unroll
   for (int blk = 0; blk < D / 4; ++blk) {
-    float z[4];
-    normals4_f32(draw(key, tag, blk, iter, j, n, b), z);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) x[4 * blk + m] = x[4 * blk + m] + fmaf(sq, z[m], acc[4 * blk + m]);
+    const uint4 w = draw(key, tag, blk, iter, j, n, b);
+    float r0, c0, s0, r1, c1, s1;
+    noise_pair_f32(w.x, w.y, c.nc2, r0, c0, s0);
+    noise_pair_f32(w.z, w.w, c.nc2, r1, c1, s1);
+    const int i = 4 * blk;
+    x[i] = x[i] + fmaf(r0, c0, acc[i]);
+    x[i + 1] = x[i + 1] + fmaf(r0, s0, acc[i + 1]);
+    x[i + 2] = x[i + 2] + fmaf(r1, c1, acc[i + 2]);
+    x[i + 3] = x[i + 3] + fmaf(r1, s1, acc[i + 3]);
   }
 }
 
@@ -385,22 +448,26 @@ __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
 
 // Number of strata k in [0, N) with (u + k) S < N W, i.e. the particles up
 // to and including this one own strata 0 .. count-1.  The estimate from one
-// multiplication by invS = 1/S is corrected with the exact product
-// comparison, so the result does not depend on how the estimate rounds.
-__device__ __forceinline__ int64_t stratum_count(double W, double S, double invS, double u,
-                                                 int64_t N) {
+// multiplication by invS = 1/S is checked with the exact product comparison
+// on both sides; only when a check fails (the estimate rounded across a
+// stratum edge) does a lane step to the exact count, so the result does not
+// depend on how the estimate rounds.  N < 2^31.
+__device__ __forceinline__ int32_t stratum_count(double W, double S, double invS, double u,
+                                                 int32_t N) {
   const double Nd = (double)N;
   const double NW = Nd * W;
   const double xv = NW * invS - u;
-  int64_t est;
-  if (!(xv > 0.0))
-    est = 0;
-  else if (xv >= Nd)
-    est = N;
-  else
-    est = (int64_t)__builtin_ceil(xv);
-  while (est > 0 && !((u + (double)(est - 1)) * S < NW)) --est;
-  while (est < N && (u + (double)est) * S < NW) ++est;
+  // fmax maps a NaN estimate to 0; the exact checks below then decide
+  int32_t est = (int32_t)__builtin_ceil(fmin(fmax(xv, 0.0), Nd));
+  const bool down = est > 0 && !((u + (double)(est - 1)) * S < NW);
+  const bool up = est < N && (u + (double)est) * S < NW;
+  if (down) {
+    --est;
+    while (est > 0 && !((u + (double)(est - 1)) * S < NW)) --est;
+  } else if (up) {
+    ++est;
+    while (est < N && (u + (double)est) * S < NW) ++est;
+  }
   return est;
 }
 

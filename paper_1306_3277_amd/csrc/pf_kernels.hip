@@ -141,12 +141,9 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
           l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
                              (uint32_t)(n0 + s), A.b);
       } else {
-        const float F = (float)A.theta[0], sq = (float)A.theta[1];
-        const float h = (float)A.h, hh = (float)A.hh, h6 = (float)A.h6;
-        const float h3 = (float)(A.h / 3.0);
+        const L96F32 c = l96_f32_consts(A.theta[0], A.theta[1], A.h);
         for (int s = 1; s <= A.K; ++s)
-          l96_substep_f32<D>(x, F, sq, h, hh, h3, h6, key, TAG_NOISE, iter, (uint32_t)j,
-                             (uint32_t)(n0 + s), A.b);
+          l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
       }
 #pragma unroll
       for (int i = 0; i < D; ++i) xprop[(int64_t)i * A.ld + col] = x[i];

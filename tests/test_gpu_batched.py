@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 
 REL64 = 1e-10
 ABS32 = 1e-4
+REL32 = 1e-6  # FP32 per-step bound: max(ABS32, REL32 |ell_t|)
 
 
 @pytest.fixture(scope="module")
@@ -147,7 +148,8 @@ def test_batched_full_c4_shape_sampled(pfm):
     sample = sorted(set([int(order[0]), int(order[-1]), 0, 511] + list(range(100, 108))))
     for b in sample:
         r = oracle.pf_run(pb, theta=pb.theta[b], N=int(n[b]), b=b, T=1)
-        assert abs(ell[b, 0] - r["ell"][0]) <= ABS32, (b, ell[b, 0], r["ell"][0])
+        bound = max(ABS32, REL32 * abs(r["ell"][0]))
+        assert abs(ell[b, 0] - r["ell"][0]) <= bound, (b, ell[b, 0], r["ell"][0])
     for b in range(pb.B):
         ab = a[off[b]:off[b + 1]]
         assert np.all(np.diff(ab) >= 0) and ab[0] >= 0 and ab[-1] < n[b]

@@ -5,7 +5,10 @@ oracle's except where a stratum lies within 1e-9 (normalised) of a
 cumulative weight; each likelihood increment and the running
 log-likelihood within 1e-10 relative.  FP32 mixed: under teacher forcing
 (both sides start each interval from the oracle's state rounded to FP32)
-every likelihood increment within 1e-4 absolute.  Sizes span several 256-particle blocks and
+every likelihood increment within 1e-4 absolute, or within 1e-6 of |ell_t|
+where that is larger (a filter collapsed onto one particle, |ell_t| in the
+hundreds, where the FP32 state's own precision sets the floor).  Sizes span
+several 256-particle blocks and
 a ragged tail; the full-size workloads are checked on sampled particles and
 on properties that hold at any size.
 """
@@ -23,6 +26,15 @@ pytestmark = pytest.mark.gpu
 BAND = 1e-9
 REL64 = 1e-10
 ABS32 = 1e-4
+REL32 = 1e-6
+
+
+def fp32_bound(ell_ref):
+    """Per-step FP32 bound: 1e-4 absolute, relaxed to 1e-6 relative once
+    |ell_t| exceeds 100 (FP32 rounds the state to 2^-24 relative; a collapsed
+    filter's increment is one particle's log-weight, whose relative error is
+    then a few times that)."""
+    return max(ABS32, REL32 * abs(ell_ref))
 
 
 @pytest.fixture(scope="module")
@@ -137,7 +149,7 @@ def _teacher_forced_fp32(pfm, pb, steps):
         ell, ess = f.trace()
         err = abs(ell[0, t - 1] - ell_ref)
         worst = max(worst, err)
-        assert err <= ABS32, (t, ell[0, t - 1], ell_ref)
+        assert err <= fp32_bound(ell_ref), (t, ell[0, t - 1], ell_ref)
         assert ess[0, t - 1] == pytest.approx(ess_ref, rel=1e-2)
         x = oracle.gather(xp, a)
     f.close()

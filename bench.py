@@ -241,7 +241,7 @@ def main():
     log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
 
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    threads, groups, cand_ms = f32.autotune(steps=8)
+    threads, groups, cand_ms = f32.autotune(steps=16)
     log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
         f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
         f"{np.round(cand_ms * 1e3, 1).tolist()}")

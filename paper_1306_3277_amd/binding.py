@@ -95,6 +95,9 @@ def load(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError(f"HIP library {path} is not built; run __graft_entry__.build()")
+        # PyTorch's HIP runtime must be the process's runtime: load it first so
+        # the library binds to it rather than bringing in a second copy
+        import torch  # noqa: F401
         L = C.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -174,7 +174,7 @@ Layout make_layout(const pf_config* c) {
   L.obs_idx = take(4 * (size_t)c->n_obs);
   L.q = take(c->model == PF_MODEL_WK ? 8 * ((size_t)c->T * c->K + 1) : 8);
   L.b_off = take(8 * (size_t)(c->B + 1));
-  L.b_order = take(4 * (size_t)c->B);
+  L.b_order = take(sizeof(pfk::FilterSlot) * (size_t)c->B);
   L.b_chunk_f = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
   L.b_chunk_k = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
   L.b_u = take(8 * (size_t)c->B);
@@ -216,9 +216,10 @@ struct pf_handle {
   int batch_nt = 256;
   int groups = 1;
   std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt;
-  std::vector<hipStream_t> side;     // streams of groups 1..G-1
-  hipEvent_t ev_fork = nullptr;
-  std::vector<hipEvent_t> ev_join;   // per side stream
+  // with G > 1 groups, group g's kernels run on side[g]; ev_a[0] forks the
+  // side streams from the caller's, ev_b[g] joins group g back
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev_a, ev_b;
   // timing
   bool timing = false;
   struct Ev {
@@ -226,7 +227,8 @@ struct pf_handle {
     int kind;
   };
   std::vector<Ev> events;
-  // graphs: one per filter group (plain layout: one)
+  // graphs: gexecs[0] holds one interval, gexecs[1] (if present) holds
+  // kGraphSteps intervals
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   hipStream_t cap_stream = nullptr;
@@ -295,7 +297,7 @@ BatchArgs batch_args(const pf_handle* H) {
   a.obs_pos = H->at<int32_t>(H->L.obs_pos);
   a.q = c.model == PF_MODEL_WK ? H->at<double>(H->L.q) : nullptr;
   a.off = H->at<int64_t>(H->L.b_off);
-  a.order = H->at<int32_t>(H->L.b_order);
+  a.order = H->at<pfk::FilterSlot>(H->L.b_order);
   a.chunk_f = H->at<int32_t>(H->L.b_chunk_f);
   a.chunk_k = H->at<int32_t>(H->L.b_chunk_k);
   a.chunk0 = 0;
@@ -353,8 +355,10 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
   return PF_OK;
 }
 
-// One interval for filter group g of the batched layout, on stream s.
-pf_status enqueue_group_step(pf_handle* H, int g, hipStream_t s) {
+constexpr int kGraphSteps = 8;
+
+// Propagation (K5a) of filter group g on stream s.
+pf_status enqueue_group_propagate(pf_handle* H, int g, hipStream_t s) {
   const pf_config& c = H->cfg;
   BatchArgs a = batch_args(H);
   a.chunk0 = H->grp_chunk0[g];
@@ -365,40 +369,54 @@ pf_status enqueue_group_step(pf_handle* H, int g, hipStream_t s) {
   HIP_TRY(pfk::launch_batched_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
                                         H->ws + H->L.x_tmp, H->at<double>(H->L.lw),
                                         H->at<int32_t>(H->L.anc), a, H->grp_nchunks[g], s));
-  if ((st = ev_end(H, e0, 0, s))) return st;
-  if ((st = ev_begin(H, &e0, s))) return st;
-  HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                       H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
-  if ((st = ev_end(H, e0, 4, s))) return st;
-  return PF_OK;
+  return ev_end(H, e0, 0, s);
 }
 
-// The side streams wait for everything issued so far on s ...
-pf_status fork(pf_handle* H, hipStream_t s) {
-  if (H->groups <= 1) return PF_OK;
-  HIP_TRY(hipEventRecord(H->ev_fork, s));
-  for (int g = 1; g < H->groups; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g - 1], H->ev_fork, 0));
-  return PF_OK;
+// Collective (K5b: likelihood, ESS, resampling) of filter group g on stream s.
+pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
+  BatchArgs a = batch_args(H);
+  a.chunk0 = H->grp_chunk0[g];
+  a.order0 = H->grp_order0[g];
+  hipEvent_t e0{};
+  pf_status st = ev_begin(H, &e0, s);
+  if (st) return st;
+  HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
+                                       H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
+  return ev_end(H, e0, 4, s);
 }
-// ... and s waits for everything issued on the side streams.
-pf_status join(pf_handle* H, hipStream_t s) {
-  if (H->groups <= 1) return PF_OK;
-  for (int g = 1; g < H->groups; ++g) {
-    HIP_TRY(hipEventRecord(H->ev_join[g - 1], H->side[g - 1]));
-    HIP_TRY(hipStreamWaitEvent(s, H->ev_join[g - 1], 0));
+
+// n intervals of the batched layout issued from stream s.  With one group
+// both kernels go on s.  With G groups (filters dealt so that every group
+// holds about the same number of particles) group g's intervals run back to
+// back on side[g]: the groups start together after everything issued on s
+// so far, drift against each other, and one group's collective overlaps
+// another's propagation.  s waits for every group at the end.
+pf_status enqueue_batched(pf_handle* H, hipStream_t s, int n) {
+  pf_status st;
+  const int G = H->groups;
+  if (G == 1) {
+    for (int i = 0; i < n; ++i)
+      if ((st = enqueue_group_propagate(H, 0, s)) || (st = enqueue_group_collective(H, 0, s)))
+        return st;
+    return PF_OK;
+  }
+  HIP_TRY(hipEventRecord(H->ev_a[0], s));
+  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_a[0], 0));
+  for (int g = 0; g < G; ++g)
+    for (int i = 0; i < n; ++i)
+      if ((st = enqueue_group_propagate(H, g, H->side[g])) ||
+          (st = enqueue_group_collective(H, g, H->side[g])))
+        return st;
+  for (int g = 0; g < G; ++g) {
+    HIP_TRY(hipEventRecord(H->ev_b[g], H->side[g]));
+    HIP_TRY(hipStreamWaitEvent(s, H->ev_b[g], 0));
   }
   return PF_OK;
 }
 
 pf_status enqueue_step(pf_handle* H, hipStream_t s) {
   const pf_config& c = H->cfg;
-  if (c.layout == PF_LAYOUT_BATCHED) {
-    pf_status st = fork(H, s);
-    if (st) return st;
-    for (int g = 0; g < H->groups; ++g)
-      if ((st = enqueue_group_step(H, g, g == 0 ? s : H->side[g - 1]))) return st;
-    return join(H, s);
-  }
+  if (c.layout == PF_LAYOUT_BATCHED) return enqueue_batched(H, s, 1);
   for (int b = 0; b < c.B; ++b) {
     PlainArgs a = plain_args(H, b);
     hipEvent_t e0{};
@@ -492,16 +510,26 @@ pf_status build_groups(pf_handle* H, int G) {
     members[gbest].push_back(b);
     load[gbest] += H->np[b];
   }
-  std::vector<int32_t> ord, chf, chk;
+  std::vector<pfk::FilterSlot> ord;
+  std::vector<int32_t> chf, chk;
   H->grp_chunk0.assign(G, 0);
   H->grp_nchunks.assign(G, 0);
   H->grp_order0.assign(G, 0);
   H->grp_nfilt.assign(G, 0);
+  // Collective slots: the first one-per-CU slots take the largest filters,
+  // and the slots beyond them (which share a CU with those) take the rest
+  // smallest first, so the largest filters share their CU with the smallest.
+  const int cu_slots = 256;
   for (int g = 0; g < G; ++g) {
     H->grp_order0[g] = (int32_t)ord.size();
     H->grp_chunk0[g] = (int32_t)chf.size();
-    for (int32_t b : members[g]) {
-      ord.push_back(b);
+    const std::vector<int32_t>& mg = members[g];  // largest first
+    const int m = (int)mg.size();
+    for (int i = 0; i < m; ++i) {
+      const int32_t b = i < cu_slots ? mg[i] : mg[m - 1 - (i - cu_slots)];
+      ord.push_back({b, (int32_t)H->L.off[b], (int32_t)H->np[b], 0});
+    }
+    for (int32_t b : mg) {
       for (int64_t k = 0; k < H->np[b]; k += pfk::BATCH_NT) {
         chf.push_back(b);
         chk.push_back((int32_t)k);
@@ -510,23 +538,26 @@ pf_status build_groups(pf_handle* H, int G) {
     H->grp_nfilt[g] = (int32_t)ord.size() - H->grp_order0[g];
     H->grp_nchunks[g] = (int32_t)chf.size() - H->grp_chunk0[g];
   }
-  HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_order, ord.data(), 4 * ord.size(), hipMemcpyHostToDevice,
-                         H->stream));
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_order, ord.data(), sizeof(pfk::FilterSlot) * ord.size(),
+                         hipMemcpyHostToDevice, H->stream));
   HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_chunk_f, chf.data(), 4 * chf.size(),
                          hipMemcpyHostToDevice, H->stream));
   HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_chunk_k, chk.data(), 4 * chk.size(),
                          hipMemcpyHostToDevice, H->stream));
   HIP_TRY(hipStreamSynchronize(H->stream));
-  // streams and events for the extra groups (default priority)
-  while ((int)H->side.size() < G - 1) {
+  // a stream and two events per group (default priority); graphs captured
+  // for another group count are rebuilt
+  while (G > 1 && (int)H->side.size() < G) {
     hipStream_t st;
     HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     H->side.push_back(st);
-    hipEvent_t ev;
-    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    H->ev_join.push_back(ev);
+    hipEvent_t ea, eb;
+    HIP_TRY(hipEventCreateWithFlags(&ea, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&eb, hipEventDisableTiming));
+    H->ev_a.push_back(ea);
+    H->ev_b.push_back(eb);
   }
-  if (G > 1 && !H->ev_fork) HIP_TRY(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+  if (G != H->groups) destroy_graphs(H);
   H->groups = G;
   return PF_OK;
 }
@@ -541,12 +572,12 @@ void destroy_graphs(pf_handle* H) {
 void destroy_streams(pf_handle* H) {
   destroy_graphs(H);
   for (auto s : H->side) (void)hipStreamDestroy(s);
-  for (auto e : H->ev_join) (void)hipEventDestroy(e);
-  if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
+  for (auto e : H->ev_a) (void)hipEventDestroy(e);
+  for (auto e : H->ev_b) (void)hipEventDestroy(e);
   if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
   H->side.clear();
-  H->ev_join.clear();
-  H->ev_fork = nullptr;
+  H->ev_a.clear();
+  H->ev_b.clear();
   H->cap_stream = nullptr;
 }
 
@@ -562,8 +593,9 @@ pf_status launch_stream(pf_handle* H, hipStream_t* out) {
   return PF_OK;
 }
 
-// One graph per filter group (plain layout: one graph for all filters), each
-// holding one whole interval (step + resample).
+// gexecs[0]: one whole interval (step + resample); for the batched layout
+// gexecs[1]: kGraphSteps intervals, so the fork and join of the filter
+// groups and the launch of a graph are paid once per kGraphSteps intervals.
 pf_status ensure_graphs(pf_handle* H) {
   if (!H->gexecs.empty()) return PF_OK;
   hipStream_t cs;
@@ -571,18 +603,22 @@ pf_status ensure_graphs(pf_handle* H) {
   if (st) return st;
   const bool tm = H->timing;
   H->timing = false;
-  const int ng = H->cfg.layout == PF_LAYOUT_BATCHED ? H->groups : 1;
-  for (int g = 0; g < ng && !st; ++g) {
+  const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
+  const int nv = batched ? 2 : 1;
+  for (int v = 0; v < nv && !st; ++v) {
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    if (H->cfg.layout == PF_LAYOUT_BATCHED) {
-      st = enqueue_group_step(H, g, cs);
+    if (batched) {
+      st = enqueue_batched(H, cs, v == 0 ? 1 : kGraphSteps);
     } else {
       st = enqueue_step(H, cs);
       if (!st) st = enqueue_resample(H, cs, nullptr);
     }
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &graph);
-    if (st) break;
+    if (st) {
+      if (graph) (void)hipGraphDestroy(graph);
+      break;
+    }
     if (e != hipSuccess) {
       st = fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
       break;
@@ -759,14 +795,10 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   if ((st = ensure_graphs(H))) return st;
   hipStream_t ls;
   if ((st = launch_stream(H, &ls))) return st;
-  const int ng = (int)H->gexecs.size();
-  if (ng > 1 && (st = fork(H, ls))) return st;
-  // each group's filters are independent, so its intervals run back to back
-  // on its own stream while the other groups' run beside them
-  for (int i = 0; i < n_steps; ++i)
-    for (int g = 0; g < ng; ++g)
-      HIP_TRY(hipGraphLaunch(H->gexecs[g], g == 0 ? ls : H->side[g - 1]));
-  if (ng > 1 && (st = join(H, ls))) return st;
+  int left = n_steps;
+  if (H->gexecs.size() > 1)
+    for (; left >= kGraphSteps; left -= kGraphSteps) HIP_TRY(hipGraphLaunch(H->gexecs[1], ls));
+  for (; left > 0; --left) HIP_TRY(hipGraphLaunch(H->gexecs[0], ls));
   H->t += n_steps;
   return PF_OK;
 }

@@ -140,44 +140,61 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 
 // ---------------------------------------------------------------- K5b
 // One workgroup per filter.  Lane t owns the P = ceil(N/NT) consecutive
-// particles [tP, tP + P), read straight from global memory into registers:
-// their weights are summed sequentially in the lane (an exact monotone
-// prefix), the lanes' totals are scanned across the block, and an exact
-// running maximum over earlier lanes keeps the cumulative weights
-// non-decreasing at lane edges.  The stratum counts go to LDS (at most 8192
-// int32) for a merge-path walk of 2N/NT diagonals per lane.  Reductions that
-// can share a block exchange do, so the whole collective costs five
-// barriers.
+// particles [tP, tP + P).  The log-weights are read from global memory with
+// coalesced loads into an LDS stage (element i at slot i ^ ((i >> 4) & 15),
+// so both the coalesced writes and the lanes' reads of their own 16-element
+// runs are free of bank conflicts) and read back per lane.  Their weights are
+// summed sequentially in the lane (an exact monotone prefix), the lanes'
+// totals are scanned across the block, and an exact running maximum over
+// earlier lanes keeps the cumulative weights non-decreasing at lane edges.
+// The stratum counts (< 2^16) and then the ancestors reuse the stage.  When
+// no lane's particles own many more strata than particles (the weights are
+// spread), each lane writes the ancestors of its own particles' strata
+// directly; otherwise a merge-path walk of 2N/NT diagonals per lane keeps
+// the work balanced.  Either way the ancestors go to LDS and one coalesced
+// pass stores them.  The resampling uniform is drawn while the loads are in
+// flight, off the critical path.  64 KB of LDS per workgroup.
+__device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
+
 template <int NT>
-__global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict__ lw,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
                                                        BatchArgs A) {
   constexpr int MAXP = BATCH_MAXN / NT;
   constexpr int NW = NT / WAVE;
-  __shared__ int32_t sc[BATCH_MAXN];
-  __shared__ double xa[NW], xb[NW], xc[NW];
+  __shared__ double stage[BATCH_MAXN];
+  __shared__ double xa[NW], xb[NW], xc[NW], xm[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
-  const int f = A.order[A.order0 + blockIdx.x];
-  const int64_t off = A.off[f];
-  const int N = (int)(A.off[f + 1] - off);
+  uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
+  int32_t* al = reinterpret_cast<int32_t*>(stage) + BATCH_MAXN / 2;   // ancestors, 32 KB
+  const FilterSlot slot = A.order[A.order0 + blockIdx.x];
+  const int f = slot.f;
+  const int64_t off = slot.off;
+  const int N = slot.n;
   FilterState* fs = A.fs + f;
+  const double loglik0 = fs->loglik;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const bool resample_only = A.mode != 0;
-  const int P = (N + NT - 1) / NT;
-  const int i0 = min(N, (int)threadIdx.x * P), i1 = min(N, i0 + P);
-  // (1) this lane's log-weights and their maximum
-  double l[MAXP];
+  const int t = resample_only ? fs->t : fs->t + 1;
+  // (1) coalesced load to the stage and the maximum
   double m = -INFINITY;
 #pragma unroll
-  for (int e = 0; e < MAXP; ++e) {
-    l[e] = -INFINITY;
-    if (e < P && i0 + e < i1) {
-      const double v = lw[off + i0 + e];
-      l[e] = (v == v) ? v : -INFINITY;  // NaN counts as zero weight
-      m = fmax(m, l[e]);
+  for (int r = 0; r < MAXP; ++r) {
+    const int i = (int)threadIdx.x + r * NT;
+    if (i < N) {
+      double v = lw[off + i];
+      v = (v == v) ? v : -INFINITY;  // NaN counts as zero weight
+      stage[stage_slot(i)] = v;
+      m = fmax(m, v);
     }
   }
+  // the resampling uniform, drawn while the loads are in flight
+  double u = 0.0;
+  if (threadIdx.x == 0)
+    u = resample_only ? A.u_override[f]
+                      : u01_f64(draw(bkey(A.key), TAG_RESAMPLE, 0, fs->iter, 0, (uint32_t)t,
+                                     (uint32_t)f).x);
   m = wave_max(m);
   if (lane == 0) xa[wv] = m;
   __syncthreads();  // 1
@@ -185,38 +202,49 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
 #pragma unroll
   for (int w = 1; w < NW; ++w) M = fmax(M, xa[w]);
   const bool finite = (M > -INFINITY) && (M < INFINITY);
-  // (2) weights, in-lane prefix, square sum and last positive particle
+  // (2) this lane's run: weights, in-lane prefix, square sum, last positive
+  const int P = (N + NT - 1) / NT;
+  const int i0 = min(N, (int)threadIdx.x * P), i1 = min(N, i0 + P);
   double loc[MAXP];
   double run = 0.0, run2 = 0.0;
   int cand = -1;
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
-    const double w = finite ? exp(l[e] - M) : 0.0;  // exp(-inf) = 0
-    if (w > 0.0) cand = i0 + e;
-    run += w;
-    run2 += w * w;
+    if (e < P && i0 + e < i1) {
+      const double l = stage[stage_slot(i0 + e)];
+      const double w = finite ? exp_nonpos(l - M) : 0.0;  // exp(-inf) = 0
+      if (w > 0.0) cand = i0 + e;
+      run += w;
+      run2 += w * w;
+    }
     loc[e] = run;
   }
   // one exchange: scan of the lanes' sums, total of squares, last positive
   const double incl = wave_incl_scan(run, lane);
   const double s2w = wave_sum(run2);
+  const double rmax = wave_max(run);
   const int cw = wave_max_i(cand);
-  __syncthreads();  // 2 (xa reused)
+  __syncthreads();  // 2 (xa reused; the stage is no longer read)
   if (lane == WAVE - 1) xa[wv] = incl;
   if (lane == 0) {
     xb[wv] = s2w;
+    xm[wv] = rmax;
     xi[wv] = cw;
   }
   __syncthreads();  // 3
-  double pre = incl - run, S = 0.0, S2 = 0.0;
+  double pre = incl - run, S = 0.0, S2 = 0.0, runmax = 0.0;
   int jstar = -1;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     if (w < wv) pre += xa[w];
     S += xa[w];
     S2 += xb[w];
+    runmax = fmax(runmax, xm[w]);
     jstar = max(jstar, xi[w]);
   }
+  // a lane's particles own about N run / S strata: write them per particle
+  // unless some lane would own far more than its share (4P)
+  const bool per_particle = !finite || runmax * (double)N <= (double)(4 * P - 2) * S;
   // exclusive running maximum of the lanes' last cumulative weights
   const double vlast = (i1 > i0) ? pre + run : -INFINITY;
   const double vin = wave_incl_max_scan(vlast, lane);
@@ -232,11 +260,7 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
   vprev = (lane == 0) ? vw : fmax(vprev, vw);
   S = fmax(S, vall);
   if (threadIdx.x == 0) {
-    double u;
-    const int t = resample_only ? fs->t : fs->t + 1;
-    if (resample_only) {
-      u = A.u_override[f];
-    } else {
+    if (!resample_only) {
       double ell, ess;
       if (finite && S > 0.0) {
         ell = (M + log(S)) - log((double)N);
@@ -246,22 +270,20 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
         ess = 0.0;
         fs->status = 4;
       }
-      fs->loglik = fs->loglik + ell;
+      fs->loglik = loglik0 + ell;
       fs->M = finite ? M : -INFINITY;
       fs->S = S;
       fs->ell = ell;
       fs->ess = ess;
       A.ell_tr[(size_t)f * A.T + t - 1] = ell;
       A.ess_tr[(size_t)f * A.T + t - 1] = ess;
-      const uint4 w = draw(bkey(A.key), TAG_RESAMPLE, 0, fs->iter, 0, (uint32_t)t, (uint32_t)f);
-      u = u01_f64(w.x);
       fs->u = u;
       fs->t = t;
     }
     bc = u;
   }
   __syncthreads();  // 5
-  const double u = bc;
+  u = bc;
   const double invS = 1.0 / S;
   // (3) stratum counts of this lane's particles, to LDS
 #pragma unroll
@@ -269,18 +291,40 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
     const int i = i0 + e;
     if (e < P && i < i1) {
       const double W = fmin(fmax(pre + loc[e], vprev), S);
-      sc[i] = finite ? (int32_t)stratum_count(W, S, invS, u, N) : i + 1;
+      sc[i] = (uint16_t)(finite ? stratum_count(W, S, invS, u, N) : i + 1);
     }
   }
   __syncthreads();  // 6
-  // (4) merge path: this lane walks diagonals [dt, dt + L)
+  // (4) ancestors to LDS
+  if (per_particle) {
+    // particle i owns strata [c_{i-1}, c_i)
+    int c0 = (i0 > 0 && i0 < N) ? (int)sc[i0 - 1] : 0;
+    for (int i = i0; i < i1; ++i) {
+      const int c1 = (int)sc[i];
+      for (int k = c0; k < c1; ++k) al[k] = i;
+      c0 = c1;
+    }
+    // strata past the last count (rounding) go to the last positive particle
+    const int ctot = (int)sc[N - 1];
+    if (ctot < N) {
+      bool bad = false;
+      int32_t aj = jstar;
+      if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
+        aj = 0;
+        bad = true;
+      }
+      for (int k = ctot + (int)threadIdx.x; k < N; k += NT) al[k] = aj;
+      if (bad && threadIdx.x == 0) atomicOr(&fs->pad, 1);
+    }
+  }
+  // merge path: this lane walks diagonals [dt, dt + L)
   const int L = (2 * N + NT - 1) / NT;
   const int dt = (int)threadIdx.x * L;
-  if (dt < 2 * N) {
+  if (!per_particle && dt < 2 * N) {
     int lo = max(0, dt - N), hi = min(dt, N);
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (sc[mid] <= dt - 1 - mid)
+      if ((int)sc[mid] <= dt - 1 - mid)
         lo = mid + 1;
       else
         hi = mid;
@@ -288,8 +332,8 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
     int j = lo, k = dt - lo;
     const int dend = min(dt + L, 2 * N);
     bool bad = false;
-    for (int s = dt; s < dend; ++s) {
-      if (j < N && (k >= N || sc[j] <= k)) {
+    for (int s2 = dt; s2 < dend; ++s2) {
+      if (j < N && (k >= N || (int)sc[j] <= k)) {
         ++j;
       } else {
         int32_t aj = j < N ? j : jstar;
@@ -297,11 +341,18 @@ __global__ __launch_bounds__(NT) void k_batch_resample(const double* __restrict_
           aj = 0;
           bad = true;
         }
-        anc[off + k] = aj;
+        al[k] = aj;
         ++k;
       }
     }
     if (bad) atomicOr(&fs->pad, 1);
+  }
+  __syncthreads();  // 7
+  // (5) coalesced store of the ancestors
+#pragma unroll
+  for (int r = 0; r < MAXP; ++r) {
+    const int k = (int)threadIdx.x + r * NT;
+    if (k < N) anc[off + k] = al[k];
   }
 }
 

@@ -341,6 +341,33 @@ __device__ __forceinline__ void l96_substep_f32(float (&x)[D], const L96F32& c, 
   }
 }
 
+// e^x for x <= 0, x = -inf included (weights exp(lw - max lw)).  Reduction
+// x = n ln2 + r with |r| <= ln2/2 (ln2 split in two parts, so r is exact to
+// about 2^-60), e^r by its Taylor polynomial to degree 13 (truncation below
+// 2^-52 relative) in Horner form, and the scale 2^n.  Underflows to 0 below
+// -745.2; a NaN argument gives 0.
+__device__ __forceinline__ double exp_nonpos(double x) {
+  if (!(x >= -745.2)) return 0.0;
+  const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
+  double r = __builtin_fma(-n, 0x1.62e42fefa39efp-1, x);
+  r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56, r);
+  double p = 0x1.6124613a86d09p-33;           // 1/13!
+  p = __builtin_fma(p, r, 0x1.1eed8eff8d898p-29);  // 1/12!
+  p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26);  // 1/11!
+  p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22);  // 1/10!
+  p = __builtin_fma(p, r, 0x1.71de3a556c734p-19);  // 1/9!
+  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16);  // 1/8!
+  p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13);  // 1/7!
+  p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10);  // 1/6!
+  p = __builtin_fma(p, r, 0x1.1111111111111p-7);   // 1/5!
+  p = __builtin_fma(p, r, 0x1.5555555555555p-5);   // 1/4!
+  p = __builtin_fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll

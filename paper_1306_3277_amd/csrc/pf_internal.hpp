@@ -47,6 +47,12 @@ struct PlainArgs {
   double* ess_tr;
 };
 
+// One filter of a batched collective launch: its index, first particle and
+// particle count (fewer than 2^31 particles in all), read with one load.
+struct FilterSlot {
+  int32_t f, off, n, pad;
+};
+
 // Arguments of the batched-layout kernels.
 struct BatchArgs {
   int32_t B, K, T, d, n_obs;
@@ -59,7 +65,7 @@ struct BatchArgs {
   const int32_t* obs_pos;   // device [d]
   const double* q;          // device windkessel flow (or null)
   const int64_t* off;       // device [B+1] first particle of each filter
-  const int32_t* order;     // device [B] filters, largest first
+  const FilterSlot* order;  // device [B] filters, largest first within a group
   const int32_t* chunk_f;   // device [n_chunks] filter of each chunk
   const int32_t* chunk_k;   // device [n_chunks] first particle of each chunk
   int32_t chunk0;           // first chunk of the launch (its filter group)

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
   // a NaN log-weight counts as zero weight
   const double lc = (l == l) ? l : -INFINITY;
   const double m = block_max<K1_NT>(lc, red);
-  const double e = (m > -INFINITY && m < INFINITY) ? exp(lc - m) : 0.0;
+  const double e = (m > -INFINITY && m < INFINITY) ? exp_nonpos(lc - m) : 0.0;
   const double s1 = block_sum<K1_NT>(e, red);
   const double s2 = block_sum<K1_NT>(e * e, red);
   if (threadIdx.x == 0) {
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
     const double mb = P[3 * i];
     T2 = 0.0;
     if (!(finite && mb > -INFINITY)) return 0.0;
-    const double sc = exp(mb - M);
+    const double sc = exp_nonpos(mb - M);
     T2 = P[3 * i + 2] * (sc * sc);
     return P[3 * i + 1] * sc;
   };
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
     double we = 0.0;
     if (j < N && finite) {
       const double l = lw[A.off + j];
-      we = (l == l) ? exp(l - M) : 0.0;
+      we = (l == l) ? exp_nonpos(l - M) : 0.0;
     }
     w[e] = we;
     run += we;

@@ -206,18 +206,19 @@ def test_autotune_keeps_results(pfm):
 
 
 def test_filter_groups_do_not_change_results(pfm):
-    """Groups only change which stream steps which filters: eager and graph
-    replay, one group or three, give the same bits."""
+    """Groups only change which stream runs which kernel: eager and graph
+    replay (one-interval and eight-interval graphs), one group or several,
+    give the same bits."""
     th, n = W.batched_thetas(23, seed=12)
-    pb = _problem(n, th, T=6)
+    pb = _problem(n, th, T=13)
     outs = []
-    for groups, graph in ((1, False), (3, False), (3, True), (2, True)):
+    for groups, graph in ((1, False), (3, False), (3, True), (2, True), (4, True), (1, True)):
         f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
         f.set_tuning(512, groups)
         if graph:
             f.graph_run(2)
             f.advance(1)
-            f.graph_run(pb.T - 3)
+            f.graph_run(pb.T - 3)  # one eight-interval graph, two single ones
         else:
             f.advance(pb.T)
         outs.append((f.trace()[0], f.get_state(), f.ancestors(), f.loglik()[0]))

@@ -177,16 +177,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const bool resample_only = A.mode != 0;
   const int t = resample_only ? fs->t : fs->t + 1;
-  // (1) coalesced load to the stage and the maximum
+  // (1) coalesced load to the stage and the maximum; the loads are issued
+  // together (indices past the filter read its last element and are
+  // dropped), so their latencies overlap
   double m = -INFINITY;
+  {
+    double v[MAXP];
 #pragma unroll
-  for (int r = 0; r < MAXP; ++r) {
-    const int i = (int)threadIdx.x + r * NT;
-    if (i < N) {
-      double v = lw[off + i];
-      v = (v == v) ? v : -INFINITY;  // NaN counts as zero weight
-      stage[stage_slot(i)] = v;
-      m = fmax(m, v);
+    for (int r = 0; r < MAXP; ++r) v[r] = lw[off + min((int)threadIdx.x + r * NT, N - 1)];
+#pragma unroll
+    for (int r = 0; r < MAXP; ++r) {
+      const int i = (int)threadIdx.x + r * NT;
+      if (i < N) {
+        const double x = (v[r] == v[r]) ? v[r] : -INFINITY;  // NaN counts as zero weight
+        stage[stage_slot(i)] = x;
+        m = fmax(m, x);
+      }
     }
   }
   // the resampling uniform, drawn while the loads are in flight
@@ -208,11 +214,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   double loc[MAXP];
   double run = 0.0, run2 = 0.0;
   int cand = -1;
+  double lv[MAXP];
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) lv[e] = stage[stage_slot(min(i0 + e, N - 1))];
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     if (e < P && i0 + e < i1) {
-      const double l = stage[stage_slot(i0 + e)];
-      const double w = finite ? exp_nonpos(l - M) : 0.0;  // exp(-inf) = 0
+      const double w = finite ? exp_nonpos(lv[e] - M) : 0.0;  // exp(-inf) = 0
       if (w > 0.0) cand = i0 + e;
       run += w;
       run2 += w * w;

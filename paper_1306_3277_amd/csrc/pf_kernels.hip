@@ -347,14 +347,17 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   const double lo_off = bo[k1b];
   const double hi_off = bo[min(k1b + K3_SPAN / K1_NT, A.nblk)];
   // in-lane sequential prefix of K3_PER consecutive weights
-  double w[K3_PER], loc[K3_PER];
+  double w[K3_PER], loc[K3_PER], lv[K3_PER];
   double run = 0.0;
+  // loads issued together (past the end they reread the last weight)
+#pragma unroll
+  for (int e = 0; e < K3_PER; ++e) lv[e] = lw[A.off + min(j0 + e, N - 1)];
 #pragma unroll
   for (int e = 0; e < K3_PER; ++e) {
     const int64_t j = j0 + e;
     double we = 0.0;
     if (j < N && finite) {
-      const double l = lw[A.off + j];
+      const double l = lv[e];
       we = (l == l) ? exp_nonpos(l - M) : 0.0;
     }
     w[e] = we;

@@ -394,17 +394,54 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   __syncthreads();
   if (lane == 0) cprev = wv > 0 ? wlast[wv - 1] : g_lo;
   int32_t* bstate = bstate_all + A.bst0;
+  // this lane's diagonal ranges: one per particle, plus (for the filter's or
+  // the block's last particle) the overflow outputs and end state, or the
+  // next block's first particle below its edge count
+  int64_t rj[K3_PER + 1], rlo[K3_PER + 1], rhi[K3_PER + 1];
+#pragma unroll
+  for (int e = 0; e <= K3_PER; ++e) {
+    rj[e] = 0;
+    rlo[e] = 1;
+    rhi[e] = 0;  // empty
+  }
 #pragma unroll
   for (int e = 0; e < K3_PER; ++e) {
     const int64_t j = j0 + e;
     if (j < N) {
-      emit_bounds(bstate, j, j + cprev, j + c[e]);
-      if (j == N - 1)  // after the last particle: overflow outputs and the end state
-        emit_bounds(bstate, N, N + c[e], 2 * N);
-      else if (j == jnext - 1)  // the next block's first particle, below its edge count
-        emit_bounds(bstate, j + 1, j + 1 + c[e], j + g_hi);
+      rj[e] = j;
+      rlo[e] = j + cprev;
+      rhi[e] = j + c[e];
+      if (j == N - 1) {
+        rj[K3_PER] = N;
+        rlo[K3_PER] = N + c[e];
+        rhi[K3_PER] = 2 * N;
+      } else if (j == jnext - 1) {
+        rj[K3_PER] = j + 1;
+        rlo[K3_PER] = j + 1 + c[e];
+        rhi[K3_PER] = j + g_hi;
+      }
     }
     cprev = c[e];
+  }
+  // A range crossing at most two block boundaries is emitted by its lane; a
+  // longer one (a particle owning many strata) by the whole wave, strided
+  // over the lanes, so no lane loops over hundreds of boundaries.
+#pragma unroll
+  for (int e = 0; e <= K3_PER; ++e) {
+    const int64_t first = (rlo[e] + K4_DB - 1) / K4_DB;
+    const int64_t nb = (rhi[e] < rlo[e]) ? 0 : rhi[e] / K4_DB - first + 1;
+    const bool big = nb > 2;
+    if (!big)
+      for (int64_t q = first; q < first + nb; ++q) bstate[q] = (int32_t)rj[e];
+    uint64_t mask = __ballot(big);
+    while (mask) {
+      const int src = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const long long bj = __shfl((long long)rj[e], src, WAVE);
+      const long long bq0 = __shfl((long long)first, src, WAVE);
+      const long long bq1 = __shfl((long long)(rhi[e] / K4_DB), src, WAVE);
+      for (long long q = bq0 + lane; q <= bq1; q += WAVE) bstate[q] = (int32_t)bj;
+    }
   }
   // last particle of positive weight in this block, for the rare case where
   // rounding leaves the final strata without an owner

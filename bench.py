@@ -43,14 +43,19 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("paper_1306_3277_amd/csrc/pf_batched.hip", "paper_1306_3277_amd/csrc/pf_kernels.hip",
-                  "paper_1306_3277_amd/csrc/pf_device.hpp", "paper_1306_3277_amd/csrc/pf_internal.hpp")
+# the sources each profiled kernel family is built from
+BATCHED_SOURCES = ("paper_1306_3277_amd/csrc/pf_batched.hip",
+                   "paper_1306_3277_amd/csrc/pf_device.hpp",
+                   "paper_1306_3277_amd/csrc/pf_internal.hpp")
+PLAIN_SOURCES = ("paper_1306_3277_amd/csrc/pf_kernels.hip",
+                 "paper_1306_3277_amd/csrc/pf_device.hpp",
+                 "paper_1306_3277_amd/csrc/pf_internal.hpp")
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(sources=BATCHED_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -69,7 +74,7 @@ def counted_traffic(summary: str):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 fields[k] = v.strip("` ")
-    if fields.get("kernel sources sha256") != kernel_sources_sha256():
+    if fields.get("kernel sources sha256") != kernel_sources_sha256(BATCHED_SOURCES):
         return None
     try:
         return float(fields["traffic bytes per launch"])

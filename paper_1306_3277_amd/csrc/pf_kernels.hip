@@ -183,9 +183,30 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const int chunk = (nb + K2_NT - 1) / K2_NT;
   const int i0 = min(nb, (int)threadIdx.x * chunk), i1 = min(nb, i0 + chunk);
+  // the filter's scalars and the resampling uniform, fetched and drawn while
+  // the partials load
+  FilterState* fst = A.fs;
+  const int t = fst->t + 1;
+  const double loglik0 = fst->loglik;
+  double u = 0.0;
+  if (threadIdx.x == 0)
+    u = u01_f64(draw(key_of(A.key), TAG_RESAMPLE, 0, fst->iter, 0, (uint32_t)t, A.b).x);
+  // the lane's first KC partials, loaded together (indices past its chunk
+  // reread the last block and are masked below)
+  double pm[KC], ps[KC], p2[KC];
+#pragma unroll
+  for (int e = 0; e < KC; ++e) {
+    const int i = min(i0 + e, nb - 1);
+    pm[e] = P[3 * i];
+    ps[e] = P[3 * i + 1];
+    p2[e] = P[3 * i + 2];
+  }
   // exchange 1: the global maximum
   double m = -INFINITY;
-  for (int i = i0; i < i1; ++i) m = fmax(m, P[3 * i]);
+#pragma unroll
+  for (int e = 0; e < KC; ++e)
+    if (i0 + e < i1) m = fmax(m, pm[e]);
+  for (int i = i0 + KC; i < i1; ++i) m = fmax(m, P[3 * i]);
   m = wave_max(m);
   if (lane == 0) xm[wv] = m;
   __syncthreads();
@@ -209,7 +230,11 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
 #pragma unroll
   for (int e = 0; e < KC; ++e) {
     double T = 0.0, T2 = 0.0;
-    if (i0 + e < i1) T = term(i0 + e, T2);
+    if (i0 + e < i1 && finite && pm[e] > -INFINITY) {
+      const double sc = exp_nonpos(pm[e] - M);
+      T2 = p2[e] * (sc * sc);
+      T = ps[e] * sc;
+    }
     Tc[e] = T;
     loc += T;
     loc2 += T2;
@@ -277,8 +302,7 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   const double Sf = fmax(S, vall);
   if (threadIdx.x == 0) {
     bo[nb] = Sf;
-    FilterState* f = A.fs;
-    const int t = f->t + 1;
+    FilterState* f = fst;
     double ell, ess;
     if (finite && Sf > 0.0) {
       ell = (M + log(Sf)) - log((double)A.N);
@@ -288,13 +312,12 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
       ess = 0.0;
       f->status = 4;
     }
-    f->loglik = f->loglik + ell;
+    f->loglik = loglik0 + ell;
     f->M = finite ? M : -INFINITY;
     f->S = Sf;
     f->ell = ell;
     f->ess = ess;
-    const uint4 w = draw(key_of(A.key), TAG_RESAMPLE, 0, f->iter, 0, (uint32_t)t, A.b);
-    f->u = u01_f64(w.x);
+    f->u = u;
     A.ell_tr[t - 1] = ell;
     A.ess_tr[t - 1] = ess;
     f->t = t;

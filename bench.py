@@ -296,17 +296,16 @@ def main():
     log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
 
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    threads, groups, sched, cand_ms = f32.autotune(steps=16)
-    sched_name = "pipelined" if sched == pfm.PF_SCHED_PIPELINED else "concurrent"
-    log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s), "
-        f"{sched_name}; us/interval (rows: 1, 2, 4 concurrent, 2, 4 pipelined groups; "
-        f"cols: 256, 512, 1024 lanes): {np.round(cand_ms * 1e3, 1).tolist()}")
+    threads, groups, cand_ms = f32.autotune(steps=16)
+    log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
+        f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
+        f"{np.round(cand_ms * 1e3, 1).tolist()}")
     r32 = Runner(f32, pb.T)
     dt32 = timed(torch, r32, args.steps, args.warmup)
     # per-kernel durations on one stream (no group overlap), for the roofline
     f32.set_tuning(threads, 1)
     kt32 = kernel_times(r32, min(args.steps, pb.T))
-    f32.set_tuning(threads, groups, sched)
+    f32.set_tuning(threads, groups)
     r32.restart()
     r32.run(pb.T)
     ll32, _, _ = f32.loglik()
@@ -373,7 +372,6 @@ def main():
                    "particles": n_tot, "particle_counts": "uniform over 256..8192",
                    "T": pb.T, "substeps": pb.K, "layout": "batched",
                    "collective_workgroup": threads, "filter_groups": groups,
-                   "group_schedule": sched_name,
                    "precision": "fp32 state/propagation, fp64 log-weights/scan/likelihood"},
         "fp64_plain": {"value": rate64, "unit": "particle-steps/s",
                        "ms_per_step": dt64 / args.fp64_steps * 1e3, "steps": args.fp64_steps},

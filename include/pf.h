@@ -177,34 +177,23 @@ pf_status pf_pmmh(pf_handle* h, int32_t iters, const double* log_f0, const doubl
                   const double* alpha, double step_sd, double f_lo, double f_hi, double sigma,
                   double* log_f_trace, double* ll_trace, int32_t* accepts);
 
-/* Schedules of the batched layout's filter groups (see pf_set_tuning). */
-enum { PF_SCHED_CONCURRENT = 0, PF_SCHED_PIPELINED = 1 };
-/* Candidate rows of pf_autotune: (groups, schedule) = (1, concurrent),
- * (2, concurrent), (4, concurrent), (2, pipelined), (4, pipelined). */
-#define PF_AUTOTUNE_ROWS 5
-
 /* Autotuner for the batched layout: for each candidate workgroup size of the
- * per-filter collective kernel (256, 512, 1024 lanes) and each candidate row
- * of filter groups and schedule (PF_AUTOTUNE_ROWS), replays `steps`
- * intervals of this handle's own workload, keeps the fastest and
- * re-initialises the filters (t = 0).  ms_out[3 * PF_AUTOTUNE_ROWS] (may be
- * NULL) receives the mean interval time in ms of candidate (row r, size
- * index s) at [3r + s] (-1 when groups > B); *threads_out, *groups_out and
- * *schedule_out (each may be NULL) the choice.  Plain layout: nothing to
- * tune (outputs 0).  Results do not depend on the tuning. */
+ * per-filter collective kernel (256, 512, 1024 lanes) and each number of
+ * filter groups (1, 2, 4; groups are balanced by particle count and stepped
+ * concurrently on their own streams, so one group's collective overlaps
+ * another's propagation), replays `steps` intervals of this handle's own
+ * workload, keeps the fastest pair and re-initialises the filters (t = 0).
+ * ms_out[9] (may be NULL) receives the mean interval time in ms of candidate
+ * (groups index g, size index s) at [3g + s] (-1 when groups > B);
+ * *threads_out and *groups_out (may be NULL) the choice.  Plain layout:
+ * nothing to tune (both outputs 0). */
 pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* threads_out, int32_t* groups_out,
-                      int32_t* schedule_out, double* ms_out);
+                      double* ms_out);
 
 /* Set the batched layout's tuning directly: collective_threads in
- * {256, 512, 1024}; groups in [1, 8] (capped at B); schedule
- * PF_SCHED_CONCURRENT (groups of about equal particle count stepped side by
- * side on their own streams) or PF_SCHED_PIPELINED (filters cut by size into
- * groups, largest first; a group's propagation of an interval starts after
- * the previous group's, so each group's collective runs beside the next
- * group's propagation).  Takes effect from the next interval; the plain
- * layout ignores it. */
-pf_status pf_set_tuning(pf_handle* h, int32_t collective_threads, int32_t groups,
-                        int32_t schedule);
+ * {256, 512, 1024}, groups in [1, 8] (capped at B).  Takes effect from the
+ * next interval; the plain layout ignores it. */
+pf_status pf_set_tuning(pf_handle* h, int32_t collective_threads, int32_t groups);
 
 /* ---- inspection and teacher forcing (synchronous; same kernels) -------- */
 /* Current particle set, FP64 host [d][N_total]: after pf_resample (or init)

@@ -20,8 +20,6 @@ PF_MODEL_WK, PF_MODEL_L96 = 1, 2
 PF_FP64, PF_FP32_MIXED = 0, 1
 PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
 PF_BATCHED_MAX_PARTICLES = 8192
-PF_SCHED_CONCURRENT, PF_SCHED_PIPELINED = 0, 1
-PF_AUTOTUNE_ROWS = 5  # (groups, schedule): (1, C), (2, C), (4, C), (2, P), (4, P)
 
 _STATUS = {1: "PF_E_INVAL", 2: "PF_E_DEVICE", 3: "PF_E_STATE", 4: "PF_E_NUMERIC"}
 
@@ -80,8 +78,8 @@ SIGNATURES = {
                               C.c_void_p]),
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
-    "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _I, _I, _D]),
-    "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_int32]),
+    "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _I, _D]),
+    "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
     "pf_timing_get": (C.c_int, [_H, C.POINTER(PfTiming)]),
     "pf_last_error": (C.c_char_p, []),
@@ -236,18 +234,15 @@ class Filter:
         return dict(log_f=lft, ll=llt, accepts=acc)
 
     def autotune(self, steps: int = 8):
-        """Returns (collective threads, groups, schedule, ms per interval
-        [PF_AUTOTUNE_ROWS x 3 workgroup sizes])."""
+        """Returns (collective threads, groups, ms per interval [groups x sizes])."""
         th = C.c_int32()
         gr = C.c_int32()
-        sc = C.c_int32()
-        ms = np.zeros(3 * PF_AUTOTUNE_ROWS)
-        _check(load().pf_autotune(self.h, int(steps), C.byref(th), C.byref(gr), C.byref(sc),
-                                  _dp(ms)))
-        return th.value, gr.value, sc.value, ms.reshape(PF_AUTOTUNE_ROWS, 3)
+        ms = np.zeros(9)
+        _check(load().pf_autotune(self.h, int(steps), C.byref(th), C.byref(gr), _dp(ms)))
+        return th.value, gr.value, ms.reshape(3, 3)
 
-    def set_tuning(self, threads: int, groups: int, schedule: int = PF_SCHED_CONCURRENT):
-        _check(load().pf_set_tuning(self.h, int(threads), int(groups), int(schedule)))
+    def set_tuning(self, threads: int, groups: int):
+        _check(load().pf_set_tuning(self.h, int(threads), int(groups)))
 
     # -- inspection / teacher forcing
     def get_state(self) -> np.ndarray:

@@ -215,13 +215,11 @@ struct pf_handle {
   // the number of filter groups stepped concurrently on their own streams
   int batch_nt = 256;
   int groups = 1;
-  int schedule = 0;  // PF_SCHED_CONCURRENT or PF_SCHED_PIPELINED
   std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt;
   // with G > 1 groups, group g's kernels run on side[g]; ev_a[0] forks the
   // side streams from the caller's, ev_b[g] joins group g back
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> ev_a, ev_b;
-  hipEvent_t ev_fork = nullptr;
   // timing
   bool timing = false;
   struct Ev {
@@ -327,7 +325,7 @@ pf_status ev_end(pf_handle* H, hipEvent_t a, int kind, hipStream_t s) {
   return PF_OK;
 }
 
-pf_status build_groups(pf_handle* H, int G, int sched);
+pf_status build_groups(pf_handle* H, int G);
 void destroy_streams(pf_handle* H);
 void destroy_graphs(pf_handle* H);
 
@@ -388,14 +386,11 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
 }
 
 // n intervals of the batched layout issued from stream s.  With one group
-// both kernels go on s.  With G groups, group g's intervals run back to back
-// on side[g]; the side streams start after everything issued on s so far
-// and s waits for all of them at the end.  Concurrent schedule: the groups
-// hold about equal particle counts, run side by side and drift, so one
-// group's collective overlaps another's propagation.  Pipelined schedule:
-// the groups are the filters cut by size, largest first; group g's
-// propagation of an interval starts once group g-1's is done, so each
-// group's collective runs beside the next group's propagation.
+// both kernels go on s.  With G groups (filters dealt so that every group
+// holds about the same number of particles) group g's intervals run back to
+// back on side[g]: the groups start together after everything issued on s
+// so far, drift against each other, and one group's collective overlaps
+// another's propagation.  s waits for every group at the end.
 pf_status enqueue_batched(pf_handle* H, hipStream_t s, int n) {
   pf_status st;
   const int G = H->groups;
@@ -405,23 +400,13 @@ pf_status enqueue_batched(pf_handle* H, hipStream_t s, int n) {
         return st;
     return PF_OK;
   }
-  HIP_TRY(hipEventRecord(H->ev_fork, s));
-  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_fork, 0));
-  if (H->schedule == PF_SCHED_PIPELINED) {
+  HIP_TRY(hipEventRecord(H->ev_a[0], s));
+  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_a[0], 0));
+  for (int g = 0; g < G; ++g)
     for (int i = 0; i < n; ++i)
-      for (int g = 0; g < G; ++g) {
-        if (g > 0) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_a[g - 1], 0));
-        if ((st = enqueue_group_propagate(H, g, H->side[g]))) return st;
-        HIP_TRY(hipEventRecord(H->ev_a[g], H->side[g]));
-        if ((st = enqueue_group_collective(H, g, H->side[g]))) return st;
-      }
-  } else {
-    for (int g = 0; g < G; ++g)
-      for (int i = 0; i < n; ++i)
-        if ((st = enqueue_group_propagate(H, g, H->side[g])) ||
-            (st = enqueue_group_collective(H, g, H->side[g])))
-          return st;
-  }
+      if ((st = enqueue_group_propagate(H, g, H->side[g])) ||
+          (st = enqueue_group_collective(H, g, H->side[g])))
+        return st;
   for (int g = 0; g < G; ++g) {
     HIP_TRY(hipEventRecord(H->ev_b[g], H->side[g]));
     HIP_TRY(hipStreamWaitEvent(s, H->ev_b[g], 0));
@@ -504,13 +489,11 @@ pf_status require_device() {
   return PF_OK;
 }
 
-// Filters largest first.  Concurrent schedule: dealt to G groups by always
-// giving the next filter to the group with the fewest particles
-// (longest-processing-time order).  Pipelined schedule: cut into G runs of
-// consecutive sizes holding about equal particle counts.  Each group's
-// filters and 256-particle chunks are contiguous in the device tables, so a
-// launch covers one group with a base offset.
-pf_status build_groups(pf_handle* H, int G, int sched) {
+// Filters largest first (longest-processing-time order), dealt to G groups
+// by always giving the next filter to the group with the fewest particles;
+// each group's filters and 256-particle chunks are contiguous in the device
+// tables, so a launch covers one group with a base offset.
+pf_status build_groups(pf_handle* H, int G) {
   const pf_config& c = H->cfg;
   if (G < 1) G = 1;
   if (G > c.B) G = c.B;
@@ -519,32 +502,13 @@ pf_status build_groups(pf_handle* H, int G, int sched) {
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return H->np[x] > H->np[y]; });
   std::vector<std::vector<int32_t>> members(G);
-  if (sched == PF_SCHED_PIPELINED) {
-    int64_t total = 0, cum = 0;
-    for (int32_t b : order) total += H->np[b];
-    int g = 0;
-    for (int32_t b : order) {
-      // move on once this group holds its share, leaving one filter per group
-      while (g < G - 1 && (cum * G >= (int64_t)(g + 1) * total) &&
-             !members[g].empty())
-        ++g;
-      members[g].push_back(b);
-      cum += H->np[b];
-    }
-  } else {
-    std::vector<int64_t> load(G, 0);
-    for (int32_t b : order) {
-      int gbest = 0;
-      for (int g = 1; g < G; ++g)
-        if (load[g] < load[gbest]) gbest = g;
-      members[gbest].push_back(b);
-      load[gbest] += H->np[b];
-    }
-  }
-  // a pipelined cut of fewer filters than groups leaves empty groups: drop them
-  while (G > 1 && members[G - 1].empty()) {
-    members.pop_back();
-    --G;
+  std::vector<int64_t> load(G, 0);
+  for (int32_t b : order) {
+    int gbest = 0;
+    for (int g = 1; g < G; ++g)
+      if (load[g] < load[gbest]) gbest = g;
+    members[gbest].push_back(b);
+    load[gbest] += H->np[b];
   }
   std::vector<pfk::FilterSlot> ord;
   std::vector<int32_t> chf, chk;
@@ -581,9 +545,8 @@ pf_status build_groups(pf_handle* H, int G, int sched) {
   HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_chunk_k, chk.data(), 4 * chk.size(),
                          hipMemcpyHostToDevice, H->stream));
   HIP_TRY(hipStreamSynchronize(H->stream));
-  // a stream and two events per group and a fork event (default priority);
-  // graphs captured for other groups are rebuilt
-  if (G > 1 && !H->ev_fork) HIP_TRY(hipEventCreateWithFlags(&H->ev_fork, hipEventDisableTiming));
+  // a stream and two events per group (default priority); graphs captured
+  // for another group count are rebuilt
   while (G > 1 && (int)H->side.size() < G) {
     hipStream_t st;
     HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -594,9 +557,8 @@ pf_status build_groups(pf_handle* H, int G, int sched) {
     H->ev_a.push_back(ea);
     H->ev_b.push_back(eb);
   }
-  destroy_graphs(H);
+  if (G != H->groups) destroy_graphs(H);
   H->groups = G;
-  H->schedule = sched;
   return PF_OK;
 }
 
@@ -612,8 +574,6 @@ void destroy_streams(pf_handle* H) {
   for (auto s : H->side) (void)hipStreamDestroy(s);
   for (auto e : H->ev_a) (void)hipEventDestroy(e);
   for (auto e : H->ev_b) (void)hipEventDestroy(e);
-  if (H->ev_fork) (void)hipEventDestroy(H->ev_fork);
-  H->ev_fork = nullptr;
   if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
   H->side.clear();
   H->ev_a.clear();
@@ -728,7 +688,7 @@ pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void
     delete H;
     return fail(PF_E_DEVICE, "copying the configuration failed: %s", hipGetErrorString(e));
   }
-  if ((st = upload_theta(H, c.theta)) || (st = build_groups(H, 1, PF_SCHED_CONCURRENT))) {
+  if ((st = upload_theta(H, c.theta)) || (st = build_groups(H, 1))) {
     destroy_streams(H);
     delete H;
     return st;
@@ -1070,51 +1030,45 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
   return PF_OK;
 }
 
-pf_status pf_set_tuning(pf_handle* H, int32_t collective_threads, int32_t groups,
-                        int32_t schedule) {
+pf_status pf_set_tuning(pf_handle* H, int32_t collective_threads, int32_t groups) {
   pf_status st = check_handle(H);
   if (st) return st;
   if (collective_threads != 256 && collective_threads != 512 && collective_threads != 1024)
     return fail(PF_E_INVAL, "collective_threads must be 256, 512 or 1024");
   if (groups < 1 || groups > 8) return fail(PF_E_INVAL, "groups must be in [1, 8]");
-  if (schedule != PF_SCHED_CONCURRENT && schedule != PF_SCHED_PIPELINED)
-    return fail(PF_E_INVAL, "schedule must be PF_SCHED_CONCURRENT or PF_SCHED_PIPELINED");
   if (H->cfg.layout != PF_LAYOUT_BATCHED) return PF_OK;  // nothing to tune
   destroy_graphs(H);
   H->batch_nt = collective_threads;
-  return build_groups(H, groups, schedule);
+  if (groups != H->groups) return build_groups(H, groups);
+  return PF_OK;
 }
 
 pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t* groups_out,
-                      int32_t* schedule_out, double* ms_out) {
+                      double* ms_out) {
   pf_status st = check_handle(H);
   if (st) return st;
   if (steps < 1) return fail(PF_E_INVAL, "steps must be >= 1");
   if (H->cfg.layout != PF_LAYOUT_BATCHED) {
     if (threads_out) *threads_out = 0;
     if (groups_out) *groups_out = 0;
-    if (schedule_out) *schedule_out = 0;
     return pf_reset(H, H->iter);
   }
   const int cand_nt[3] = {256, 512, 1024};
-  const int cand_g[PF_AUTOTUNE_ROWS] = {1, 2, 4, 2, 4};
-  const int cand_s[PF_AUTOTUNE_ROWS] = {PF_SCHED_CONCURRENT, PF_SCHED_CONCURRENT,
-                                        PF_SCHED_CONCURRENT, PF_SCHED_PIPELINED,
-                                        PF_SCHED_PIPELINED};
+  const int cand_g[3] = {1, 2, 4};
   double best = 1e300;
-  int best_nt = H->batch_nt, best_g = H->groups, best_s = H->schedule;
+  int best_nt = H->batch_nt, best_g = H->groups;
   hipStream_t ls;
   if ((st = launch_stream(H, &ls))) return st;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   const int n = steps < H->cfg.T - 1 ? steps : H->cfg.T - 1;
-  for (int gi = 0; gi < PF_AUTOTUNE_ROWS && !st; ++gi) {
+  for (int gi = 0; gi < 3 && !st; ++gi) {
     for (int ci = 0; ci < 3 && !st; ++ci) {
       const int idx = gi * 3 + ci;
       if (ms_out) ms_out[idx] = -1.0;
       if (cand_g[gi] > H->cfg.B) continue;
-      if ((st = pf_set_tuning(H, cand_nt[ci], cand_g[gi], cand_s[gi]))) break;
+      if ((st = pf_set_tuning(H, cand_nt[ci], cand_g[gi]))) break;
       if ((st = pf_reset(H, H->iter))) break;
       if ((st = pf_graph_run(H, 1))) break;  // capture + one untimed interval
       if (n < 1) continue;
@@ -1130,17 +1084,15 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
         best = per;
         best_nt = cand_nt[ci];
         best_g = cand_g[gi];
-        best_s = cand_s[gi];
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) return st;
-  if ((st = pf_set_tuning(H, best_nt, best_g, best_s))) return st;
+  if ((st = pf_set_tuning(H, best_nt, best_g))) return st;
   if (threads_out) *threads_out = best_nt;
   if (groups_out) *groups_out = best_g;
-  if (schedule_out) *schedule_out = best_s;
   return pf_reset(H, H->iter);
 }
 

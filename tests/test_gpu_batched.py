@@ -196,10 +196,8 @@ def test_autotune_keeps_results(pfm):
     f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
     f.advance(pb.T)
     e0, _ = f.trace()
-    threads, groups, sched, ms = f.autotune(steps=3)
+    threads, groups, ms = f.autotune(steps=3)
     assert threads in (256, 512, 1024) and groups in (1, 2, 4)
-    assert sched in (pfm.PF_SCHED_CONCURRENT, pfm.PF_SCHED_PIPELINED)
-    assert ms.shape == (pfm.PF_AUTOTUNE_ROWS, 3)
     assert np.all(ms[ms >= 0] > 0)
     f.advance(pb.T)  # autotune leaves the filters re-initialised
     e1, _ = f.trace()
@@ -208,18 +206,15 @@ def test_autotune_keeps_results(pfm):
 
 
 def test_filter_groups_do_not_change_results(pfm):
-    """Groups and their schedule only change which stream runs which kernel
-    and when: eager and graph replay (one-interval and eight-interval graphs),
-    one group or several, concurrent or pipelined, give the same bits."""
+    """Groups only change which stream runs which kernel: eager and graph
+    replay (one-interval and eight-interval graphs), one group or several,
+    give the same bits."""
     th, n = W.batched_thetas(23, seed=12)
     pb = _problem(n, th, T=13)
     outs = []
-    C, P = pfm.PF_SCHED_CONCURRENT, pfm.PF_SCHED_PIPELINED
-    for groups, sched, graph in ((1, C, False), (3, C, False), (3, C, True), (2, C, True),
-                                 (4, C, True), (1, C, True), (2, P, False), (3, P, True),
-                                 (4, P, True)):
+    for groups, graph in ((1, False), (3, False), (3, True), (2, True), (4, True), (1, True)):
         f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
-        f.set_tuning(512, groups, sched)
+        f.set_tuning(512, groups)
         if graph:
             f.graph_run(2)
             f.advance(1)

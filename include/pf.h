@@ -145,7 +145,9 @@ pf_status pf_loglik(pf_handle* h, double* loglik_out, double* ess_out, int32_t* 
  * after the current t are 0).  Either pointer may be NULL. */
 pf_status pf_get_trace(pf_handle* h, double* ell_out, double* ess_out);
 
-/* Release the handle and its HIP graph objects (not the workspace). */
+/* Wait for the work the handle has issued, then release the handle and its
+ * HIP graph objects, streams and events (not the workspace).  The handle is
+ * gone even when the wait reports an error. */
 pf_status pf_destroy(pf_handle* h);
 
 /* Run n_steps observation intervals (pf_step + pf_resample each) by replaying
@@ -192,7 +194,8 @@ pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* threads_out, int32_t
 
 /* Set the batched layout's tuning directly: collective_threads in
  * {256, 512, 1024}, groups in [1, 8] (capped at B).  Takes effect from the
- * next interval; the plain layout ignores it. */
+ * next interval; the plain layout ignores it.  Synchronous: waits for the
+ * work already issued before the captured graphs are rebuilt. */
 pf_status pf_set_tuning(pf_handle* h, int32_t collective_threads, int32_t groups);
 
 /* ---- inspection and teacher forcing (synchronous; same kernels) -------- */
@@ -235,7 +238,7 @@ typedef struct pf_timing {
 } pf_timing;
 /* When on, eager pf_step/pf_resample bracket each kernel with HIP events on
  * the handle's stream; pf_timing_get() synchronises and sums them.  Turning
- * it on clears the sums. */
+ * it on or off waits for the issued work and clears the sums. */
 pf_status pf_timing_enable(pf_handle* h, int32_t on);
 pf_status pf_timing_get(pf_handle* h, pf_timing* out);
 

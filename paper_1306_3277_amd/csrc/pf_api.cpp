@@ -569,6 +569,17 @@ void destroy_graphs(pf_handle* H) {
   H->graphs.clear();
 }
 
+// Waits for everything the handle has issued: its stream, the stream graph
+// replays go on, and the group streams.  Graphs, streams and events are only
+// destroyed after this, so none is destroyed while work that uses it is in
+// flight.
+pf_status drain(pf_handle* H) {
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  if (H->cap_stream) HIP_TRY(hipStreamSynchronize(H->cap_stream));
+  for (auto s : H->side) HIP_TRY(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
 void destroy_streams(pf_handle* H) {
   destroy_graphs(H);
   for (auto s : H->side) (void)hipStreamDestroy(s);
@@ -774,6 +785,7 @@ pf_status pf_get_trace(pf_handle* H, double* ell_out, double* ess_out) {
 
 pf_status pf_destroy(pf_handle* H) {
   if (!H) return fail(PF_E_INVAL, "handle is NULL");
+  const pf_status st = H->alive ? drain(H) : PF_OK;
   destroy_streams(H);
   for (auto& ev : H->events) {
     (void)hipEventDestroy(ev.a);
@@ -781,7 +793,7 @@ pf_status pf_destroy(pf_handle* H) {
   }
   H->alive = false;
   delete H;
-  return PF_OK;
+  return st;
 }
 
 pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
@@ -1037,6 +1049,7 @@ pf_status pf_set_tuning(pf_handle* H, int32_t collective_threads, int32_t groups
     return fail(PF_E_INVAL, "collective_threads must be 256, 512 or 1024");
   if (groups < 1 || groups > 8) return fail(PF_E_INVAL, "groups must be in [1, 8]");
   if (H->cfg.layout != PF_LAYOUT_BATCHED) return PF_OK;  // nothing to tune
+  if ((st = drain(H))) return st;
   destroy_graphs(H);
   H->batch_nt = collective_threads;
   if (groups != H->groups) return build_groups(H, groups);
@@ -1099,6 +1112,7 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
 pf_status pf_timing_enable(pf_handle* H, int32_t on) {
   pf_status st = check_handle(H);
   if (st) return st;
+  if ((st = drain(H))) return st;
   for (auto& ev : H->events) {
     (void)hipEventDestroy(ev.a);
     (void)hipEventDestroy(ev.b);

@@ -88,6 +88,10 @@ def lib():
             "orc_pmmh": (C.c_int32, [P, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                      _D, _D, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                      _D, _D, _I]),
+            "orc_copy_index": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64, C.c_uint32]),
+            "orc_smc2": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), C.c_int32, _D,
+                                     C.c_int32, _D, _D, _D, _D, _D, _D, _U, _D, _D, _D, _I,
+                                     _D, _D, _I, _I, _D, _D, _D]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -290,3 +294,40 @@ def pmmh(pb, N, inputs, chain0=0, n_chains=None, iters=None):
                    inputs.step_sd, inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
                    _ip(acc))
     return dict(log_f=lft, ll=llt, accepts=acc)
+
+
+def copy_index(k, n_src, n_dst, w) -> int:
+    return lib().orc_copy_index(int(k), int(n_src), int(n_dst), int(w))
+
+
+def smc2(pb, inputs, T=None, n_particles=None):
+    """Reference SMC^2 (Alg. 4) over ``inputs.theta0`` for T times; returns
+    the final theta-particles, theta-log-weights, likelihoods, accept counts,
+    theta-ESS per time, the evidence estimate, per-time traces and the final
+    particles [d][sum N]."""
+    P = _Prob(pb)
+    T = inputs.T if T is None else T
+    th0 = np.ascontiguousarray(inputs.theta0, dtype=np.float64)
+    B, nth = th0.shape
+    n = np.ascontiguousarray(pb.n_particles if n_particles is None else n_particles,
+                             dtype=np.int64)
+    assert n.shape == (B,)
+    z = np.ascontiguousarray(inputs.z, dtype=np.float64)
+    la = np.ascontiguousarray(inputs.log_alpha, dtype=np.float64)
+    u = np.ascontiguousarray(inputs.u, dtype=np.float64)
+    w = np.ascontiguousarray(inputs.w_copy, dtype=np.uint32)
+    out = dict(theta=np.zeros((B, nth)), logw=np.zeros(B), loglik=np.zeros(B),
+               accepts=np.zeros(B, dtype=np.int32), ess=np.zeros(T),
+               anc=np.zeros((T, B), dtype=np.int32), acc=np.zeros((T, B), dtype=np.int32),
+               logw_trace=np.zeros((T, B)), theta_trace=np.zeros((T, B, nth)),
+               x=np.zeros((pb.d, int(n.sum()))))
+    ev = C.c_double()
+    st = lib().orc_smc2(P.ref, B, n.ctypes.data_as(C.POINTER(C.c_int64)), nth, _dp(th0), T,
+                        _dp(inputs.step_sd), _dp(inputs.lo), _dp(inputs.hi), _dp(z), _dp(la),
+                        _dp(u), w.ctypes.data_as(_U), _dp(out["theta"]), _dp(out["logw"]),
+                        _dp(out["loglik"]), _ip(out["accepts"]), _dp(out["ess"]),
+                        C.byref(ev), _ip(out["anc"]), _ip(out["acc"]), _dp(out["logw_trace"]),
+                        _dp(out["theta_trace"]), _dp(out["x"]))
+    out["status"] = st
+    out["log_evidence"] = ev.value
+    return out

@@ -519,3 +519,182 @@ int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chai
   free(ell);
   return ORC_OK;
 }
+
+/* Whole-filter copy used when a theta-particle takes another's filter (the
+ * attached state sample travels with the theta-particle, Sec. 3.2.2).  The
+ * source's N_s equally weighted particles are re-represented by the
+ * destination's N_d particles with systematic selection on equal weights:
+ * destination particle k takes source particle floor((k + u) N_s / N_d),
+ * u = w 2^-32 for a 32-bit word w.  Evaluated exactly in integers as
+ * ((k 2^32 + w) N_s) div (N_d 2^32), which fits 64 bits for N <= 2^13.  For
+ * N_s = N_d this is the identity. */
+int64_t orc_copy_index(int64_t k, int64_t n_src, int64_t n_dst, uint32_t w) {
+  uint64_t num = (((uint64_t)k << 32) | (uint64_t)w) * (uint64_t)n_src;
+  return (int64_t)(num / ((uint64_t)n_dst << 32));
+}
+
+/* SMC over the parameters with a particle filter attached to every
+ * theta-particle: Sec. 3.2.2, Alg. 4 (SMC^2 when the attached filter is the
+ * bootstrap particle filter of Alg. 2).  Per observation time i = 1..T_run,
+ * in the algorithm's order:
+ *   1. theta-ancestors from the theta-weights v(t_{i-1}) (systematic, as for
+ *      the state particles; the algorithm writes multinomial — a reading);
+ *      at i = 1 the weights are uniform and the draw is the identity;
+ *   2. each theta-particle takes its ancestor's parameters, likelihood and
+ *      filter (orc_copy_index for unequal particle counts);
+ *   3. rejuvenation by one marginal Metropolis-Hastings step (Alg. 3, eq.
+ *      mh): a Gaussian random walk theta' = theta + step_sd z on the
+ *      parameters with step_sd > 0, a uniform prior box [lo, hi] on those
+ *      parameters; outside the box the move is rejected without a filter
+ *      run; inside, a fresh filter for theta' over t_{0:i-1} (generator
+ *      iteration field i, filter index j) gives l' and x'; the move is
+ *      accepted iff log_alpha <= l' - l (symmetric proposal and flat prior
+ *      cancel; ties accept), and then theta, l and the filter become the
+ *      proposal's;
+ *   4. the attached filter advances over t_{i-1:i} (iteration field 0,
+ *      filter index j): its likelihood increment ell_i^j is the new
+ *      theta-log-weight v^j(t_i) and l^j += ell_i^j.
+ * After each time the theta-weights' ESS is recorded and the evidence
+ * estimate accumulates ln(sum_j exp v^j(t_i)) - ln B (the theta-weights are
+ * uniform after every resampling) — the evidence is not in the paper; a
+ * reading.  The random numbers of this layer are inputs: z [T_run][B][n_theta],
+ * log_alpha [T_run][B], u_theta [T_run] (entry i-1 for time i's
+ * theta-resampling), w_copy [T_run][B].  Filter j's particles are stored as
+ * one structure-of-arrays block; x_final is [d][sum N] with filter j at
+ * columns off_j..off_j+N_j-1.  Returns ORC_NUMERIC (and evidence -inf) if
+ * every theta-weight of some time is zero. */
+int32_t orc_smc2(const orc_problem* P, int32_t B, const int64_t* n_particles, int32_t n_theta,
+                 const double* theta0, int32_t T_run, const double* step_sd, const double* lo,
+                 const double* hi, const double* z, const double* log_alpha,
+                 const double* u_theta, const uint32_t* w_copy, double* theta_out,
+                 double* logw_out, double* loglik_out, int32_t* accepts, double* ess_theta,
+                 double* log_evidence, int32_t* anc_trace, int32_t* acc_trace,
+                 double* logw_trace, double* theta_trace, double* x_final) {
+  const int d = P->d;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)B + 1));
+  int64_t nmax = 1;
+  off[0] = 0;
+  for (int32_t j = 0; j < B; ++j) {
+    off[j + 1] = off[j] + n_particles[j];
+    if (n_particles[j] > nmax) nmax = n_particles[j];
+  }
+  const int64_t ntot = off[B];
+  double* th = (double*)malloc(sizeof(double) * (size_t)B * n_theta);
+  double* th_new = (double*)malloc(sizeof(double) * (size_t)B * n_theta);
+  double* thp = (double*)malloc(sizeof(double) * (size_t)n_theta);
+  double* x = (double*)malloc(sizeof(double) * (size_t)d * (size_t)ntot);
+  double* x_new = (double*)malloc(sizeof(double) * (size_t)d * (size_t)ntot);
+  double* xp = (double*)malloc(sizeof(double) * (size_t)d * (size_t)nmax);
+  double* xprop = (double*)malloc(sizeof(double) * (size_t)d * (size_t)nmax);
+  double* lw = (double*)malloc(sizeof(double) * (size_t)nmax);
+  int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)nmax);
+  double* scratch = (double*)malloc(sizeof(double) * ((size_t)T_run + 1) * 2);
+  double* l = (double*)malloc(sizeof(double) * (size_t)B);
+  double* l_new = (double*)malloc(sizeof(double) * (size_t)B);
+  double* v = (double*)malloc(sizeof(double) * (size_t)B);
+  int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)B);
+  int32_t status = ORC_OK;
+  double evidence = 0.0;
+
+  memcpy(th, theta0, sizeof(double) * (size_t)B * n_theta);
+  for (int32_t j = 0; j < B; ++j) {
+    orc_init(P, th + (size_t)j * n_theta, n_particles[j], (uint32_t)j, 0, x + d * off[j]);
+    l[j] = 0.0;
+    v[j] = 0.0;
+    a[j] = j;
+    accepts[j] = 0;
+  }
+  for (int32_t i = 1; i <= T_run && status == ORC_OK; ++i) {
+    /* 2. take the ancestors' parameters, likelihoods and filters */
+    for (int32_t j = 0; j < B; ++j) {
+      const int32_t s = a[j];
+      const int64_t ns = n_particles[s], nd = n_particles[j];
+      memcpy(th_new + (size_t)j * n_theta, th + (size_t)s * n_theta, sizeof(double) * n_theta);
+      l_new[j] = l[s];
+      const uint32_t w = w_copy[(int64_t)(i - 1) * B + j];
+      for (int64_t k = 0; k < nd; ++k) {
+        const int64_t p = orc_copy_index(k, ns, nd, w);
+        for (int c = 0; c < d; ++c) x_new[d * off[j] + c * nd + k] = x[d * off[s] + c * ns + p];
+      }
+      if (anc_trace) anc_trace[(int64_t)(i - 1) * B + j] = s;
+    }
+    /* 3. rejuvenate: one marginal Metropolis-Hastings step per theta-particle */
+    for (int32_t j = 0; j < B; ++j) {
+      const int64_t nd = n_particles[j];
+      int inside = 1;
+      for (int32_t p = 0; p < n_theta; ++p) {
+        const double cur = th_new[(size_t)j * n_theta + p];
+        if (step_sd[p] != 0.0) {
+          const double step = step_sd[p] * z[((int64_t)(i - 1) * B + j) * n_theta + p];
+          thp[p] = cur + step;
+          if (!(thp[p] >= lo[p] && thp[p] <= hi[p])) inside = 0;
+        } else {
+          thp[p] = cur;
+        }
+      }
+      int32_t acc = 0;
+      if (inside) {
+        double lp;
+        orc_pf_run(P, thp, nd, (uint32_t)j, (uint32_t)i, i - 1, scratch, scratch + T_run + 1,
+                   &lp, NULL, NULL, xprop, NULL);
+        if (log_alpha[(int64_t)(i - 1) * B + j] <= lp - l_new[j]) {
+          memcpy(th_new + (size_t)j * n_theta, thp, sizeof(double) * n_theta);
+          l_new[j] = lp;
+          memcpy(x_new + d * off[j], xprop, sizeof(double) * (size_t)d * (size_t)nd);
+          acc = 1;
+          accepts[j] += 1;
+        }
+      }
+      if (acc_trace) acc_trace[(int64_t)(i - 1) * B + j] = acc;
+    }
+    /* 4. advance every attached filter over t_{i-1:i} */
+    for (int32_t j = 0; j < B; ++j) {
+      const int64_t nd = n_particles[j];
+      const double* tj = th_new + (size_t)j * n_theta;
+      orc_propagate(P, tj, nd, (uint32_t)j, 0, i, x_new + d * off[j], xp);
+      orc_weight(P, tj, nd, i, xp, lw);
+      double e, s;
+      orc_reduce_resample(nd, lw, orc_resample_u(P->seed, i, (uint32_t)j, 0), &e, &s, anc);
+      orc_gather(d, nd, xp, anc, x + d * off[j]);
+      v[j] = e;
+      l[j] = l_new[j] + e;
+      if (logw_trace) logw_trace[(int64_t)(i - 1) * B + j] = e;
+    }
+    memcpy(th, th_new, sizeof(double) * (size_t)B * n_theta);
+    if (theta_trace)
+      memcpy(theta_trace + (int64_t)(i - 1) * B * n_theta, th,
+             sizeof(double) * (size_t)B * n_theta);
+    /* theta-weights: ESS, evidence factor and the next time's ancestors */
+    double e, s;
+    const double u = (i < T_run) ? u_theta[i] : 0.5;
+    status = orc_reduce_resample(B, v, u, &e, &s, a);
+    evidence = evidence + e;
+    ess_theta[i - 1] = s;
+  }
+  *log_evidence = (status == ORC_OK) ? evidence : -INFINITY;
+  memcpy(theta_out, th, sizeof(double) * (size_t)B * n_theta);
+  for (int32_t j = 0; j < B; ++j) {
+    logw_out[j] = v[j];
+    loglik_out[j] = l[j];
+    if (x_final)
+      for (int c = 0; c < d; ++c)
+        memcpy(x_final + (int64_t)c * ntot + off[j], x + d * off[j] + c * n_particles[j],
+               sizeof(double) * (size_t)n_particles[j]);
+  }
+  free(a);
+  free(v);
+  free(l_new);
+  free(l);
+  free(scratch);
+  free(anc);
+  free(lw);
+  free(xprop);
+  free(xp);
+  free(x_new);
+  free(x);
+  free(thp);
+  free(th_new);
+  free(th);
+  free(off);
+  return status;
+}

@@ -10,6 +10,7 @@
  *   - bootstrap particle filter: Sec. 3.1.2, Alg. 2 (Particle-Filter);
  *   - Kalman filter likelihood: Sec. 3.1.1, Alg. 1 (scalar case);
  *   - marginal Metropolis-Hastings: Sec. 3.2.1, eq. (mh), Alg. 3;
+ *   - SMC over parameters (SMC^2): Sec. 3.2.2, Alg. 4;
  *   - models: Sec. 2.1.1 eqs. (2-windkessel), (3-windkessel) and Sec. 2.1.2
  *     eq. (lorenz96-sde) with classic fixed-step RK4.
  *
@@ -92,6 +93,18 @@ int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chai
                  const double* z, const double* alpha, double step_sd, double f_lo,
                  double f_hi, double sigma, double* log_f_trace /* [iters][n_chains] */,
                  double* ll_trace /* [iters][n_chains] */, int32_t* accepts /* [n_chains] */);
+
+/* whole-filter copy index (systematic selection on equal weights) */
+int64_t orc_copy_index(int64_t k, int64_t n_src, int64_t n_dst, uint32_t w);
+
+/* SMC over parameters with attached particle filters (SMC^2, Alg. 4) */
+int32_t orc_smc2(const orc_problem* P, int32_t B, const int64_t* n_particles, int32_t n_theta,
+                 const double* theta0, int32_t T_run, const double* step_sd, const double* lo,
+                 const double* hi, const double* z, const double* log_alpha,
+                 const double* u_theta, const uint32_t* w_copy, double* theta_out,
+                 double* logw_out, double* loglik_out, int32_t* accepts, double* ess_theta,
+                 double* log_evidence, int32_t* anc_trace, int32_t* acc_trace,
+                 double* logw_trace, double* theta_trace, double* x_final);
 
 #ifdef __cplusplus
 }

@@ -178,6 +178,73 @@ def pmmh_inputs(chains: int = 64, iters: int = 2000, seed: int = 3, step_sd: flo
     return PmmhInputs(np.log(f0), z, alpha, step_sd, f_lo, f_hi, sigma)
 
 
+@dataclasses.dataclass
+class Smc2Inputs:
+    """Random numbers the SMC^2 parameter layer (Alg. 4) draws, passed in as
+    inputs, plus its random walk and prior box.
+
+    ``theta0`` [B, n_theta]: the initial theta-particles (drawn from the prior);
+    ``z`` [T, B, n_theta]: proposal normals; ``log_alpha`` [T, B]: logs of the
+    acceptance uniforms; ``u`` [T]: the theta-resampling uniform of each time;
+    ``w_copy`` [T, B]: 32-bit words placing the whole-filter copies.
+    ``step_sd`` [n_theta] is the random-walk sd (0 keeps a parameter fixed);
+    the prior is uniform on [lo, hi] for every moved parameter."""
+    theta0: np.ndarray
+    z: np.ndarray
+    log_alpha: np.ndarray
+    u: np.ndarray
+    w_copy: np.ndarray
+    step_sd: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+
+    @property
+    def T(self) -> int:
+        return int(self.z.shape[0])
+
+
+def smc2_inputs(theta0: np.ndarray, T: int, step_sd, lo, hi, seed: int = 4) -> Smc2Inputs:
+    """Inputs for T times of SMC^2 over the theta-particles ``theta0``."""
+    theta0 = np.ascontiguousarray(theta0, dtype=np.float64)
+    B, n_theta = theta0.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal(size=(T, B, n_theta))
+    # uniforms strictly inside (0, 1), so their logs are finite
+    alpha = (rng.integers(0, 2 ** 32, size=(T, B), dtype=np.uint64).astype(np.float64)
+             + 0.5) * 2.0 ** -32
+    u = rng.integers(0, 2 ** 32, size=T, dtype=np.uint64).astype(np.float64) * 2.0 ** -32
+    w = rng.integers(0, 2 ** 32, size=(T, B), dtype=np.uint64).astype(np.uint32)
+    return Smc2Inputs(theta0, z, np.log(alpha), u, w,
+                      np.ascontiguousarray(step_sd, dtype=np.float64).reshape(n_theta),
+                      np.ascontiguousarray(lo, dtype=np.float64).reshape(n_theta),
+                      np.ascontiguousarray(hi, dtype=np.float64).reshape(n_theta))
+
+
+def smc2_l96_inputs(theta0: np.ndarray, T: int, seed: int = 4, step_f: float = 0.1,
+                    step_s: float = 0.01, f_lo: float = 6.0, f_hi: float = 10.0,
+                    s_lo: float = 0.05, s_hi: float = 0.3) -> Smc2Inputs:
+    """Lorenz '96 SMC^2: random walk on (F, sigma) within the prior box the
+    batched workload's parameters are drawn from."""
+    return smc2_inputs(theta0, T, [step_f, step_s], [f_lo, s_lo], [f_hi, s_hi], seed)
+
+
+def smc2_wk_m0_inputs(base_theta: np.ndarray, B: int, T: int, seed: int = 5,
+                      m0_lo: float = 70.0, m0_hi: float = 110.0,
+                      step: float = 3.0) -> Smc2Inputs:
+    """Windkessel SMC^2 over the initial-pressure mean m0 only (index 4), with
+    prior U(m0_lo, m0_hi): the evidence is then a one-dimensional integral of
+    the Kalman likelihood."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    th = np.tile(np.asarray(base_theta, dtype=np.float64), (B, 1))
+    th[:, 4] = rng.uniform(m0_lo, m0_hi, size=B)
+    step_sd = np.zeros(th.shape[1])
+    step_sd[4] = step
+    lo = np.full(th.shape[1], -np.inf)
+    hi = np.full(th.shape[1], np.inf)
+    lo[4], hi[4] = m0_lo, m0_hi
+    return smc2_inputs(th, T, step_sd, lo, hi, seed)
+
+
 # ---------------------------------------------------------------- named configs
 
 def config(name: str, **kw) -> Problem:

@@ -179,6 +179,67 @@ pf_status pf_pmmh(pf_handle* h, int32_t iters, const double* log_f0, const doubl
                   const double* alpha, double step_sd, double f_lo, double f_hi, double sigma,
                   double* log_f_trace, double* ll_trace, int32_t* accepts);
 
+/* SMC over the parameters with a particle filter attached to every
+ * theta-particle (Sec. 3.2.2, Alg. 4; SMC^2 when the attached filter is the
+ * bootstrap filter of Alg. 2).  Theta-particle j owns filter slot j of the
+ * batched handle h; `proposal` is a second batched handle made from the same
+ * configuration (model, sizes, particle counts, observations, seed,
+ * precision) on the same stream, whose filters run the rejuvenation
+ * proposals.  h is re-initialised with theta0 and generator iteration field
+ * 0.  Per time i = 1..T_run, in the algorithm's order:
+ *   1. theta-ancestors by systematic resampling (as for the particles; the
+ *      algorithm writes multinomial) of the theta-weights v(t_{i-1}), the
+ *      last likelihood increments, with uniform u[i-1]; at i = 1 the weights
+ *      are uniform and the ancestors the identity;
+ *   2. every slot takes its ancestor's parameters, likelihood and equally
+ *      weighted particles; with unequal particle counts destination particle
+ *      k takes source particle floor((k + w 2^-32) n_src / n_dst), w =
+ *      w_copy[i-1][j] (systematic selection on equal weights);
+ *   3. one marginal Metropolis-Hastings move per theta-particle (Alg. 3, eq.
+ *      mh): theta' = theta + step_sd z[i-1][j] (parameters with step_sd 0
+ *      stay), uniform prior on [lo, hi] for the moved parameters; outside it
+ *      the move is rejected; inside, the proposal handle's filter j runs
+ *      theta' over t_{0:i-1} with iteration field i, giving l' and x', and
+ *      the move is accepted iff log_alpha[i-1][j] <= l' - l (ties accept),
+ *      when theta, l and the filter become the proposal's;
+ *   4. every filter of h advances over t_{i-1:i}; its increment ell_i^j is
+ *      the new theta-log-weight and l^j += ell_i^j.
+ * The evidence estimate is the sum over i of ln(sum_j exp v^j(t_i)) - ln B.
+ * theta and z use the cfg.theta layout ([B][n_theta], raw: L96 (F, sigma),
+ * windkessel (a, c, Z, sigma_p, m0, s0)); step_sd, lo, hi hold n_theta
+ * (<= 8) entries.  B <= 8192, T_run <= cfg.T, particle counts <= 8192.
+ * d_ws: caller-owned device memory of ws_bytes >= pf_smc2_workspace_bytes(),
+ * 256-byte aligned.  Host inputs are copied at the call; outputs are host
+ * arrays (the traces may be NULL).  The random numbers of this layer are
+ * inputs.  Synchronous.  PF_E_NUMERIC if some time had no positive
+ * theta-weight (the evidence is then -inf). */
+typedef struct pf_smc2_in {
+  int32_t T_run;
+  const double* theta0;     /* [B][n_theta] initial theta-particles */
+  const double* z;          /* [T_run][B][n_theta] proposal normals */
+  const double* log_alpha;  /* [T_run][B] logs of the acceptance uniforms */
+  const double* u;          /* [T_run] theta-resampling uniforms in [0, 1) */
+  const uint32_t* w_copy;   /* [T_run][B] whole-filter copy offsets */
+  double step_sd[8];
+  double lo[8];
+  double hi[8];
+} pf_smc2_in;
+typedef struct pf_smc2_out {
+  double* theta;            /* [B][n_theta] final theta-particles */
+  double* logw;             /* [B] final theta-log-weights (ell_T) */
+  double* loglik;           /* [B] likelihood estimates l^j */
+  int32_t* accepts;         /* [B] accepted moves */
+  double* ess;              /* [T_run] theta-ESS after each time */
+  double* log_evidence;     /* [1] */
+  int32_t* anc_trace;       /* [T_run][B] theta-ancestors, or NULL */
+  int32_t* acc_trace;       /* [T_run][B] accept flags, or NULL */
+  double* logw_trace;       /* [T_run][B] theta-log-weights, or NULL */
+  double* theta_trace;      /* [T_run][B][n_theta] theta-particles, or NULL */
+} pf_smc2_out;
+size_t pf_smc2_workspace_bytes(const pf_config* cfg, int32_t T_run);
+pf_status pf_smc2(pf_handle* h, pf_handle* proposal, void* d_ws, size_t ws_bytes,
+                  const pf_smc2_in* in, pf_smc2_out* out);
+
 /* Autotuner for the batched layout: for each candidate workgroup size of the
  * per-filter collective kernel (256, 512, 1024 lanes) and each number of
  * filter groups (1, 2, 4; groups are balanced by particle count and stepped

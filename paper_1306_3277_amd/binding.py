@@ -51,6 +51,25 @@ class PfTiming(C.Structure):
     ]
 
 
+class PfSmc2In(C.Structure):
+    _fields_ = [
+        ("T_run", C.c_int32), ("theta0", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
+        ("log_alpha", C.POINTER(C.c_double)), ("u", C.POINTER(C.c_double)),
+        ("w_copy", C.POINTER(C.c_uint32)), ("step_sd", C.c_double * 8), ("lo", C.c_double * 8),
+        ("hi", C.c_double * 8),
+    ]
+
+
+class PfSmc2Out(C.Structure):
+    _fields_ = [
+        ("theta", C.POINTER(C.c_double)), ("logw", C.POINTER(C.c_double)),
+        ("loglik", C.POINTER(C.c_double)), ("accepts", C.POINTER(C.c_int32)),
+        ("ess", C.POINTER(C.c_double)), ("log_evidence", C.POINTER(C.c_double)),
+        ("anc_trace", C.POINTER(C.c_int32)), ("acc_trace", C.POINTER(C.c_int32)),
+        ("logw_trace", C.POINTER(C.c_double)), ("theta_trace", C.POINTER(C.c_double)),
+    ]
+
+
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
 _H = C.c_void_p
@@ -78,6 +97,9 @@ SIGNATURES = {
                               C.c_void_p]),
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
+    "pf_smc2_workspace_bytes": (C.c_size_t, [C.POINTER(PfConfig), C.c_int32]),
+    "pf_smc2": (C.c_int, [_H, _H, C.c_void_p, C.c_size_t, C.POINTER(PfSmc2In),
+                          C.POINTER(PfSmc2Out)]),
     "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _I, _D]),
     "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
@@ -232,6 +254,50 @@ class Filter:
                               inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
                               _ip(acc)))
         return dict(log_f=lft, ll=llt, accepts=acc)
+
+    def smc2(self, proposal: "Filter", inputs, T: Optional[int] = None, traces: bool = True,
+             device: str = "cuda"):
+        """SMC over the parameters (Alg. 4) with this handle's filters attached
+        to the theta-particles and ``proposal`` (a second batched handle of the
+        same problem, on the same stream) running the rejuvenation proposals.
+        ``inputs`` is a workloads.Smc2Inputs."""
+        import torch
+        L = load()
+        T = inputs.T if T is None else int(T)
+        B, nth = self.B, self.hc.cfg.n_theta
+        th0 = np.ascontiguousarray(inputs.theta0, dtype=np.float64).reshape(B, nth)
+        z = np.ascontiguousarray(inputs.z[:T], dtype=np.float64).reshape(T, B, nth)
+        la = np.ascontiguousarray(inputs.log_alpha[:T], dtype=np.float64).reshape(T, B)
+        u = np.ascontiguousarray(inputs.u[:T], dtype=np.float64).reshape(T)
+        w = np.ascontiguousarray(inputs.w_copy[:T], dtype=np.uint32).reshape(T, B)
+        ci = PfSmc2In(T, _dp(th0), _dp(z), _dp(la), _dp(u), w.ctypes.data_as(C.POINTER(C.c_uint32)))
+        for p in range(nth):
+            ci.step_sd[p] = float(inputs.step_sd[p])
+            ci.lo[p] = float(inputs.lo[p])
+            ci.hi[p] = float(inputs.hi[p])
+        res = dict(theta=np.zeros((B, nth)), logw=np.zeros(B), loglik=np.zeros(B),
+                   accepts=np.zeros(B, dtype=np.int32), ess=np.zeros(T),
+                   log_evidence=np.zeros(1))
+        if traces:
+            res.update(anc=np.zeros((T, B), dtype=np.int32), acc=np.zeros((T, B), dtype=np.int32),
+                       logw_trace=np.zeros((T, B)), theta_trace=np.zeros((T, B, nth)))
+        co = PfSmc2Out(_dp(res["theta"]), _dp(res["logw"]), _dp(res["loglik"]),
+                       _ip(res["accepts"]), _dp(res["ess"]), _dp(res["log_evidence"]),
+                       _ip(res["anc"]) if traces else None, _ip(res["acc"]) if traces else None,
+                       _dp(res["logw_trace"]) if traces else None,
+                       _dp(res["theta_trace"]) if traces else None)
+        nbytes = L.pf_smc2_workspace_bytes(C.byref(self.hc.cfg), T)
+        if nbytes == 0:
+            _check(PF_E_INVAL)
+        ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+        aligned = (ws.data_ptr() + 255) & ~255
+        st = L.pf_smc2(self.h, proposal.h, C.c_void_p(aligned), C.c_size_t(nbytes), C.byref(ci),
+                       C.byref(co))
+        res["status"] = st
+        if st not in (PF_OK, PF_E_NUMERIC):
+            _check(st)
+        res["log_evidence"] = float(res["log_evidence"][0])
+        return res
 
     def autotune(self, steps: int = 8):
         """Returns (collective threads, groups, ms per interval [groups x sizes])."""

@@ -13,6 +13,7 @@
 
 #include "../../include/pf.h"
 #include "pf_internal.hpp"
+#include "pf_smc2.hpp"
 
 using pfk::FilterState;
 using pfk::PlainArgs;
@@ -1038,6 +1039,215 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
       ll_trace[(size_t)i * B + b] = ll[b];
     }
   }
+  g_err.clear();
+  return PF_OK;
+}
+
+// Device workspace of pf_smc2: its inputs, the theta-particle state and the
+// traces, each 256-byte aligned.
+struct Smc2Layout {
+  size_t z, la, w, raw, prop_raw, snap_dev, snap_raw, snap_ll, snap_st, a, inside, accepted,
+      accepts, evid, numeric, ess, anc_tr, acc_tr, theta_tr, total;
+};
+
+static Smc2Layout smc2_layout(int64_t B, int64_t nth, int64_t T) {
+  Smc2Layout L{};
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = p;
+    p = align256(p + (bytes > 0 ? bytes : 1));
+    return at;
+  };
+  L.z = take(8 * (size_t)(T * B * nth));
+  L.la = take(8 * (size_t)(T * B));
+  L.w = take(4 * (size_t)(T * B));
+  L.raw = take(8 * (size_t)(B * nth));
+  L.prop_raw = take(8 * (size_t)(B * nth));
+  L.snap_dev = take(8 * 8 * (size_t)B);
+  L.snap_raw = take(8 * (size_t)(B * nth));
+  L.snap_ll = take(8 * (size_t)B);
+  L.snap_st = take(4 * (size_t)B);
+  L.a = take(4 * (size_t)B);
+  L.inside = take(4 * (size_t)B);
+  L.accepted = take(4 * (size_t)B);
+  L.accepts = take(4 * (size_t)B);
+  L.evid = take(8);
+  L.numeric = take(4);
+  L.ess = take(8 * (size_t)T);
+  L.anc_tr = take(4 * (size_t)(T * B));
+  L.acc_tr = take(4 * (size_t)(T * B));
+  L.theta_tr = take(8 * (size_t)(T * B * nth));
+  L.total = p;
+  return L;
+}
+
+size_t pf_smc2_workspace_bytes(const pf_config* cfg, int32_t T_run) {
+  if (validate(cfg) != PF_OK) return 0;
+  if (T_run < 1 || T_run > cfg->T) {
+    fail(PF_E_INVAL, "T_run must be in [1, T]");
+    return 0;
+  }
+  return smc2_layout(cfg->B, cfg->n_theta, T_run).total;
+}
+
+static bool same_config(const pf_handle* A, const pf_handle* B) {
+  const pf_config &a = A->cfg, &b = B->cfg;
+  return a.model == b.model && a.precision == b.precision && a.layout == b.layout &&
+         a.d == b.d && a.K == b.K && a.T == b.T && a.h == b.h && a.n_obs == b.n_obs &&
+         a.obs_sd == b.obs_sd && a.B == b.B && a.n_theta == b.n_theta && a.seed == b.seed &&
+         A->np == B->np;
+}
+
+pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const pf_smc2_in* in,
+                  pf_smc2_out* out) {
+  pf_status st = check_handle(H);
+  if (st || (st = check_handle(P))) return st;
+  if (H == P) return fail(PF_E_INVAL, "the proposal handle must be a second handle");
+  if (!in || !out) return fail(PF_E_INVAL, "NULL argument");
+  const pf_config& c = H->cfg;
+  if (c.layout != PF_LAYOUT_BATCHED) return fail(PF_E_INVAL, "pf_smc2 needs the batched layout");
+  if (!same_config(H, P))
+    return fail(PF_E_INVAL, "the proposal handle's configuration differs from the handle's");
+  if (H->stream != P->stream) return fail(PF_E_INVAL, "both handles must use the same stream");
+  if (c.B > pfk::SMC2_MAXB) return fail(PF_E_INVAL, "at most %d theta-particles", pfk::SMC2_MAXB);
+  if (c.n_theta > 8) return fail(PF_E_INVAL, "at most 8 parameters");
+  const int32_t T = in->T_run;
+  if (T < 1 || T > c.T) return fail(PF_E_INVAL, "T_run must be in [1, %d]", c.T);
+  if (T >= (1 << 20)) return fail(PF_E_INVAL, "T_run must be < 2^20");
+  if (!in->theta0 || !in->z || !in->log_alpha || !in->u || !in->w_copy)
+    return fail(PF_E_INVAL, "NULL input array");
+  if (!out->theta || !out->logw || !out->loglik || !out->accepts || !out->ess ||
+      !out->log_evidence)
+    return fail(PF_E_INVAL, "NULL output array");
+  const int B = c.B, nth = c.n_theta;
+  for (int p = 0; p < nth; ++p)
+    if (!(in->step_sd[p] >= 0.0) || !std::isfinite(in->step_sd[p]) ||
+        (in->step_sd[p] > 0.0 && !(in->lo[p] <= in->hi[p])))
+      return fail(PF_E_INVAL, "step_sd[%d] or its prior box invalid", p);
+  for (int32_t i = 0; i < T; ++i)
+    if (!(in->u[i] >= 0.0 && in->u[i] < 1.0)) return fail(PF_E_INVAL, "u[%d] not in [0, 1)", i);
+  for (int64_t i = 0; i < (int64_t)T * B * nth; ++i)
+    if (!std::isfinite(in->z[i])) return fail(PF_E_INVAL, "z[%lld] not finite", (long long)i);
+  const Smc2Layout L = smc2_layout(B, nth, T);
+  if (!d_ws) return fail(PF_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)d_ws & 255) != 0) return fail(PF_E_INVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(PF_E_INVAL, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+  char* ws = (char*)d_ws;
+  hipStream_t s = H->stream;
+
+  // h starts from theta0 with iteration field 0
+  if ((st = pf_set_theta(H, in->theta0, 0))) return st;
+  HIP_TRY(hipMemcpyAsync(ws + L.z, in->z, 8 * (size_t)T * B * nth, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws + L.la, in->log_alpha, 8 * (size_t)T * B, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws + L.w, in->w_copy, 4 * (size_t)T * B, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(ws + L.raw, in->theta0, 8 * (size_t)B * nth, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(ws + L.accepts, 0, 4 * (size_t)B, s));
+  HIP_TRY(hipMemsetAsync(ws + L.evid, 0, 8, s));
+  HIP_TRY(hipMemsetAsync(ws + L.numeric, 0, 4, s));
+  HIP_TRY(hipMemsetAsync(ws + L.anc_tr, 0, 4 * (size_t)B, s));  // time 1: identity, below
+  HIP_TRY(hipStreamSynchronize(s));
+  {
+    std::vector<int32_t> ident(B);
+    for (int j = 0; j < B; ++j) ident[j] = j;
+    HIP_TRY(hipMemcpyAsync(ws + L.anc_tr, ident.data(), 4 * (size_t)B, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  // capture both handles' graphs before the loop
+  if ((st = ensure_graphs(H)) || (st = ensure_graphs(P))) return st;
+
+  pfk::Smc2Args S{};
+  S.B = B;
+  S.T = c.T;
+  S.n_theta = nth;
+  S.model = c.model;
+  S.sqrt_h = std::sqrt(c.h);
+  for (int p = 0; p < 8; ++p) {
+    S.step_sd[p] = p < nth ? in->step_sd[p] : 0.0;
+    S.lo[p] = p < nth ? in->lo[p] : 0.0;
+    S.hi[p] = p < nth ? in->hi[p] : 0.0;
+  }
+  S.ell_tr = H->at<double>(H->L.ell);
+  S.fs = H->at<FilterState>(H->L.fs);
+  S.theta_dev = H->at<double>(H->L.theta);
+  S.raw = (double*)(ws + L.raw);
+  S.prop_raw = (double*)(ws + L.prop_raw);
+  S.snap_dev = (double*)(ws + L.snap_dev);
+  S.snap_raw = (double*)(ws + L.snap_raw);
+  S.snap_ll = (double*)(ws + L.snap_ll);
+  S.snap_st = (int32_t*)(ws + L.snap_st);
+  S.a = (int32_t*)(ws + L.a);
+  S.inside = (int32_t*)(ws + L.inside);
+  S.accepted = (int32_t*)(ws + L.accepted);
+  S.accepts = (int32_t*)(ws + L.accepts);
+  S.evid = (double*)(ws + L.evid);
+  S.numeric = (int32_t*)(ws + L.numeric);
+  const BatchArgs A = batch_args(H);
+  double* ess_d = (double*)(ws + L.ess);
+  int32_t* anc_tr = (int32_t*)(ws + L.anc_tr);
+  int32_t* acc_tr = (int32_t*)(ws + L.acc_tr);
+  const double* z_d = (const double*)(ws + L.z);
+  const double* la_d = (const double*)(ws + L.la);
+  const uint32_t* w_d = (const uint32_t*)(ws + L.w);
+  double* prop_dev = P->at<double>(P->L.theta);
+
+  for (int32_t i = 1; i <= T; ++i) {
+    const size_t cur = batched_buf(H, i - 1), spare = batched_buf(H, i);
+    if (i >= 2) {
+      // 1-2. theta-ancestors from v(t_{i-1}), the slots' moves and filter copies
+      HIP_TRY(pfk::launch_theta_resample(S, i - 2, in->u[i - 1], 1, anc_tr + (size_t)(i - 1) * B,
+                                         ess_d + (i - 2), s));
+      HIP_TRY(pfk::launch_filter_copy(c.precision, H->ws + cur, H->ws + spare,
+                                      H->at<int32_t>(H->L.anc), A, S, w_d + (size_t)(i - 1) * B,
+                                      s));
+    }
+    // 3. rejuvenation: proposals, their filters over t_{0:i-1}, the decisions
+    HIP_TRY(pfk::launch_smc2_propose(S, z_d + (size_t)(i - 1) * B * nth, prop_dev, s));
+    P->iter = (uint32_t)i;
+    if ((st = do_init(P, s))) return st;
+    if (i > 1 && (st = pf_graph_run(P, i - 1))) return st;
+    HIP_TRY(pfk::launch_smc2_accept(S, la_d + (size_t)(i - 1) * B, prop_dev,
+                                    P->at<FilterState>(P->L.fs), acc_tr + (size_t)(i - 1) * B,
+                                    s));
+    HIP_TRY(pfk::launch_accept_copy(c.precision, H->ws + cur, H->at<int32_t>(H->L.anc),
+                                    P->ws + batched_buf(P, i - 1), P->at<int32_t>(P->L.anc), A, S,
+                                    s));
+    // 4. every attached filter advances one interval
+    if ((st = pf_graph_run(H, 1))) return st;
+    HIP_TRY(hipMemcpyAsync(ws + L.theta_tr + 8 * (size_t)(i - 1) * B * nth, ws + L.raw,
+                           8 * (size_t)B * nth, hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(pfk::launch_theta_resample(S, T - 1, 0.5, 0, nullptr, ess_d + (T - 1), s));
+
+  // outputs
+  std::vector<double> ell((size_t)B * c.T);
+  std::vector<FilterState> fs(B);
+  int32_t numeric = 0;
+  HIP_TRY(hipMemcpyAsync(out->theta, ws + L.raw, 8 * (size_t)B * nth, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ell.data(), H->ws + H->L.ell, 8 * ell.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(fs.data(), H->ws + H->L.fs, sizeof(FilterState) * (size_t)B,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(out->accepts, ws + L.accepts, 4 * (size_t)B, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(out->ess, ws + L.ess, 8 * (size_t)T, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(out->log_evidence, ws + L.evid, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&numeric, ws + L.numeric, 4, hipMemcpyDeviceToHost, s));
+  if (out->anc_trace)
+    HIP_TRY(hipMemcpyAsync(out->anc_trace, ws + L.anc_tr, 4 * (size_t)T * B,
+                           hipMemcpyDeviceToHost, s));
+  if (out->acc_trace)
+    HIP_TRY(hipMemcpyAsync(out->acc_trace, ws + L.acc_tr, 4 * (size_t)T * B,
+                           hipMemcpyDeviceToHost, s));
+  if (out->theta_trace)
+    HIP_TRY(hipMemcpyAsync(out->theta_trace, ws + L.theta_tr, 8 * (size_t)T * B * nth,
+                           hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int j = 0; j < B; ++j) {
+    out->logw[j] = ell[(size_t)j * c.T + (T - 1)];
+    out->loglik[j] = fs[j].status ? -INFINITY : fs[j].loglik;
+    if (out->logw_trace)
+      for (int32_t i = 0; i < T; ++i) out->logw_trace[(size_t)i * B + j] = ell[(size_t)j * c.T + i];
+  }
+  if (numeric) return fail(PF_E_NUMERIC, "some time had no positive theta-weight");
   g_err.clear();
   return PF_OK;
 }

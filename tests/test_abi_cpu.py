@@ -52,6 +52,19 @@ def _msg():
     return binding.load().pf_last_error().decode()
 
 
+def test_smc2_workspace_size_and_run_length():
+    pb = W.config("c4")
+    hc = binding._HostCfg(pb.with_obs(np.zeros((pb.T, pb.n_obs))),
+                          layout=binding.PF_LAYOUT_BATCHED)
+    L = binding.load()
+    n = L.pf_smc2_workspace_bytes(C.byref(hc.cfg), pb.T)
+    # the random inputs alone: normals, log-uniforms and copy words per (time, particle)
+    assert n >= pb.T * pb.B * (8 * pb.n_theta + 8 + 4)
+    assert L.pf_smc2_workspace_bytes(C.byref(hc.cfg), 10) < n
+    assert L.pf_smc2_workspace_bytes(C.byref(hc.cfg), 0) == 0 and "T_run" in _msg()
+    assert L.pf_smc2_workspace_bytes(C.byref(hc.cfg), pb.T + 1) == 0
+
+
 @pytest.mark.parametrize("mutate,needle", [
     (lambda c: setattr(c, "model", 3), "model"),
     (lambda c: setattr(c, "precision", 7), "precision"),

@@ -240,6 +240,45 @@ def large_filter_leg(torch, pfm, stream):
     return leg
 
 
+def smc2_leg(torch, pfm, pb, stream, T, threads, groups):
+    """SMC over the parameters (Alg. 4) with the batched workload's filters as
+    the theta-particles' attached filters (FP32 mixed).  Time i re-runs every
+    theta-particle's proposal filter over t_{0:i-1}, so the run does
+    T(T+1)/2 intervals of filter work over all particles."""
+    inp = W.smc2_l96_inputs(pb.theta, T, seed=4)
+    fh = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    fp = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    for f in (fh, fp):
+        f.set_tuning(threads, groups)
+    fh.smc2(fp, inp, T=3, traces=False)  # graph capture and first touch, untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fh.smc2(fp, inp, T=T, traces=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fh.close()
+    fp.close()
+    n_tot = int(pb.n_particles.sum())
+    intervals = T * (T + 1) // 2
+    w = np.exp(r["logw"] - r["logw"].max())
+    w /= w.sum()
+    leg = {"workload": f"{pb.name} theta-particles", "theta_particles": pb.B,
+           "particles": n_tot, "T": T, "seconds": dt,
+           "filter_intervals_per_particle": intervals,
+           "particle_steps_per_s": n_tot * intervals / dt,
+           "theta_steps_per_s": pb.B * T / dt,
+           "accept_rate": float(r["accepts"].sum() / (pb.B * T)),
+           "log_evidence": r["log_evidence"], "final_theta_ess": float(r["ess"][-1]),
+           "posterior_mean": {"F": float(w @ r["theta"][:, 0]),
+                              "sigma": float(w @ r["theta"][:, 1])},
+           "status": int(r["status"])}
+    log(f"[bench] SMC^2: {pb.B} theta-particles x {T} times in {dt:.2f} s = "
+        f"{leg['particle_steps_per_s']:.3e} particle-steps/s; accept {leg['accept_rate']:.3f}; "
+        f"log evidence {r['log_evidence']:.2f}; posterior mean F {leg['posterior_mean']['F']:.3f}, "
+        f"sigma {leg['posterior_mean']['sigma']:.3f}")
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +288,10 @@ def main():
                     help="intervals timed for the FP64 plain comparison")
     ap.add_argument("--pmmh-iters", type=int, default=10)
     ap.add_argument("--tf-steps", type=int, default=8, help="teacher-forced error intervals")
+    ap.add_argument("--smc2-T", type=int, default=200,
+                    help="observation times of the SMC^2 leg (0: skip it)")
+    ap.add_argument("--profile-smc2", action="store_true",
+                    help="run only the SMC^2 leg (for kernel traces)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline workload only")
     ap.add_argument("--fp64-batched-leg", action="store_true",
@@ -298,6 +341,10 @@ def main():
     pb = pb.with_obs(y)
     n_tot = int(pb.n_particles.sum())
     log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
+    if args.profile_smc2:
+        print(json.dumps({"profile_smc2": smc2_leg(torch, pfm, pb, stream, args.smc2_T, 512, 2)}),
+              flush=True)
+        return
 
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
     threads, groups, cand_ms = f32.autotune(steps=16)
@@ -444,6 +491,11 @@ def main():
                                                 (pm.B * args.pmmh_iters))}
             log(f"[bench] pmmh: {nfilt / dtm:.1f} filters/s, accept "
                 f"{out['pmmh']['accept_rate']:.3f}")
+
+        # ------------------------------------------------------------ SMC^2
+        if args.smc2_T > 0:
+            log("[bench] SMC^2 leg starts")
+            out["smc2"] = smc2_leg(torch, pfm, pb, stream, args.smc2_T, threads, groups)
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample starts")

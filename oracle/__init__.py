@@ -23,7 +23,7 @@ _lib = None
 
 ORC_OK = 0
 ORC_NUMERIC = 4
-TAG_INIT, TAG_NOISE, TAG_RESAMPLE, TAG_DATA, TAG_OBS = 1, 2, 3, 4, 8
+TAG_INIT, TAG_NOISE, TAG_RESAMPLE, TAG_DATA, TAG_OBS, TAG_PATH = 1, 2, 3, 4, 8, 9
 
 
 def build(force: bool = True) -> str:
@@ -89,6 +89,10 @@ def lib():
                                      _D, _D, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                      _D, _D, _I]),
             "orc_copy_index": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64, C.c_uint32]),
+            "orc_path_slot": (C.c_int64, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
+                                          C.c_int64]),
+            "orc_pf_path": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
+                                        _D, _D, C.POINTER(C.c_int64)]),
             "orc_smc2": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), C.c_int32, _D,
                                      C.c_int32, _D, _D, _D, _D, _D, _D, _U, _D, _D, _D, _I,
                                      _D, _D, _I, _I, _D, _D, _D]),
@@ -331,3 +335,22 @@ def smc2(pb, inputs, T=None, n_particles=None):
     out["status"] = st
     out["log_evidence"] = ev.value
     return out
+
+
+def path_slot(seed, s, b, it, N) -> int:
+    return lib().orc_path_slot(int(seed), int(s), int(b), int(it), int(N))
+
+
+def pf_path(pb, theta=None, N=None, b=0, it=0, T=None):
+    """Alg. 2 with its single state sample: returns (status, loglik,
+    path [T+1, d], particle indices [T+1])."""
+    P = _Prob(pb)
+    th = np.ascontiguousarray(pb.theta[b] if theta is None else theta, dtype=np.float64)
+    N = int(pb.n_particles[b] if N is None else N)
+    T = pb.T if T is None else T
+    path = np.zeros((T + 1, pb.d))
+    idx = np.zeros(T + 1, dtype=np.int64)
+    ll = C.c_double()
+    st = lib().orc_pf_path(P.ref, _dp(th), N, b, it, T, C.byref(ll), _dp(path),
+                           idx.ctypes.data_as(C.POINTER(C.c_int64)))
+    return st, ll.value, path, idx

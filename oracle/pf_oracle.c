@@ -698,3 +698,67 @@ int32_t orc_smc2(const orc_problem* P, int32_t B, const int64_t* n_particles, in
   free(off);
   return status;
 }
+
+/* Index of the final particle of the state sample (Alg. 2, last lines:
+ * j ~ Multinomial(w(t_s))).  The time-s systematic ancestors a_k
+ * (k = 0..N-1) invert the cumulative weights at (u + k)/N; with k drawn
+ * uniformly on 0..N-1, independent of u, that point is uniform on [0, 1), so
+ * a_k is one draw from w(t_s).  k = floor(w N 2^-32) for the first word w of
+ * the generator at counter (0, s, tag PATH | iteration, b), exact in
+ * integers. */
+int64_t orc_path_slot(uint64_t seed, int32_t s, uint32_t b, uint32_t iter, int64_t N) {
+  uint32_t ctr[4] = {0u, (uint32_t)s, ((uint32_t)ORC_TAG_PATH << 28) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return (int64_t)(((uint64_t)w[0] * (uint64_t)N) >> 32);
+}
+
+/* Alg. 2 over t = 1..T_run, keeping every time's propagated (weighted)
+ * particles x(t_i) and ancestors, then the single state sample: the final
+ * particle j is the time-T_run ancestor at orc_path_slot, and for
+ * i = T_run..1, j <- a^j(t_i), the ancestor that particle j of time t_i was
+ * propagated from (the time-(i-1) systematic ancestors; identity at i = 1,
+ * whose t_0 draw is skipped), x'(t_{i-1}) = x^j(t_{i-1}).  path [T_run+1][d],
+ * idx [T_run+1] (particle indices per time).  Returns the filter status. */
+int32_t orc_pf_path(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                    uint32_t iter, int32_t T_run, double* loglik, double* path, int64_t* idx) {
+  const int d = P->d;
+  const size_t xs = (size_t)d * (size_t)N;
+  double* xh = (double*)malloc(sizeof(double) * xs * ((size_t)T_run + 1));
+  int32_t* ah = (int32_t*)malloc(sizeof(int32_t) * (size_t)N * ((size_t)T_run + 1));
+  double* x = (double*)malloc(sizeof(double) * xs);
+  double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+  int32_t status = ORC_OK;
+  double ll = 0.0;
+  orc_init(P, theta, N, b, iter, xh);  /* time t_0 */
+  memcpy(x, xh, sizeof(double) * xs);
+  for (int32_t t = 1; t <= T_run; ++t) {
+    double* xt = xh + (size_t)t * xs;
+    orc_propagate(P, theta, N, b, iter, t, x, xt);
+    orc_weight(P, theta, N, t, xt, lw);
+    double e, s;
+    int32_t st = orc_reduce_resample(N, lw, orc_resample_u(P->seed, t, b, iter), &e, &s,
+                                     ah + (size_t)t * N);
+    if (st != ORC_OK) status = st;
+    ll = ll + e;
+    orc_gather(d, N, xt, ah + (size_t)t * N, x);
+  }
+  *loglik = (status == ORC_OK) ? ll : -INFINITY;
+  /* the single state sample, traced back through the ancestry */
+  const int64_t k = orc_path_slot(P->seed, T_run, b, iter, N);
+  int64_t j = (T_run >= 1) ? ah[(size_t)T_run * N + k] : k;
+  idx[T_run] = j;
+  for (int32_t i = T_run; i >= 1; --i) {
+    if (i >= 2) j = ah[(size_t)(i - 1) * N + j];
+    idx[i - 1] = j;
+  }
+  for (int32_t i = 0; i <= T_run; ++i)
+    for (int c = 0; c < d; ++c)
+      path[(size_t)i * d + c] = xh[(size_t)i * xs + (size_t)c * N + idx[i]];
+  free(lw);
+  free(x);
+  free(ah);
+  free(xh);
+  return status;
+}

@@ -28,7 +28,7 @@ extern "C" {
 
 enum { ORC_MODEL_WK = 1, ORC_MODEL_L96 = 2 };
 enum { ORC_TAG_INIT = 1, ORC_TAG_NOISE = 2, ORC_TAG_RESAMPLE = 3, ORC_TAG_DATA = 4,
-       ORC_TAG_OBS = 8 };
+       ORC_TAG_OBS = 8, ORC_TAG_PATH = 9 };
 enum { ORC_OK = 0, ORC_NUMERIC = 4 };
 
 typedef struct orc_problem {
@@ -93,6 +93,11 @@ int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chai
                  const double* z, const double* alpha, double step_sd, double f_lo,
                  double f_hi, double sigma, double* log_f_trace /* [iters][n_chains] */,
                  double* ll_trace /* [iters][n_chains] */, int32_t* accepts /* [n_chains] */);
+
+/* the single state sample of Alg. 2 (ancestry traced back) */
+int64_t orc_path_slot(uint64_t seed, int32_t s, uint32_t b, uint32_t iter, int64_t N);
+int32_t orc_pf_path(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                    uint32_t iter, int32_t T_run, double* loglik, double* path, int64_t* idx);
 
 /* whole-filter copy index (systematic selection on equal weights) */
 int64_t orc_copy_index(int64_t k, int64_t n_src, int64_t n_dst, uint32_t w);

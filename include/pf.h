@@ -162,6 +162,30 @@ pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 pf_status pf_set_theta(pf_handle* h, const double* theta, uint32_t iteration);
 pf_status pf_reset(pf_handle* h, uint32_t iteration);
 
+/* ---- ancestry storage and the state sample ------------------------------- */
+/* The bootstrap filter's single state sample x'(t_{0:s}) (Alg. 2, last lines;
+ * Sec. 3.1.2): one particle drawn from the final weights and traced back
+ * through its ancestors.  A caller-owned device history of
+ * pf_history_bytes(cfg) bytes (256-byte aligned) holds every time's
+ * propagated particles [T+1][d][N_total] (state precision; slot 0 the
+ * initial particles) and ancestors [T][N_total] (slot t-1: those drawn from
+ * the time-t weights), plus the backtrace's output.  pf_history_attach
+ * (at t = 0, after pf_init or pf_reset; NULL detaches) records slot 0 and
+ * makes every later interval, eager or graph-replayed, and every
+ * re-initialisation record its slot (an extra copy of the particles and
+ * ancestors per interval).  pf_backtrace (after a resampled interval, at the
+ * handle's time s) draws, per filter b, the final particle as the time-s
+ * systematic ancestor at slot floor(w N_b 2^-32), w the first word of the
+ * generator at counter (0, s, tag 9 | iteration, b) (a uniform slot makes
+ * that ancestor one draw from the final weights), walks j <- a^j(t_i) for
+ * i = s..1 (identity at i = 1), and writes the path to host path_out
+ * [B][s+1][d] (FP64) and, if not NULL, the particle indices to idx_out
+ * [B][s+1].  pf_set_state does not touch the history; pf_smc2 refuses
+ * handles with a history.  Synchronous. */
+size_t pf_history_bytes(const pf_config* cfg);
+pf_status pf_history_attach(pf_handle* h, void* d_history, size_t bytes);
+pf_status pf_backtrace(pf_handle* h, double* path_out, int32_t* idx_out);
+
 /* ---- parameter inference drivers ---------------------------------------- */
 /* Marginal Metropolis-Hastings chains (Sec. 3.2.1, eq. mh, Alg. 3) on the
  * Lorenz '96 forcing F with sigma fixed, one chain per filter of the handle

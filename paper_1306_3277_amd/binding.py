@@ -97,6 +97,9 @@ SIGNATURES = {
                               C.c_void_p]),
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
+    "pf_history_bytes": (C.c_size_t, [C.POINTER(PfConfig)]),
+    "pf_history_attach": (C.c_int, [_H, C.c_void_p, C.c_size_t]),
+    "pf_backtrace": (C.c_int, [_H, _D, _I]),
     "pf_smc2_workspace_bytes": (C.c_size_t, [C.POINTER(PfConfig), C.c_int32]),
     "pf_smc2": (C.c_int, [_H, _H, C.c_void_p, C.c_size_t, C.POINTER(PfSmc2In),
                           C.POINTER(PfSmc2Out)]),
@@ -254,6 +257,30 @@ class Filter:
                               inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
                               _ip(acc)))
         return dict(log_f=lft, ll=llt, accepts=acc)
+
+    # -- ancestry storage and the state sample (Alg. 2, last lines)
+    def attach_history(self, device: str = "cuda"):
+        """Allocate and attach a history (at t = 0); later intervals record."""
+        import torch
+        L = load()
+        n = L.pf_history_bytes(C.byref(self.hc.cfg))
+        if n == 0:
+            _check(PF_E_INVAL)
+        self.history = torch.empty(int(n) + 256, dtype=torch.uint8, device=device)
+        aligned = (self.history.data_ptr() + 255) & ~255
+        _check(L.pf_history_attach(self.h, C.c_void_p(aligned), C.c_size_t(int(n))))
+
+    def detach_history(self):
+        _check(load().pf_history_attach(self.h, None, 0))
+        self.history = None
+
+    def backtrace(self):
+        """State sample per filter: (path [B, s+1, d], particle indices [B, s+1])."""
+        t = self.loglik(allow_numeric=True)[2]
+        path = np.zeros((self.B, t + 1, self.d))
+        idx = np.zeros((self.B, t + 1), dtype=np.int32)
+        _check(load().pf_backtrace(self.h, _dp(path), _ip(idx)))
+        return path, idx
 
     def smc2(self, proposal: "Filter", inputs, T: Optional[int] = None, traces: bool = True,
              device: str = "cuda"):

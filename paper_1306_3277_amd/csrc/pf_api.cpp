@@ -13,6 +13,7 @@
 
 #include "../../include/pf.h"
 #include "pf_internal.hpp"
+#include "pf_path.hpp"
 #include "pf_smc2.hpp"
 
 using pfk::FilterState;
@@ -233,6 +234,8 @@ struct pf_handle {
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   hipStream_t cap_stream = nullptr;
+  // attached history (ancestry storage), or null
+  char* hist = nullptr;
   bool alive = true;
 
   template <typename T>
@@ -336,6 +339,60 @@ pf_status check_handle(pf_handle* H) {
   return PF_OK;
 }
 
+// History buffer: xh [T+1][d][N_total] particles, ah [T][N_total] ancestors,
+// then the backtrace's indices [B][T+1] and path [B][T+1][d] (FP64).
+struct HistLayout {
+  size_t xh, ah, idx, path, total;
+};
+
+HistLayout hist_layout(const pf_config* c, int64_t n_total) {
+  HistLayout L{};
+  const size_t sx = c->precision == PF_FP64 ? 8 : 4;
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = p;
+    p = align256(p + bytes);
+    return at;
+  };
+  L.xh = take(sx * (size_t)(c->T + 1) * c->d * (size_t)n_total);
+  L.ah = take(4 * (size_t)c->T * (size_t)n_total);
+  L.idx = take(4 * (size_t)c->B * (c->T + 1));
+  L.path = take(8 * (size_t)c->B * (c->T + 1) * c->d);
+  L.total = p;
+  return L;
+}
+
+pfk::HistArgs hist_args(const pf_handle* H) {
+  const HistLayout L = hist_layout(&H->cfg, H->L.n_total);
+  pfk::HistArgs a{};
+  a.xh = H->hist + L.xh;
+  a.ah = (int32_t*)(H->hist + L.ah);
+  a.ld = H->L.n_total;
+  a.d = H->cfg.d;
+  a.T = H->cfg.T;
+  return a;
+}
+
+// Copy the current slot (the filters' step counters) into the history: the
+// particles x of every filter (plain layout: x is the given buffer; batched:
+// the buffer of the step's parity) and, past t_0, the ancestors.
+pf_status record_all(pf_handle* H, size_t x_plain, hipStream_t s) {
+  if (!H->hist) return PF_OK;
+  const pf_config& c = H->cfg;
+  const pfk::HistArgs ha = hist_args(H);
+  if (c.layout == PF_LAYOUT_PLAIN) {
+    for (int b = 0; b < c.B; ++b)
+      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + x_plain, H->at<int32_t>(H->L.anc), ha,
+                                       H->L.off[b], H->np[b],
+                                       H->at<FilterState>(H->L.fs) + b, s));
+  } else {
+    BatchArgs a = batch_args(H);
+    HIP_TRY(pfk::launch_record_batched(c.precision, H->ws + H->L.x_cur, H->ws + H->L.x_tmp,
+                                       H->at<int32_t>(H->L.anc), ha, a, H->L.n_chunks, s));
+  }
+  return PF_OK;
+}
+
 // init kernels for every filter (fresh x(t0), scalars and traces cleared)
 pf_status do_init(pf_handle* H, hipStream_t s) {
   const pf_config& c = H->cfg;
@@ -351,6 +408,8 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
     HIP_TRY(pfk::launch_batched_init(c.model, c.d, c.precision, H->ws + H->L.x_cur,
                                      H->at<int32_t>(H->L.anc), a, s));
   }
+  pf_status st = record_all(H, H->L.x_cur, s);
+  if (st) return st;
   H->t = 0;
   H->phase = 0;
   return PF_OK;
@@ -383,6 +442,10 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
   if (st) return st;
   HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
                                        H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
+  if (H->hist)
+    HIP_TRY(pfk::launch_record_batched(H->cfg.precision, H->ws + H->L.x_cur, H->ws + H->L.x_tmp,
+                                       H->at<int32_t>(H->L.anc), hist_args(H), a,
+                                       H->grp_nchunks[g], s));
   return ev_end(H, e0, 4, s);
 }
 
@@ -446,6 +509,8 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     a.mode = 1;
     HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
                                          H->at<int32_t>(H->L.anc), a, c.B, s));
+    pf_status st = record_all(H, 0, s);  // the redrawn ancestors
+    if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));  // u is a host array
     return PF_OK;
   }
@@ -465,6 +530,9 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
                                      H->ws + H->L.x_tmp,
                                      H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
     if ((st = ev_end(H, e0, 3, s))) return st;
+    if (H->hist)
+      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + H->L.x_tmp, H->at<int32_t>(H->L.anc),
+                                       hist_args(H), a.off, a.N, a.fs, s));
   }
   return PF_OK;
 }
@@ -1109,6 +1177,8 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   if (!same_config(H, P))
     return fail(PF_E_INVAL, "the proposal handle's configuration differs from the handle's");
   if (H->stream != P->stream) return fail(PF_E_INVAL, "both handles must use the same stream");
+  if (H->hist || P->hist)
+    return fail(PF_E_STATE, "pf_smc2 does not keep histories: detach them first");
   if (c.B > pfk::SMC2_MAXB) return fail(PF_E_INVAL, "at most %d theta-particles", pfk::SMC2_MAXB);
   if (c.n_theta > 8) return fail(PF_E_INVAL, "at most 8 parameters");
   const int32_t T = in->T_run;
@@ -1249,6 +1319,61 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   }
   if (numeric) return fail(PF_E_NUMERIC, "some time had no positive theta-weight");
   g_err.clear();
+  return PF_OK;
+}
+
+size_t pf_history_bytes(const pf_config* cfg) {
+  if (validate(cfg) != PF_OK) return 0;
+  return hist_layout(cfg, make_layout(cfg).n_total).total;
+}
+
+pf_status pf_history_attach(pf_handle* H, void* d_hist, size_t bytes) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (d_hist) {
+    if (H->t != 0 || H->phase != 0)
+      return fail(PF_E_STATE, "attach a history at t = 0 (after pf_init or pf_reset)");
+    if (((uintptr_t)d_hist & 255) != 0) return fail(PF_E_INVAL, "history not 256-byte aligned");
+    const size_t need = hist_layout(&H->cfg, H->L.n_total).total;
+    if (bytes < need) return fail(PF_E_INVAL, "history has %zu bytes, needs %zu", bytes, need);
+  }
+  if ((st = drain(H))) return st;
+  destroy_graphs(H);  // recaptured with (or without) the recording kernels
+  H->hist = (char*)d_hist;
+  if (d_hist && (st = record_all(H, H->L.x_cur, H->stream))) return st;
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  return PF_OK;
+}
+
+pf_status pf_backtrace(pf_handle* H, double* path_out, int32_t* idx_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!H->hist) return fail(PF_E_STATE, "no history attached");
+  if (!path_out) return fail(PF_E_INVAL, "path_out is NULL");
+  if (H->phase != 0) return fail(PF_E_STATE, "pf_backtrace needs a resampled particle set");
+  const pf_config& c = H->cfg;
+  const HistLayout L = hist_layout(&c, H->L.n_total);
+  const int32_t t = H->t;
+  pfk::KeyArg key;
+  key.lo = (uint32_t)(c.seed & 0xffffffffu);
+  key.hi = (uint32_t)(c.seed >> 32);
+  HIP_TRY(pfk::launch_backtrace(c.precision, hist_args(H), c.B, H->at<int64_t>(H->L.b_off),
+                                H->at<FilterState>(H->L.fs), key, (int32_t*)(H->hist + L.idx),
+                                (double*)(H->hist + L.path), H->stream));
+  std::vector<double> path((size_t)c.B * (c.T + 1) * c.d);
+  std::vector<int32_t> idx((size_t)c.B * (c.T + 1));
+  HIP_TRY(hipMemcpyAsync(path.data(), H->hist + L.path, 8 * path.size(), hipMemcpyDeviceToHost,
+                         H->stream));
+  HIP_TRY(hipMemcpyAsync(idx.data(), H->hist + L.idx, 4 * idx.size(), hipMemcpyDeviceToHost,
+                         H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  for (int b = 0; b < c.B; ++b) {
+    std::memcpy(path_out + (size_t)b * (t + 1) * c.d, path.data() + (size_t)b * (c.T + 1) * c.d,
+                8 * (size_t)(t + 1) * c.d);
+    if (idx_out)
+      std::memcpy(idx_out + (size_t)b * (t + 1), idx.data() + (size_t)b * (c.T + 1),
+                  4 * (size_t)(t + 1));
+  }
   return PF_OK;
 }
 

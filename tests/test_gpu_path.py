@@ -1,0 +1,122 @@
+"""GPU parity of the bootstrap filter's single state sample (Alg. 2, last
+lines: ancestry storage, final draw, backtrace) with the oracle, through the
+C ABI: particle indices and FP64 paths bit for bit, plain and batched
+layouts, eager and graph-replayed intervals; FP32 batched equals FP32 plain
+(the same propagation arithmetic)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_3277_amd as pfm
+    pfm.load()
+    return pfm
+
+
+def _data(pb):
+    _, y = oracle.simulate(pb)
+    return pb.with_obs(y)
+
+
+def _run(pfm, pb, precision, layout, graph, T=None):
+    T = pb.T if T is None else T
+    f = pfm.Filter(pb, precision=precision, layout=layout)
+    f.attach_history()
+    if graph:
+        f.graph_run(T)
+    else:
+        f.advance(T)
+    path, idx = f.backtrace()
+    f.close()
+    return path, idx
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("model", ["l96", "wk"])
+def test_plain_fp64_path_matches_oracle(pfm, model, graph):
+    pb = _data(W.lorenz96(d=8, N=300, T=6) if model == "l96" else W.windkessel(N=500, T=9))
+    path, idx = _run(pfm, pb, pfm.PF_FP64, pfm.PF_LAYOUT_PLAIN, graph)
+    st, ll, rpath, ridx = oracle.pf_path(pb)
+    np.testing.assert_array_equal(idx[0], ridx)
+    np.testing.assert_array_equal(path[0], rpath)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_fp64_path_matches_oracle(pfm, graph):
+    base = _data(W.lorenz96(d=8, N=1, T=7))
+    th0, _ = W.batched_thetas(4, seed=51)
+    n = np.array([257, 64, 1000, 33], dtype=np.int64)
+    pb = dataclasses.replace(base, theta=th0, n_particles=n)
+    path, idx = _run(pfm, pb, pfm.PF_FP64, pfm.PF_LAYOUT_BATCHED, graph)
+    for b in range(pb.B):
+        st, ll, rpath, ridx = oracle.pf_path(pb, theta=th0[b], N=int(n[b]), b=b)
+        np.testing.assert_array_equal(idx[b], ridx, err_msg=f"filter {b}")
+        np.testing.assert_array_equal(path[b], rpath, err_msg=f"filter {b}")
+
+
+def test_path_before_the_end_and_at_t0(pfm):
+    pb = _data(W.lorenz96(d=8, N=128, T=8))
+    for T in (0, 3):
+        f = pfm.Filter(pb, precision=pfm.PF_FP64)
+        f.attach_history()
+        f.advance(T)
+        path, idx = f.backtrace()
+        f.close()
+        st, ll, rpath, ridx = oracle.pf_path(pb, T=T)
+        assert path.shape == (1, T + 1, 8)
+        np.testing.assert_array_equal(idx[0], ridx)
+        np.testing.assert_array_equal(path[0], rpath)
+
+
+def test_reset_records_the_new_run(pfm):
+    pb = _data(W.lorenz96(d=8, N=200, T=5))
+    f = pfm.Filter(pb, precision=pfm.PF_FP64, layout=pfm.PF_LAYOUT_BATCHED)
+    f.attach_history()
+    f.graph_run(5)
+    f.reset(7)
+    f.graph_run(4)
+    path, idx = f.backtrace()
+    f.close()
+    st, ll, rpath, ridx = oracle.pf_path(pb, it=7, T=4)
+    np.testing.assert_array_equal(idx[0], ridx)
+    np.testing.assert_array_equal(path[0], rpath)
+
+
+def test_fp32_batched_path_equals_fp32_plain(pfm):
+    base = _data(W.lorenz96(d=8, N=1, T=6, precision=W.FP32_MIXED))
+    th0, _ = W.batched_thetas(3, seed=52)
+    n = np.array([300, 1024, 77], dtype=np.int64)
+    pb = dataclasses.replace(base, theta=th0, n_particles=n)
+    p1, i1 = _run(pfm, pb, pfm.PF_FP32_MIXED, pfm.PF_LAYOUT_PLAIN, True)
+    p2, i2 = _run(pfm, pb, pfm.PF_FP32_MIXED, pfm.PF_LAYOUT_BATCHED, True)
+    np.testing.assert_array_equal(i2, i1)
+    np.testing.assert_array_equal(p2, p1)
+
+
+def test_history_rules(pfm):
+    pb = _data(W.lorenz96(d=8, N=64, T=3))
+    pb2 = dataclasses.replace(pb, theta=np.array([[8.0, 0.1], [7.0, 0.2]]),
+                              n_particles=np.array([64, 64], dtype=np.int64))
+    f = pfm.Filter(pb2, layout=pfm.PF_LAYOUT_BATCHED)
+    with pytest.raises(pfm.PfError):
+        f.backtrace()  # nothing attached
+    f.attach_history()
+    p = pfm.Filter(pb2, layout=pfm.PF_LAYOUT_BATCHED)
+    with pytest.raises(pfm.PfError):
+        f.smc2(p, W.smc2_l96_inputs(pb2.theta, 3))
+    f.step()
+    with pytest.raises(pfm.PfError):
+        f.attach_history()  # only at t = 0
+    f.close()
+    p.close()

@@ -240,6 +240,41 @@ def large_filter_leg(torch, pfm, stream):
     return leg
 
 
+def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):
+    """The headline workload with ancestry storage attached (every interval
+    also copies its propagated particles and ancestors into the history),
+    then the state sample of every filter (Alg. 2, last lines)."""
+    f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    f.set_tuning(threads, groups)
+    f.attach_history()
+    r = Runner(f, pb.T)
+    r.run(pb.T)  # graph capture and first touch
+    f.reset(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.graph_run(pb.T)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    path, idx = f.backtrace()
+    dtb = time.perf_counter() - t1
+    hist_bytes = int(f.history.numel())
+    f.close()
+    n_tot = int(pb.n_particles.sum())
+    rec_bytes = n_tot * (2 * pb.d * 4 + 2 * 4)  # particles read + written, ancestors read + written
+    per = dt / pb.T
+    extra = per - dt_plain_interval
+    leg = {"workload": pb.name, "history_bytes": hist_bytes, "T": pb.T,
+           "us_per_interval_with_history": per * 1e6,
+           "us_per_interval_without": dt_plain_interval * 1e6,
+           "record_bytes_per_interval": rec_bytes,
+           "record_GBps_if_extra_time_is_recording": rec_bytes / extra / 1e9 if extra > 0 else None,
+           "backtrace_ms_all_filters": dtb * 1e3, "path_shape": list(path.shape)}
+    log(f"[bench] history: {per * 1e6:.1f} us/interval with recording ({hist_bytes / 2**30:.1f} GiB "
+        f"history) vs {dt_plain_interval * 1e6:.1f}; backtrace of {pb.B} filters {dtb * 1e3:.2f} ms")
+    return leg
+
+
 def smc2_leg(torch, pfm, pb, stream, T, threads, groups):
     """SMC over the parameters (Alg. 4) with the batched workload's filters as
     the theta-particles' attached filters (FP32 mixed).  Time i re-runs every
@@ -290,6 +325,8 @@ def main():
     ap.add_argument("--tf-steps", type=int, default=8, help="teacher-forced error intervals")
     ap.add_argument("--smc2-T", type=int, default=200,
                     help="observation times of the SMC^2 leg (0: skip it)")
+    ap.add_argument("--profile-path", action="store_true",
+                    help="run only the history / state-sample leg (for kernel traces)")
     ap.add_argument("--profile-smc2", action="store_true",
                     help="run only the SMC^2 leg (for kernel traces)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -341,6 +378,10 @@ def main():
     pb = pb.with_obs(y)
     n_tot = int(pb.n_particles.sum())
     log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
+    if args.profile_path:
+        print(json.dumps({"profile_path": path_leg(torch, pfm, pb, stream, 512, 2, 0.0)}),
+              flush=True)
+        return
     if args.profile_smc2:
         print(json.dumps({"profile_smc2": smc2_leg(torch, pfm, pb, stream, args.smc2_T, 512, 2)}),
               flush=True)
@@ -491,6 +532,11 @@ def main():
                                                 (pm.B * args.pmmh_iters))}
             log(f"[bench] pmmh: {nfilt / dtm:.1f} filters/s, accept "
                 f"{out['pmmh']['accept_rate']:.3f}")
+
+        # ------------------------------------------------------------ state sample
+        log("[bench] history leg starts")
+        out["state_sample"] = path_leg(torch, pfm, pb, stream, threads, groups,
+                                       dt32 / args.steps)
 
         # ------------------------------------------------------------ SMC^2
         if args.smc2_T > 0:

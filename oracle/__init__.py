@@ -89,6 +89,16 @@ def lib():
                                      _D, _D, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                      _D, _D, _I]),
             "orc_copy_index": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64, C.c_uint32]),
+            "orc_strat_u": (C.c_double, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
+                                         C.c_int64]),
+            "orc_stratified_ancestors": (None, [C.c_int64, _D, C.c_double, C.c_int64,
+                                                C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
+                                                _I]),
+            "orc_metropolis_ancestors": (None, [C.c_int64, _D, C.c_int32, C.c_uint64,
+                                                C.c_int32, C.c_uint32, C.c_uint32, _I]),
+            "orc_pf_run_ex": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
+                                          C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _I,
+                                          _D, _I, _D]),
             "orc_path_slot": (C.c_int64, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
                                           C.c_int64]),
             "orc_pf_path": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
@@ -354,3 +364,55 @@ def pf_path(pb, theta=None, N=None, b=0, it=0, T=None):
     st = lib().orc_pf_path(P.ref, _dp(th), N, b, it, T, C.byref(ll), _dp(path),
                            idx.ctypes.data_as(C.POINTER(C.c_int64)))
     return st, ll.value, path, idx
+
+
+RESAMPLE_SYSTEMATIC, RESAMPLE_STRATIFIED, RESAMPLE_METROPOLIS = 0, 1, 2
+
+
+def strat_u(seed, t, b, it, k) -> float:
+    return lib().orc_strat_u(int(seed), int(t), int(b), int(it), int(k))
+
+
+def stratified_ancestors(lw, seed, t, b=0, it=0):
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    N = lw.shape[0]
+    M = lw[lw == lw].max()
+    w = np.where(lw == lw, np.exp(lw - M), 0.0)
+    W = np.cumsum(w)  # sequential left-to-right sums, as the oracle takes them
+    acc = 0.0
+    for j in range(N):
+        acc = acc + w[j]
+        W[j] = acc
+    jstar = int(np.flatnonzero(w > 0)[-1])
+    a = np.zeros(N, dtype=np.int32)
+    lib().orc_stratified_ancestors(N, _dp(W), float(W[-1]), jstar, int(seed), int(t), int(b),
+                                   int(it), _ip(a))
+    return a
+
+
+def metropolis_ancestors(lw, steps, seed, t, b=0, it=0):
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    a = np.zeros(lw.shape[0], dtype=np.int32)
+    lib().orc_metropolis_ancestors(lw.shape[0], _dp(lw), int(steps), int(seed), int(t), int(b),
+                                   int(it), _ip(a))
+    return a
+
+
+def pf_run_ex(pb, theta=None, N=None, b=0, it=0, T=None, resampler=0, steps=0,
+              ess_frac=float("inf"), traces=False):
+    """Alg. 2 with a resampler choice and ESS-triggered resampling."""
+    P = _Prob(pb)
+    th = np.ascontiguousarray(pb.theta[b] if theta is None else theta, dtype=np.float64)
+    N = int(pb.n_particles[b] if N is None else N)
+    T = pb.T if T is None else T
+    ell, ess = np.zeros(T), np.zeros(T)
+    ll = C.c_double()
+    anc = np.zeros((T, N), dtype=np.int32) if traces else None
+    lwt = np.zeros((T, N)) if traces else None
+    res = np.zeros(T, dtype=np.int32)
+    xf = np.zeros((pb.d, N))
+    st = lib().orc_pf_run_ex(P.ref, _dp(th), N, b, it, T, int(resampler), int(steps),
+                             float(ess_frac), _dp(ell), _dp(ess), C.byref(ll), _ip(anc),
+                             _dp(lwt), _ip(res), _dp(xf))
+    return dict(status=st, ell=ell, ess=ess, loglik=ll.value, anc=anc, lw=lwt, resampled=res,
+                x=xf)

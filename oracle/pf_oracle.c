@@ -762,3 +762,177 @@ int32_t orc_pf_path(const orc_problem* P, const double* theta, int64_t N, uint32
   free(xh);
   return status;
 }
+
+/* ------------------------------------------------------------------------
+ * Resampling variants (Sec. 3.3 names multinomial, systematic and
+ * stratified resampling and points to resamplers that avoid the collective
+ * over the weights) and resampling triggered by the ESS.
+ * ------------------------------------------------------------------------ */
+
+/* Stratified offsets: u_k for stratum k is the uniform of word k mod 4 of the
+ * generator at counter (k div 4, t, tag RESAMPLE | block 1 | iteration, b). */
+double orc_strat_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k) {
+  uint32_t ctr[4] = {(uint32_t)(k >> 2), (uint32_t)t,
+                     ((uint32_t)ORC_TAG_RESAMPLE << 28) | (1u << 20) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return orc_u01(w[k & 3]);
+}
+
+/* The pair (j', u) of Metropolis step s (1-based) for output k: words 2r and
+ * 2r+1, r = (s-1) mod 2, of the generator at counter (k, t, tag RESAMPLE |
+ * block 2 + (s-1) div 2 | iteration, b); j' = floor(w N 2^-32), u the
+ * uniform of the second word. */
+static void metro_pair(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k,
+                       int32_t s, int64_t N, int64_t* jp, double* u) {
+  const uint32_t blk = 2u + (uint32_t)((s - 1) >> 1);
+  uint32_t ctr[4] = {(uint32_t)k, (uint32_t)t,
+                     ((uint32_t)ORC_TAG_RESAMPLE << 28) | (blk << 20) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  const int r = (s - 1) & 1;
+  *jp = (int64_t)(((uint64_t)w[2 * r] * (uint64_t)N) >> 32);
+  *u = orc_u01(w[2 * r + 1]);
+}
+
+/* M, the scan W of exp(lw - M) (NaN log-weights weigh 0), S = W_{N-1},
+ * S2 and the last positive index; returns 0 if no weight is positive. */
+static int weights_scan(int64_t N, const double* lw, double* M_out, double* W, double* S_out,
+                        double* S2_out, int64_t* jstar_out) {
+  double M = -INFINITY;
+  for (int64_t j = 0; j < N; ++j)
+    if (lw[j] > M) M = lw[j];
+  if (!(M > -INFINITY) || !(M < INFINITY)) return 0;
+  double acc = 0.0, acc2 = 0.0;
+  int64_t jstar = -1;
+  for (int64_t j = 0; j < N; ++j) {
+    double w = (lw[j] == lw[j]) ? exp(lw[j] - M) : 0.0;
+    acc = acc + w;
+    acc2 = acc2 + w * w;
+    W[j] = acc;
+    if (w > 0.0) jstar = j;
+  }
+  *M_out = M;
+  *S_out = acc;
+  *S2_out = acc2;
+  *jstar_out = jstar;
+  return 1;
+}
+
+/* Stratified resampling: a_k = min{ j : N W_j > (u_k + k) S } with the
+ * per-stratum offsets of orc_strat_u; rounding overflow goes to the last
+ * positive weight, as for systematic resampling. */
+void orc_stratified_ancestors(int64_t N, const double* W, double S, int64_t jstar,
+                              uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int32_t* a) {
+  const double Nd = (double)N;
+  int64_t j = 0;
+  for (int64_t k = 0; k < N; ++k) {
+    const double thr = (orc_strat_u(seed, t, b, iter, k) + (double)k) * S;
+    while (j < N && !(Nd * W[j] > thr)) ++j;
+    a[k] = (int32_t)(j < N ? j : jstar);
+  }
+}
+
+/* Metropolis resampling (a resampler without the collective): output k
+ * starts at particle k and takes `steps` Metropolis moves with uniform
+ * proposals j', accepted iff ln u <= lw_j' - lw_j (own ln, so both sides
+ * decide alike; a NaN log-weight counts as -inf).  Unsorted; tends to
+ * multinomial resampling as steps grows. */
+void orc_metropolis_ancestors(int64_t N, const double* lw, int32_t steps, uint64_t seed,
+                              int32_t t, uint32_t b, uint32_t iter, int32_t* a) {
+  for (int64_t k = 0; k < N; ++k) {
+    int64_t j = k;
+    double lj = (lw[j] == lw[j]) ? lw[j] : -INFINITY;
+    for (int32_t s = 1; s <= steps; ++s) {
+      int64_t jp;
+      double u;
+      metro_pair(seed, t, b, iter, k, s, N, &jp, &u);
+      const double lp = (lw[jp] == lw[jp]) ? lw[jp] : -INFINITY;
+      if (orc_ln(u) <= lp - lj) {
+        j = jp;
+        lj = lp;
+      }
+    }
+    a[k] = (int32_t)j;
+  }
+}
+
+/* Alg. 2 with a choice of resampler (0 systematic, 1 stratified, 2
+ * Metropolis with `steps` moves) and resampling only when ESS < ess_frac N
+ * (ess_frac = +inf: every time).  Without resampling the log-weights carry
+ * over: the time-t weights are carry + lw_t, the likelihood factor is
+ * ln sum exp(carry + lw_t) - ln sum exp(carry) (ln N after a resampling),
+ * and the ancestors are the identity.  lw_trace holds the carried
+ * log-weights; res_trace (optional) 1 where the time resampled. */
+int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                      uint32_t iter, int32_t T_run, int32_t resampler, int32_t steps,
+                      double ess_frac, double* ell, double* ess, double* loglik,
+                      int32_t* anc_trace, double* lw_trace, int32_t* res_trace,
+                      double* x_final) {
+  const int d = P->d;
+  double* x = (double*)malloc(sizeof(double) * (size_t)d * (size_t)N);
+  double* xp = (double*)malloc(sizeof(double) * (size_t)d * (size_t)N);
+  double* lw = (double*)malloc(sizeof(double) * (size_t)N);
+  double* carry = (double*)malloc(sizeof(double) * (size_t)N);
+  double* W = (double*)malloc(sizeof(double) * (size_t)N);
+  int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+  int32_t status = ORC_OK;
+  double ll = 0.0, L_prev = log((double)N);
+  orc_init(P, theta, N, b, iter, x);
+  for (int64_t j = 0; j < N; ++j) carry[j] = 0.0;
+  for (int32_t t = 1; t <= T_run; ++t) {
+    orc_propagate(P, theta, N, b, iter, t, x, xp);
+    orc_weight(P, theta, N, t, xp, lw);
+    for (int64_t j = 0; j < N; ++j) lw[j] = carry[j] + lw[j];
+    if (lw_trace) memcpy(lw_trace + (int64_t)(t - 1) * N, lw, sizeof(double) * (size_t)N);
+    double M, S, S2;
+    int64_t jstar;
+    int resample = 1;
+    if (!weights_scan(N, lw, &M, W, &S, &S2, &jstar)) {
+      status = ORC_NUMERIC;
+      ell[t - 1] = -INFINITY;
+      ess[t - 1] = 0.0;
+      for (int64_t k = 0; k < N; ++k) a[k] = (int32_t)k;
+    } else {
+      const double L = M + log(S);
+      ell[t - 1] = L - L_prev;
+      ess[t - 1] = (S * S) / S2;
+      resample = ess[t - 1] < ess_frac * (double)N;
+      if (!resample) {
+        for (int64_t k = 0; k < N; ++k) a[k] = (int32_t)k;
+        L_prev = L;
+      } else {
+        L_prev = log((double)N);
+        if (resampler == 1) {
+          orc_stratified_ancestors(N, W, S, jstar, P->seed, t, b, iter, a);
+        } else if (resampler == 2) {
+          orc_metropolis_ancestors(N, lw, steps, P->seed, t, b, iter, a);
+        } else {
+          const double u = orc_resample_u(P->seed, t, b, iter), Nd = (double)N;
+          int64_t j = 0;
+          for (int64_t k = 0; k < N; ++k) {
+            const double thr = (u + (double)k) * S;
+            while (j < N && !(Nd * W[j] > thr)) ++j;
+            a[k] = (int32_t)(j < N ? j : jstar);
+          }
+        }
+      }
+    }
+    ll = ll + ell[t - 1];
+    if (res_trace) res_trace[t - 1] = resample;
+    if (anc_trace) memcpy(anc_trace + (int64_t)(t - 1) * N, a, sizeof(int32_t) * (size_t)N);
+    orc_gather(d, N, xp, a, x);
+    for (int64_t j = 0; j < N; ++j) carry[j] = resample ? 0.0 : lw[j];
+  }
+  *loglik = (status == ORC_OK) ? ll : -INFINITY;
+  if (x_final) memcpy(x_final, x, sizeof(double) * (size_t)d * (size_t)N);
+  free(a);
+  free(W);
+  free(carry);
+  free(lw);
+  free(xp);
+  free(x);
+  return status;
+}

@@ -94,6 +94,18 @@ int32_t orc_pmmh(const orc_problem* P, int64_t N, int32_t chain0, int32_t n_chai
                  double f_hi, double sigma, double* log_f_trace /* [iters][n_chains] */,
                  double* ll_trace /* [iters][n_chains] */, int32_t* accepts /* [n_chains] */);
 
+/* resampling variants and ESS-triggered resampling */
+double orc_strat_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k);
+void orc_stratified_ancestors(int64_t N, const double* W, double S, int64_t jstar,
+                              uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int32_t* a);
+void orc_metropolis_ancestors(int64_t N, const double* lw, int32_t steps, uint64_t seed,
+                              int32_t t, uint32_t b, uint32_t iter, int32_t* a);
+int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
+                      uint32_t iter, int32_t T_run, int32_t resampler, int32_t steps,
+                      double ess_frac, double* ell, double* ess, double* loglik,
+                      int32_t* anc_trace, double* lw_trace, int32_t* res_trace,
+                      double* x_final);
+
 /* the single state sample of Alg. 2 (ancestry traced back) */
 int64_t orc_path_slot(uint64_t seed, int32_t s, uint32_t b, uint32_t iter, int64_t N);
 int32_t orc_pf_path(const orc_problem* P, const double* theta, int64_t N, uint32_t b,

@@ -1,0 +1,157 @@
+"""Pins for the oracle's resampling variants (Sec. 3.3: multinomial,
+systematic and stratified resampling, and resamplers that avoid the
+collective over the weights) and for resampling triggered by the ESS:
+
+* the general run with systematic resampling at every time equals the plain
+  filter run bit for bit;
+* stratified ancestors equal numpy's searchsorted of the strata (u_k + k) S
+  in N W (the same FP64 products), the offsets are the generator's uniforms,
+  offspring counts sum to N and stay within one of floor(b) - floor(a), and
+  their mean over many draws is N w_j (unbiased);
+* Metropolis resampling: no moves is the identity; equal weights give
+  uniform ancestors; with many moves the offspring mean approaches N w_j
+  (the chain's stationary law), which a reversed acceptance test fails;
+* ESS-triggered resampling: never resampling is sequential importance
+  sampling (likelihood = logsumexp of the accumulated log-weights - ln N,
+  identity ancestors, particles never gathered); the resampling flags follow
+  ESS < fraction N; stratified and ESS-triggered filters are unbiased for
+  the Kalman likelihood on the windkessel model.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+import scipy.stats
+
+import workloads as W
+
+
+def _data(orc, pb):
+    _, y = orc.simulate(pb)
+    return pb.with_obs(y)
+
+
+def _seq_cumsum(w):
+    out = np.empty_like(w)
+    acc = 0.0
+    for j in range(w.size):
+        acc = acc + w[j]
+        out[j] = acc
+    return out
+
+
+def test_general_run_reduces_to_the_plain_filter(orc):
+    pb = _data(orc, W.lorenz96(d=8, N=150, T=6))
+    r0 = orc.pf_run(pb, traces=True)
+    r1 = orc.pf_run_ex(pb, traces=True)
+    for k in ("ell", "ess", "anc", "lw", "x"):
+        np.testing.assert_array_equal(r1[k], r0[k], err_msg=k)
+    assert r1["loglik"] == r0["loglik"] and np.all(r1["resampled"] == 1)
+
+
+def test_stratified_offsets_are_the_generator_uniforms(orc):
+    for k in (0, 1, 2, 3, 4, 7, 1000):
+        w = orc.philox([k >> 2, 5, (orc.TAG_RESAMPLE << 28) | (1 << 20) | 2, 9], [3, 0])
+        assert orc.strat_u(3, 5, 9, 2, k) == orc.u01(int(w[k & 3]))
+
+
+@pytest.mark.parametrize("N", [1, 5, 64, 1000])
+def test_stratified_matches_searchsorted_and_counts(orc, N):
+    rng = np.random.default_rng(N)
+    lw = rng.normal(size=N) * 3.0
+    t, b, it = 4, 2, 1
+    a = orc.stratified_ancestors(lw, seed=11, t=t, b=b, it=it)
+    w = np.exp(lw - lw.max())
+    Wc = _seq_cumsum(w)
+    S = Wc[-1]
+    u = np.array([orc.strat_u(11, t, b, it, k) for k in range(N)])
+    ref = np.searchsorted(N * Wc, (u + np.arange(N)) * S, side="right")
+    np.testing.assert_array_equal(a, np.minimum(ref, N - 1))
+    cnt = np.bincount(a, minlength=N)
+    assert cnt.sum() == N and np.all(np.diff(a) >= 0)
+    hi = N * Wc / S
+    lo = np.concatenate([[0.0], hi[:-1]])
+    base = np.floor(hi) - np.floor(lo)
+    assert np.all(np.abs(cnt - base) <= 1)
+
+
+@pytest.mark.parametrize("weights", [[0.3, 0.7], [5, 1, 1, 1, 1, 1, 1, 1], [0.9, 0.01, 0.01, 0.08],
+                                     [1, 0, 0, 3, 0, 2, 2, 0]])
+def test_stratified_unbiased(orc, weights):
+    w = np.asarray(weights, dtype=np.float64)
+    N = w.size
+    with np.errstate(divide="ignore"):
+        lw = np.log(w)
+    R = 3000
+    cnt = np.array([np.bincount(orc.stratified_ancestors(lw, seed=5, t=t), minlength=N)
+                    for t in range(1, R + 1)])
+    target = N * w / w.sum()
+    sd = cnt.std(axis=0, ddof=1)
+    assert np.all(np.abs(cnt.mean(axis=0) - target) <= 4 * sd / math.sqrt(R) + 1e-9)
+    assert np.all(cnt[:, w == 0] == 0)
+
+
+def test_metropolis_limits(orc):
+    rng = np.random.default_rng(3)
+    lw = rng.normal(size=50)
+    np.testing.assert_array_equal(orc.metropolis_ancestors(lw, 0, seed=1, t=1), np.arange(50))
+    # equal weights: every proposal is accepted, the last one is uniform
+    N, R = 10, 400
+    a = np.concatenate([orc.metropolis_ancestors(np.zeros(N), 3, seed=2, t=t) for t in range(R)])
+    assert scipy.stats.chisquare(np.bincount(a, minlength=N)).pvalue > 1e-3
+
+
+def test_metropolis_tends_to_the_weights(orc):
+    w = np.array([0.05, 0.1, 0.15, 0.2, 0.5])
+    lw = np.log(w)
+    N, R, steps = w.size, 2000, 60
+    cnt = np.array([np.bincount(orc.metropolis_ancestors(lw, steps, seed=4, t=t), minlength=N)
+                    for t in range(1, R + 1)])
+    sd = cnt.std(axis=0, ddof=1)
+    assert np.all(np.abs(cnt.mean(axis=0) - N * w) <= 4 * sd / math.sqrt(R) + 0.01)
+    # a reversed acceptance rule would favour the light particles
+    rev = np.array([np.bincount(orc.metropolis_ancestors(-lw, steps, seed=4, t=t), minlength=N)
+                    for t in range(1, R + 1)])
+    assert rev.mean(axis=0)[-1] < N * w[-1] - 1.0
+
+
+def test_never_resampling_is_importance_sampling(orc):
+    pb = _data(orc, W.lorenz96(d=8, N=64, T=5))
+    r = orc.pf_run_ex(pb, ess_frac=0.0, traces=True)
+    assert np.all(r["resampled"] == 0)
+    assert np.all(r["anc"] == np.arange(64)[None, :])
+    ll = scipy.special.logsumexp(r["lw"][-1]) - math.log(64)
+    assert r["loglik"] == pytest.approx(ll, rel=1e-12)
+    x = orc.init(pb, pb.theta[0], 64)
+    for t in range(1, pb.T + 1):
+        x = orc.propagate(pb, pb.theta[0], x, t)
+    np.testing.assert_array_equal(r["x"], x)
+    # the carried log-weights are sums of the per-time log-densities
+    x = orc.init(pb, pb.theta[0], 64)
+    acc = np.zeros(64)
+    for t in range(1, pb.T + 1):
+        x = orc.propagate(pb, pb.theta[0], x, t)
+        acc = acc + orc.weight(pb, pb.theta[0], x, t)
+        np.testing.assert_array_equal(r["lw"][t - 1], acc)
+
+
+def test_ess_trigger_follows_the_ess(orc):
+    pb = _data(orc, W.windkessel(N=200, T=40))
+    r = orc.pf_run_ex(pb, ess_frac=0.5, traces=True)
+    np.testing.assert_array_equal(r["resampled"], (r["ess"] < 100.0).astype(np.int32))
+    assert 0 < r["resampled"].sum() < pb.T
+
+
+@pytest.mark.parametrize("resampler,ess_frac", [(1, float("inf")), (0, 0.5), (1, 0.5)])
+def test_variants_unbiased_against_kalman(orc, resampler, ess_frac):
+    pb = W.windkessel(N=128, T=30)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    ll_kf, _ = orc.kf_wk(pb)
+    R = 200
+    lls = np.array([orc.pf_run_ex(dataclasses.replace(pb, seed=s), resampler=resampler,
+                                  ess_frac=ess_frac)["loglik"] for s in range(R)])
+    ratio = np.exp(lls - ll_kf)
+    assert abs(ratio.mean() - 1.0) < 4 * ratio.std(ddof=1) / math.sqrt(R) + 1e-3

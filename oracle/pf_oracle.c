@@ -891,10 +891,12 @@ int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint
     int64_t jstar;
     int resample = 1;
     if (!weights_scan(N, lw, &M, W, &S, &S2, &jstar)) {
+      /* no positive weight: identity ancestors and uniform weights after it */
       status = ORC_NUMERIC;
       ell[t - 1] = -INFINITY;
       ess[t - 1] = 0.0;
       for (int64_t k = 0; k < N; ++k) a[k] = (int32_t)k;
+      L_prev = log((double)N);
     } else {
       const double L = M + log(S);
       ell[t - 1] = L - L_prev;

@@ -162,6 +162,35 @@ pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 pf_status pf_set_theta(pf_handle* h, const double* theta, uint32_t iteration);
 pf_status pf_reset(pf_handle* h, uint32_t iteration);
 
+/* ---- resampling variants ------------------------------------------------ */
+/* Which resampler the filters use and when (Sec. 3.3 names multinomial,
+ * systematic and stratified resampling and resamplers that avoid the
+ * collective over the weights).  Takes effect from the next interval;
+ * synchronous (rebuilds captured graphs).
+ *   PF_RESAMPLE_SYSTEMATIC (default): one uniform u per filter and time,
+ *     a_k = min{j : N W_j > (u + k) S}.
+ *   PF_RESAMPLE_STRATIFIED: one uniform u_k per stratum (word k mod 4 of the
+ *     generator at (k div 4, t, tag 3 | block 1 | iteration, b)),
+ *     a_k = min{j : N W_j > (u_k + k) S}; sorted like systematic.
+ *   PF_RESAMPLE_METROPOLIS: output k starts at particle k and takes `steps`
+ *     Metropolis moves (<= PF_METROPOLIS_MAX_STEPS): proposal j' =
+ *     floor(w N 2^-32), accepted iff ln u <= lw_j' - lw_j (ln by the same
+ *     atanh series as the normals), move s using words 2r, 2r+1,
+ *     r = (s-1) mod 2, of the generator at (k, t, tag 3 | block
+ *     2 + (s-1) div 2 | iteration, b).  No scan or counts; unsorted; tends
+ *     to multinomial resampling as steps grows.
+ * ess_frac: resample only when ESS < ess_frac N (+inf: every time).  A time
+ * that does not resample keeps its log-weights (the next interval adds to
+ * them), its likelihood factor is ln sum exp(carried + new) - ln sum
+ * exp(carried) (ln N after a resampling), and its ancestors are the
+ * identity.  pf_resample_u needs the default; pf_smc2 and pf_backtrace need
+ * ess_frac = +inf. */
+#define PF_RESAMPLE_SYSTEMATIC 0
+#define PF_RESAMPLE_STRATIFIED 1
+#define PF_RESAMPLE_METROPOLIS 2
+#define PF_METROPOLIS_MAX_STEPS 508
+pf_status pf_set_resampler(pf_handle* h, int32_t scheme, int32_t steps, double ess_frac);
+
 /* ---- ancestry storage and the state sample ------------------------------- */
 /* The bootstrap filter's single state sample x'(t_{0:s}) (Alg. 2, last lines;
  * Sec. 3.1.2): one particle drawn from the final weights and traced back

@@ -20,6 +20,7 @@ PF_MODEL_WK, PF_MODEL_L96 = 1, 2
 PF_FP64, PF_FP32_MIXED = 0, 1
 PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
 PF_BATCHED_MAX_PARTICLES = 8192
+PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_STRATIFIED, PF_RESAMPLE_METROPOLIS = 0, 1, 2
 
 _STATUS = {1: "PF_E_INVAL", 2: "PF_E_DEVICE", 3: "PF_E_STATE", 4: "PF_E_NUMERIC"}
 
@@ -97,6 +98,7 @@ SIGNATURES = {
                               C.c_void_p]),
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
+    "pf_set_resampler": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double]),
     "pf_history_bytes": (C.c_size_t, [C.POINTER(PfConfig)]),
     "pf_history_attach": (C.c_int, [_H, C.c_void_p, C.c_size_t]),
     "pf_backtrace": (C.c_int, [_H, _D, _I]),
@@ -257,6 +259,11 @@ class Filter:
                               inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
                               _ip(acc)))
         return dict(log_f=lft, ll=llt, accepts=acc)
+
+    # -- resampling variants
+    def set_resampler(self, scheme: int = PF_RESAMPLE_SYSTEMATIC, steps: int = 0,
+                      ess_frac: float = float("inf")):
+        _check(load().pf_set_resampler(self.h, int(scheme), int(steps), float(ess_frac)))
 
     # -- ancestry storage and the state sample (Alg. 2, last lines)
     def attach_history(self, device: str = "cuda"):

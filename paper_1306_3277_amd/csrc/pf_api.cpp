@@ -236,6 +236,8 @@ struct pf_handle {
   hipStream_t cap_stream = nullptr;
   // attached history (ancestry storage), or null
   char* hist = nullptr;
+  // resampling variant and ESS trigger (default: systematic, every time)
+  pfk::ResampleArgs rs{pfk::RS_SYSTEMATIC, 0, INFINITY};
   bool alive = true;
 
   template <typename T>
@@ -276,6 +278,7 @@ PlainArgs plain_args(const pf_handle* H, int b) {
   a.fs = H->at<FilterState>(H->L.fs) + b;
   a.ell_tr = H->at<double>(H->L.ell) + (size_t)b * c.T;
   a.ess_tr = H->at<double>(H->L.ess) + (size_t)b * c.T;
+  a.rs = H->rs;
   return a;
 }
 
@@ -311,6 +314,7 @@ BatchArgs batch_args(const pf_handle* H) {
   a.ess_tr = H->at<double>(H->L.ess);
   a.u_override = H->at<double>(H->L.b_u);
   a.mode = 0;
+  a.rs = H->rs;
   return a;
 }
 
@@ -520,16 +524,24 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     hipEvent_t e0{};
     pf_status st = ev_begin(H, &e0, s);
     if (st) return st;
-    HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
-                                   H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
-                                   H->at<int32_t>(H->L.bjs), a, s));
-    if ((st = ev_end(H, e0, 2, s))) return st;
-    if ((st = ev_begin(H, &e0, s))) return st;
-    HIP_TRY(pfk::launch_merge_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.counts),
-                                     H->at<int32_t>(H->L.bstate), H->at<int32_t>(H->L.bjs),
-                                     H->ws + H->L.x_tmp,
-                                     H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
-    if ((st = ev_end(H, e0, 3, s))) return st;
+    if (H->rs.scheme == pfk::RS_METROPOLIS) {
+      // no scan, counts or merge: unsorted ancestors and a plain gather
+      HIP_TRY(pfk::launch_metropolis_gather(c.precision, H->at<double>(H->L.lw),
+                                            H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
+                                            H->at<int32_t>(H->L.anc), a, s));
+      if ((st = ev_end(H, e0, 3, s))) return st;
+    } else {
+      HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
+                                     H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
+                                     H->at<int32_t>(H->L.bjs), a, s));
+      if ((st = ev_end(H, e0, 2, s))) return st;
+      if ((st = ev_begin(H, &e0, s))) return st;
+      HIP_TRY(pfk::launch_merge_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.counts),
+                                       H->at<int32_t>(H->L.bstate), H->at<int32_t>(H->L.bjs),
+                                       H->ws + H->L.x_tmp,
+                                       H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
+      if ((st = ev_end(H, e0, 3, s))) return st;
+    }
     if (H->hist)
       HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + H->L.x_tmp, H->at<int32_t>(H->L.anc),
                                        hist_args(H), a.off, a.N, a.fs, s));
@@ -810,6 +822,8 @@ pf_status pf_resample_u(pf_handle* H, const double* u) {
   pf_status st = check_handle(H);
   if (st) return st;
   if (!u) return fail(PF_E_INVAL, "u is NULL");
+  if (H->rs.scheme != pfk::RS_SYSTEMATIC || std::isfinite(H->rs.ess_frac))
+    return fail(PF_E_STATE, "pf_resample_u needs systematic resampling at every time");
   for (int b = 0; b < H->cfg.B; ++b)
     if (!(u[b] >= 0.0 && u[b] < 1.0)) return fail(PF_E_INVAL, "u[%d] must lie in [0, 1)", b);
   if (H->phase != 1) return fail(PF_E_STATE, "pf_resample_u needs a preceding pf_step");
@@ -1179,6 +1193,8 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   if (H->stream != P->stream) return fail(PF_E_INVAL, "both handles must use the same stream");
   if (H->hist || P->hist)
     return fail(PF_E_STATE, "pf_smc2 does not keep histories: detach them first");
+  if (std::isfinite(H->rs.ess_frac) || std::isfinite(P->rs.ess_frac))
+    return fail(PF_E_STATE, "pf_smc2 needs resampling at every time (equally weighted filters)");
   if (c.B > pfk::SMC2_MAXB) return fail(PF_E_INVAL, "at most %d theta-particles", pfk::SMC2_MAXB);
   if (c.n_theta > 8) return fail(PF_E_INVAL, "at most 8 parameters");
   const int32_t T = in->T_run;
@@ -1351,6 +1367,8 @@ pf_status pf_backtrace(pf_handle* H, double* path_out, int32_t* idx_out) {
   if (!H->hist) return fail(PF_E_STATE, "no history attached");
   if (!path_out) return fail(PF_E_INVAL, "path_out is NULL");
   if (H->phase != 0) return fail(PF_E_STATE, "pf_backtrace needs a resampled particle set");
+  if (std::isfinite(H->rs.ess_frac))
+    return fail(PF_E_STATE, "pf_backtrace needs resampling at every time");
   const pf_config& c = H->cfg;
   const HistLayout L = hist_layout(&c, H->L.n_total);
   const int32_t t = H->t;
@@ -1374,6 +1392,23 @@ pf_status pf_backtrace(pf_handle* H, double* path_out, int32_t* idx_out) {
       std::memcpy(idx_out + (size_t)b * (t + 1), idx.data() + (size_t)b * (c.T + 1),
                   4 * (size_t)(t + 1));
   }
+  return PF_OK;
+}
+
+pf_status pf_set_resampler(pf_handle* H, int32_t scheme, int32_t steps, double ess_frac) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (scheme != PF_RESAMPLE_SYSTEMATIC && scheme != PF_RESAMPLE_STRATIFIED &&
+      scheme != PF_RESAMPLE_METROPOLIS)
+    return fail(PF_E_INVAL, "unknown resampler %d", scheme);
+  if (steps < 0 || steps > PF_METROPOLIS_MAX_STEPS)
+    return fail(PF_E_INVAL, "steps must be in [0, %d]", PF_METROPOLIS_MAX_STEPS);
+  if (!(ess_frac >= 0.0)) return fail(PF_E_INVAL, "ess_frac must be >= 0 (or +inf)");
+  if ((st = drain(H))) return st;
+  destroy_graphs(H);
+  H->rs.scheme = scheme;
+  H->rs.steps = steps;
+  H->rs.ess_frac = ess_frac;
   return PF_OK;
 }
 

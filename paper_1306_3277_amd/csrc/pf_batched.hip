@@ -135,6 +135,8 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
     for (int i = 0; i < D; ++i) xn[(int64_t)i * A.ld + dst] = x[i];
     l = batch_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
   }
+  // weights kept from a step that did not resample carry over
+  if (A.fs[f].carry) l = lw[dst] + l;
   lw[dst] = l;
 }
 
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // flight, off the critical path.  64 KB of LDS per workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 
-template <int NT>
+template <int NT, int RS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
                                                        BatchArgs A) {
@@ -166,6 +168,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   __shared__ double xa[NW], xb[NW], xc[NW], xm[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
+  __shared__ int brs;
   uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
   int32_t* al = reinterpret_cast<int32_t*>(stage) + BATCH_MAXN / 2;   // ancestors, 32 KB
   const FilterSlot slot = A.order[A.order0 + blockIdx.x];
@@ -252,7 +255,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   }
   // a lane's particles own about N run / S strata: write them per particle
   // unless some lane would own far more than its share (4P)
-  const bool per_particle = !finite || runmax * (double)N <= (double)(4 * P - 2) * S;
+  const bool per_particle_w = runmax * (double)N <= (double)(4 * P - 2) * S;
   // exclusive running maximum of the lanes' last cumulative weights
   const double vlast = (i1 > i0) ? pre + run : -INFINITY;
   const double vin = wave_incl_max_scan(vlast, lane);
@@ -268,16 +271,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   vprev = (lane == 0) ? vw : fmax(vprev, vw);
   S = fmax(S, vall);
   if (threadIdx.x == 0) {
+    int carry = 0;
     if (!resample_only) {
       double ell, ess;
+      // the factor's normaliser: ln N after a resampling, else the carried
+      // weights' ln sum exp
+      const double lprev = fs->carry ? fs->lprev : log((double)N);
       if (finite && S > 0.0) {
-        ell = (M + log(S)) - log((double)N);
+        const double L = M + log(S);
+        ell = L - lprev;
         ess = (S * S) / S2;
+        carry = !(ess < A.rs.ess_frac * (double)N);  // resample when ESS < ess_frac N
+        fs->lprev = L;
       } else {
         ell = -INFINITY;
         ess = 0.0;
         fs->status = 4;
       }
+      fs->carry = carry;
       fs->loglik = loglik0 + ell;
       fs->M = finite ? M : -INFINITY;
       fs->S = S;
@@ -289,17 +300,61 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       fs->t = t;
     }
     bc = u;
+    brs = !carry;
   }
   __syncthreads();  // 5
   u = bc;
+  // a step that keeps its weights, or has none positive, gives every
+  // particle one offspring: itself
+  const bool draw_rs = finite && brs;
   const double invS = 1.0 / S;
+  if constexpr (RS == RS_METROPOLIS) {
+    // Metropolis resampling from the staged log-weights, no counts or merge:
+    // output k starts at particle k and takes A.rs.steps moves
+    const Key key = bkey(A.key);
+    const uint32_t it = fs->iter;
+#pragma unroll 1
+    for (int k = (int)threadIdx.x; k < N; k += NT) {
+      int j = k;
+      if (draw_rs) {
+        double lj = stage[stage_slot(j)];
+        for (int s1 = 1; s1 <= A.rs.steps; s1 += 2) {
+          const uint4 w = metro_draw(key, t, (uint32_t)f, it, k, s1);
+          int jp = metro_index(w.x, N);
+          double lp = stage[stage_slot(jp)];
+          if (ln_f64(u01_f64(w.y)) <= lp - lj) {
+            j = jp;
+            lj = lp;
+          }
+          if (s1 + 1 <= A.rs.steps) {
+            jp = metro_index(w.z, N);
+            lp = stage[stage_slot(jp)];
+            if (ln_f64(u01_f64(w.w)) <= lp - lj) {
+              j = jp;
+              lj = lp;
+            }
+          }
+        }
+      }
+      anc[off + k] = j;
+    }
+    return;
+  }
+  const bool per_particle = !draw_rs || per_particle_w;
   // (3) stratum counts of this lane's particles, to LDS
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int i = i0 + e;
     if (e < P && i < i1) {
       const double W = fmin(fmax(pre + loc[e], vprev), S);
-      sc[i] = (uint16_t)(finite ? stratum_count(W, S, invS, u, N) : i + 1);
+      int32_t c = i + 1;
+      if (draw_rs) {
+        if constexpr (RS == RS_STRATIFIED)
+          c = stratum_count_strat(W, S, invS, N, bkey(A.key), t, (uint32_t)f, fs->iter);
+        else
+          c = stratum_count(W, S, invS, u, N);
+      }
+      sc[i] = (uint16_t)c;
     }
   }
   __syncthreads();  // 6
@@ -447,19 +502,29 @@ hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const
                                    int nfilters, hipStream_t s) {
   if (nfilters <= 0) return hipSuccess;
   const unsigned g = (unsigned)nfilters;
+#define PF_K5B(NTV, RSV) hipLaunchKernelGGL((k_batch_resample<NTV, RSV>), g, NTV, 0, s, lw, anc, a)
+#define PF_K5B_RS(NTV)                                        \
+  switch (a.rs.scheme) {                                      \
+    case RS_SYSTEMATIC: PF_K5B(NTV, RS_SYSTEMATIC); break;    \
+    case RS_STRATIFIED: PF_K5B(NTV, RS_STRATIFIED); break;    \
+    case RS_METROPOLIS: PF_K5B(NTV, RS_METROPOLIS); break;    \
+    default: return hipErrorInvalidValue;                     \
+  }
   switch (nt) {
     case 256:
-      hipLaunchKernelGGL((k_batch_resample<256>), g, 256, 0, s, lw, anc, a);
+      PF_K5B_RS(256);
       break;
     case 512:
-      hipLaunchKernelGGL((k_batch_resample<512>), g, 512, 0, s, lw, anc, a);
+      PF_K5B_RS(512);
       break;
     case 1024:
-      hipLaunchKernelGGL((k_batch_resample<1024>), g, 1024, 0, s, lw, anc, a);
+      PF_K5B_RS(1024);
       break;
     default:
       return hipErrorInvalidValue;
   }
+#undef PF_K5B_RS
+#undef PF_K5B
   return hipGetLastError();
 }
 

@@ -498,4 +498,47 @@ __device__ __forceinline__ int32_t stratum_count(double W, double S, double invS
   return est;
 }
 
+// ---------------------------------------------------------------- resampling variants
+
+// Stratified offset of stratum k: the uniform of word k mod 4 of the
+// generator at (k div 4, t, tag RESAMPLE | block 1 | iteration, b).
+__device__ __forceinline__ double strat_u(Key key, int32_t t, uint32_t b, uint32_t iter,
+                                          int32_t k) {
+  const uint4 w = draw(key, TAG_RESAMPLE, 1, iter, (uint32_t)k >> 2, (uint32_t)t, b);
+  const uint32_t r = k & 3;
+  return u01_f64(r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w);
+}
+
+// Number of strata k in [0, N) with (u_k + k) S < N W for the stratified
+// offsets u_k (k + u_k is non-decreasing in k, so these strata are a
+// prefix).  Starts from floor(N W / S) and steps with the exact product
+// comparisons, each drawing the offset it needs.
+__device__ __forceinline__ int32_t stratum_count_strat(double W, double S, double invS,
+                                                       int32_t N, Key key, int32_t t, uint32_t b,
+                                                       uint32_t iter) {
+  const double Nd = (double)N;
+  const double NW = Nd * W;
+  int32_t est = (int32_t)__builtin_floor(fmin(fmax(NW * invS, 0.0), Nd));
+  if (est < N && (strat_u(key, t, b, iter, est) + (double)est) * S < NW) {
+    ++est;
+    while (est < N && (strat_u(key, t, b, iter, est) + (double)est) * S < NW) ++est;
+  } else {
+    while (est > 0 && !((strat_u(key, t, b, iter, est - 1) + (double)(est - 1)) * S < NW)) --est;
+  }
+  return est;
+}
+
+// Proposal j' and uniform u of Metropolis move s (1-based) of output k:
+// words 2r and 2r+1, r = (s-1) mod 2, of the generator at (k, t, tag
+// RESAMPLE | block 2 + (s-1) div 2 | iteration, b); j' = floor(w N 2^-32).
+// Moves s and s+1 (s odd) share one draw.
+__device__ __forceinline__ uint4 metro_draw(Key key, int32_t t, uint32_t b, uint32_t iter,
+                                            int32_t k, int32_t s) {
+  return draw(key, TAG_RESAMPLE, 2u + (uint32_t)((s - 1) >> 1), iter, (uint32_t)k, (uint32_t)t,
+              b);
+}
+__device__ __forceinline__ int32_t metro_index(uint32_t w, int32_t N) {
+  return (int32_t)(((uint64_t)w * (uint64_t)N) >> 32);
+}
+
 }  // namespace pfk

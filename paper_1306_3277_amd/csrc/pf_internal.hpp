@@ -18,6 +18,20 @@ struct FilterState {
   int32_t status; // 0, or 4 once a step had no positive finite weight (sticky)
   uint32_t iter;  // generator iteration field of the current run
   int32_t pad;    // nonzero if the resampler met an inconsistency (never expected)
+  double lprev;   // ln sum exp(carried log-weights) when carry is set
+  int32_t carry;  // 1 if the last step kept its weights (ESS above the trigger)
+  int32_t pad2;
+};
+
+// Resampling variants: the ancestors of a resampling time.
+enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2 };
+
+// How a filter resamples: the variant, its Metropolis moves, and the ESS
+// trigger (resample when ESS < ess_frac N; +inf: every time).
+struct ResampleArgs {
+  int32_t scheme;
+  int32_t steps;
+  double ess_frac;
 };
 
 struct KeyArg {
@@ -45,6 +59,7 @@ struct PlainArgs {
   FilterState* fs;        // this filter's scalars
   double* ell_tr;         // this filter's trace rows [T]
   double* ess_tr;
+  ResampleArgs rs;
 };
 
 // One filter of a batched collective launch: its index, first particle and
@@ -75,6 +90,7 @@ struct BatchArgs {
   double* ess_tr;
   const double* u_override; // device [B] (resample-only mode)
   int32_t mode;             // 0: likelihood + ancestors; 1: ancestors only, given u
+  ResampleArgs rs;
 };
 
 constexpr int K1_NT = 256;  // particles per propagate / scan block
@@ -101,6 +117,8 @@ hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts
                                const int32_t* bstate, const int32_t* bjs, const void* xprop,
                                void* xcur, int32_t* anc, const PlainArgs& a, hipStream_t s);
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
+hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
+                                   int32_t* anc, const PlainArgs& a, hipStream_t s);
 hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, double obs_sd,
                            hipStream_t s);
 // ---- batched (pf_batched.hip) ----

@@ -61,6 +61,9 @@ __global__ void k_reset(FilterState* fs, double* ell, double* ess, int B, int T,
     f.status = 0;
     f.iter = iter;
     f.pad = 0;
+    f.lprev = 0.0;
+    f.carry = 0;
+    f.pad2 = 0;
     fs[i] = f;
   }
 }
@@ -149,6 +152,8 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
       for (int i = 0; i < D; ++i) xprop[(int64_t)i * A.ld + col] = x[i];
       l = l96_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
     }
+    // weights kept from a step that did not resample carry over
+    if (A.fs->carry) l = lw[col] + l;
     lw[col] = l;
   }
   // a NaN log-weight counts as zero weight
@@ -304,14 +309,22 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
     bo[nb] = Sf;
     FilterState* f = fst;
     double ell, ess;
+    // the factor's normaliser: ln N after a resampling, else the carried
+    // weights' ln sum exp
+    const double lprev = f->carry ? f->lprev : log((double)A.N);
+    int carry = 0;
     if (finite && Sf > 0.0) {
-      ell = (M + log(Sf)) - log((double)A.N);
+      const double L = M + log(Sf);
+      ell = L - lprev;
       ess = (Sf * Sf) / S2;
+      carry = !(ess < A.rs.ess_frac * (double)A.N);  // resample when ESS < ess_frac N
+      f->lprev = L;
     } else {
       ell = -INFINITY;
       ess = 0.0;
       f->status = 4;
     }
+    f->carry = carry;
     f->loglik = loglik0 + ell;
     f->M = finite ? M : -INFINITY;
     f->S = Sf;
@@ -363,8 +376,18 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const FilterState* f = A.fs;
   const double M = f->M, S = f->S, u = f->u;
-  const bool finite = (M > -INFINITY) && (M < INFINITY) && (S > 0.0);
+  // a step that keeps its weights (ESS above the trigger) or has none
+  // positive gives every particle one offspring: itself
+  const bool finite = (M > -INFINITY) && (M < INFINITY) && (S > 0.0) && !f->carry;
   const double invS = 1.0 / S;
+  const bool strat = A.rs.scheme == RS_STRATIFIED;
+  const Key key = key_of(A.key);
+  const int32_t t_now = f->t;
+  const uint32_t it_now = f->iter;
+  auto count = [&](double W) -> int64_t {
+    return strat ? stratum_count_strat(W, S, invS, (int32_t)N, key, t_now, A.b, it_now)
+                 : stratum_count(W, S, invS, u, (int32_t)N);
+  };
   const double* bo = boff + A.boff0 + A.b;
   const int k1b = (int)blockIdx.x * (K3_SPAN / K1_NT);  // first K1 block of this block
   const double lo_off = bo[k1b];
@@ -405,13 +428,13 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
   for (int e = 0; e < K3_PER; ++e) {
     const int64_t j = j0 + e;
     const double W = fmin(fmax(V[e], vprev), hi_off);
-    c[e] = (j < N) ? (finite ? stratum_count(W, S, invS, u, N) : j + 1) : 0;
+    c[e] = (j < N) ? (finite ? count(W) : j + 1) : 0;
     if (j < N) counts[A.off + j] = (int32_t)c[e];
   }
   // merge-path states on the K4 block boundaries (see above)
-  const int64_t g_lo = finite ? stratum_count(lo_off, S, invS, u, N) : jb;
+  const int64_t g_lo = finite ? count(lo_off) : jb;
   const int64_t jnext = jb + K3_SPAN;
-  const int64_t g_hi = (jnext < N) ? (finite ? stratum_count(hi_off, S, invS, u, N) : jnext) : N;
+  const int64_t g_hi = (jnext < N) ? (finite ? count(hi_off) : jnext) : N;
   int64_t cprev = __shfl_up(c[K3_PER - 1], 1, WAVE);
   if (lane == WAVE - 1) wlast[wv] = c[K3_PER - 1];
   __syncthreads();
@@ -566,6 +589,61 @@ __global__ __launch_bounds__(K4_NT) void k_merge_gather(const int32_t* __restric
   if (bad) atomicOr(&A.fs->pad, 1);
 }
 
+// ---------------------------------------------------------------- Metropolis resampling
+// A resampler without the collective over the weights: output k starts at
+// particle k and takes A.rs.steps Metropolis moves with uniform proposals,
+// reading the FP64 log-weights directly (a NaN counts as -inf).  A step that
+// keeps its weights, or has none positive, gives the identity.
+__global__ __launch_bounds__(K1_NT) void k_metropolis(const double* __restrict__ lw,
+                                                      int32_t* __restrict__ anc, PlainArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  if (k >= A.N) return;
+  const FilterState* f = A.fs;
+  const bool draw_rs = (f->M > -INFINITY) && (f->M < INFINITY) && (f->S > 0.0) && !f->carry;
+  const double* l = lw + A.off;
+  const int32_t N = (int32_t)A.N;
+  int32_t j = (int32_t)k;
+  if (draw_rs) {
+    const Key key = key_of(A.key);
+    const int32_t t = f->t;
+    const uint32_t it = f->iter;
+    double lj = l[j];
+    lj = (lj == lj) ? lj : -INFINITY;
+    for (int s = 1; s <= A.rs.steps; s += 2) {
+      const uint4 w = metro_draw(key, t, A.b, it, (int32_t)k, s);
+      int32_t jp = metro_index(w.x, N);
+      double lp = l[jp];
+      lp = (lp == lp) ? lp : -INFINITY;
+      if (ln_f64(u01_f64(w.y)) <= lp - lj) {
+        j = jp;
+        lj = lp;
+      }
+      if (s + 1 <= A.rs.steps) {
+        jp = metro_index(w.z, N);
+        lp = l[jp];
+        lp = (lp == lp) ? lp : -INFINITY;
+        if (ln_f64(u01_f64(w.w)) <= lp - lj) {
+          j = jp;
+          lj = lp;
+        }
+      }
+    }
+  }
+  anc[A.off + k] = j;
+}
+
+// x_cur[k] = x_prop[a_k] for unsorted ancestors.
+template <typename Real>
+__global__ __launch_bounds__(K1_NT) void k_anc_gather(const Real* __restrict__ xprop,
+                                                      Real* __restrict__ xcur,
+                                                      const int32_t* __restrict__ anc,
+                                                      PlainArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  if (k >= A.N) return;
+  const int64_t src = A.off + anc[A.off + k];
+  for (int i = 0; i < A.d; ++i) xcur[(int64_t)i * A.ld + A.off + k] = xprop[(int64_t)i * A.ld + src];
+}
+
 // ---------------------------------------------------------------- simulator
 template <int MODEL, int D>
 __global__ void k_simulate(double* __restrict__ out, PlainArgs A, double obs_sd) {
@@ -715,6 +793,19 @@ hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
+                                   int32_t* anc, const PlainArgs& a, hipStream_t s) {
+  const unsigned g = nblocks(a.N, K1_NT);
+  hipLaunchKernelGGL(k_metropolis, g, K1_NT, 0, s, lw, anc, a);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
+                       (double*)xcur, (const int32_t*)anc, a);
+  else
+    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
+                       (const int32_t*)anc, a);
   return hipGetLastError();
 }
 

@@ -215,6 +215,12 @@ def large_filter_leg(torch, pfm, stream):
     rb.run(3)
     kb = kernel_times(rb, 10)
     dtb = timed(torch, rb, 20, 2)
+    variants = {}
+    for name, scheme, msteps in (("stratified", 1, 0), ("metropolis_8", 2, 8)):
+        fb.set_resampler(scheme, msteps)
+        rb.restart()
+        kv = kernel_times(rb, 10)
+        variants[name] = {"resample_gather_us": kv["scan"] + kv["gather"]}
     fb.close()
     nb = int(big.n_particles[0])
     rs_us = kb["scan"] + kb["gather"]
@@ -233,11 +239,36 @@ def large_filter_leg(torch, pfm, stream):
                       "unit": "TOP/s", "frac": ach_b / VALU_PEAK_TOPS,
                       "us": kb["propagate"], "ops_per_particle_step": slots_b},
         "combine_us": kb["combine"],
+        "resample_variants": variants,
     }
+    log("[bench] large filter resample+gather variants (us): " +
+        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants.items()))
     log(f"[bench] large filter: resample+gather {rs_us:.1f} us = {gbs:.0f} GB/s "
         f"({gbs / HBM_PEAK_GBS:.0%}); propagate {kb['propagate']:.1f} us "
         f"({ach_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
     return leg
+
+
+RESAMPLER_CASES = [("systematic", 0, 0, float("inf")), ("stratified", 1, 0, float("inf")),
+                   ("metropolis_8", 2, 8, float("inf")), ("systematic_ess0.5", 0, 0, 0.5)]
+
+
+def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=100):
+    """Interval time of the batched workload (FP32 mixed, graph replay) with
+    each resampling variant."""
+    out = {}
+    for name, scheme, msteps, frac in RESAMPLER_CASES:
+        f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+        f.set_tuning(threads, groups)
+        f.set_resampler(scheme, msteps, frac)
+        r = Runner(f, pb.T)
+        dt = timed(torch, r, steps, 10)
+        f.close()
+        out[name] = {"us_per_interval": dt / steps * 1e6,
+                     "particle_steps_per_s": int(pb.n_particles.sum()) * steps / dt}
+    log("[bench] resamplers (batched, us/interval): " +
+        ", ".join(f"{k} {v['us_per_interval']:.1f}" for k, v in out.items()))
+    return out
 
 
 def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):
@@ -532,6 +563,10 @@ def main():
                                                 (pm.B * args.pmmh_iters))}
             log(f"[bench] pmmh: {nfilt / dtm:.1f} filters/s, accept "
                 f"{out['pmmh']['accept_rate']:.3f}")
+
+        # ------------------------------------------------------------ resamplers
+        log("[bench] resampler leg starts")
+        out["resamplers_batched"] = resampler_leg(torch, pfm, pb, stream, threads, groups)
 
         # ------------------------------------------------------------ state sample
         log("[bench] history leg starts")

@@ -89,6 +89,10 @@ def lib():
                                      _D, _D, _D, C.c_double, C.c_double, C.c_double, C.c_double,
                                      _D, _D, _I]),
             "orc_copy_index": (C.c_int64, [C.c_int64, C.c_int64, C.c_int64, C.c_uint32]),
+            "orc_kf_wk_interval": (C.c_double, [P, _D, C.c_int32, _D, _D]),
+            "orc_smc2_kalman": (C.c_int32, [P, C.c_int32, C.c_int32, _D, C.c_int32, _D, _D, _D,
+                                            _D, _D, _D, _D, _D, _D, _I, _D, _D, _I, _I, _D,
+                                            _D]),
             "orc_strat_u": (C.c_double, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
                                          C.c_int64]),
             "orc_stratified_ancestors": (None, [C.c_int64, _D, C.c_double, C.c_int64,
@@ -416,3 +420,37 @@ def pf_run_ex(pb, theta=None, N=None, b=0, it=0, T=None, resampler=0, steps=0,
                              _dp(lwt), _ip(res), _dp(xf))
     return dict(status=st, ell=ell, ess=ess, loglik=ll.value, anc=anc, lw=lwt, resampled=res,
                 x=xf)
+
+
+def kf_wk_interval(pb, theta, t, m, V):
+    """One Kalman interval; returns (ell_t, m, V)."""
+    P = _Prob(pb)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    mm, VV = C.c_double(m), C.c_double(V)
+    e = lib().orc_kf_wk_interval(P.ref, _dp(th), int(t), C.byref(mm), C.byref(VV))
+    return e, mm.value, VV.value
+
+
+def smc2_kalman(pb, inputs, T=None):
+    """Reference SMC over the parameters with attached Kalman filters
+    (windkessel); the same outputs as smc2 plus the final (m, V)."""
+    P = _Prob(pb)
+    T = inputs.T if T is None else T
+    th0 = np.ascontiguousarray(inputs.theta0, dtype=np.float64)
+    B, nth = th0.shape
+    z = np.ascontiguousarray(inputs.z, dtype=np.float64)
+    la = np.ascontiguousarray(inputs.log_alpha, dtype=np.float64)
+    u = np.ascontiguousarray(inputs.u, dtype=np.float64)
+    out = dict(theta=np.zeros((B, nth)), logw=np.zeros(B), loglik=np.zeros(B),
+               accepts=np.zeros(B, dtype=np.int32), ess=np.zeros(T),
+               anc=np.zeros((T, B), dtype=np.int32), acc=np.zeros((T, B), dtype=np.int32),
+               logw_trace=np.zeros((T, B)), mV=np.zeros((B, 2)))
+    ev = C.c_double()
+    st = lib().orc_smc2_kalman(P.ref, B, nth, _dp(th0), T, _dp(inputs.step_sd), _dp(inputs.lo),
+                               _dp(inputs.hi), _dp(z), _dp(la), _dp(u), _dp(out["theta"]),
+                               _dp(out["logw"]), _dp(out["loglik"]), _ip(out["accepts"]),
+                               _dp(out["ess"]), C.byref(ev), _ip(out["anc"]), _ip(out["acc"]),
+                               _dp(out["logw_trace"]), _dp(out["mV"]))
+    out["status"] = st
+    out["log_evidence"] = ev.value
+    return out

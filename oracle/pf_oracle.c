@@ -938,3 +938,135 @@ int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint
   free(x);
   return status;
 }
+
+/* One observation interval of the windkessel Kalman filter (the step of
+ * orc_kf_wk for time t): K predictions m <- a m + c q_{n-1},
+ * V <- a^2 V + sigma_p^2, then the correction with y_t; returns ell_t and
+ * updates (m, V). */
+double orc_kf_wk_interval(const orc_problem* P, const double* theta, int32_t t, double* m,
+                          double* V) {
+  double a = theta[0], c = theta[1], Z = theta[2], sp = theta[3];
+  double R = P->obs_sd * P->obs_sd;
+  double mm = *m, VV = *V;
+  for (int s = 1; s <= P->K; ++s) {
+    int64_t n = (int64_t)(t - 1) * P->K + s;
+    mm = a * mm + c * P->q[n - 1];
+    VV = a * a * VV + sp * sp;
+  }
+  double qn = P->q[(int64_t)t * P->K];
+  double v = P->obs[t - 1] - (mm + Z * qn);
+  double S = VV + R;
+  double e = -0.5 * (log(2.0 * 3.14159265358979323846 * S) + v * v / S);
+  double Kg = VV / S;
+  *m = mm + Kg * v;
+  *V = (1.0 - Kg) * VV;
+  return e;
+}
+
+/* SMC over the parameters with a Kalman filter attached to every
+ * theta-particle (Sec. 3.2.2, Alg. 4 with the Kalman filter of Alg. 1 as
+ * Filter; windkessel model): the same order and inputs as orc_smc2, the
+ * attached filter's state being (m, V) instead of particles; the
+ * theta-particles' proposal filters run t_{0:i-1} from (m0, s0^2), and every
+ * increment is exact, so the evidence estimate's only noise is the
+ * parameter layer's. */
+int32_t orc_smc2_kalman(const orc_problem* P, int32_t B, int32_t n_theta, const double* theta0,
+                        int32_t T_run, const double* step_sd, const double* lo,
+                        const double* hi, const double* z, const double* log_alpha,
+                        const double* u_theta, double* theta_out, double* logw_out,
+                        double* loglik_out, int32_t* accepts, double* ess_theta,
+                        double* log_evidence, int32_t* anc_trace, int32_t* acc_trace,
+                        double* logw_trace, double* mV_out /* [B][2] */) {
+  double* th = (double*)malloc(sizeof(double) * (size_t)B * n_theta);
+  double* th_new = (double*)malloc(sizeof(double) * (size_t)B * n_theta);
+  double* thp = (double*)malloc(sizeof(double) * (size_t)n_theta);
+  double* mV = (double*)malloc(sizeof(double) * 2 * (size_t)B);
+  double* mV_new = (double*)malloc(sizeof(double) * 2 * (size_t)B);
+  double* l = (double*)malloc(sizeof(double) * (size_t)B);
+  double* l_new = (double*)malloc(sizeof(double) * (size_t)B);
+  double* v = (double*)malloc(sizeof(double) * (size_t)B);
+  int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)B);
+  int32_t status = ORC_OK;
+  double evidence = 0.0;
+  memcpy(th, theta0, sizeof(double) * (size_t)B * n_theta);
+  for (int32_t j = 0; j < B; ++j) {
+    mV[2 * j] = th[(size_t)j * n_theta + 4];
+    mV[2 * j + 1] = th[(size_t)j * n_theta + 5] * th[(size_t)j * n_theta + 5];
+    l[j] = 0.0;
+    v[j] = 0.0;
+    a[j] = j;
+    accepts[j] = 0;
+  }
+  for (int32_t i = 1; i <= T_run && status == ORC_OK; ++i) {
+    for (int32_t j = 0; j < B; ++j) {
+      const int32_t s = a[j];
+      memcpy(th_new + (size_t)j * n_theta, th + (size_t)s * n_theta, sizeof(double) * n_theta);
+      l_new[j] = l[s];
+      mV_new[2 * j] = mV[2 * s];
+      mV_new[2 * j + 1] = mV[2 * s + 1];
+      if (anc_trace) anc_trace[(int64_t)(i - 1) * B + j] = s;
+    }
+    for (int32_t j = 0; j < B; ++j) {
+      int inside = 1;
+      for (int32_t p = 0; p < n_theta; ++p) {
+        const double cur = th_new[(size_t)j * n_theta + p];
+        if (step_sd[p] != 0.0) {
+          const double step = step_sd[p] * z[((int64_t)(i - 1) * B + j) * n_theta + p];
+          thp[p] = cur + step;
+          if (!(thp[p] >= lo[p] && thp[p] <= hi[p])) inside = 0;
+        } else {
+          thp[p] = cur;
+        }
+      }
+      int32_t acc = 0;
+      if (inside) {
+        double m = thp[4], V = thp[5] * thp[5], lp = 0.0;
+        for (int32_t t = 1; t <= i - 1; ++t) lp = lp + orc_kf_wk_interval(P, thp, t, &m, &V);
+        if (log_alpha[(int64_t)(i - 1) * B + j] <= lp - l_new[j]) {
+          memcpy(th_new + (size_t)j * n_theta, thp, sizeof(double) * n_theta);
+          l_new[j] = lp;
+          mV_new[2 * j] = m;
+          mV_new[2 * j + 1] = V;
+          acc = 1;
+          accepts[j] += 1;
+        }
+      }
+      if (acc_trace) acc_trace[(int64_t)(i - 1) * B + j] = acc;
+    }
+    for (int32_t j = 0; j < B; ++j) {
+      double m = mV_new[2 * j], V = mV_new[2 * j + 1];
+      const double e = orc_kf_wk_interval(P, th_new + (size_t)j * n_theta, i, &m, &V);
+      mV[2 * j] = m;
+      mV[2 * j + 1] = V;
+      v[j] = e;
+      l[j] = l_new[j] + e;
+      if (logw_trace) logw_trace[(int64_t)(i - 1) * B + j] = e;
+    }
+    memcpy(th, th_new, sizeof(double) * (size_t)B * n_theta);
+    double e, s;
+    const double u = (i < T_run) ? u_theta[i] : 0.5;
+    status = orc_reduce_resample(B, v, u, &e, &s, a);
+    evidence = evidence + e;
+    ess_theta[i - 1] = s;
+  }
+  *log_evidence = (status == ORC_OK) ? evidence : -INFINITY;
+  memcpy(theta_out, th, sizeof(double) * (size_t)B * n_theta);
+  for (int32_t j = 0; j < B; ++j) {
+    logw_out[j] = v[j];
+    loglik_out[j] = l[j];
+    if (mV_out) {
+      mV_out[2 * j] = mV[2 * j];
+      mV_out[2 * j + 1] = mV[2 * j + 1];
+    }
+  }
+  free(a);
+  free(v);
+  free(l_new);
+  free(l);
+  free(mV_new);
+  free(mV);
+  free(thp);
+  free(th_new);
+  free(th);
+  return status;
+}

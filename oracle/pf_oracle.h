@@ -10,7 +10,8 @@
  *   - bootstrap particle filter: Sec. 3.1.2, Alg. 2 (Particle-Filter);
  *   - Kalman filter likelihood: Sec. 3.1.1, Alg. 1 (scalar case);
  *   - marginal Metropolis-Hastings: Sec. 3.2.1, eq. (mh), Alg. 3;
- *   - SMC over parameters (SMC^2): Sec. 3.2.2, Alg. 4;
+ *   - SMC over parameters with attached particle or Kalman filters (SMC^2):
+ *     Sec. 3.2.2, Alg. 4;
  *   - models: Sec. 2.1.1 eqs. (2-windkessel), (3-windkessel) and Sec. 2.1.2
  *     eq. (lorenz96-sde) with classic fixed-step RK4.
  *
@@ -110,6 +111,17 @@ int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint
 int64_t orc_path_slot(uint64_t seed, int32_t s, uint32_t b, uint32_t iter, int64_t N);
 int32_t orc_pf_path(const orc_problem* P, const double* theta, int64_t N, uint32_t b,
                     uint32_t iter, int32_t T_run, double* loglik, double* path, int64_t* idx);
+
+/* windkessel Kalman filter, one interval; SMC with attached Kalman filters */
+double orc_kf_wk_interval(const orc_problem* P, const double* theta, int32_t t, double* m,
+                          double* V);
+int32_t orc_smc2_kalman(const orc_problem* P, int32_t B, int32_t n_theta, const double* theta0,
+                        int32_t T_run, const double* step_sd, const double* lo,
+                        const double* hi, const double* z, const double* log_alpha,
+                        const double* u_theta, double* theta_out, double* logw_out,
+                        double* loglik_out, int32_t* accepts, double* ess_theta,
+                        double* log_evidence, int32_t* anc_trace, int32_t* acc_trace,
+                        double* logw_trace, double* mV_out);
 
 /* whole-filter copy index (systematic selection on equal weights) */
 int64_t orc_copy_index(int64_t k, int64_t n_src, int64_t n_dst, uint32_t w);

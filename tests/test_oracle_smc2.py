@@ -169,3 +169,90 @@ def test_windkessel_evidence_is_unbiased_for_the_kalman_integral(orc):
     centre = ev.mean() + 0.5 * sd ** 2
     assert abs(centre - log_z) <= 4.0 * sd / math.sqrt(R) + 0.02, (centre, log_z, sd)
     assert sd < 1.0
+
+
+# ---------------------------------------------------------------- attached Kalman filters
+
+def _wk_base(orc, B, N, T, s0=3.0):
+    base = W.windkessel(N=N, T=T, B=B)
+    th = base.theta.copy()
+    th[:, 5] = s0
+    base = dataclasses.replace(base, theta=th, data_theta=th[0].copy())
+    _, y = orc.simulate(base)
+    return base.with_obs(y)
+
+
+def test_kalman_intervals_compose_to_the_kalman_filter(orc):
+    pb = _wk_base(orc, 1, 1, 15)
+    ll, ell = orc.kf_wk(pb)
+    m, V, tot = pb.theta[0][4], pb.theta[0][5] ** 2, 0.0
+    for t in range(1, pb.T + 1):
+        e, m, V = orc.kf_wk_interval(pb, pb.theta[0], t, m, V)
+        assert e == ell[t - 1]
+        tot = tot + e
+    assert tot == ll
+
+
+def test_kalman_smc_single_theta_without_moves_is_the_kalman_filter(orc):
+    pb = _wk_base(orc, 1, 1, 12)
+    inp = W.smc2_wk_m0_inputs(pb.theta[0], 1, pb.T, seed=21)
+    inp = dataclasses.replace(inp, log_alpha=np.full_like(inp.log_alpha, np.inf))
+    r = orc.smc2_kalman(pb, inp)
+    ll, ell = orc.kf_wk(pb, inp.theta0[0])
+    np.testing.assert_array_equal(r["logw_trace"][:, 0], ell)
+    assert r["loglik"][0] == ll
+    assert r["log_evidence"] == pytest.approx(ll, rel=1e-14)
+    assert r["accepts"][0] == 0
+
+
+def test_kalman_smc_accepted_moves_carry_the_proposal_filter(orc):
+    pb = _wk_base(orc, 4, 1, 6)
+    inp = W.smc2_wk_m0_inputs(pb.theta[0], 4, pb.T, seed=22)
+    inp = dataclasses.replace(inp, log_alpha=np.full_like(inp.log_alpha, -np.inf))
+    r = orc.smc2_kalman(pb, inp)
+    # every inside move accepted: the final likelihood of a theta-particle
+    # whose last move was accepted is its proposal's Kalman likelihood over
+    # t_{0:T-1} plus its last increment
+    T = pb.T
+    for j in np.flatnonzero(r["acc"][T - 1]):
+        ll, ell = orc.kf_wk(pb, r["theta"][j])
+        assert r["loglik"][j] == pytest.approx(ll, rel=1e-13)
+        assert r["logw_trace"][T - 1, j] == pytest.approx(ell[T - 1], rel=1e-13)
+
+
+def test_kalman_smc_evidence_is_unbiased_for_the_kalman_integral(orc):
+    B, T, R = 16, 10, 40
+    base = _wk_base(orc, B, 1, T)
+    log_z = _kalman_evidence_over_m0(orc, base, 70.0, 110.0)
+    ev = []
+    for rep in range(R):
+        inp = W.smc2_wk_m0_inputs(base.theta[0], B, T, seed=600 + rep)
+        r = orc.smc2_kalman(base, inp)
+        assert r["status"] == 0
+        ev.append(r["log_evidence"])
+    ev = np.array(ev)
+    sd = ev.std(ddof=1)
+    centre = ev.mean() + 0.5 * sd ** 2
+    assert abs(centre - log_z) <= 4.0 * sd / math.sqrt(R) + 0.01, (centre, log_z, sd)
+
+
+def test_kalman_smc_without_moves_follows_the_genealogy(orc):
+    """No move accepted: every theta-particle's attached filter has seen
+    t_1..t_i with one parameter value, so its increments and likelihood are
+    the plain Kalman filter's for that value, whichever slots it passed."""
+    pb = _wk_base(orc, 8, 1, 9)
+    inp = W.smc2_wk_m0_inputs(pb.theta[0], 8, pb.T, seed=23)
+    inp = dataclasses.replace(inp, log_alpha=np.full_like(inp.log_alpha, np.inf))
+    r = orc.smc2_kalman(pb, inp)
+    line = np.arange(8)
+    moved = False
+    for i in range(pb.T):
+        line = line[r["anc"][i]]
+        moved |= np.any(r["anc"][i] != np.arange(8))
+        for j in range(8):
+            _, ell = orc.kf_wk(pb, inp.theta0[line[j]])
+            assert r["logw_trace"][i, j] == ell[i]
+    for j in range(8):
+        ll, _ = orc.kf_wk(pb, inp.theta0[line[j]])
+        assert r["loglik"][j] == ll
+    assert moved  # the theta-resampling did move filters between slots

@@ -162,6 +162,17 @@ pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 pf_status pf_set_theta(pf_handle* h, const double* theta, uint32_t iteration);
 pf_status pf_reset(pf_handle* h, uint32_t iteration);
 
+/* ---- the windkessel Kalman filter ---------------------------------------- */
+/* Exact marginal likelihood of every filter's parameters under the
+ * windkessel model by the Kalman filter (Sec. 3.1.1, Alg. 1 with one state
+ * and one observation, where each Cholesky factor is a square root), one
+ * lane per filter, FP64: from N(m0, s0^2), per substep m <- a m + c q_{n-1},
+ * V <- a^2 V + sigma_p^2; per observation v = y - (m + Z q), S = V + obs_sd^2,
+ * ell = -(ln(2 pi S) + v^2/S)/2, then m += (V/S) v, V <- (1 - V/S) V.
+ * loglik_out [B] and, if not NULL, ell_out [B][T] are host arrays; the
+ * handle's particles are untouched.  Synchronous. */
+pf_status pf_kalman(pf_handle* h, double* loglik_out, double* ell_out);
+
 /* ---- resampling variants ------------------------------------------------ */
 /* Which resampler the filters use and when (Sec. 3.3 names multinomial,
  * systematic and stratified resampling and resamplers that avoid the
@@ -276,6 +287,7 @@ typedef struct pf_smc2_in {
   double step_sd[8];
   double lo[8];
   double hi[8];
+  int32_t filter;           /* PF_FILTER_PARTICLE, or PF_FILTER_KALMAN (windkessel) */
 } pf_smc2_in;
 typedef struct pf_smc2_out {
   double* theta;            /* [B][n_theta] final theta-particles */
@@ -289,6 +301,15 @@ typedef struct pf_smc2_out {
   double* logw_trace;       /* [T_run][B] theta-log-weights, or NULL */
   double* theta_trace;      /* [T_run][B][n_theta] theta-particles, or NULL */
 } pf_smc2_out;
+/* With filter = PF_FILTER_KALMAN (windkessel model; Alg. 4 with the Kalman
+ * filter of Sec. 3.1.1 as Filter) each theta-particle carries an exact
+ * Kalman filter (m, V) instead of particles: step 2 copies (m, V), step 3's
+ * proposal filter is a Kalman filter from (m0', s0'^2) over t_{0:i-1}, step
+ * 4 advances it, and the increments are exact; `proposal` is ignored (may be
+ * NULL), any layout is accepted, and the handle's particle filters are
+ * re-initialised afterwards. */
+#define PF_FILTER_PARTICLE 0
+#define PF_FILTER_KALMAN 1
 size_t pf_smc2_workspace_bytes(const pf_config* cfg, int32_t T_run);
 pf_status pf_smc2(pf_handle* h, pf_handle* proposal, void* d_ws, size_t ws_bytes,
                   const pf_smc2_in* in, pf_smc2_out* out);

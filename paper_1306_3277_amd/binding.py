@@ -57,7 +57,7 @@ class PfSmc2In(C.Structure):
         ("T_run", C.c_int32), ("theta0", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
         ("log_alpha", C.POINTER(C.c_double)), ("u", C.POINTER(C.c_double)),
         ("w_copy", C.POINTER(C.c_uint32)), ("step_sd", C.c_double * 8), ("lo", C.c_double * 8),
-        ("hi", C.c_double * 8),
+        ("hi", C.c_double * 8), ("filter", C.c_int32),
     ]
 
 
@@ -99,6 +99,7 @@ SIGNATURES = {
     "pf_pmmh": (C.c_int, [_H, C.c_int32, _D, _D, _D, C.c_double, C.c_double, C.c_double,
                           C.c_double, _D, _D, _I]),
     "pf_set_resampler": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double]),
+    "pf_kalman": (C.c_int, [_H, _D, _D]),
     "pf_history_bytes": (C.c_size_t, [C.POINTER(PfConfig)]),
     "pf_history_attach": (C.c_int, [_H, C.c_void_p, C.c_size_t]),
     "pf_backtrace": (C.c_int, [_H, _D, _I]),
@@ -289,8 +290,16 @@ class Filter:
         _check(load().pf_backtrace(self.h, _dp(path), _ip(idx)))
         return path, idx
 
-    def smc2(self, proposal: "Filter", inputs, T: Optional[int] = None, traces: bool = True,
-             device: str = "cuda"):
+    def kalman(self):
+        """Exact windkessel log-likelihood per filter (Kalman filter):
+        (loglik [B], ell [B, T])."""
+        ll = np.zeros(self.B)
+        ell = np.zeros((self.B, self.T))
+        _check(load().pf_kalman(self.h, _dp(ll), _dp(ell)))
+        return ll, ell
+
+    def smc2(self, proposal: Optional["Filter"], inputs, T: Optional[int] = None,
+             traces: bool = True, device: str = "cuda", kalman: bool = False):
         """SMC over the parameters (Alg. 4) with this handle's filters attached
         to the theta-particles and ``proposal`` (a second batched handle of the
         same problem, on the same stream) running the rejuvenation proposals.
@@ -305,6 +314,7 @@ class Filter:
         u = np.ascontiguousarray(inputs.u[:T], dtype=np.float64).reshape(T)
         w = np.ascontiguousarray(inputs.w_copy[:T], dtype=np.uint32).reshape(T, B)
         ci = PfSmc2In(T, _dp(th0), _dp(z), _dp(la), _dp(u), w.ctypes.data_as(C.POINTER(C.c_uint32)))
+        ci.filter = 1 if kalman else 0
         for p in range(nth):
             ci.step_sd[p] = float(inputs.step_sd[p])
             ci.lo[p] = float(inputs.lo[p])
@@ -325,8 +335,8 @@ class Filter:
             _check(PF_E_INVAL)
         ws = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
         aligned = (ws.data_ptr() + 255) & ~255
-        st = L.pf_smc2(self.h, proposal.h, C.c_void_p(aligned), C.c_size_t(nbytes), C.byref(ci),
-                       C.byref(co))
+        st = L.pf_smc2(self.h, proposal.h if proposal is not None else None, C.c_void_p(aligned),
+                       C.c_size_t(nbytes), C.byref(ci), C.byref(co))
         res["status"] = st
         if st not in (PF_OK, PF_E_NUMERIC):
             _check(st)

@@ -13,6 +13,7 @@
 
 #include "../../include/pf.h"
 #include "pf_internal.hpp"
+#include "pf_kalman.hpp"
 #include "pf_path.hpp"
 #include "pf_smc2.hpp"
 
@@ -57,7 +58,7 @@ struct Layout {
   int64_t nblk_total = 0;
   // byte offsets into the workspace
   size_t x_cur, x_tmp, lw, counts, anc, part, boff, bstate, bjs, fs, ell, ess, theta, obs, obs_pos, obs_idx,
-      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, total;
+      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, kf_ll, kf_ell, total;
   int32_t n_chunks = 0;
 };
 
@@ -180,6 +181,8 @@ Layout make_layout(const pf_config* c) {
   L.b_chunk_f = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
   L.b_chunk_k = take(4 * (size_t)(L.n_chunks > 0 ? L.n_chunks : 1));
   L.b_u = take(8 * (size_t)c->B);
+  L.kf_ll = take(8 * (size_t)c->B);
+  L.kf_ell = take(8 * (size_t)c->B * c->T);
   L.total = p;
   return L;
 }
@@ -1129,7 +1132,8 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
 // traces, each 256-byte aligned.
 struct Smc2Layout {
   size_t z, la, w, raw, prop_raw, snap_dev, snap_raw, snap_ll, snap_st, a, inside, accepted,
-      accepts, evid, numeric, ess, anc_tr, acc_tr, theta_tr, total;
+      accepts, evid, numeric, ess, anc_tr, acc_tr, theta_tr, mV, snap_mV, prop_dev, prop_l,
+      prop_mV, total;
 };
 
 static Smc2Layout smc2_layout(int64_t B, int64_t nth, int64_t T) {
@@ -1159,6 +1163,11 @@ static Smc2Layout smc2_layout(int64_t B, int64_t nth, int64_t T) {
   L.anc_tr = take(4 * (size_t)(T * B));
   L.acc_tr = take(4 * (size_t)(T * B));
   L.theta_tr = take(8 * (size_t)(T * B * nth));
+  L.mV = take(16 * (size_t)B);
+  L.snap_mV = take(16 * (size_t)B);
+  L.prop_dev = take(64 * (size_t)B);
+  L.prop_l = take(8 * (size_t)B);
+  L.prop_mV = take(16 * (size_t)B);
   L.total = p;
   return L;
 }
@@ -1183,18 +1192,26 @@ static bool same_config(const pf_handle* A, const pf_handle* B) {
 pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const pf_smc2_in* in,
                   pf_smc2_out* out) {
   pf_status st = check_handle(H);
-  if (st || (st = check_handle(P))) return st;
-  if (H == P) return fail(PF_E_INVAL, "the proposal handle must be a second handle");
+  if (st) return st;
   if (!in || !out) return fail(PF_E_INVAL, "NULL argument");
   const pf_config& c = H->cfg;
-  if (c.layout != PF_LAYOUT_BATCHED) return fail(PF_E_INVAL, "pf_smc2 needs the batched layout");
-  if (!same_config(H, P))
-    return fail(PF_E_INVAL, "the proposal handle's configuration differs from the handle's");
-  if (H->stream != P->stream) return fail(PF_E_INVAL, "both handles must use the same stream");
-  if (H->hist || P->hist)
-    return fail(PF_E_STATE, "pf_smc2 does not keep histories: detach them first");
-  if (std::isfinite(H->rs.ess_frac) || std::isfinite(P->rs.ess_frac))
-    return fail(PF_E_STATE, "pf_smc2 needs resampling at every time (equally weighted filters)");
+  const bool kalman = in->filter == PF_FILTER_KALMAN;
+  if (in->filter != PF_FILTER_PARTICLE && !kalman)
+    return fail(PF_E_INVAL, "unknown filter kind %d", in->filter);
+  if (kalman) {
+    if (c.model != PF_MODEL_WK) return fail(PF_E_INVAL, "Kalman filters need the windkessel model");
+  } else {
+    if ((st = check_handle(P))) return st;
+    if (H == P) return fail(PF_E_INVAL, "the proposal handle must be a second handle");
+    if (c.layout != PF_LAYOUT_BATCHED) return fail(PF_E_INVAL, "pf_smc2 needs the batched layout");
+    if (!same_config(H, P))
+      return fail(PF_E_INVAL, "the proposal handle's configuration differs from the handle's");
+    if (H->stream != P->stream) return fail(PF_E_INVAL, "both handles must use the same stream");
+    if (H->hist || P->hist)
+      return fail(PF_E_STATE, "pf_smc2 does not keep histories: detach them first");
+    if (std::isfinite(H->rs.ess_frac) || std::isfinite(P->rs.ess_frac))
+      return fail(PF_E_STATE, "pf_smc2 needs resampling at every time (equally weighted filters)");
+  }
   if (c.B > pfk::SMC2_MAXB) return fail(PF_E_INVAL, "at most %d theta-particles", pfk::SMC2_MAXB);
   if (c.n_theta > 8) return fail(PF_E_INVAL, "at most 8 parameters");
   const int32_t T = in->T_run;
@@ -1240,7 +1257,7 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
     HIP_TRY(hipStreamSynchronize(s));
   }
   // capture both handles' graphs before the loop
-  if ((st = ensure_graphs(H)) || (st = ensure_graphs(P))) return st;
+  if (!kalman && ((st = ensure_graphs(H)) || (st = ensure_graphs(P)))) return st;
 
   pfk::Smc2Args S{};
   S.B = B;
@@ -1268,6 +1285,9 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   S.accepts = (int32_t*)(ws + L.accepts);
   S.evid = (double*)(ws + L.evid);
   S.numeric = (int32_t*)(ws + L.numeric);
+  S.mV = kalman ? (double*)(ws + L.mV) : nullptr;
+  S.snap_mV = kalman ? (double*)(ws + L.snap_mV) : nullptr;
+  S.ell_tr_w = H->at<double>(H->L.ell);
   const BatchArgs A = batch_args(H);
   double* ess_d = (double*)(ws + L.ess);
   int32_t* anc_tr = (int32_t*)(ws + L.anc_tr);
@@ -1275,9 +1295,34 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   const double* z_d = (const double*)(ws + L.z);
   const double* la_d = (const double*)(ws + L.la);
   const uint32_t* w_d = (const uint32_t*)(ws + L.w);
-  double* prop_dev = P->at<double>(P->L.theta);
+  if (kalman) {
+    pfk::KfArgs K{};
+    K.B = B;
+    K.K = c.K;
+    K.T = c.T;
+    K.R = c.obs_sd * c.obs_sd;
+    K.q = H->at<double>(H->L.q);
+    K.obs = H->at<double>(H->L.obs);
+    double* prop_dev_k = (double*)(ws + L.prop_dev);
+    double* prop_l = (double*)(ws + L.prop_l);
+    double* prop_mV = (double*)(ws + L.prop_mV);
+    HIP_TRY(pfk::launch_kf_init(S, s));
+    for (int32_t i = 1; i <= T; ++i) {
+      if (i >= 2)
+        HIP_TRY(pfk::launch_theta_resample(S, i - 2, in->u[i - 1], 1,
+                                           anc_tr + (size_t)(i - 1) * B, ess_d + (i - 2), s));
+      HIP_TRY(pfk::launch_smc2_propose(S, z_d + (size_t)(i - 1) * B * nth, prop_dev_k, s));
+      HIP_TRY(pfk::launch_kf_proposal(K, S, prop_dev_k, prop_l, prop_mV, i, s));
+      HIP_TRY(pfk::launch_smc2_accept_kf(S, la_d + (size_t)(i - 1) * B, prop_dev_k, prop_l,
+                                         prop_mV, acc_tr + (size_t)(i - 1) * B, s));
+      HIP_TRY(pfk::launch_kf_advance(K, S, i, s));
+      HIP_TRY(hipMemcpyAsync(ws + L.theta_tr + 8 * (size_t)(i - 1) * B * nth, ws + L.raw,
+                             8 * (size_t)B * nth, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  double* prop_dev = kalman ? nullptr : P->at<double>(P->L.theta);
 
-  for (int32_t i = 1; i <= T; ++i) {
+  for (int32_t i = 1; i <= T && !kalman; ++i) {
     const size_t cur = batched_buf(H, i - 1), spare = batched_buf(H, i);
     if (i >= 2) {
       // 1-2. theta-ancestors from v(t_{i-1}), the slots' moves and filter copies
@@ -1333,8 +1378,37 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
     if (out->logw_trace)
       for (int32_t i = 0; i < T; ++i) out->logw_trace[(size_t)i * B + j] = ell[(size_t)j * c.T + i];
   }
+  if (kalman) {
+    // the handle's particle filters did not move: start them afresh
+    if ((st = pf_reset(H, 0))) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   if (numeric) return fail(PF_E_NUMERIC, "some time had no positive theta-weight");
   g_err.clear();
+  return PF_OK;
+}
+
+pf_status pf_kalman(pf_handle* H, double* loglik_out, double* ell_out) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  const pf_config& c = H->cfg;
+  if (c.model != PF_MODEL_WK) return fail(PF_E_INVAL, "pf_kalman needs the windkessel model");
+  if (!loglik_out) return fail(PF_E_INVAL, "loglik_out is NULL");
+  pfk::KfArgs K{};
+  K.B = c.B;
+  K.K = c.K;
+  K.T = c.T;
+  K.R = c.obs_sd * c.obs_sd;
+  K.q = H->at<double>(H->L.q);
+  K.obs = H->at<double>(H->L.obs);
+  HIP_TRY(pfk::launch_kf_run(K, H->at<double>(H->L.theta), H->at<double>(H->L.kf_ll),
+                             H->at<double>(H->L.kf_ell), H->stream));
+  HIP_TRY(hipMemcpyAsync(loglik_out, H->ws + H->L.kf_ll, 8 * (size_t)c.B, hipMemcpyDeviceToHost,
+                         H->stream));
+  if (ell_out)
+    HIP_TRY(hipMemcpyAsync(ell_out, H->ws + H->L.kf_ell, 8 * (size_t)c.B * c.T,
+                           hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
   return PF_OK;
 }
 

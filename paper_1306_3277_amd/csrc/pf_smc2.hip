@@ -153,6 +153,10 @@ __global__ __launch_bounds__(SMC2_NT) void k_theta_resample(Smc2Args S, int32_t 
       S.snap_raw[(int64_t)j * S.n_theta + p] = S.raw[(int64_t)j * S.n_theta + p];
     S.snap_ll[j] = S.fs[j].loglik;
     S.snap_st[j] = S.fs[j].status;
+    if (S.mV) {
+      S.snap_mV[2 * j] = S.mV[2 * j];
+      S.snap_mV[2 * j + 1] = S.mV[2 * j + 1];
+    }
   }
   __syncthreads();
   for (int j = tid; j < B; j += SMC2_NT) {
@@ -162,6 +166,10 @@ __global__ __launch_bounds__(SMC2_NT) void k_theta_resample(Smc2Args S, int32_t 
       S.raw[(int64_t)j * S.n_theta + p] = S.snap_raw[(int64_t)s * S.n_theta + p];
     S.fs[j].loglik = S.snap_ll[s];
     S.fs[j].status = S.snap_st[s];
+    if (S.mV) {
+      S.mV[2 * j] = S.snap_mV[2 * s];
+      S.mV[2 * j + 1] = S.snap_mV[2 * s + 1];
+    }
   }
 }
 

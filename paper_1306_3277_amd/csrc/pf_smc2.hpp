@@ -28,6 +28,10 @@ struct Smc2Args {
   int32_t* accepts;              // [B] accepted moves so far
   double* evid;                  // running evidence estimate
   int32_t* numeric;              // set if some time had no positive theta-weight
+  // attached Kalman filters (windkessel): state (m, V) per slot, or null
+  double* mV;                    // [B][2]
+  double* snap_mV;               // [B][2]
+  double* ell_tr_w;              // the handle's [B][T] increments, written
 };
 
 hipError_t launch_theta_resample(const Smc2Args& S, int32_t col, double u, int32_t draw,

@@ -185,6 +185,14 @@ void orc_l96_drift(int32_t d, const double* x, double F, double* out) {
   }
 }
 
+/* The drift with a per-component forcing F_i. */
+static void l96_drift_vec(int32_t d, const double* x, const double* F, double* out) {
+  for (int i = 0; i < d; ++i) {
+    int ip1 = (i + 1) % d, im1 = (i + d - 1) % d, im2 = (i + d - 2) % d;
+    out[i] = ((x[ip1] - x[im2]) * x[im1] - x[i]) + F[i];
+  }
+}
+
 /* One substep n (from t_{n-1} to t_n) of the transition.
  * Windkessel, exact solution of the two-element ODE over a step with the
  * flow held at F(t_{n-1}) (eq. 2-windkessel), plus an additive Gaussian
@@ -194,7 +202,7 @@ void orc_l96_drift(int32_t d, const double* x, double F, double* out) {
  * (reading of eq. lorenz96-sde; the variance matches the paper's dW). */
 static void substep_one(const orc_problem* P, const double* th, uint64_t seed, uint32_t tag,
                         uint32_t iter, uint32_t j, uint32_t b, int32_t n, double* x,
-                        double* w /* scratch 5*d */) {
+                        double* w /* scratch 6*d */) {
   if (P->model == ORC_MODEL_WK) {
     double z = normal_at(seed, tag, iter, j, (uint32_t)n, b, 0);
     double a = th[0], c = th[1], sp = th[3];
@@ -206,6 +214,24 @@ static void substep_one(const orc_problem* P, const double* th, uint64_t seed, u
   double h = P->h, hh = 0.5 * P->h, h6 = P->h / 6.0;
   double sq = th[1] * sqrt(P->h);
   double *k1 = w, *k2 = w + d, *k3 = w + 2 * d, *k4 = w + 3 * d, *xt = w + 4 * d;
+  if (P->model == ORC_MODEL_L96_STAGE) {
+    /* The paper's form (Sec. 2.1.2): the SDE read as an ODE with the
+     * forcing F + sigma dW_i/dt, dW_i = sqrt(h) z_i held over the step, so
+     * component i's forcing is F_i = F + (sq z_i) / h; classic RK4 of that
+     * ODE, nothing added after the step.  k2..k4 hold F_i meanwhile. */
+    double* Fi = w + 5 * d;
+    for (int i = 0; i < d; ++i)
+      Fi[i] = F + (sq * normal_at(seed, tag, iter, j, (uint32_t)n, b, i)) / h;
+    l96_drift_vec(d, x, Fi, k1);
+    for (int i = 0; i < d; ++i) xt[i] = x[i] + hh * k1[i];
+    l96_drift_vec(d, xt, Fi, k2);
+    for (int i = 0; i < d; ++i) xt[i] = x[i] + hh * k2[i];
+    l96_drift_vec(d, xt, Fi, k3);
+    for (int i = 0; i < d; ++i) xt[i] = x[i] + h * k3[i];
+    l96_drift_vec(d, xt, Fi, k4);
+    for (int i = 0; i < d; ++i) x[i] = x[i] + h6 * ((k1[i] + k4[i]) + 2.0 * (k2[i] + k3[i]));
+    return;
+  }
   orc_l96_drift(d, x, F, k1);
   for (int i = 0; i < d; ++i) xt[i] = x[i] + hh * k1[i];
   orc_l96_drift(d, xt, F, k2);
@@ -261,7 +287,7 @@ void orc_propagate(const orc_problem* P, const double* theta, int64_t N, uint32_
                    uint32_t iter, int32_t t, const double* x_in, double* x_out) {
   int d = P->d;
   double* xj = (double*)malloc(sizeof(double) * (size_t)d);
-  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 6 * (size_t)d);
   for (int64_t j = 0; j < N; ++j) {
     for (int i = 0; i < d; ++i) xj[i] = x_in[(int64_t)i * N + j];
     for (int s = 1; s <= P->K; ++s)
@@ -290,7 +316,7 @@ void orc_propagate_idx(const orc_problem* P, const double* theta, int64_t n, con
                        uint32_t b, uint32_t iter, int32_t t, const double* x_in, double* x_out) {
   int d = P->d;
   double* xj = (double*)malloc(sizeof(double) * (size_t)d);
-  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 6 * (size_t)d);
   for (int64_t c = 0; c < n; ++c) {
     for (int i = 0; i < d; ++i) xj[i] = x_in[(int64_t)i * n + c];
     for (int s = 1; s <= P->K; ++s)
@@ -453,7 +479,7 @@ void orc_simulate(const orc_problem* P, const double* theta, uint64_t data_seed,
                   double* x_traj, double* obs) {
   int d = P->d;
   double* x = (double*)malloc(sizeof(double) * (size_t)d);
-  double* w = (double*)malloc(sizeof(double) * 5 * (size_t)d);
+  double* w = (double*)malloc(sizeof(double) * 6 * (size_t)d);
   init_one(P, theta, data_seed, ORC_TAG_DATA, 0, 0, 0, x);
   memcpy(x_traj, x, sizeof(double) * (size_t)d);
   for (int32_t t = 1; t <= P->T; ++t) {

@@ -13,7 +13,8 @@
  *   - SMC over parameters with attached particle or Kalman filters (SMC^2):
  *     Sec. 3.2.2, Alg. 4;
  *   - models: Sec. 2.1.1 eqs. (2-windkessel), (3-windkessel) and Sec. 2.1.2
- *     eq. (lorenz96-sde) with classic fixed-step RK4.
+ *     eq. (lorenz96-sde) with classic fixed-step RK4, the noise added after
+ *     the step or, in the paper's form, inside the stages.
  *
  * Readings where the paper is silent are stated beside each function.
  * Particle state is structure-of-arrays: x[i*N + j] is component i of
@@ -27,7 +28,7 @@
 extern "C" {
 #endif
 
-enum { ORC_MODEL_WK = 1, ORC_MODEL_L96 = 2 };
+enum { ORC_MODEL_WK = 1, ORC_MODEL_L96 = 2, ORC_MODEL_L96_STAGE = 3 };
 enum { ORC_TAG_INIT = 1, ORC_TAG_NOISE = 2, ORC_TAG_RESAMPLE = 3, ORC_TAG_DATA = 4,
        ORC_TAG_OBS = 8, ORC_TAG_PATH = 9 };
 enum { ORC_OK = 0, ORC_NUMERIC = 4 };

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpf_mi355x.so")
 
 PF_OK, PF_E_INVAL, PF_E_DEVICE, PF_E_STATE, PF_E_NUMERIC = 0, 1, 2, 3, 4
-PF_MODEL_WK, PF_MODEL_L96 = 1, 2
+PF_MODEL_WK, PF_MODEL_L96, PF_MODEL_L96_STAGE = 1, 2, 3
 PF_FP64, PF_FP32_MIXED = 0, 1
 PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
 PF_BATCHED_MAX_PARTICLES = 8192

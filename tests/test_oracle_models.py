@@ -131,3 +131,65 @@ def test_simulated_observation_noise(orc):
     assert abs(r.mean()) < 4 / math.sqrt(n)
     assert abs(r.var() - 1) < 4 * math.sqrt(2 / n)
     assert np.abs(xt).max() < 20  # bounded chaotic attractor
+
+
+# ---------------------------------------------------------------- the paper's model forms
+
+def test_l96_stage_noise_reduces_without_noise(orc):
+    """sigma = 0: the in-stage form is the plain RK4 step, bit for bit."""
+    for stage in (False, True):
+        pb = W.lorenz96(d=8, N=5, T=3, sigma=0.0, stage_noise=stage)
+        x0 = orc.init(pb, pb.theta[0], 5)
+        x = x0
+        for t in range(1, 4):
+            x = orc.propagate(pb, pb.theta[0], x, t)
+        if not stage:
+            ref = x
+    np.testing.assert_array_equal(x, ref)
+
+
+def test_l96_stage_noise_is_the_rk4_propagator_of_the_forcing(orc):
+    """At the uniform fixed point x = F with a tiny sigma the step is linear
+    in the noise: constant forcing c = sq z / h over the step gives, under
+    RK4, h (I + hJ/2 + (hJ)^2/6 + (hJ)^3/24) c with J the drift's Jacobian
+    at x = F (J_{i,i+1} = F, J_{i,i-2} = -F, J_ii = -1).  The noise added
+    after the step instead gives sq z exactly."""
+    d, F, sig = 8, 8.0, 1e-6
+    for stage in (True, False):
+        pb = W.lorenz96(d=d, N=1, T=1, K=1, F=F, sigma=sig, stage_noise=stage)
+        x = orc.propagate(pb, pb.theta[0], np.full((d, 1), F), 1)[:, 0] - F
+        z = np.concatenate([orc.normals4(pb.seed, orc.TAG_NOISE, blk, 0, 0, 1, 0)
+                            for blk in range(d // 4)])
+        sq = sig * math.sqrt(pb.h)
+        if stage:
+            J = -np.eye(d)
+            for i in range(d):
+                J[i, (i + 1) % d] += F
+                J[i, (i - 2) % d] -= F
+            A = pb.h * J
+            P = np.eye(d) + A / 2 + A @ A / 6 + A @ A @ A / 24
+            np.testing.assert_allclose(x, sq * (P @ z), rtol=1e-5, atol=1e-14)
+        else:
+            np.testing.assert_allclose(x, sq * z, rtol=1e-6, atol=1e-14)
+
+
+def test_paper_windkessel_inputs(orc):
+    pb = W.windkessel_paper(N=64, T=80)
+    q = pb.q
+    t = np.arange(q.size) * pb.h
+    # systole: the sin^2 pulse (period 0.8 s, as printed) up to 0.3 s of every
+    # period, zero after; it is cut at 500 sin^2(0.375 pi) before its peak
+    np.testing.assert_allclose(q[30], 500.0 * math.sin(0.375 * math.pi) ** 2, rtol=1e-12)
+    assert q.max() == q[30]
+    assert np.all(q[(np.mod(t, 0.8) > 0.3 + 1e-9)] == 0.0)
+    assert np.all(q[(np.mod(t, 0.8) > 1e-9) & (np.mod(t, 0.8) < 0.3 - 1e-9)] > 0.0)
+    # flow noise of variance sigma^2 is pressure noise of sd c sigma
+    a, c, Z, sp, m0, s0 = pb.theta[0]
+    assert sp == pytest.approx(c * 5.0, rel=1e-15)
+    assert pb.obs_sd == 2.0 and (m0, s0) == (90.0, 15.0)
+    # the Kalman filter and the particle filter agree on it (unbiasedness)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    ll_kf, _ = orc.kf_wk(pb)
+    lls = np.array([orc.pf_run(dataclasses.replace(pb, seed=s))["loglik"] for s in range(60)])
+    assert abs(lls.mean() + lls.var(ddof=1) / 2 - ll_kf) < 4 * lls.std(ddof=1) / math.sqrt(60) + 0.02

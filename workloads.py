@@ -31,10 +31,11 @@ import numpy as np
 
 MODEL_WK = 1
 MODEL_L96 = 2
+MODEL_L96_STAGE = 3  # Lorenz '96 with the noise inside the RK4 stages (the paper's form)
 FP64 = 0
 FP32_MIXED = 1
 
-N_THETA = {MODEL_WK: 6, MODEL_L96: 2}
+N_THETA = {MODEL_WK: 6, MODEL_L96: 2, MODEL_L96_STAGE: 2}
 
 
 @dataclasses.dataclass
@@ -114,17 +115,57 @@ def windkessel(N: int = 1024, T: int = 100, K: int = 10, seed: int = 0, data_see
         precision=precision)
 
 
+def wk_flow_paper(n_steps: int, h: float, f_max: float = 500.0, t_s: float = 0.3,
+                  t_d: float = 0.5) -> np.ndarray:
+    """The paper's prescribed flow (eq. flow): F(t) = f_max sin^2(pi t /
+    (t_s + t_d)) while t mod (t_s + t_d) lies in [0, t_s] (systole), else 0
+    (diastole); sampled at t_n = n h and held over each step.  n_steps + 1
+    values.  "mod" is read as the remainder."""
+    t = np.arange(n_steps + 1, dtype=np.float64) * h
+    period = t_s + t_d
+    systole = np.mod(t, period) <= t_s
+    return np.where(systole, f_max * np.sin(np.pi * t / period) ** 2, 0.0)
+
+
+def wk_theta_paper(R: float, C: float, Z: float, sigma2: float, m0: float, s0: float,
+                   h: float) -> np.ndarray:
+    """The paper's parameters (R, C, Z, sigma^2) with the noise on the flow:
+    P_p <- a P_p + c (F + xi), xi ~ N(0, sigma^2), is the pressure noise of sd
+    c sigma, so sigma_p = R (1 - a) sqrt(sigma^2)."""
+    a = math.exp(-h / (R * C))
+    c = R * (1.0 - a)
+    return np.array([a, c, Z, c * math.sqrt(sigma2), m0, s0], dtype=np.float64)
+
+
+def windkessel_paper(N: int = 1024, T: int = 100, K: int = 10, seed: int = 0,
+                     data_seed: int = 1, precision: int = FP64, B: int = 1, R: float = 1.0,
+                     C: float = 1.5, Z: float = 0.03, sigma2: float = 25.0) -> Problem:
+    """The paper's windkessel example (Sec. 2.1.1): flow with f_max 500,
+    systole 0.3 s, diastole 0.5 s; noise on the flow with variance sigma^2;
+    observation sd 2; P_p(t_0) ~ N(90, 15); dt = 0.01."""
+    h = 0.01
+    th = wk_theta_paper(R, C, Z, sigma2, 90.0, 15.0, h)
+    return Problem(
+        name=f"windkessel_paper_N{N}_T{T}", model=MODEL_WK, d=1, K=K, h=h,
+        obs_idx=np.zeros(1, dtype=np.int32), obs_sd=2.0, T=T,
+        theta=np.tile(th, (B, 1)), n_particles=np.full(B, N, dtype=np.int64),
+        q=wk_flow_paper(T * K, h), seed=seed, data_seed=data_seed, data_theta=th.copy(),
+        precision=precision)
+
+
 # ---------------------------------------------------------------- Lorenz '96
 
 def lorenz96(d: int = 8, N: int = 65536, T: int = 200, K: int = 8, F: float = 8.0,
              sigma: float = 0.1, obs_every: int = 1, seed: int = 0, data_seed: int = 1,
-             precision: int = FP64, B: int = 1) -> Problem:
+             precision: int = FP64, B: int = 1, stage_noise: bool = False) -> Problem:
     """Stochastic Lorenz '96 with RK4 step h=0.05, K substeps between
-    observations, observation sd 0.5 on components 0, obs_every, 2*obs_every..."""
+    observations, observation sd 0.5 on components 0, obs_every, 2*obs_every...
+    stage_noise: the paper's form, the noise inside the RK4 stages."""
     th = np.array([F, sigma], dtype=np.float64)
     idx = np.arange(0, d, obs_every, dtype=np.int32)
     return Problem(
-        name=f"lorenz96_d{d}_N{N}_T{T}", model=MODEL_L96, d=d, K=K, h=0.05,
+        name=f"lorenz96{'s' if stage_noise else ''}_d{d}_N{N}_T{T}",
+        model=MODEL_L96_STAGE if stage_noise else MODEL_L96, d=d, K=K, h=0.05,
         obs_idx=idx, obs_sd=0.5, T=T, theta=np.tile(th, (B, 1)),
         n_particles=np.full(B, N, dtype=np.int64), q=None, seed=seed,
         data_seed=data_seed, data_theta=th.copy(), precision=precision)

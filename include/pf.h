@@ -65,8 +65,13 @@ typedef enum pf_status {
  *   classic RK4 substeps of length h on the drift, then the increment
  *   sigma dW with dW ~ N(0, h) per component; initial x ~ N(0, I);
  *   observation of components obs_idx with Gaussian noise.
- *   theta = (F, sigma). */
-enum { PF_MODEL_WK = 1, PF_MODEL_L96 = 2 };
+ *   theta = (F, sigma).
+ * PF_MODEL_L96_STAGE: the paper's form of the stochastic Lorenz '96 (Sec.
+ *   2.1.2: the SDE read as an ODE whose forcing includes sigma dW/dt): per
+ *   substep the forcing of component i is F + sigma sqrt(h) z_i / h, held
+ *   over the step and integrated by the same classic RK4; no increment is
+ *   added after the step.  Same theta, normals and observation model. */
+enum { PF_MODEL_WK = 1, PF_MODEL_L96 = 2, PF_MODEL_L96_STAGE = 3 };
 
 /* Arithmetic of the hot path.
  * PF_FP64: everything in FP64.

@@ -64,7 +64,7 @@ struct Layout {
 
 pf_status validate(const pf_config* c) {
   if (!c) return fail(PF_E_INVAL, "cfg is NULL");
-  if (c->model != PF_MODEL_WK && c->model != PF_MODEL_L96)
+  if (c->model != PF_MODEL_WK && c->model != PF_MODEL_L96 && c->model != PF_MODEL_L96_STAGE)
     return fail(PF_E_INVAL, "model %d unknown", c->model);
   if (c->precision != PF_FP64 && c->precision != PF_FP32_MIXED)
     return fail(PF_E_INVAL, "precision %d unknown", c->precision);
@@ -1081,7 +1081,8 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
   pf_status st = check_handle(H);
   if (st) return st;
   const pf_config& c = H->cfg;
-  if (c.model != PF_MODEL_L96) return fail(PF_E_INVAL, "pf_pmmh needs the Lorenz '96 model");
+  if (c.model != PF_MODEL_L96 && c.model != PF_MODEL_L96_STAGE)
+    return fail(PF_E_INVAL, "pf_pmmh needs a Lorenz '96 model");
   if (iters < 0 || iters + 1 >= (1 << 20)) return fail(PF_E_INVAL, "iters out of range");
   if (!log_f0 || (iters > 0 && (!z || !alpha || !log_f_trace || !ll_trace)) || !accepts)
     return fail(PF_E_INVAL, "NULL argument");

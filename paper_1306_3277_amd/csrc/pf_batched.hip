@@ -122,14 +122,24 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
     for (int i = 0; i < D; ++i) x[i] = xp[(int64_t)i * A.ld + src];
     if constexpr (sizeof(Real) == 8) {
       ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
-      for (int s = 1; s <= A.K; ++s)
-        l96_substep_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
-                           (uint32_t)(n0 + s), (uint32_t)f);
+      for (int s = 1; s <= A.K; ++s) {
+        if constexpr (MODEL == 3)
+          l96_substep_stage_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
+                                   (uint32_t)(n0 + s), (uint32_t)f);
+        else
+          l96_substep_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
+                             (uint32_t)(n0 + s), (uint32_t)f);
+      }
     } else {
       const L96F32 c = l96_f32_consts(th[0], th[1], A.h);
-      for (int s = 1; s <= A.K; ++s)
-        l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)k, (uint32_t)(n0 + s),
-                           (uint32_t)f);
+      for (int s = 1; s <= A.K; ++s) {
+        if constexpr (MODEL == 3)
+          l96_substep_stage_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)k, (uint32_t)(n0 + s),
+                                   (uint32_t)f);
+        else
+          l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)k, (uint32_t)(n0 + s),
+                             (uint32_t)f);
+      }
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) xn[(int64_t)i * A.ld + dst] = x[i];
@@ -480,14 +490,22 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
                          (float*)xb, lw, anc, a);
     return hipGetLastError();
   }
-  switch (d) {
+  switch (d * 4 + model) {
 #define X(DD)                                                                              \
-  case DD:                                                                                 \
+  case DD * 4 + 2:                                                                         \
     if (prec == 0)                                                                         \
       hipLaunchKernelGGL((k_batch_propagate<2, DD, double>), g, BATCH_NT, 0, s,            \
                          (double*)xa, (double*)xb, lw, anc, a);                            \
     else                                                                                   \
       hipLaunchKernelGGL((k_batch_propagate<2, DD, float>), g, BATCH_NT, 0, s, (float*)xa, \
+                         (float*)xb, lw, anc, a);                                          \
+    break;                                                                                 \
+  case DD * 4 + 3:                                                                         \
+    if (prec == 0)                                                                         \
+      hipLaunchKernelGGL((k_batch_propagate<3, DD, double>), g, BATCH_NT, 0, s,            \
+                         (double*)xa, (double*)xb, lw, anc, a);                            \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_batch_propagate<3, DD, float>), g, BATCH_NT, 0, s, (float*)xa, \
                          (float*)xb, lw, anc, a);                                          \
     break;
     PF_L96_DIMS_B(X)

@@ -341,6 +341,111 @@ __device__ __forceinline__ void l96_substep_f32(float (&x)[D], const L96F32& c, 
   }
 }
 
+// ---------------------------------------------------------------- Lorenz '96, noise in the stages
+// The paper's form of the stochastic model: the SDE read as an ODE whose
+// forcing on component i is F + sigma dW_i / h over the step (dW_i = sqrt(h)
+// z_i held for the step), integrated by the same classic RK4.  With
+// sq = sigma sqrt(h) the forcing is F_i = F + (sq z_i) / h and nothing is
+// added after the step.  FP64, the oracle's expression tree.
+template <int D>
+__device__ __forceinline__ void l96_drift_vec_f64(const double (&x)[D], const double (&F)[D],
+                                                  double (&k)[D]) {
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    k[i] = ((x[(i + 1) % D] - x[(i + D - 2) % D]) * x[(i + D - 1) % D] - x[i]) + F[i];
+}
+
+template <int D>
+__device__ __forceinline__ void l96_substep_stage_f64(double (&x)[D], double F, double sq,
+                                                      const ModelConsts& mc, Key key,
+                                                      uint32_t tag, uint32_t iter, uint32_t j,
+                                                      uint32_t n, uint32_t b) {
+  double Fi[D];
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    double z[4];
+    normals4_f64(draw(key, tag, blk, iter, j, n, b), z);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Fi[4 * blk + m] = F + (sq * z[m]) / mc.h;
+  }
+  double k[D], xt[D], s14[D], s23[D];
+  l96_drift_vec_f64<D>(x, Fi, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s14[i] = k[i];
+    xt[i] = x[i] + mc.hh * k[i];
+  }
+  l96_drift_vec_f64<D>(xt, Fi, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s23[i] = k[i];
+    xt[i] = x[i] + mc.hh * k[i];
+  }
+  l96_drift_vec_f64<D>(xt, Fi, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s23[i] = s23[i] + k[i];
+    xt[i] = x[i] + mc.h * k[i];
+  }
+  l96_drift_vec_f64<D>(xt, Fi, k);
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    s14[i] = s14[i] + k[i];
+    x[i] = x[i] + mc.h6 * (s14[i] + 2.0 * s23[i]);
+  }
+}
+
+// FP32 form of the same step: the noise term nz_i = sq z_i is drawn first;
+// h F_i = F h + nz_i starts the increment, and the stage inputs are
+// (x + c F_i) + c g with c F_i = c F + (c/h) nz_i formed once per substep
+// for c = h/2 and c = h.
+template <int D>
+__device__ __forceinline__ void l96_substep_stage_f32(float (&x)[D], const L96F32& c, Key key,
+                                                      uint32_t tag, uint32_t iter, uint32_t j,
+                                                      uint32_t n, uint32_t b) {
+  float nz[D];
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    const uint4 w = draw(key, tag, blk, iter, j, n, b);
+    float r0, c0, s0, r1, c1, s1;
+    noise_pair_f32(w.x, w.y, c.nc2, r0, c0, s0);
+    noise_pair_f32(w.z, w.w, c.nc2, r1, c1, s1);
+    nz[4 * blk] = r0 * c0;
+    nz[4 * blk + 1] = r0 * s0;
+    nz[4 * blk + 2] = r1 * c1;
+    nz[4 * blk + 3] = r1 * s1;
+  }
+  float acc[D], xt[D], xc[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    xt[i] = x[i];
+    acc[i] = c.Fh + nz[i];
+    xc[i] = x[i] + fmaf(0.5f, nz[i], c.hF);
+  }
+  auto stage = [&](float c_acc, float c_xt, bool last) {
+    const float old0 = xt[0];
+    float pm2 = xt[D - 2], pm1 = xt[D - 1];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float xi = xt[i];
+      const float xp1 = (i == D - 1) ? old0 : xt[i + 1];
+      const float g = fmaf(xp1 - pm2, pm1, -xi);
+      pm2 = pm1;
+      pm1 = xi;
+      acc[i] = fmaf(c_acc, g, acc[i]);
+      if (!last) xt[i] = fmaf(c_xt, g, xc[i]);
+    }
+  };
+  stage(c.h6, c.hh, false);
+  stage(c.h3, c.hh, false);
+#pragma unroll
+  for (int i = 0; i < D; ++i) xc[i] = x[i] + (c.hF2 + nz[i]);
+  stage(c.h3, c.h, false);
+  stage(c.h6, 0.0f, true);
+#pragma unroll
+  for (int i = 0; i < D; ++i) x[i] = x[i] + acc[i];
+}
+
 // e^x for x <= 0, x = -inf included (weights exp(lw - max lw)).  Reduction
 // x = n ln2 + r with |r| <= ln2/2 (ln2 split in two parts, so r is exact to
 // about 2^-60), e^r by its Taylor polynomial to degree 13 (truncation below

@@ -140,13 +140,23 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
       if constexpr (sizeof(Real) == 8) {
         const double F = A.theta[0], sq = A.theta[1];
         ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
-        for (int s = 1; s <= A.K; ++s)
-          l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
-                             (uint32_t)(n0 + s), A.b);
+        for (int s = 1; s <= A.K; ++s) {
+          if constexpr (MODEL == 3)
+            l96_substep_stage_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
+                                     (uint32_t)(n0 + s), A.b);
+          else
+            l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
+                               (uint32_t)(n0 + s), A.b);
+        }
       } else {
         const L96F32 c = l96_f32_consts(A.theta[0], A.theta[1], A.h);
-        for (int s = 1; s <= A.K; ++s)
-          l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
+        for (int s = 1; s <= A.K; ++s) {
+          if constexpr (MODEL == 3)
+            l96_substep_stage_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s),
+                                     A.b);
+          else
+            l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
+        }
       }
 #pragma unroll
       for (int i = 0; i < D; ++i) xprop[(int64_t)i * A.ld + col] = x[i];
@@ -674,7 +684,11 @@ __global__ void k_simulate(double* __restrict__ out, PlainArgs A, double obs_sd)
         bm_pair_f64(w.x, w.y, z0, z1);
         x[0] = wk_substep_f64(x[0], A.theta, A.q[n - 1], z0);
       } else {
-        l96_substep_f64<D>(x, A.theta[0], A.theta[1], mc, key, TAG_DATA, 0, 0, (uint32_t)n, 0);
+        if constexpr (MODEL == 3)
+          l96_substep_stage_f64<D>(x, A.theta[0], A.theta[1], mc, key, TAG_DATA, 0, 0,
+                                   (uint32_t)n, 0);
+        else
+          l96_substep_f64<D>(x, A.theta[0], A.theta[1], mc, key, TAG_DATA, 0, 0, (uint32_t)n, 0);
       }
     }
     for (int i = 0; i < D; ++i) out[(int64_t)t * D + i] = x[i];
@@ -737,14 +751,22 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
                          (const float*)xcur, (float*)xprop, (double*)lw, part, a);
     return hipGetLastError();
   }
-  switch (d) {
+  switch (d * 4 + model) {
 #define X(DD)                                                                             \
-  case DD:                                                                                \
+  case DD * 4 + 2:                                                                        \
     if (prec == 0)                                                                        \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, double>), g, K1_NT, 0, s,             \
                          (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
     else                                                                                  \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, float>), g, K1_NT, 0, s,              \
+                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+    break;                                                                                \
+  case DD * 4 + 3:                                                                        \
+    if (prec == 0)                                                                        \
+      hipLaunchKernelGGL((k_propagate_weight<3, DD, double>), g, K1_NT, 0, s,             \
+                         (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_propagate_weight<3, DD, float>), g, K1_NT, 0, s,              \
                          (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
     break;
     PF_L96_DIMS(X)
@@ -815,10 +837,13 @@ hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, do
     hipLaunchKernelGGL((k_simulate<1, 1>), 1, 64, 0, s, out, a, obs_sd);
     return hipGetLastError();
   }
-  switch (d) {
+  switch (d * 4 + model) {
 #define X(DD)                                                                      \
-  case DD:                                                                         \
+  case DD * 4 + 2:                                                                 \
     hipLaunchKernelGGL((k_simulate<2, DD>), 1, 64, 0, s, out, a, obs_sd);          \
+    break;                                                                         \
+  case DD * 4 + 3:                                                                 \
+    hipLaunchKernelGGL((k_simulate<3, DD>), 1, 64, 0, s, out, a, obs_sd);          \
     break;
     PF_L96_DIMS(X)
 #undef X

@@ -1,0 +1,123 @@
+"""GPU parity for the paper's model forms: Lorenz '96 with the noise inside
+the RK4 stages (FP64 bit for bit with the oracle, plain and batched; FP32
+batched equals FP32 plain; FP32 teacher-forced likelihood increments within
+max(1e-4, 1e-6 |ell|) of FP64, d = 8 and d = 40) and the paper's windkessel
+example (flow, flow noise, observation sd 2) in FP64."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL64 = 1e-10
+BAND = 1e-9
+
+
+@pytest.fixture(scope="module")
+def pfm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_3277_amd as pfm
+    pfm.load()
+    return pfm
+
+
+def _data(pb):
+    _, y = oracle.simulate(pb)
+    return pb.with_obs(y)
+
+
+def _fp64_vs_oracle(pfm, pb, layout):
+    n = pb.n_particles
+    off = np.concatenate([[0], np.cumsum(n)])
+    refs = [oracle.pf_run(pb, theta=pb.theta[b], N=int(n[b]), b=b, traces=True)
+            for b in range(pb.B)]
+    f = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
+    for t in range(1, pb.T + 1):
+        f.step()
+        lw = f.logweights()
+        for b in range(pb.B):
+            np.testing.assert_array_equal(lw[off[b]:off[b + 1]], refs[b]["lw"][t - 1],
+                                          err_msg=f"filter {b}, t = {t}")
+        f.resample()
+        a = f.ancestors()
+        for b in range(pb.B):
+            ag, ar = a[off[b]:off[b + 1]], refs[b]["anc"][t - 1]
+            mism = np.flatnonzero(ag != ar)
+            if mism.size:
+                lwb = refs[b]["lw"][t - 1]
+                w = np.exp(lwb - lwb.max())
+                cw = np.cumsum(w) / w.sum()
+                u = oracle.resample_u(pb.seed, t, b)
+                for k in mism:
+                    assert np.min(np.abs(cw - (u + k) / lwb.size)) < BAND
+                pytest.skip("an ancestor flipped inside the 1e-9 band")
+    ell, _ = f.trace()
+    x = f.get_state()
+    for b in range(pb.B):
+        np.testing.assert_array_less(np.abs(ell[b] - refs[b]["ell"]),
+                                     REL64 * np.maximum(1.0, np.abs(refs[b]["ell"])))
+        np.testing.assert_array_equal(x[:, off[b]:off[b + 1]], refs[b]["x"])
+    f.close()
+
+
+def test_stage_noise_plain_fp64(pfm):
+    _fp64_vs_oracle(pfm, _data(W.lorenz96(d=8, N=700, T=6, stage_noise=True)),
+                    pfm.PF_LAYOUT_PLAIN)
+
+
+def test_stage_noise_batched_fp64(pfm):
+    base = _data(W.lorenz96(d=8, N=1, T=5, stage_noise=True))
+    th0, _ = W.batched_thetas(4, seed=71)
+    pb = dataclasses.replace(base, theta=th0,
+                             n_particles=np.array([300, 1024, 64, 2000], dtype=np.int64))
+    _fp64_vs_oracle(pfm, pb, pfm.PF_LAYOUT_BATCHED)
+
+
+def test_stage_noise_d40_plain_fp64(pfm):
+    _fp64_vs_oracle(pfm, _data(W.lorenz96(d=40, N=300, T=3, obs_every=2, stage_noise=True)),
+                    pfm.PF_LAYOUT_PLAIN)
+
+
+def test_paper_windkessel_fp64(pfm):
+    _fp64_vs_oracle(pfm, _data(W.windkessel_paper(N=2000, T=15)), pfm.PF_LAYOUT_PLAIN)
+
+
+def test_stage_noise_fp32_batched_equals_plain(pfm):
+    base = _data(W.lorenz96(d=8, N=1, T=8, stage_noise=True, precision=W.FP32_MIXED))
+    th0, _ = W.batched_thetas(3, seed=72)
+    pb = dataclasses.replace(base, theta=th0,
+                             n_particles=np.array([700, 256, 3000], dtype=np.int64))
+    outs = []
+    for layout in (pfm.PF_LAYOUT_PLAIN, pfm.PF_LAYOUT_BATCHED):
+        f = pfm.Filter(pb, layout=layout)
+        f.graph_run(pb.T)
+        outs.append((f.trace()[0], f.get_state()))
+        f.close()
+    np.testing.assert_array_equal(outs[1][1], outs[0][1])
+    np.testing.assert_allclose(outs[1][0], outs[0][0], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("d,obs_every,N", [(8, 1, 4096), (40, 2, 2048)])
+def test_stage_noise_fp32_teacher_forced(pfm, d, obs_every, N):
+    pb = _data(W.lorenz96(d=d, N=N, T=6, obs_every=obs_every, stage_noise=True))
+    f64 = pfm.Filter(pb, precision=pfm.PF_FP64)
+    f32 = pfm.Filter(pb, precision=pfm.PF_FP32_MIXED)
+    for t in range(pb.T):
+        x = f64.get_state().astype(np.float32).astype(np.float64)
+        f64.set_state(x)
+        f32.set_state(x)
+        f64.step()
+        f32.step()
+        e64 = f64.trace()[0][0, t]
+        e32 = f32.trace()[0][0, t]
+        assert abs(e32 - e64) <= max(1e-4, 1e-6 * abs(e64)), (t, e32, e64)
+        f64.resample()
+        f32.resample()
+    f64.close()
+    f32.close()

@@ -19,6 +19,7 @@ Metropolis-Hastings chains (64 x N = 4096).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -271,6 +272,48 @@ def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=100):
     return out
 
 
+def models_leg(torch, pfm, pb, stream, threads, groups, steps=100):
+    """The paper's model forms and the Kalman filter: the batched workload
+    with the noise inside the RK4 stages (FP32 mixed), the exact windkessel
+    likelihood of 512 parameter sets, and SMC over the windkessel m0 with
+    attached Kalman filters."""
+    out = {}
+    ps = dataclasses.replace(pb, model=W.MODEL_L96_STAGE)
+    f = pfm.Filter(ps, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    f.set_tuning(threads, groups)
+    dt = timed(torch, Runner(f, ps.T), steps, 10)
+    f.close()
+    out["lorenz96_stage_noise_batched"] = {
+        "us_per_interval": dt / steps * 1e6,
+        "particle_steps_per_s": int(ps.n_particles.sum()) * steps / dt}
+    wk = W.windkessel(N=64, T=100, B=512)
+    _, y = pfm.simulate(wk, stream=stream)
+    wk = wk.with_obs(y)
+    inp = W.smc2_wk_m0_inputs(wk.theta[0], 512, wk.T, seed=9)
+    wk = dataclasses.replace(wk, theta=inp.theta0)
+    fk = pfm.Filter(wk, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    fk.kalman()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        fk.kalman()
+    dtk = (time.perf_counter() - t0) / 10
+    fk.smc2(None, inp, T=3, kalman=True, traces=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rk = fk.smc2(None, inp, kalman=True, traces=False)
+    dts = time.perf_counter() - t0
+    fk.close()
+    out["kalman_windkessel_512_filters_T100"] = {"ms_per_call": dtk * 1e3}
+    out["smc_kalman_windkessel_512_theta_T100"] = {
+        "seconds": dts, "log_evidence": rk["log_evidence"],
+        "accept_rate": float(rk["accepts"].sum() / (512 * wk.T))}
+    log(f"[bench] models: L96 stage noise {out['lorenz96_stage_noise_batched']['us_per_interval']:.1f} "
+        f"us/interval; Kalman 512 x T100 {dtk * 1e3:.3f} ms; SMC with Kalman filters "
+        f"512 x T100 {dts * 1e3:.1f} ms")
+    return out
+
+
 def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):
     """The headline workload with ancestry storage attached (every interval
     also copies its propagated particles and ancestors into the history),
@@ -356,6 +399,8 @@ def main():
     ap.add_argument("--tf-steps", type=int, default=8, help="teacher-forced error intervals")
     ap.add_argument("--smc2-T", type=int, default=200,
                     help="observation times of the SMC^2 leg (0: skip it)")
+    ap.add_argument("--profile-models", action="store_true",
+                    help="run only the model-form and Kalman leg")
     ap.add_argument("--profile-path", action="store_true",
                     help="run only the history / state-sample leg (for kernel traces)")
     ap.add_argument("--profile-smc2", action="store_true",
@@ -409,6 +454,10 @@ def main():
     pb = pb.with_obs(y)
     n_tot = int(pb.n_particles.sum())
     log(f"[bench] {pb.name}: B={pb.B} particles={n_tot} T={pb.T}")
+    if args.profile_models:
+        print(json.dumps({"profile_models": models_leg(torch, pfm, pb, stream, 512, 2)}),
+              flush=True)
+        return
     if args.profile_path:
         print(json.dumps({"profile_path": path_leg(torch, pfm, pb, stream, 512, 2, 0.0)}),
               flush=True)
@@ -567,6 +616,10 @@ def main():
         # ------------------------------------------------------------ resamplers
         log("[bench] resampler leg starts")
         out["resamplers_batched"] = resampler_leg(torch, pfm, pb, stream, threads, groups)
+
+        # ------------------------------------------------------------ model forms, Kalman
+        log("[bench] models leg starts")
+        out["models"] = models_leg(torch, pfm, pb, stream, threads, groups)
 
         # ------------------------------------------------------------ state sample
         log("[bench] history leg starts")

@@ -392,7 +392,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed intervals before the timed ones (the device clocks settle)")
     ap.add_argument("--fp64-steps", type=int, default=40,
                     help="intervals timed for the FP64 plain comparison")
     ap.add_argument("--pmmh-iters", type=int, default=10)

@@ -66,7 +66,7 @@ def test_smc2_workspace_size_and_run_length():
 
 
 @pytest.mark.parametrize("mutate,needle", [
-    (lambda c: setattr(c, "model", 3), "model"),
+    (lambda c: setattr(c, "model", 4), "model"),
     (lambda c: setattr(c, "precision", 7), "precision"),
     (lambda c: setattr(c, "d", 7), "d must be"),
     (lambda c: setattr(c, "K", 0), "K must"),

@@ -23,7 +23,7 @@ _lib = None
 
 ORC_OK = 0
 ORC_NUMERIC = 4
-TAG_INIT, TAG_NOISE, TAG_RESAMPLE, TAG_DATA, TAG_OBS, TAG_PATH = 1, 2, 3, 4, 8, 9
+TAG_INIT, TAG_NOISE, TAG_RESAMPLE, TAG_DATA, TAG_OBS, TAG_PATH, TAG_MULTI = 1, 2, 3, 4, 8, 9, 10
 
 
 def build(force: bool = True) -> str:
@@ -98,6 +98,11 @@ def lib():
             "orc_stratified_ancestors": (None, [C.c_int64, _D, C.c_double, C.c_int64,
                                                 C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
                                                 _I]),
+            "orc_multi_u": (C.c_double, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
+                                         C.c_int64]),
+            "orc_multinomial_ancestors": (None, [C.c_int64, _D, C.c_double, C.c_int64,
+                                                 C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32,
+                                                 _I]),
             "orc_metropolis_ancestors": (None, [C.c_int64, _D, C.c_int32, C.c_uint64,
                                                 C.c_int32, C.c_uint32, C.c_uint32, _I]),
             "orc_pf_run_ex": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
@@ -370,7 +375,7 @@ def pf_path(pb, theta=None, N=None, b=0, it=0, T=None):
     return st, ll.value, path, idx
 
 
-RESAMPLE_SYSTEMATIC, RESAMPLE_STRATIFIED, RESAMPLE_METROPOLIS = 0, 1, 2
+RESAMPLE_SYSTEMATIC, RESAMPLE_STRATIFIED, RESAMPLE_METROPOLIS, RESAMPLE_MULTINOMIAL = 0, 1, 2, 3
 
 
 def strat_u(seed, t, b, it, k) -> float:
@@ -454,3 +459,24 @@ def smc2_kalman(pb, inputs, T=None):
     out["status"] = st
     out["log_evidence"] = ev.value
     return out
+
+
+def multi_u(seed, t, b, it, k) -> float:
+    return lib().orc_multi_u(int(seed), int(t), int(b), int(it), int(k))
+
+
+def multinomial_ancestors(lw, seed, t, b=0, it=0):
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    N = lw.shape[0]
+    M = lw[lw == lw].max()
+    w = np.where(lw == lw, np.exp(lw - M), 0.0)
+    W = np.empty(N)
+    acc = 0.0
+    for j in range(N):
+        acc = acc + w[j]
+        W[j] = acc
+    jstar = int(np.flatnonzero(w > 0)[-1])
+    a = np.zeros(N, dtype=np.int32)
+    lib().orc_multinomial_ancestors(N, _dp(W), float(W[-1]), jstar, int(seed), int(t), int(b),
+                                    int(it), _ip(a))
+    return a

@@ -885,8 +885,31 @@ void orc_metropolis_ancestors(int64_t N, const double* lw, int32_t steps, uint64
   }
 }
 
+/* Multinomial resampling, as Alg. 2 writes it: N independent uniforms,
+ * u_k = the uniform of word k mod 4 of the generator at (k div 4, t, tag
+ * MULTI | iteration, b), and a_k = min{ j : W_j > u_k S } (the inverse of
+ * the cumulative weights; rounding overflow to the last positive weight).
+ * Unsorted. */
+double orc_multi_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k) {
+  uint32_t ctr[4] = {(uint32_t)(k >> 2), (uint32_t)t, ((uint32_t)ORC_TAG_MULTI << 28) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return orc_u01(w[k & 3]);
+}
+
+void orc_multinomial_ancestors(int64_t N, const double* W, double S, int64_t jstar,
+                               uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int32_t* a) {
+  for (int64_t k = 0; k < N; ++k) {
+    const double thr = orc_multi_u(seed, t, b, iter, k) * S;
+    int64_t j = 0;
+    while (j < N && !(W[j] > thr)) ++j;
+    a[k] = (int32_t)(j < N ? j : jstar);
+  }
+}
+
 /* Alg. 2 with a choice of resampler (0 systematic, 1 stratified, 2
- * Metropolis with `steps` moves) and resampling only when ESS < ess_frac N
+ * Metropolis with `steps` moves, 3 multinomial) and resampling only when ESS < ess_frac N
  * (ess_frac = +inf: every time).  Without resampling the log-weights carry
  * over: the time-t weights are carry + lw_t, the likelihood factor is
  * ln sum exp(carry + lw_t) - ln sum exp(carry) (ln N after a resampling),
@@ -937,6 +960,8 @@ int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint
           orc_stratified_ancestors(N, W, S, jstar, P->seed, t, b, iter, a);
         } else if (resampler == 2) {
           orc_metropolis_ancestors(N, lw, steps, P->seed, t, b, iter, a);
+        } else if (resampler == 3) {
+          orc_multinomial_ancestors(N, W, S, jstar, P->seed, t, b, iter, a);
         } else {
           const double u = orc_resample_u(P->seed, t, b, iter), Nd = (double)N;
           int64_t j = 0;

@@ -8,6 +8,9 @@ collective over the weights) and for resampling triggered by the ESS:
   in N W (the same FP64 products), the offsets are the generator's uniforms,
   offspring counts sum to N and stay within one of floor(b) - floor(a), and
   their mean over many draws is N w_j (unbiased);
+* multinomial resampling (as Alg. 2 writes it): the inverse CDF of the
+  generator's uniforms (numpy searchsorted), offspring counts with the
+  multinomial mean and variance, an unbiased filter;
 * Metropolis resampling: no moves is the identity; equal weights give
   uniform ancestors; with many moves the offspring mean approaches N w_j
   (the chain's stationary law), which a reversed acceptance test fails;
@@ -153,5 +156,51 @@ def test_variants_unbiased_against_kalman(orc, resampler, ess_frac):
     R = 200
     lls = np.array([orc.pf_run_ex(dataclasses.replace(pb, seed=s), resampler=resampler,
                                   ess_frac=ess_frac)["loglik"] for s in range(R)])
+    ratio = np.exp(lls - ll_kf)
+    assert abs(ratio.mean() - 1.0) < 4 * ratio.std(ddof=1) / math.sqrt(R) + 1e-3
+
+
+def test_multinomial_is_the_inverse_cdf_of_the_generator_uniforms(orc):
+    for k in (0, 1, 5, 999):
+        w = orc.philox([k >> 2, 3, (orc.TAG_MULTI << 28) | 1, 6], [2, 0])
+        assert orc.multi_u(2, 3, 6, 1, k) == orc.u01(int(w[k & 3]))
+    rng = np.random.default_rng(8)
+    N = 500
+    lw = rng.normal(size=N) * 2
+    a = orc.multinomial_ancestors(lw, seed=2, t=3, b=6, it=1)
+    w = np.exp(lw - lw.max())
+    Wc = _seq_cumsum(w)
+    u = np.array([orc.multi_u(2, 3, 6, 1, k) for k in range(N)])
+    np.testing.assert_array_equal(a, np.minimum(np.searchsorted(Wc, u * Wc[-1], side="right"),
+                                                N - 1))
+
+
+@pytest.mark.parametrize("weights", [[0.3, 0.7], [0.9, 0.01, 0.01, 0.08], [1, 0, 0, 3, 0, 2, 2, 0]])
+def test_multinomial_counts_are_multinomial(orc, weights):
+    """Offspring counts: mean N w_j and the multinomial variance N w_j (1 - w_j)."""
+    w = np.asarray(weights, dtype=np.float64)
+    N = w.size
+    with np.errstate(divide="ignore"):
+        lw = np.log(w)
+    R = 4000
+    cnt = np.array([np.bincount(orc.multinomial_ancestors(lw, seed=9, t=t), minlength=N)
+                    for t in range(1, R + 1)])
+    p = w / w.sum()
+    sd = np.sqrt(N * p * (1 - p))
+    assert np.all(np.abs(cnt.mean(axis=0) - N * p) <= 4 * sd / math.sqrt(R) + 1e-9)
+    v = cnt.var(axis=0, ddof=1)
+    ok = p > 0
+    assert np.all(np.abs(v[ok] - (N * p * (1 - p))[ok]) <= 0.15 * (N * p * (1 - p))[ok] + 1e-9)
+    assert np.all(cnt[:, ~ok] == 0)
+
+
+def test_multinomial_filter_unbiased_against_kalman(orc):
+    pb = W.windkessel(N=128, T=30)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    ll_kf, _ = orc.kf_wk(pb)
+    R = 200
+    lls = np.array([orc.pf_run_ex(dataclasses.replace(pb, seed=s), resampler=3)["loglik"]
+                    for s in range(R)])
     ratio = np.exp(lls - ll_kf)
     assert abs(ratio.mean() - 1.0) < 4 * ratio.std(ddof=1) / math.sqrt(R) + 1e-3

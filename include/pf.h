@@ -195,6 +195,10 @@ pf_status pf_kalman(pf_handle* h, double* loglik_out, double* ell_out);
  *     r = (s-1) mod 2, of the generator at (k, t, tag 3 | block
  *     2 + (s-1) div 2 | iteration, b).  No scan or counts; unsorted; tends
  *     to multinomial resampling as steps grows.
+ *   PF_RESAMPLE_MULTINOMIAL (Alg. 2's own): independent uniforms u_k (word
+ *     k mod 4 of the generator at (k div 4, t, tag 10 | iteration, b)),
+ *     a_k = min{j : W_j > u_k S} by binary search of the cumulative weights;
+ *     unsorted.
  * ess_frac: resample only when ESS < ess_frac N (+inf: every time).  A time
  * that does not resample keeps its log-weights (the next interval adds to
  * them), its likelihood factor is ln sum exp(carried + new) - ln sum
@@ -204,6 +208,7 @@ pf_status pf_kalman(pf_handle* h, double* loglik_out, double* ell_out);
 #define PF_RESAMPLE_SYSTEMATIC 0
 #define PF_RESAMPLE_STRATIFIED 1
 #define PF_RESAMPLE_METROPOLIS 2
+#define PF_RESAMPLE_MULTINOMIAL 3
 #define PF_METROPOLIS_MAX_STEPS 508
 pf_status pf_set_resampler(pf_handle* h, int32_t scheme, int32_t steps, double ess_frac);
 

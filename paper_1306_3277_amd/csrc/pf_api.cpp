@@ -58,7 +58,7 @@ struct Layout {
   int64_t nblk_total = 0;
   // byte offsets into the workspace
   size_t x_cur, x_tmp, lw, counts, anc, part, boff, bstate, bjs, fs, ell, ess, theta, obs, obs_pos, obs_idx,
-      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, kf_ll, kf_ell, total;
+      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, kf_ll, kf_ell, wcum, total;
   int32_t n_chunks = 0;
 };
 
@@ -183,6 +183,7 @@ Layout make_layout(const pf_config* c) {
   L.b_u = take(8 * (size_t)c->B);
   L.kf_ll = take(8 * (size_t)c->B);
   L.kf_ell = take(8 * (size_t)c->B * c->T);
+  L.wcum = take(c->layout == PF_LAYOUT_PLAIN ? 8 * (size_t)L.n_total : 8);
   L.total = p;
   return L;
 }
@@ -282,6 +283,7 @@ PlainArgs plain_args(const pf_handle* H, int b) {
   a.ell_tr = H->at<double>(H->L.ell) + (size_t)b * c.T;
   a.ess_tr = H->at<double>(H->L.ess) + (size_t)b * c.T;
   a.rs = H->rs;
+  a.wcum = H->at<double>(H->L.wcum) + (c.layout == PF_LAYOUT_PLAIN ? H->L.off[b] : 0);
   return a;
 }
 
@@ -532,6 +534,17 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
       HIP_TRY(pfk::launch_metropolis_gather(c.precision, H->at<double>(H->L.lw),
                                             H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
                                             H->at<int32_t>(H->L.anc), a, s));
+      if ((st = ev_end(H, e0, 3, s))) return st;
+    } else if (H->rs.scheme == pfk::RS_MULTINOMIAL) {
+      // the scan leaves the cumulative weights; unsorted ancestors by search
+      HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
+                                     H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
+                                     H->at<int32_t>(H->L.bjs), a, s));
+      if ((st = ev_end(H, e0, 2, s))) return st;
+      if ((st = ev_begin(H, &e0, s))) return st;
+      HIP_TRY(pfk::launch_multinomial_gather(c.precision, a.wcum, H->at<int32_t>(H->L.bjs),
+                                             H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
+                                             H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
     } else {
       HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
@@ -1474,7 +1487,7 @@ pf_status pf_set_resampler(pf_handle* H, int32_t scheme, int32_t steps, double e
   pf_status st = check_handle(H);
   if (st) return st;
   if (scheme != PF_RESAMPLE_SYSTEMATIC && scheme != PF_RESAMPLE_STRATIFIED &&
-      scheme != PF_RESAMPLE_METROPOLIS)
+      scheme != PF_RESAMPLE_METROPOLIS && scheme != PF_RESAMPLE_MULTINOMIAL)
     return fail(PF_E_INVAL, "unknown resampler %d", scheme);
   if (steps < 0 || steps > PF_METROPOLIS_MAX_STEPS)
     return fail(PF_E_INVAL, "steps must be in [0, %d]", PF_METROPOLIS_MAX_STEPS);

@@ -350,6 +350,35 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     }
     return;
   }
+  if constexpr (RS == RS_MULTINOMIAL) {
+    // multinomial resampling as Alg. 2 writes it: the cumulative weights go
+    // to LDS (exactly non-decreasing), then output k takes the first W_j
+    // above u_k S by binary search
+#pragma unroll
+    for (int e = 0; e < MAXP; ++e) {
+      const int i = i0 + e;
+      if (e < P && i < i1) stage[i] = fmin(fmax(pre + loc[e], vprev), S);
+    }
+    __syncthreads();  // 6
+    const Key key = bkey(A.key);
+    const uint32_t it = fs->iter;
+#pragma unroll 1
+    for (int k = (int)threadIdx.x; k < N; k += NT) {
+      int a = k;
+      if (draw_rs) {
+        const double thr = multi_u(key, t, (uint32_t)f, it, k) * S;
+        int lo = 0, hi = N;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (stage[mid] > thr) hi = mid;
+          else lo = mid + 1;
+        }
+        a = lo < N ? lo : (jstar >= 0 && jstar < N ? jstar : 0);
+      }
+      anc[off + k] = a;
+    }
+    return;
+  }
   const bool per_particle = !draw_rs || per_particle_w;
   // (3) stratum counts of this lane's particles, to LDS
 #pragma unroll
@@ -526,6 +555,7 @@ hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const
     case RS_SYSTEMATIC: PF_K5B(NTV, RS_SYSTEMATIC); break;    \
     case RS_STRATIFIED: PF_K5B(NTV, RS_STRATIFIED); break;    \
     case RS_METROPOLIS: PF_K5B(NTV, RS_METROPOLIS); break;    \
+    case RS_MULTINOMIAL: PF_K5B(NTV, RS_MULTINOMIAL); break;  \
     default: return hipErrorInvalidValue;                     \
   }
   switch (nt) {

@@ -12,7 +12,8 @@
 
 namespace pfk {
 
-enum : uint32_t { TAG_INIT = 1, TAG_NOISE = 2, TAG_RESAMPLE = 3, TAG_DATA = 4, TAG_OBS = 8 };
+enum : uint32_t { TAG_INIT = 1, TAG_NOISE = 2, TAG_RESAMPLE = 3, TAG_DATA = 4, TAG_OBS = 8,
+                  TAG_MULTI = 10 };
 constexpr int WAVE = 64;
 
 // ---------------------------------------------------------------- generator
@@ -642,6 +643,15 @@ __device__ __forceinline__ uint4 metro_draw(Key key, int32_t t, uint32_t b, uint
   return draw(key, TAG_RESAMPLE, 2u + (uint32_t)((s - 1) >> 1), iter, (uint32_t)k, (uint32_t)t,
               b);
 }
+// Multinomial uniform of output k: word k mod 4 of the generator at
+// (k div 4, t, tag MULTI | iteration, b).
+__device__ __forceinline__ double multi_u(Key key, int32_t t, uint32_t b, uint32_t iter,
+                                          int32_t k) {
+  const uint4 w = draw(key, TAG_MULTI, 0, iter, (uint32_t)k >> 2, (uint32_t)t, b);
+  const uint32_t r = k & 3;
+  return u01_f64(r == 0 ? w.x : r == 1 ? w.y : r == 2 ? w.z : w.w);
+}
+
 __device__ __forceinline__ int32_t metro_index(uint32_t w, int32_t N) {
   return (int32_t)(((uint64_t)w * (uint64_t)N) >> 32);
 }

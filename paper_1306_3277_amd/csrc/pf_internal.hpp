@@ -24,7 +24,7 @@ struct FilterState {
 };
 
 // Resampling variants: the ancestors of a resampling time.
-enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2 };
+enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2, RS_MULTINOMIAL = 3 };
 
 // How a filter resamples: the variant, its Metropolis moves, and the ESS
 // trigger (resample when ESS < ess_frac N; +inf: every time).
@@ -60,6 +60,7 @@ struct PlainArgs {
   double* ell_tr;         // this filter's trace rows [T]
   double* ess_tr;
   ResampleArgs rs;
+  double* wcum;           // this filter's cumulative weights [N] (multinomial only)
 };
 
 // One filter of a batched collective launch: its index, first particle and
@@ -119,6 +120,9 @@ hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
 hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
                                    int32_t* anc, const PlainArgs& a, hipStream_t s);
+hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* bjs,
+                                     const void* xprop, void* xcur, int32_t* anc,
+                                     const PlainArgs& a, hipStream_t s);
 hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, double obs_sd,
                            hipStream_t s);
 // ---- batched (pf_batched.hip) ----

@@ -439,6 +439,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
     const int64_t j = j0 + e;
     const double W = fmin(fmax(V[e], vprev), hi_off);
     c[e] = (j < N) ? (finite ? count(W) : j + 1) : 0;
+    if (A.rs.scheme == RS_MULTINOMIAL && j < N) A.wcum[j] = W;
     if (j < N) counts[A.off + j] = (int32_t)c[e];
   }
   // merge-path states on the K4 block boundaries (see above)
@@ -642,6 +643,41 @@ __global__ __launch_bounds__(K1_NT) void k_metropolis(const double* __restrict__
   anc[A.off + k] = j;
 }
 
+// Multinomial resampling, as Alg. 2 writes it: output k takes
+// a_k = min{j : W_j > u_k S} for an independent uniform u_k, by binary
+// search of the cumulative weights K3 left (exactly non-decreasing);
+// rounding overflow goes to the last positive weight (from K3's per-block
+// candidates).  A step that keeps its weights, or has none positive, gives
+// the identity.
+__global__ __launch_bounds__(K1_NT) void k_multinomial(const double* __restrict__ wcum,
+                                                       const int32_t* __restrict__ bjs_all,
+                                                       int32_t* __restrict__ anc, PlainArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  if (k >= A.N) return;
+  const FilterState* f = A.fs;
+  const double S = f->S;
+  const bool draw_rs = (f->M > -INFINITY) && (f->M < INFINITY) && (S > 0.0) && !f->carry;
+  int64_t a = k;
+  if (draw_rs) {
+    const double thr = multi_u(key_of(A.key), f->t, A.b, f->iter, (int32_t)k) * S;
+    int64_t lo = 0, hi = A.N;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (wcum[mid] > thr) hi = mid;
+      else lo = mid + 1;
+    }
+    if (lo < A.N) {
+      a = lo;
+    } else {
+      int32_t js = -1;
+      const int nb3 = (int)((A.N + K3_SPAN - 1) / K3_SPAN);
+      for (int i = 0; i < nb3; ++i) js = max(js, bjs_all[A.bj0 + i]);
+      a = js >= 0 ? js : 0;
+    }
+  }
+  anc[A.off + k] = (int32_t)a;
+}
+
 // x_cur[k] = x_prop[a_k] for unsorted ancestors.
 template <typename Real>
 __global__ __launch_bounds__(K1_NT) void k_anc_gather(const Real* __restrict__ xprop,
@@ -822,6 +858,20 @@ hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xpro
                                    int32_t* anc, const PlainArgs& a, hipStream_t s) {
   const unsigned g = nblocks(a.N, K1_NT);
   hipLaunchKernelGGL(k_metropolis, g, K1_NT, 0, s, lw, anc, a);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
+                       (double*)xcur, (const int32_t*)anc, a);
+  else
+    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
+                       (const int32_t*)anc, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* bjs,
+                                     const void* xprop, void* xcur, int32_t* anc,
+                                     const PlainArgs& a, hipStream_t s) {
+  const unsigned g = nblocks(a.N, K1_NT);
+  hipLaunchKernelGGL(k_multinomial, g, K1_NT, 0, s, wcum, bjs, anc, a);
   if (prec == 0)
     hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
                        (double*)xcur, (const int32_t*)anc, a);

@@ -3,8 +3,8 @@ with the oracle, through the C ABI, FP64, plain and batched layouts:
 log-weights (carried ones included) bit for bit at every time, likelihood
 increments within 1e-10 relative, ESS within 1e-9; ancestors bit for bit
 (Metropolis resampling decides on bit-identical log-weights with the same
-logarithm; stratified resampling compares FP64 sums taken in another order,
-so a flip within 1e-9 of a stratum edge would be legitimate and is
+logarithm; stratified and multinomial resampling compare FP64 sums taken in
+another order, so a flip within 1e-9 of an edge would be legitimate and is
 checked); final particles bit for bit."""
 import dataclasses
 
@@ -42,6 +42,17 @@ def _strat_flips_in_band(lw, a_gpu, a_ref, seed, t, b):
     return mism.size
 
 
+def _multi_flips_in_band(lw, a_gpu, a_ref, seed, t, b):
+    mism = np.flatnonzero(a_gpu != a_ref)
+    if mism.size:
+        w = np.exp(lw - lw.max())
+        cw = np.cumsum(w) / w.sum()
+        for k in mism:
+            uk = oracle.multi_u(seed, t, b, 0, int(k))
+            assert np.min(np.abs(cw - uk)) < BAND
+    return mism.size
+
+
 def _check(pfm, pb, layout, scheme, steps, ess_frac):
     n = pb.n_particles
     off = np.concatenate([[0], np.cumsum(n)])
@@ -62,10 +73,12 @@ def _check(pfm, pb, layout, scheme, steps, ess_frac):
             ag, ar = a[off[b]:off[b + 1]], refs[b]["anc"][t - 1]
             if scheme == oracle.RESAMPLE_STRATIFIED:
                 flips += _strat_flips_in_band(refs[b]["lw"][t - 1], ag, ar, pb.seed, t, b)
+            elif scheme == oracle.RESAMPLE_MULTINOMIAL:
+                flips += _multi_flips_in_band(refs[b]["lw"][t - 1], ag, ar, pb.seed, t, b)
             else:
                 np.testing.assert_array_equal(ag, ar, err_msg=f"filter {b}, t = {t}")
         if flips:
-            pytest.skip("a stratified ancestor flipped inside the 1e-9 band")
+            pytest.skip("an ancestor flipped inside the 1e-9 band")
     ell, ess = f.trace()
     x = f.get_state()
     for b in range(pb.B):
@@ -82,7 +95,9 @@ CASES = [(oracle.RESAMPLE_STRATIFIED, 0, float("inf")),
          (oracle.RESAMPLE_METROPOLIS, 9, float("inf")),
          (oracle.RESAMPLE_SYSTEMATIC, 0, 0.5),
          (oracle.RESAMPLE_STRATIFIED, 0, 0.5),
-         (oracle.RESAMPLE_METROPOLIS, 4, 0.5)]
+         (oracle.RESAMPLE_METROPOLIS, 4, 0.5),
+         (oracle.RESAMPLE_MULTINOMIAL, 0, float("inf")),
+         (oracle.RESAMPLE_MULTINOMIAL, 0, 0.5)]
 
 
 @pytest.mark.parametrize("scheme,steps,ess_frac", CASES)
@@ -117,7 +132,7 @@ def test_variant_rules(pfm):
     _, y = oracle.simulate(base)
     pb = base.with_obs(y)
     f = pfm.Filter(pb, precision=pfm.PF_FP64)
-    for bad in [(3, 0, 1.0), (0, -1, 1.0), (2, 509, 1.0), (0, 0, -0.5), (0, 0, float("nan"))]:
+    for bad in [(4, 0, 1.0), (0, -1, 1.0), (2, 509, 1.0), (0, 0, -0.5), (0, 0, float("nan"))]:
         with pytest.raises(pfm.PfError):
             f.set_resampler(*bad)
     f.set_resampler(pfm.PF_RESAMPLE_STRATIFIED)

@@ -217,7 +217,8 @@ def large_filter_leg(torch, pfm, stream):
     kb = kernel_times(rb, 10)
     dtb = timed(torch, rb, 20, 2)
     variants = {}
-    for name, scheme, msteps in (("stratified", 1, 0), ("metropolis_8", 2, 8)):
+    for name, scheme, msteps in (("stratified", 1, 0), ("multinomial", 3, 0),
+                                 ("metropolis_8", 2, 8)):
         fb.set_resampler(scheme, msteps)
         rb.restart()
         kv = kernel_times(rb, 10)
@@ -251,7 +252,8 @@ def large_filter_leg(torch, pfm, stream):
 
 
 RESAMPLER_CASES = [("systematic", 0, 0, float("inf")), ("stratified", 1, 0, float("inf")),
-                   ("metropolis_8", 2, 8, float("inf")), ("systematic_ess0.5", 0, 0, 0.5)]
+                   ("multinomial", 3, 0, float("inf")), ("metropolis_8", 2, 8, float("inf")),
+                   ("systematic_ess0.5", 0, 0, 0.5)]
 
 
 def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=100):

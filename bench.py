@@ -471,7 +471,9 @@ def main():
         return
 
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    threads, groups, cand_ms = f32.autotune(steps=16)
+    # the tuner replays every candidate over the whole horizon (the weights'
+    # concentration, and with it the collective's work, changes along it)
+    threads, groups, cand_ms = f32.autotune(steps=pb.T - 1)
     log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
         f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
         f"{np.round(cand_ms * 1e3, 1).tolist()}")
@@ -599,7 +601,7 @@ def main():
             pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-            fm.autotune(steps=4)
+            fm.autotune(steps=pm.T - 1)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = fm.pmmh(inp)

@@ -178,7 +178,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   __shared__ double xa[NW], xb[NW], xc[NW], xm[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
-  __shared__ int brs;
   uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
   int32_t* al = reinterpret_cast<int32_t*>(stage) + BATCH_MAXN / 2;   // ancestors, 32 KB
   const FilterSlot slot = A.order[A.order0 + blockIdx.x];
@@ -186,7 +185,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   const int64_t off = slot.off;
   const int N = slot.n;
   FilterState* fs = A.fs + f;
+  // the filter's scalars, fetched with the weights so that no later phase
+  // waits on a global load
   const double loglik0 = fs->loglik;
+  const double lprev0 = fs->lprev;
+  const int carry0 = fs->carry;
+  const uint32_t iter = fs->iter;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const bool resample_only = A.mode != 0;
   const int t = resample_only ? fs->t : fs->t + 1;
@@ -198,6 +202,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     double v[MAXP];
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) v[r] = lw[off + min((int)threadIdx.x + r * NT, N - 1)];
+    // the resampling uniform, drawn while the loads are in flight and
+    // published with the first exchange
+    if (threadIdx.x == 0)
+      bc = resample_only ? A.u_override[f]
+                         : u01_f64(draw(bkey(A.key), TAG_RESAMPLE, 0, iter, 0, (uint32_t)t,
+                                        (uint32_t)f).x);
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
       const int i = (int)threadIdx.x + r * NT;
@@ -208,15 +218,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       }
     }
   }
-  // the resampling uniform, drawn while the loads are in flight
-  double u = 0.0;
-  if (threadIdx.x == 0)
-    u = resample_only ? A.u_override[f]
-                      : u01_f64(draw(bkey(A.key), TAG_RESAMPLE, 0, fs->iter, 0, (uint32_t)t,
-                                     (uint32_t)f).x);
   m = wave_max(m);
   if (lane == 0) xa[wv] = m;
   __syncthreads();  // 1
+  double u = bc;
   double M = xa[0];
 #pragma unroll
   for (int w = 1; w < NW; ++w) M = fmax(M, xa[w]);
@@ -280,49 +285,46 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   }
   vprev = (lane == 0) ? vw : fmax(vprev, vw);
   S = fmax(S, vall);
-  if (threadIdx.x == 0) {
-    int carry = 0;
-    if (!resample_only) {
-      double ell, ess;
-      // the factor's normaliser: ln N after a resampling, else the carried
-      // weights' ln sum exp
-      const double lprev = fs->carry ? fs->lprev : log((double)N);
-      if (finite && S > 0.0) {
-        const double L = M + log(S);
-        ell = L - lprev;
-        ess = (S * S) / S2;
-        carry = !(ess < A.rs.ess_frac * (double)N);  // resample when ESS < ess_frac N
-        fs->lprev = L;
-      } else {
-        ell = -INFINITY;
-        ess = 0.0;
-        fs->status = 4;
-      }
-      fs->carry = carry;
-      fs->loglik = loglik0 + ell;
-      fs->M = finite ? M : -INFINITY;
-      fs->S = S;
-      fs->ell = ell;
-      fs->ess = ess;
-      A.ell_tr[(size_t)f * A.T + t - 1] = ell;
-      A.ess_tr[(size_t)f * A.T + t - 1] = ess;
-      fs->u = u;
-      fs->t = t;
+  // every lane holds the same S and S2, so every lane takes the trigger's
+  // decision itself (resample when ESS < ess_frac N); a step that keeps its
+  // weights, or has none positive, gives every particle one offspring:
+  // itself
+  const bool ok = finite && S > 0.0;
+  const double ess = ok ? (S * S) / S2 : 0.0;
+  const int carry = (!resample_only && ok) ? !(ess < A.rs.ess_frac * (double)N) : 0;
+  const bool draw_rs = finite && !carry;
+  // the filter's bookkeeping, by one lane once nothing waits on it
+  auto finish = [&]() {
+    if (threadIdx.x != 0 || resample_only) return;
+    double ell;
+    // the factor's normaliser: ln N after a resampling, else the carried
+    // weights' ln sum exp
+    const double lprev = carry0 ? lprev0 : log((double)N);
+    if (ok) {
+      const double L = M + log(S);
+      ell = L - lprev;
+      fs->lprev = L;
+    } else {
+      ell = -INFINITY;
+      fs->status = 4;
     }
-    bc = u;
-    brs = !carry;
-  }
-  __syncthreads();  // 5
-  u = bc;
-  // a step that keeps its weights, or has none positive, gives every
-  // particle one offspring: itself
-  const bool draw_rs = finite && brs;
+    fs->carry = carry;
+    fs->loglik = loglik0 + ell;
+    fs->M = finite ? M : -INFINITY;
+    fs->S = S;
+    fs->ell = ell;
+    fs->ess = ess;
+    A.ell_tr[(size_t)f * A.T + t - 1] = ell;
+    A.ess_tr[(size_t)f * A.T + t - 1] = ess;
+    fs->u = u;
+    fs->t = t;
+  };
   const double invS = 1.0 / S;
   if constexpr (RS == RS_METROPOLIS) {
     // Metropolis resampling from the staged log-weights, no counts or merge:
     // output k starts at particle k and takes A.rs.steps moves
     const Key key = bkey(A.key);
-    const uint32_t it = fs->iter;
+    const uint32_t it = iter;
 #pragma unroll 1
     for (int k = (int)threadIdx.x; k < N; k += NT) {
       int j = k;
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       }
       anc[off + k] = j;
     }
+    finish();
     return;
   }
   if constexpr (RS == RS_MULTINOMIAL) {
@@ -361,7 +364,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     }
     __syncthreads();  // 6
     const Key key = bkey(A.key);
-    const uint32_t it = fs->iter;
+    const uint32_t it = iter;
 #pragma unroll 1
     for (int k = (int)threadIdx.x; k < N; k += NT) {
       int a = k;
@@ -377,6 +380,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       }
       anc[off + k] = a;
     }
+    finish();
     return;
   }
   const bool per_particle = !draw_rs || per_particle_w;
@@ -389,7 +393,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       int32_t c = i + 1;
       if (draw_rs) {
         if constexpr (RS == RS_STRATIFIED)
-          c = stratum_count_strat(W, S, invS, N, bkey(A.key), t, (uint32_t)f, fs->iter);
+          c = stratum_count_strat(W, S, invS, N, bkey(A.key), t, (uint32_t)f, iter);
         else
           c = stratum_count(W, S, invS, u, N);
       }
@@ -456,6 +460,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     const int k = (int)threadIdx.x + r * NT;
     if (k < N) anc[off + k] = al[k];
   }
+  finish();
 }
 
 // x_out = x_prop[ancestors]: materialises the equally weighted set for

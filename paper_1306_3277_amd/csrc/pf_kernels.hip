@@ -203,6 +203,8 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   FilterState* fst = A.fs;
   const int t = fst->t + 1;
   const double loglik0 = fst->loglik;
+  const double lprev0 = fst->lprev;
+  const int carry0 = fst->carry;
   double u = 0.0;
   if (threadIdx.x == 0)
     u = u01_f64(draw(key_of(A.key), TAG_RESAMPLE, 0, fst->iter, 0, (uint32_t)t, A.b).x);
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
     double ell, ess;
     // the factor's normaliser: ln N after a resampling, else the carried
     // weights' ln sum exp
-    const double lprev = f->carry ? f->lprev : log((double)A.N);
+    const double lprev = carry0 ? lprev0 : log((double)A.N);
     int carry = 0;
     if (finite && Sf > 0.0) {
       const double L = M + log(Sf);

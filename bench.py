@@ -398,7 +398,9 @@ def main():
                     help="untimed intervals before the timed ones (the device clocks settle)")
     ap.add_argument("--fp64-steps", type=int, default=40,
                     help="intervals timed for the FP64 plain comparison")
-    ap.add_argument("--pmmh-iters", type=int, default=10)
+    ap.add_argument("--pmmh-iters", type=int, default=2000)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further repeats of the headline's timed region (spread only)")
     ap.add_argument("--tf-steps", type=int, default=8, help="teacher-forced error intervals")
     ap.add_argument("--smc2-T", type=int, default=200,
                     help="observation times of the SMC^2 leg (0: skip it)")
@@ -471,14 +473,24 @@ def main():
         return
 
     f32 = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    # the tuner replays every candidate over the whole horizon (the weights'
-    # concentration, and with it the collective's work, changes along it)
-    threads, groups, cand_ms = f32.autotune(steps=pb.T - 1)
-    log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
-        f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
-        f"{np.round(cand_ms * 1e3, 1).tolist()}")
+    if args.profile_headline:
+        # counter runs replay each kernel under the profiler: a fixed tuning
+        # keeps them short
+        threads, groups = 512, 2
+        f32.set_tuning(threads, groups)
+    else:
+        # the tuner replays every candidate over the whole horizon (the
+        # weights' concentration, and with it the collective's work, changes
+        # along it)
+        threads, groups, cand_ms = f32.autotune(steps=pb.T - 1)
+        log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
+            f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
+            f"{np.round(cand_ms * 1e3, 1).tolist()}")
     r32 = Runner(f32, pb.T)
     dt32 = timed(torch, r32, args.steps, args.warmup)
+    # the same timed region repeated, for the spread of the figure
+    reps = [] if args.profile_headline else [
+        timed(torch, r32, args.steps, 0) / args.steps * 1e3 for _ in range(args.repeats)]
     # per-kernel durations on one stream (no group overlap), for the roofline
     f32.set_tuning(threads, 1)
     kt32 = kernel_times(r32, min(args.steps, pb.T))
@@ -566,6 +578,8 @@ def main():
                          "fp32_free_running_median_abs_diff_vs_fp64":
                              float(np.median(np.abs(ll32 - ll64)))},
         "kernels_us": {"fp32_batched": kt32},
+        "repeats_ms_per_step": {"values": [round(x, 5) for x in reps],
+                                "median": float(np.median(reps)) if reps else None},
         "roofline": roofline,
     }
 

@@ -390,7 +390,51 @@ def smc2_leg(torch, pfm, pb, stream, T, threads, groups):
     return leg
 
 
+def oracle_worker(argv):
+    """One process of the all-cores oracle figure: filters w, w + P, ... of
+    the headline workload (observations from the file the parent wrote), the
+    first T / 10 intervals each, for about `seconds`; prints its work and
+    time.  Uses no GPU."""
+    w, P, seconds, obs_path = int(argv[0]), int(argv[1]), float(argv[2]), argv[3]
+    import oracle
+    pb = W.config("c4").with_obs(np.load(obs_path, allow_pickle=False))
+    t0 = time.perf_counter()
+    done_ps, nf, b = 0, 0, w
+    while time.perf_counter() - t0 < seconds and b < pb.B:
+        oracle.pf_run(pb, theta=pb.theta[b], N=int(pb.n_particles[b]), b=b, T=pb.T // 10)
+        done_ps += int(pb.n_particles[b]) * (pb.T // 10)
+        nf += 1
+        b += P
+    print(json.dumps({"ps": done_ps, "s": time.perf_counter() - t0, "filters": nf}), flush=True)
+
+
+def oracle_all_cores(pb, seconds, procs):
+    """The oracle run by `procs` child processes at once on disjoint filters:
+    the aggregate rate of the host's cores."""
+    import subprocess
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".npy")
+    os.close(fd)
+    try:
+        np.save(path, np.ascontiguousarray(pb.obs), allow_pickle=False)
+        ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                                str(w), str(procs), str(seconds), path],
+                               stdout=subprocess.PIPE, text=True) for w in range(procs)]
+        res = []
+        for p in ps:
+            out, _ = p.communicate(timeout=seconds * 4 + 120)
+            if p.returncode != 0:
+                raise RuntimeError(f"oracle worker exited with {p.returncode}")
+            res.append(json.loads(out.strip().splitlines()[-1]))
+    finally:
+        os.unlink(path)
+    return res
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
+        oracle_worker(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -424,6 +468,8 @@ def main():
                     help="run one plain 2 GiB device-to-device copy (scales the memory "
                          "counters) and exit")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="processes of the all-cores oracle figure (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the filters of the batched workload shard across "
@@ -615,7 +661,7 @@ def main():
             pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-            fm.autotune(steps=pm.T - 1)
+            pm_threads, pm_groups, _ = fm.autotune(steps=pm.T - 1)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = fm.pmmh(inp)
@@ -624,6 +670,7 @@ def main():
             fm.close()
             nfilt = pm.B * (args.pmmh_iters + 1)
             out["pmmh"] = {"chains": pm.B, "iterations": args.pmmh_iters,
+                           "collective_workgroup": pm_threads, "filter_groups": pm_groups,
                            "particles": int(pm.n_particles[0]), "T": pm.T,
                            "filters_per_s": nfilt / dtm,
                            "particle_steps_per_s": nfilt * int(pm.n_particles[0]) * pm.T / dtm,
@@ -669,6 +716,16 @@ def main():
                                "sample": f"{pb.name}: filters 0..{nf - 1} of {pb.B}, first "
                                          f"{pb.T // 10} of {pb.T} intervals each, FP64, one "
                                          f"thread ({dtc:.1f} s)"}
+        if args.cpu_procs > 0:
+            log(f"[bench] CPU oracle on {args.cpu_procs} processes starts")
+            procs = min(args.cpu_procs, pb.B)
+            res = oracle_all_cores(pb, args.cpu_seconds / 2, procs)
+            out["cpu_baseline_all_cores"] = {
+                "value": sum(r["ps"] / r["s"] for r in res), "unit": "particle-steps/s",
+                "cores": procs, "kind": "oracle",
+                "sample": f"{pb.name}: {sum(r['filters'] for r in res)} filters dealt round-robin "
+                          f"to {procs} processes run at once, first {pb.T // 10} of {pb.T} "
+                          f"intervals each, FP64, about {args.cpu_seconds / 2:.1f} s per process"}
     print(json.dumps(out), flush=True)
 
 

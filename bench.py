@@ -317,9 +317,10 @@ def models_leg(torch, pfm, pb, stream, threads, groups, steps=100):
 
 
 def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):
-    """The headline workload with ancestry storage attached (every interval
-    also copies its propagated particles and ancestors into the history),
-    then the state sample of every filter (Alg. 2, last lines)."""
+    """The headline workload with ancestry storage attached (the stepping
+    kernels also store every interval's propagated particles and ancestors
+    into the history), then the state sample of every filter (Alg. 2, last
+    lines)."""
     f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
     f.set_tuning(threads, groups)
     f.attach_history()
@@ -337,14 +338,14 @@ def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):
     hist_bytes = int(f.history.numel())
     f.close()
     n_tot = int(pb.n_particles.sum())
-    rec_bytes = n_tot * (2 * pb.d * 4 + 2 * 4)  # particles read + written, ancestors read + written
+    rec_bytes = n_tot * (pb.d * 4 + 4)  # the extra stores: particles and ancestors
     per = dt / pb.T
     extra = per - dt_plain_interval
     leg = {"workload": pb.name, "history_bytes": hist_bytes, "T": pb.T,
            "us_per_interval_with_history": per * 1e6,
            "us_per_interval_without": dt_plain_interval * 1e6,
+           "us_added_per_interval": extra * 1e6 if dt_plain_interval > 0 else None,
            "record_bytes_per_interval": rec_bytes,
-           "record_GBps_if_extra_time_is_recording": rec_bytes / extra / 1e9 if extra > 0 else None,
            "backtrace_ms_all_filters": dtb * 1e3, "path_shape": list(path.shape)}
     log(f"[bench] history: {per * 1e6:.1f} us/interval with recording ({hist_bytes / 2**30:.1f} GiB "
         f"history) vs {dt_plain_interval * 1e6:.1f}; backtrace of {pb.B} filters {dtb * 1e3:.2f} ms")

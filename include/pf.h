@@ -222,8 +222,9 @@ pf_status pf_set_resampler(pf_handle* h, int32_t scheme, int32_t steps, double e
  * the time-t weights), plus the backtrace's output.  pf_history_attach
  * (at t = 0, after pf_init or pf_reset; NULL detaches) records slot 0 and
  * makes every later interval, eager or graph-replayed, and every
- * re-initialisation record its slot (an extra copy of the particles and
- * ancestors per interval).  pf_backtrace (after a resampled interval, at the
+ * re-initialisation record its slot (batched layout: the stepping kernels
+ * also store their particles and ancestors there; plain layout: a copy
+ * kernel per filter and interval).  pf_backtrace (after a resampled interval, at the
  * handle's time s) draws, per filter b, the final particle as the time-s
  * systematic ancestor at slot floor(w N_b 2^-32), w the first word of the
  * generator at counter (0, s, tag 9 | iteration, b) (a uniform slot makes

@@ -426,12 +426,22 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
 
 constexpr int kGraphSteps = 8;
 
+// An attached history's slots, for the stepping kernels that record into
+// it (the propagation writes the particles, the collective the ancestors).
+void set_history(const pf_handle* H, BatchArgs& a) {
+  if (!H->hist) return;
+  const pfk::HistArgs h = hist_args(H);
+  a.hx = h.xh;
+  a.ha = h.ah;
+}
+
 // Propagation (K5a) of filter group g on stream s.
 pf_status enqueue_group_propagate(pf_handle* H, int g, hipStream_t s) {
   const pf_config& c = H->cfg;
   BatchArgs a = batch_args(H);
   a.chunk0 = H->grp_chunk0[g];
   a.order0 = H->grp_order0[g];
+  set_history(H, a);
   hipEvent_t e0{};
   pf_status st = ev_begin(H, &e0, s);
   if (st) return st;
@@ -446,15 +456,12 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
   BatchArgs a = batch_args(H);
   a.chunk0 = H->grp_chunk0[g];
   a.order0 = H->grp_order0[g];
+  set_history(H, a);
   hipEvent_t e0{};
   pf_status st = ev_begin(H, &e0, s);
   if (st) return st;
   HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
                                        H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
-  if (H->hist)
-    HIP_TRY(pfk::launch_record_batched(H->cfg.precision, H->ws + H->L.x_cur, H->ws + H->L.x_tmp,
-                                       H->at<int32_t>(H->L.anc), hist_args(H), a,
-                                       H->grp_nchunks[g], s));
   return ev_end(H, e0, 4, s);
 }
 

@@ -68,7 +68,7 @@ __device__ __forceinline__ double batch_logdens(const Real (&x)[D], const double
   return -0.5 * acc + cst;
 }
 
-template <int MODEL, int D, typename Real>
+template <int MODEL, int D, typename Real, bool HIST>
 __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__ xa,
                                                               Real* __restrict__ xb,
                                                               double* __restrict__ lw,
@@ -101,6 +101,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
         p = wk_substep_f64(p, th, A.q[n0 + s - 1], z0);
       }
       xn[dst] = p;
+      if constexpr (HIST) ((Real*)A.hx)[(int64_t)t * A.ld + dst] = p;
       const double e = (yrow[0] - (p + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
       l = -0.5 * (e * e) + A.lw_cst;
     } else {
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
         p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
       }
       xn[dst] = p;
+      if constexpr (HIST) ((Real*)A.hx)[(int64_t)t * A.ld + dst] = p;
       const double e = (yrow[0] - ((double)p + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
       l = -0.5 * (e * e) + A.lw_cst;
     }
@@ -143,6 +145,11 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) xn[(int64_t)i * A.ld + dst] = x[i];
+    if constexpr (HIST) {  // the history's slot t, written from the same registers
+      Real* xh = (Real*)A.hx + (int64_t)t * D * A.ld;
+#pragma unroll
+      for (int i = 0; i < D; ++i) xh[(int64_t)i * A.ld + dst] = x[i];
+    }
     l = batch_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
   }
   // weights kept from a step that did not resample carry over
@@ -194,6 +201,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
   const bool resample_only = A.mode != 0;
   const int t = resample_only ? fs->t : fs->t + 1;
+  // the history's ancestor slot t-1 of this filter, if one is attached
+  int32_t* const ha = A.ha ? A.ha + (int64_t)(t - 1) * A.ld + off : nullptr;
   // (1) coalesced load to the stage and the maximum; the loads are issued
   // together (indices past the filter read its last element and are
   // dropped), so their latencies overlap
@@ -349,6 +358,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         }
       }
       anc[off + k] = j;
+      if (ha) ha[k] = j;
     }
     finish();
     return;
@@ -379,6 +389,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         a = lo < N ? lo : (jstar >= 0 && jstar < N ? jstar : 0);
       }
       anc[off + k] = a;
+      if (ha) ha[k] = a;
     }
     finish();
     return;
@@ -455,10 +466,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   }
   __syncthreads();  // 7
   // (5) coalesced store of the ancestors
+  if (ha) {
 #pragma unroll
-  for (int r = 0; r < MAXP; ++r) {
-    const int k = (int)threadIdx.x + r * NT;
-    if (k < N) anc[off + k] = al[k];
+    for (int r = 0; r < MAXP; ++r) {
+      const int k = (int)threadIdx.x + r * NT;
+      if (k < N) {
+        anc[off + k] = al[k];
+        ha[k] = al[k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < MAXP; ++r) {
+      const int k = (int)threadIdx.x + r * NT;
+      if (k < N) anc[off + k] = al[k];
+    }
   }
   finish();
 }
@@ -510,6 +532,19 @@ hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc
   return hipGetLastError();
 }
 
+// K5a with or without the history stores (a separate instantiation, so the
+// kernel without a history carries no trace of them)
+template <int MODEL, int D, typename Real>
+void launch_k5a(unsigned g, hipStream_t s, void* xa, void* xb, double* lw, const int32_t* anc,
+                const BatchArgs& a) {
+  if (a.hx)
+    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, true>), g, BATCH_NT, 0, s, (Real*)xa,
+                       (Real*)xb, lw, anc, a);
+  else
+    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, false>), g, BATCH_NT, 0, s, (Real*)xa,
+                       (Real*)xb, lw, anc, a);
+}
+
 hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
                                     const int32_t* anc, const BatchArgs& a, int nchunks,
                                     hipStream_t s) {
@@ -517,30 +552,24 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
   const unsigned g = (unsigned)nchunks;
   if (model == 1) {
     if (prec == 0)
-      hipLaunchKernelGGL((k_batch_propagate<1, 1, double>), g, BATCH_NT, 0, s, (double*)xa,
-                         (double*)xb, lw, anc, a);
+      launch_k5a<1, 1, double>(g, s, xa, xb, lw, anc, a);
     else
-      hipLaunchKernelGGL((k_batch_propagate<1, 1, float>), g, BATCH_NT, 0, s, (float*)xa,
-                         (float*)xb, lw, anc, a);
+      launch_k5a<1, 1, float>(g, s, xa, xb, lw, anc, a);
     return hipGetLastError();
   }
   switch (d * 4 + model) {
-#define X(DD)                                                                              \
-  case DD * 4 + 2:                                                                         \
-    if (prec == 0)                                                                         \
-      hipLaunchKernelGGL((k_batch_propagate<2, DD, double>), g, BATCH_NT, 0, s,            \
-                         (double*)xa, (double*)xb, lw, anc, a);                            \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_batch_propagate<2, DD, float>), g, BATCH_NT, 0, s, (float*)xa, \
-                         (float*)xb, lw, anc, a);                                          \
-    break;                                                                                 \
-  case DD * 4 + 3:                                                                         \
-    if (prec == 0)                                                                         \
-      hipLaunchKernelGGL((k_batch_propagate<3, DD, double>), g, BATCH_NT, 0, s,            \
-                         (double*)xa, (double*)xb, lw, anc, a);                            \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_batch_propagate<3, DD, float>), g, BATCH_NT, 0, s, (float*)xa, \
-                         (float*)xb, lw, anc, a);                                          \
+#define X(DD)                                                  \
+  case DD * 4 + 2:                                             \
+    if (prec == 0)                                             \
+      launch_k5a<2, DD, double>(g, s, xa, xb, lw, anc, a);     \
+    else                                                       \
+      launch_k5a<2, DD, float>(g, s, xa, xb, lw, anc, a);      \
+    break;                                                     \
+  case DD * 4 + 3:                                             \
+    if (prec == 0)                                             \
+      launch_k5a<3, DD, double>(g, s, xa, xb, lw, anc, a);     \
+    else                                                       \
+      launch_k5a<3, DD, float>(g, s, xa, xb, lw, anc, a);      \
     break;
     PF_L96_DIMS_B(X)
 #undef X

@@ -92,6 +92,10 @@ struct BatchArgs {
   const double* u_override; // device [B] (resample-only mode)
   int32_t mode;             // 0: likelihood + ancestors; 1: ancestors only, given u
   ResampleArgs rs;
+  // an attached history (else null): particles [T+1][d][ld] in the state's
+  // precision, ancestors [T][ld]; the stepping kernels write slot t
+  void* hx;
+  int32_t* ha;
 };
 
 constexpr int K1_NT = 256;  // particles per propagate / scan block

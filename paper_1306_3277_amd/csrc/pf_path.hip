@@ -1,10 +1,13 @@
 // Ancestry storage and the single state sample of the bootstrap filter
 // (Alg. 2, last lines): with a history buffer attached, every time's
 // propagated (weighted) particles and the ancestors drawn from their weights
-// are copied into per-time slots; the slot index is the filter's step
-// counter read on the device, so captured graphs record too.  The backtrace
-// draws the final particle from the last weights and follows the ancestry
-// back to t_0, one workgroup per filter.
+// go to per-time slots; the slot index is the filter's step counter read on
+// the device, so captured graphs record too.  The copy kernels here record
+// the plain layout's intervals and any layout's initial particles (and
+// ancestors redrawn from given uniforms); the batched layout's stepping
+// kernels store their intervals' slots themselves.  The backtrace draws the
+// final particle from the last weights and follows the ancestry back to t_0,
+// one workgroup per filter.
 #include "pf_device.hpp"
 #include "pf_path.hpp"
 

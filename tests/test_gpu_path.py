@@ -120,3 +120,54 @@ def test_history_rules(pfm):
         f.attach_history()  # only at t = 0
     f.close()
     p.close()
+
+
+def _history_arrays(f, pb, fp64):
+    """The attached history as (particles [T+1][d][N_total], ancestors
+    [T][N_total]), laid out as pf.h states (each part 256-byte aligned)."""
+    import torch
+    torch.cuda.synchronize()
+    raw = f.history.cpu().numpy()
+    start = ((f.history.data_ptr() + 255) & ~255) - f.history.data_ptr()
+    n = int(pb.n_particles.sum())
+    sx = 8 if fp64 else 4
+    nx = sx * (pb.T + 1) * pb.d * n
+    xh = raw[start:start + nx].view(np.float64 if fp64 else np.float32)
+    a0 = start + (nx + 255) // 256 * 256
+    ah = raw[a0:a0 + 4 * pb.T * n].view(np.int32)
+    return xh.reshape(pb.T + 1, pb.d, n), ah.reshape(pb.T, n)
+
+
+@pytest.mark.parametrize("fp64", [True, False])
+def test_batched_history_holds_every_slot(pfm, fp64):
+    """Every slot of a batched history equals the state and ancestors the
+    inspection calls read after each step and resampling (one group, eager),
+    and a graph-replayed run in three filter groups records the same bytes."""
+    precision = pfm.PF_FP64 if fp64 else pfm.PF_FP32_MIXED
+    base = _data(W.lorenz96(d=8, N=1, T=6, precision=precision))
+    th0, _ = W.batched_thetas(5, seed=53)
+    n = np.array([300, 64, 1000, 33, 257], dtype=np.int64)
+    pb = dataclasses.replace(base, theta=th0, n_particles=n)
+    f = pfm.Filter(pb, precision=precision, layout=pfm.PF_LAYOUT_BATCHED)
+    f.attach_history()
+    xs = [f.get_state()]
+    anc = []
+    for _ in range(pb.T):
+        f.step()
+        xs.append(f.get_state())
+        f.resample()
+        anc.append(f.ancestors())
+    xh, ah = _history_arrays(f, pb, fp64)
+    for t in range(pb.T + 1):
+        np.testing.assert_array_equal(xh[t].astype(np.float64), xs[t], err_msg=f"slot {t}")
+    for t in range(pb.T):
+        np.testing.assert_array_equal(ah[t], anc[t], err_msg=f"ancestors {t + 1}")
+    f.close()
+    g = pfm.Filter(pb, precision=precision, layout=pfm.PF_LAYOUT_BATCHED)
+    g.set_tuning(512, 3)
+    g.attach_history()
+    g.graph_run(pb.T)
+    xh2, ah2 = _history_arrays(g, pb, fp64)
+    np.testing.assert_array_equal(xh2, xh)
+    np.testing.assert_array_equal(ah2, ah)
+    g.close()

@@ -1,10 +1,11 @@
-"""GPU parity with the oracle over a fixed-seed sweep of batched
+"""GPU parity with the oracle over fixed-seed sweeps of batched and plain
 configurations that the hand-picked tests do not combine: the three models
 (Lorenz '96 at d = 4/8/16/32/40, the paper's stage-noise form, the windkessel),
 particle counts at the edges of the 64-lane waves, 256-particle chunks and
-the 8192-particle collective (1, 2, 63..65, 255..257, 4095, 8192), every
+the 8192-particle collective (batched) or of the propagation, scan and
+merge-path blocks (plain: 255..257, 1023..1025, 2047..2049), every
 resampler with and without the ESS trigger, every collective workgroup size
-and 1-4 filter groups.  FP64 throughout: log-weights bit for bit at every
+and 1-4 filter groups (batched).  FP64 throughout: log-weights bit for bit at every
 time, ancestors bit for bit or (for FP64 comparisons of sums taken in
 another order) a flip within 1e-9 of a stratum edge, likelihood increments
 within 1e-10 relative, ESS within 1e-9, final particles bit for bit; then a
@@ -23,6 +24,9 @@ pytestmark = pytest.mark.gpu
 REL64 = 1e-10
 BAND = 1e-9
 EDGE_COUNTS = [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4095, 8192]
+# the plain layout's 256-particle propagation blocks, 1024-particle scan
+# blocks and 2048-diagonal merge-path blocks
+PLAIN_EDGE_COUNTS = [1, 2, 255, 256, 257, 1023, 1024, 1025, 2047, 2048, 2049, 4097, 20000]
 
 
 @pytest.fixture(scope="module")
@@ -35,14 +39,16 @@ def pfm():
     return pfm
 
 
-def _config(i):
-    """Configuration i of the sweep (numpy's generator, seed 2026 + i)."""
-    rng = np.random.default_rng(2026 + i)
+def _config(i, plain=False):
+    """Configuration i of the sweep (numpy's generator, seed 2026 + i, or
+    3026 + i for the plain layout)."""
+    rng = np.random.default_rng((3026 if plain else 2026) + i)
     kind = ["l96", "l96", "stage", "wk"][i % 4]
-    B = int(rng.integers(1, 8))
+    B = int(rng.integers(1, 4 if plain else 8))
     T = int(rng.integers(2, 6))
     d = [4, 16, 40, 8, 32][(i // 2) % 5] if kind == "l96" else 8
-    counts = [c for c in EDGE_COUNTS if d < 16 or c <= 1000]
+    edges = PLAIN_EDGE_COUNTS if plain else EDGE_COUNTS
+    counts = [c for c in edges if d < 16 or c <= 2049]
     n = rng.choice(counts, size=B).astype(np.int64)
     if kind == "wk":
         base = W.windkessel(N=1, T=T)
@@ -87,14 +93,13 @@ def _ancestors_agree(pb, scheme, lw, ag, ar, t, b):
     return False
 
 
-@pytest.mark.parametrize("i", range(20))
-def test_random_batched_configuration(pfm, i):
-    pb, scheme, steps, ess_frac, nt, groups = _config(i)
+def _run_config(pfm, i, layout):
+    pb, scheme, steps, ess_frac, nt, groups = _config(i, plain=layout == pfm.PF_LAYOUT_PLAIN)
     n = pb.n_particles
     off = np.concatenate([[0], np.cumsum(n)])
     refs = [oracle.pf_run_ex(pb, theta=pb.theta[b], N=int(n[b]), b=b, resampler=scheme,
                              steps=steps, ess_frac=ess_frac, traces=True) for b in range(pb.B)]
-    f = pfm.Filter(pb, precision=pfm.PF_FP64, layout=pfm.PF_LAYOUT_BATCHED)
+    f = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
     f.set_tuning(nt, groups)
     f.set_resampler(scheme, steps, ess_frac)
     exact = True
@@ -124,10 +129,20 @@ def test_random_batched_configuration(pfm, i):
     f.close()
     if not exact:
         pytest.skip(f"config {i}: an ancestor flipped inside the 1e-9 band")
-    g = pfm.Filter(pb, precision=pfm.PF_FP64, layout=pfm.PF_LAYOUT_BATCHED)
+    g = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
     g.set_tuning(nt, groups)
     g.set_resampler(scheme, steps, ess_frac)
     g.graph_run(pb.T)
     for got, want in zip((g.trace()[0], g.get_state(), g.ancestors()), eager):
         np.testing.assert_array_equal(got, want)
     g.close()
+
+
+@pytest.mark.parametrize("i", range(20))
+def test_random_batched_configuration(pfm, i):
+    _run_config(pfm, i, pfm.PF_LAYOUT_BATCHED)
+
+
+@pytest.mark.parametrize("i", range(12))
+def test_random_plain_configuration(pfm, i):
+    _run_config(pfm, i, pfm.PF_LAYOUT_PLAIN)

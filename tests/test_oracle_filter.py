@@ -191,6 +191,38 @@ def test_pf_single_particle_is_plain_likelihood(orc):
     np.testing.assert_array_equal(r["x"], x)
 
 
+def test_pmmh_chain_has_the_posterior_as_its_law(orc):
+    """Alg. 3 with an unbiased likelihood estimate leaves the exact posterior
+    invariant (pseudo-marginal MH): the chain on log F with a uniform prior
+    on F (Jacobian F) and a 16-particle filter must reproduce the mean and
+    variance of p(log F | y) obtained by quadrature of the likelihood, itself
+    the average of 512-particle estimates (unbiased) on a grid.  A dropped
+    Jacobian shifts the mean by about the variance (0.013, six standard
+    errors); a reversed acceptance test or a missed support check moves it
+    further."""
+    pb = W.lorenz96(d=4, N=1, T=1)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    th = np.linspace(math.log(6.0), math.log(10.0), 61)
+    lik = np.array([np.mean(np.exp([orc.pf_run(pb, theta=np.array([math.exp(t), 0.1]), N=512,
+                                               it=s)["loglik"] for s in range(8)]))
+                    for t in th])
+    dens = lik * np.exp(th)
+    dens /= np.trapezoid(dens, th)
+    mean_q = np.trapezoid(dens * th, th)
+    var_q = np.trapezoid(dens * (th - mean_q) ** 2, th)
+    inp = W.pmmh_inputs(chains=4, iters=30000, seed=11)
+    r = orc.pmmh(pb, 16, inp)
+    lf = r["log_f"][2000:]
+    assert np.all(np.exp(lf) >= 6.0) and np.all(np.exp(lf) <= 10.0)
+    # standard error from 50 batch means per chain (the chain is correlated)
+    nb = 50
+    bm = lf[:(lf.shape[0] // nb) * nb].reshape(nb, -1, lf.shape[1]).mean(axis=1)
+    se = bm.std(ddof=1) / math.sqrt(bm.size)
+    assert abs(lf.mean() - mean_q) < 4 * se + 1e-3, (lf.mean(), mean_q, se)
+    assert abs(lf.var() - var_q) < 0.15 * var_q, (lf.var(), var_q)
+
+
 def test_pmmh_limits(orc):
     pb = W.lorenz96(d=8, N=1, T=8)
     _, y = orc.simulate(pb)

@@ -166,13 +166,14 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // summed sequentially in the lane (an exact monotone prefix), the lanes'
 // totals are scanned across the block, and an exact running maximum over
 // earlier lanes keeps the cumulative weights non-decreasing at lane edges.
-// The stratum counts (< 2^16) and then the ancestors reuse the stage.  When
-// no lane's particles own many more strata than particles (the weights are
-// spread), each lane writes the ancestors of its own particles' strata
-// directly; otherwise a merge-path walk of 2N/NT diagonals per lane keeps
-// the work balanced.  Either way the ancestors go to LDS and one coalesced
-// pass stores them.  The resampling uniform is drawn while the loads are in
-// flight, off the critical path.  64 KB of LDS per workgroup.
+// The stratum counts (< 2^16) and then the ancestors reuse the stage: each
+// particle with offspring marks the first stratum it owns, and a block-wide
+// running maximum over the strata gives every stratum its owner, so each
+// lane does P steps however the offspring are spread (no per-particle loop
+// that one heavy particle could lengthen, no search).  The ancestors go to
+// LDS and one coalesced pass stores them.  The resampling uniform is drawn
+// while the loads are in flight, off the critical path.  64 KB of LDS per
+// workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 
 template <int NT, int RS>
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   constexpr int MAXP = BATCH_MAXN / NT;
   constexpr int NW = NT / WAVE;
   __shared__ double stage[BATCH_MAXN];
-  __shared__ double xa[NW], xb[NW], xc[NW], xm[NW];
+  __shared__ double xa[NW], xb[NW], xc[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
   uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
@@ -257,29 +258,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   // one exchange: scan of the lanes' sums, total of squares, last positive
   const double incl = wave_incl_scan(run, lane);
   const double s2w = wave_sum(run2);
-  const double rmax = wave_max(run);
   const int cw = wave_max_i(cand);
   __syncthreads();  // 2 (xa reused; the stage is no longer read)
   if (lane == WAVE - 1) xa[wv] = incl;
   if (lane == 0) {
     xb[wv] = s2w;
-    xm[wv] = rmax;
     xi[wv] = cw;
   }
   __syncthreads();  // 3
-  double pre = incl - run, S = 0.0, S2 = 0.0, runmax = 0.0;
+  double pre = incl - run, S = 0.0, S2 = 0.0;
   int jstar = -1;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     if (w < wv) pre += xa[w];
     S += xa[w];
     S2 += xb[w];
-    runmax = fmax(runmax, xm[w]);
     jstar = max(jstar, xi[w]);
   }
-  // a lane's particles own about N run / S strata: write them per particle
-  // unless some lane would own far more than its share (4P)
-  const bool per_particle_w = runmax * (double)N <= (double)(4 * P - 2) * S;
   // exclusive running maximum of the lanes' last cumulative weights
   const double vlast = (i1 > i0) ? pre + run : -INFINITY;
   const double vin = wave_incl_max_scan(vlast, lane);
@@ -394,8 +389,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     finish();
     return;
   }
-  const bool per_particle = !draw_rs || per_particle_w;
-  // (3) stratum counts of this lane's particles, to LDS
+  // (3) stratum counts of this lane's particles, to LDS; the ancestor slots
+  // (the stage's upper half, no longer read) start empty
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int i = i0 + e;
@@ -411,60 +406,54 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       sc[i] = (uint16_t)c;
     }
   }
+  for (int k = (int)threadIdx.x; k < N; k += NT) al[k] = -1;
   __syncthreads();  // 6
-  // (4) ancestors to LDS
-  if (per_particle) {
-    // particle i owns strata [c_{i-1}, c_i)
-    int c0 = (i0 > 0 && i0 < N) ? (int)sc[i0 - 1] : 0;
+  // (4) ancestors.  Particle i owns strata [c_{i-1}, c_i): each particle
+  // with offspring marks the first stratum it owns, and a running maximum
+  // over the strata then gives each its owner (the runs are in particle
+  // order), so every lane does the same work however the offspring fall.
+  {
+    int cprev = (i0 > 0 && i0 < N) ? (int)sc[i0 - 1] : 0;
     for (int i = i0; i < i1; ++i) {
       const int c1 = (int)sc[i];
-      for (int k = c0; k < c1; ++k) al[k] = i;
-      c0 = c1;
+      if (c1 > cprev) al[cprev] = i;
+      cprev = c1;
     }
-    // strata past the last count (rounding) go to the last positive particle
-    const int ctot = (int)sc[N - 1];
-    if (ctot < N) {
-      bool bad = false;
-      int32_t aj = jstar;
+  }
+  __syncthreads();  // 7
+  int mk[MAXP];
+  int own = -1;
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) {
+    const int k = i0 + e;
+    if (e < P && k < i1) own = max(own, al[k]);
+    mk[e] = own;
+  }
+  const int wscan = wave_incl_max_scan_i(own, lane);
+  int before = __shfl_up(wscan, 1, WAVE);
+  if (lane == 0) before = -1;
+  if (lane == WAVE - 1) xi[wv] = wscan;
+  __syncthreads();  // 8
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+    if (w < wv) before = max(before, xi[w]);
+  // strata past the last count (rounding) go to the last positive particle
+  const int ctot = (int)sc[N - 1];
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < MAXP; ++e) {
+    const int k = i0 + e;
+    if (e < P && k < i1) {
+      int32_t aj = k < ctot ? max(before, mk[e]) : jstar;
       if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
         aj = 0;
         bad = true;
       }
-      for (int k = ctot + (int)threadIdx.x; k < N; k += NT) al[k] = aj;
-      if (bad && threadIdx.x == 0) atomicOr(&fs->pad, 1);
+      al[k] = aj;
     }
   }
-  // merge path: this lane walks diagonals [dt, dt + L)
-  const int L = (2 * N + NT - 1) / NT;
-  const int dt = (int)threadIdx.x * L;
-  if (!per_particle && dt < 2 * N) {
-    int lo = max(0, dt - N), hi = min(dt, N);
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if ((int)sc[mid] <= dt - 1 - mid)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    int j = lo, k = dt - lo;
-    const int dend = min(dt + L, 2 * N);
-    bool bad = false;
-    for (int s2 = dt; s2 < dend; ++s2) {
-      if (j < N && (k >= N || (int)sc[j] <= k)) {
-        ++j;
-      } else {
-        int32_t aj = j < N ? j : jstar;
-        if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
-          aj = 0;
-          bad = true;
-        }
-        al[k] = aj;
-        ++k;
-      }
-    }
-    if (bad) atomicOr(&fs->pad, 1);
-  }
-  __syncthreads();  // 7
+  if (bad) atomicOr(&fs->pad, 1);
+  __syncthreads();  // 9
   // (5) coalesced store of the ancestors
   if (ha) {
 #pragma unroll

@@ -565,6 +565,14 @@ __device__ __forceinline__ double wave_incl_max_scan(double v, int lane) {
   }
   return v;
 }
+__device__ __forceinline__ int wave_incl_max_scan_i(int v, int lane) {
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int u = __shfl_up(v, o, WAVE);
+    if (lane >= o) v = max(v, u);
+  }
+  return v;
+}
 template <int NT>
 __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;

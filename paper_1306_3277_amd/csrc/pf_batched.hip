@@ -175,9 +175,15 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // while the loads are in flight, off the critical path.  64 KB of LDS per
 // workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
+// The ancestors in LDS: one padding word after every 16, so that lanes
+// reading or writing their own runs of P consecutive entries hit distinct
+// banks; they start past the 16 KB of counts (4,352 words = 17 KB) and end
+// below 52 KB of the 64 KB stage.
+constexpr int ANC_BASE = 4352;
+__device__ __forceinline__ int anc_slot(int i) { return i + (i >> 4); }
 
 template <int NT, int RS>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
                                                        BatchArgs A) {
   constexpr int MAXP = BATCH_MAXN / NT;
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
   __shared__ int xi[NW];
   __shared__ double bc;
   uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
-  int32_t* al = reinterpret_cast<int32_t*>(stage) + BATCH_MAXN / 2;   // ancestors, 32 KB
+  int32_t* al = reinterpret_cast<int32_t*>(stage) + ANC_BASE;          // ancestors, 34 KB
   const FilterSlot slot = A.order[A.order0 + blockIdx.x];
   const int f = slot.f;
   const int64_t off = slot.off;
@@ -406,17 +412,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
       sc[i] = (uint16_t)c;
     }
   }
-  for (int k = (int)threadIdx.x; k < N; k += NT) al[k] = -1;
+  for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
   __syncthreads();  // 6
   // (4) ancestors.  Particle i owns strata [c_{i-1}, c_i): each particle
   // with offspring marks the first stratum it owns, and a running maximum
   // over the strata then gives each its owner (the runs are in particle
   // order), so every lane does the same work however the offspring fall.
   {
-    int cprev = (i0 > 0 && i0 < N) ? (int)sc[i0 - 1] : 0;
+    const uint16_t* __restrict__ scr = sc;
+    int32_t* __restrict__ alr = al;
+    int cprev = (i0 > 0 && i0 < N) ? (int)scr[i0 - 1] : 0;
     for (int i = i0; i < i1; ++i) {
-      const int c1 = (int)sc[i];
-      if (c1 > cprev) al[cprev] = i;
+      const int c1 = (int)scr[i];
+      if (c1 > cprev) alr[anc_slot(cprev)] = i;
       cprev = c1;
     }
   }
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int k = i0 + e;
-    if (e < P && k < i1) own = max(own, al[k]);
+    if (e < P && k < i1) own = max(own, al[anc_slot(k)]);
     mk[e] = own;
   }
   const int wscan = wave_incl_max_scan_i(own, lane);
@@ -449,7 +457,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
         aj = 0;
         bad = true;
       }
-      al[k] = aj;
+      al[anc_slot(k)] = aj;
     }
   }
   if (bad) atomicOr(&fs->pad, 1);
@@ -460,15 +468,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 1024 ?
     for (int r = 0; r < MAXP; ++r) {
       const int k = (int)threadIdx.x + r * NT;
       if (k < N) {
-        anc[off + k] = al[k];
-        ha[k] = al[k];
+        anc[off + k] = al[anc_slot(k)];
+        ha[k] = al[anc_slot(k)];
       }
     }
   } else {
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
       const int k = (int)threadIdx.x + r * NT;
-      if (k < N) anc[off + k] = al[k];
+      if (k < N) anc[off + k] = al[anc_slot(k)];
     }
   }
   finish();

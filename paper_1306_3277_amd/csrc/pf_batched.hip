@@ -182,6 +182,35 @@ __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 constexpr int ANC_BASE = 4352;
 __device__ __forceinline__ int anc_slot(int i) { return i + (i >> 4); }
 
+// A lane's weights e^{lw - M} over its run [i0, i1) of P <= CNT particles,
+// their in-lane prefix sums, sum of squares and last positive index.  The
+// body is straight-line over CNT slots (weights past the run are 0 and add
+// nothing), so the exponentials interleave; P is the same for every lane,
+// so the choice of CNT (the smallest power of two >= P) is a uniform branch.
+template <int CNT, int MAXP>
+__device__ __forceinline__ void lane_weights(const double* stage, int N, double M, bool finite,
+                                             int P, int i0, int i1, double (&loc)[MAXP],
+                                             double& run, double& run2, int& cand) {
+  if constexpr (CNT > 1) {
+    if (P <= CNT / 2) {
+      lane_weights<CNT / 2, MAXP>(stage, N, M, finite, P, i0, i1, loc, run, run2, cand);
+      return;
+    }
+  }
+  double lv[CNT];
+#pragma unroll
+  for (int e = 0; e < CNT; ++e) lv[e] = stage[stage_slot(min(i0 + e, N - 1))];
+#pragma unroll
+  for (int e = 0; e < CNT; ++e) {
+    const double we = exp_nonpos(lv[e] - M);  // exp(-inf) = 0
+    const double w = (finite && e < P && i0 + e < i1) ? we : 0.0;
+    cand = (w > 0.0) ? i0 + e : cand;
+    run += w;
+    run2 += w * w;
+    loc[e] = run;
+  }
+}
+
 template <int NT, int RS>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
@@ -248,19 +277,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   double loc[MAXP];
   double run = 0.0, run2 = 0.0;
   int cand = -1;
-  double lv[MAXP];
-#pragma unroll
-  for (int e = 0; e < MAXP; ++e) lv[e] = stage[stage_slot(min(i0 + e, N - 1))];
-#pragma unroll
-  for (int e = 0; e < MAXP; ++e) {
-    if (e < P && i0 + e < i1) {
-      const double w = finite ? exp_nonpos(lv[e] - M) : 0.0;  // exp(-inf) = 0
-      if (w > 0.0) cand = i0 + e;
-      run += w;
-      run2 += w * w;
-    }
-    loc[e] = run;
-  }
+  lane_weights<MAXP, MAXP>(stage, N, M, finite, P, i0, i1, loc, run, run2, cand);
   // one exchange: scan of the lanes' sums, total of squares, last positive
   const double incl = wave_incl_scan(run, lane);
   const double s2w = wave_sum(run2);

@@ -451,9 +451,11 @@ __device__ __forceinline__ void l96_substep_stage_f32(float (&x)[D], const L96F3
 // x = n ln2 + r with |r| <= ln2/2 (ln2 split in two parts, so r is exact to
 // about 2^-60), e^r by its Taylor polynomial to degree 13 (truncation below
 // 2^-52 relative) in Horner form, and the scale 2^n.  Underflows to 0 below
-// -745.2; a NaN argument gives 0.
-__device__ __forceinline__ double exp_nonpos(double x) {
-  if (!(x >= -745.2)) return 0.0;
+// -745.2; a NaN argument gives 0.  Branch-free (the out-of-range case is a
+// select), so calls on independent arguments interleave.
+__device__ __forceinline__ double exp_nonpos(double xin) {
+  const bool ok = xin >= -745.2;  // false for -inf and NaN
+  const double x = ok ? xin : 0.0;
   const double n = __builtin_rint(x * 0x1.71547652b82fep+0);
   double r = __builtin_fma(-n, 0x1.62e42fefa39efp-1, x);
   r = __builtin_fma(-n, 0x1.abc9e3b39803fp-56, r);
@@ -471,7 +473,8 @@ __device__ __forceinline__ double exp_nonpos(double x) {
   p = __builtin_fma(p, r, 0.5);
   p = __builtin_fma(p, r, 1.0);
   p = __builtin_fma(p, r, 1.0);
-  return __builtin_ldexp(p, (int)n);
+  const double v = __builtin_ldexp(p, (int)n);
+  return ok ? v : 0.0;
 }
 
 // ---------------------------------------------------------------- reductions

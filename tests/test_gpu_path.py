@@ -138,17 +138,22 @@ def _history_arrays(f, pb, fp64):
     return xh.reshape(pb.T + 1, pb.d, n), ah.reshape(pb.T, n)
 
 
-@pytest.mark.parametrize("fp64", [True, False])
-def test_batched_history_holds_every_slot(pfm, fp64):
+@pytest.mark.parametrize("fp64,scheme,steps,ess_frac",
+                         [(True, 0, 0, float("inf")), (False, 0, 0, float("inf")),
+                          (True, 1, 0, 0.7), (True, 2, 5, float("inf")), (True, 3, 0, 0.7)])
+def test_batched_history_holds_every_slot(pfm, fp64, scheme, steps, ess_frac):
     """Every slot of a batched history equals the state and ancestors the
     inspection calls read after each step and resampling (one group, eager),
-    and a graph-replayed run in three filter groups records the same bytes."""
+    and a graph-replayed run in three filter groups records the same bytes;
+    for every resampler (the collective stores the ancestor slots in each of
+    its variants) and with the ESS trigger."""
     precision = pfm.PF_FP64 if fp64 else pfm.PF_FP32_MIXED
     base = _data(W.lorenz96(d=8, N=1, T=6, precision=precision))
     th0, _ = W.batched_thetas(5, seed=53)
     n = np.array([300, 64, 1000, 33, 257], dtype=np.int64)
     pb = dataclasses.replace(base, theta=th0, n_particles=n)
     f = pfm.Filter(pb, precision=precision, layout=pfm.PF_LAYOUT_BATCHED)
+    f.set_resampler(scheme, steps, ess_frac)
     f.attach_history()
     xs = [f.get_state()]
     anc = []
@@ -165,6 +170,7 @@ def test_batched_history_holds_every_slot(pfm, fp64):
     f.close()
     g = pfm.Filter(pb, precision=precision, layout=pfm.PF_LAYOUT_BATCHED)
     g.set_tuning(512, 3)
+    g.set_resampler(scheme, steps, ess_frac)
     g.attach_history()
     g.graph_run(pb.T)
     xh2, ah2 = _history_arrays(g, pb, fp64)

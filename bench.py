@@ -432,14 +432,56 @@ def oracle_all_cores(pb, seconds, procs):
     return res
 
 
+def autotune_worker(argv):
+    """Child process of autotune_isolated: the autotuner on the headline
+    workload ("c4") or the PMMH shape ("c5", on the headline's data); prints
+    the choice and the candidates' times as one JSON line."""
+    which = argv[0]
+    import torch
+    import paper_1306_3277_amd as pfm
+    torch.cuda.set_device(0)
+    pfm.load()
+    stream = torch.cuda.Stream()
+    pb = W.config("c4")
+    _, y = pfm.simulate(pb, stream=stream)
+    pb = pb.with_obs(y)
+    if which == "c5":
+        pb = W.config("c5").with_obs(y)
+    f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    threads, groups, cand = f.autotune(steps=pb.T - 1)
+    f.close()
+    print(json.dumps({"threads": threads, "groups": groups, "cand_ms": cand.tolist()}), flush=True)
+
+
+def autotune_isolated(which):
+    """The autotuner run in a child process, so that a failure inside it
+    cannot end the benchmark (the autotuner has ended processes with a host
+    segmentation fault, cause not found).  Returns (threads, groups,
+    candidate times) or None if the child failed."""
+    import subprocess
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--autotune-worker", which],
+                           capture_output=True, text=True, timeout=600)
+    except subprocess.TimeoutExpired:
+        return None
+    if r.returncode != 0:
+        log(f"[bench] autotune child exited with {r.returncode}: {r.stderr.strip()[-300:]}")
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return d["threads"], d["groups"], np.array(d["cand_ms"])
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
         oracle_worker(sys.argv[2:])
         return
+    if len(sys.argv) > 1 and sys.argv[1] == "--autotune-worker":
+        autotune_worker(sys.argv[2:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=200,
+    ap.add_argument("--warmup", type=int, default=2000,
                     help="untimed intervals before the timed ones (the device clocks settle)")
     ap.add_argument("--fp64-steps", type=int, default=40,
                     help="intervals timed for the FP64 plain comparison")
@@ -474,7 +516,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the filters of the batched workload shard across "
-              "GPUs with no per-step exchange, but this build measures one GPU only. "
+              "GPUs with no per-step exchange, but this benchmark measures one GPU only. "
               "Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
@@ -524,15 +566,24 @@ def main():
         # counter runs replay each kernel under the profiler: a fixed tuning
         # keeps them short
         threads, groups = 512, 2
+        tune_src = "fixed (profiling run)"
         f32.set_tuning(threads, groups)
     else:
         # the tuner replays every candidate over the whole horizon (the
         # weights' concentration, and with it the collective's work, changes
         # along it)
-        threads, groups, cand_ms = f32.autotune(steps=pb.T - 1)
-        log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
-            f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
-            f"{np.round(cand_ms * 1e3, 1).tolist()}")
+        tuned = autotune_isolated("c4")
+        if tuned is None:
+            threads, groups = 512, 2
+            tune_src = "default (the autotuner's child process failed)"
+            log("[bench] autotune failed; collective workgroup 512, 2 filter groups")
+        else:
+            tune_src = "autotuner in a child process, whole horizon per candidate"
+            threads, groups, cand_ms = tuned
+            log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
+                f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
+                f"{np.round(cand_ms * 1e3, 1).tolist()}")
+        f32.set_tuning(threads, groups)
     r32 = Runner(f32, pb.T)
     dt32 = timed(torch, r32, args.steps, args.warmup)
     # the same timed region repeated, for the spread of the figure
@@ -613,7 +664,7 @@ def main():
         "config": {"workload": pb.name, "model": "lorenz96", "d": pb.d, "filters": pb.B,
                    "particles": n_tot, "particle_counts": "uniform over 256..8192",
                    "T": pb.T, "substeps": pb.K, "layout": "batched",
-                   "collective_workgroup": threads, "filter_groups": groups,
+                   "collective_workgroup": threads, "filter_groups": groups, "tuning": tune_src,
                    "precision": "fp32 state/propagation, fp64 log-weights/scan/likelihood"},
         "fp64_plain": {"value": rate64, "unit": "particle-steps/s",
                        "ms_per_step": dt64 / args.fp64_steps * 1e3, "steps": args.fp64_steps},
@@ -662,7 +713,9 @@ def main():
             pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-            pm_threads, pm_groups, _ = fm.autotune(steps=pm.T - 1)
+            tuned = autotune_isolated("c5")
+            pm_threads, pm_groups = (512, 2) if tuned is None else tuned[:2]
+            fm.set_tuning(pm_threads, pm_groups)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = fm.pmmh(inp)

@@ -2,6 +2,7 @@
 stepped together: flat propagation over all filters' particles, then one
 workgroup per filter for the collective part) against the oracle."""
 import dataclasses
+import os
 
 import numpy as np
 import pytest
@@ -191,18 +192,17 @@ def test_pmmh_prior_support_rejects(pfm):
 
 
 def test_autotune_keeps_results(pfm):
-    th, n = W.batched_thetas(40, seed=9)
-    pb = _problem(n, th, T=6)
-    f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
-    f.advance(pb.T)
-    e0, _ = f.trace()
-    threads, groups, ms = f.autotune(steps=3)
-    assert threads in (256, 512, 1024) and groups in (1, 2, 4)
-    assert np.all(ms[ms >= 0] > 0)
-    f.advance(pb.T)  # autotune leaves the filters re-initialised
-    e1, _ = f.trace()
-    np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=1e-12)
-    f.close()
+    """The autotuner leaves the handle re-initialised with the same results.
+    Run in a child process: the autotuner has ended processes with a host
+    segmentation fault (cause not found), and one there must not end the
+    rest of the suite."""
+    import subprocess
+    import sys
+    script = os.path.join(os.path.dirname(os.path.abspath(__file__)), "helpers",
+                          "autotune_scenario.py")
+    r = subprocess.run([sys.executable, script], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert r.stdout.strip().splitlines()[-1].startswith("ok"), r.stdout[-2000:]
 
 
 def test_filter_groups_do_not_change_results(pfm):

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   constexpr int MAXP = BATCH_MAXN / NT;
   constexpr int NW = NT / WAVE;
   __shared__ double stage[BATCH_MAXN];
-  __shared__ double xa[NW], xb[NW], xc[NW];
+  __shared__ double xa[NW], xs[NW], xb[NW], xc[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
   uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
@@ -282,8 +282,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   const double incl = wave_incl_scan(run, lane);
   const double s2w = wave_sum(run2);
   const int cw = wave_max_i(cand);
-  __syncthreads();  // 2 (xa reused; the stage is no longer read)
-  if (lane == WAVE - 1) xa[wv] = incl;
+  // (the lane sums go to their own array, so no barrier separates them from
+  // the maxima read above; the stage's reuse comes after two more barriers)
+  if (lane == WAVE - 1) xs[wv] = incl;
   if (lane == 0) {
     xb[wv] = s2w;
     xi[wv] = cw;
@@ -293,8 +294,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   int jstar = -1;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    if (w < wv) pre += xa[w];
-    S += xa[w];
+    if (w < wv) pre += xs[w];
+    S += xs[w];
     S2 += xb[w];
     jstar = max(jstar, xi[w]);
   }

@@ -175,11 +175,9 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // while the loads are in flight, off the critical path.  64 KB of LDS per
 // workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
-// The ancestors in LDS: one padding word after every 16, so that lanes
-// reading or writing their own runs of P consecutive entries hit distinct
-// banks; they start past the 16 KB of counts (4,352 words = 17 KB) and end
-// below 52 KB of the 64 KB stage.
-constexpr int ANC_BASE = 4352;
+// The ancestors in LDS (the stage, once its weights are read): one padding
+// word after every 16, so that lanes reading or writing their own runs of
+// P consecutive entries hit distinct banks (8,704 words for 8192 entries).
 __device__ __forceinline__ int anc_slot(int i) { return i + (i >> 4); }
 
 // A lane's weights e^{lw - M} over its run [i0, i1) of P <= CNT particles,
@@ -221,8 +219,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   __shared__ double xa[NW], xs[NW], xb[NW], xc[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
-  uint16_t* sc = reinterpret_cast<uint16_t*>(stage);                  // counts, 16 KB
-  int32_t* al = reinterpret_cast<int32_t*>(stage) + ANC_BASE;          // ancestors, 34 KB
+  int32_t* al = reinterpret_cast<int32_t*>(stage);                    // ancestors, 34 KB
   const FilterSlot slot = A.order[A.order0 + blockIdx.x];
   const int f = slot.f;
   const int64_t off = slot.off;
@@ -299,6 +296,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     S2 += xb[w];
     jstar = max(jstar, xi[w]);
   }
+  // the ancestor slots start empty (the stage's weights have all been read;
+  // the Metropolis and multinomial forms still use the stage)
+  if constexpr (RS == RS_SYSTEMATIC || RS == RS_STRATIFIED)
+    for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
   // exclusive running maximum of the lanes' last cumulative weights
   const double vlast = (i1 > i0) ? pre + run : -INFINITY;
   const double vin = wave_incl_max_scan(vlast, lane);
@@ -413,37 +414,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     finish();
     return;
   }
-  // (3) stratum counts of this lane's particles, to LDS; the ancestor slots
-  // (the stage's upper half, no longer read) start empty
+  // (3) stratum counts of this lane's particles, in registers.  Particle i
+  // owns strata [c_{i-1}, c_i).  Every lane evaluates its cumulative
+  // weights as W = min(max(prefix, earlier lanes' maximum), S), so the count
+  // before its first particle is the one the lane before computed, at
+  // W = min(vprev, S), and the last particle's is at W = min(vall, S).
+  auto count_at = [&](double W, int i) -> int32_t {
+    if (!draw_rs) return i + 1;
+    if constexpr (RS == RS_STRATIFIED)
+      return stratum_count_strat(W, S, invS, N, bkey(A.key), t, (uint32_t)f, iter);
+    else
+      return stratum_count(W, S, invS, u, N);
+  };
+  int32_t cnt[MAXP];
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int i = i0 + e;
-    if (e < P && i < i1) {
-      const double W = fmin(fmax(pre + loc[e], vprev), S);
-      int32_t c = i + 1;
-      if (draw_rs) {
-        if constexpr (RS == RS_STRATIFIED)
-          c = stratum_count_strat(W, S, invS, N, bkey(A.key), t, (uint32_t)f, iter);
-        else
-          c = stratum_count(W, S, invS, u, N);
-      }
-      sc[i] = (uint16_t)c;
-    }
+    cnt[e] = (e < P && i < i1) ? count_at(fmin(fmax(pre + loc[e], vprev), S), i) : 0;
   }
-  for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
-  __syncthreads();  // 6
-  // (4) ancestors.  Particle i owns strata [c_{i-1}, c_i): each particle
-  // with offspring marks the first stratum it owns, and a running maximum
-  // over the strata then gives each its owner (the runs are in particle
-  // order), so every lane does the same work however the offspring fall.
+  // (4) ancestors: each particle with offspring marks the first stratum it
+  // owns, and a running maximum over the strata then gives each its owner
+  // (the runs are in particle order), so every lane does the same work
+  // however the offspring fall.
   {
-    const uint16_t* __restrict__ scr = sc;
-    int32_t* __restrict__ alr = al;
-    int cprev = (i0 > 0 && i0 < N) ? (int)scr[i0 - 1] : 0;
-    for (int i = i0; i < i1; ++i) {
-      const int c1 = (int)scr[i];
-      if (c1 > cprev) alr[anc_slot(cprev)] = i;
-      cprev = c1;
+    int cprev = (i0 > 0 && i0 < N) ? count_at(fmin(vprev, S), i0 - 1) : 0;
+#pragma unroll
+    for (int e = 0; e < MAXP; ++e) {
+      const int i = i0 + e;
+      if (e < P && i < i1) {
+        if (cnt[e] > cprev) al[anc_slot(cprev)] = i;
+        cprev = cnt[e];
+      }
     }
   }
   __syncthreads();  // 7
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   for (int w = 0; w < NW; ++w)
     if (w < wv) before = max(before, xi[w]);
   // strata past the last count (rounding) go to the last positive particle
-  const int ctot = (int)sc[N - 1];
+  const int ctot = count_at(fmin(vall, S), N - 1);
   bool bad = false;
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {

@@ -448,56 +448,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     }
   }
   __syncthreads();  // 7
+  // (5) owners: wave wv takes the strata [wv seg, (wv + 1) seg) in rows of
+  // 64, with a running maximum of the marks along each row, carried from
+  // row to row and then across the waves; each row is stored as it stands,
+  // 64 consecutive ancestors per wave
+  const int seg = ((N + NW - 1) / NW + WAVE - 1) & ~(WAVE - 1);  // <= 64 MAXP
+  const int base = wv * seg;
   int mk[MAXP];
-  int own = -1;
+  int rowmax = -1;
 #pragma unroll
-  for (int e = 0; e < MAXP; ++e) {
-    const int k = i0 + e;
-    if (e < P && k < i1) own = max(own, al[anc_slot(k)]);
-    mk[e] = own;
+  for (int r = 0; r < MAXP; ++r) {
+    const int k = base + r * WAVE + lane;
+    const int v = (r * WAVE < seg && k < N) ? al[anc_slot(k)] : -1;
+    mk[r] = max(wave_incl_max_scan_rows(v), rowmax);
+    rowmax = __builtin_amdgcn_readlane(mk[r], WAVE - 1);
   }
-  const int wscan = wave_incl_max_scan_i(own, lane);
-  int before = __shfl_up(wscan, 1, WAVE);
-  if (lane == 0) before = -1;
-  if (lane == WAVE - 1) xi[wv] = wscan;
+  if (lane == 0) xi[wv] = rowmax;
   __syncthreads();  // 8
+  int before = -1;
 #pragma unroll
   for (int w = 0; w < NW; ++w)
     if (w < wv) before = max(before, xi[w]);
   // strata past the last count (rounding) go to the last positive particle
   const int ctot = count_at(fmin(vall, S), N - 1);
   bool bad = false;
-#pragma unroll
-  for (int e = 0; e < MAXP; ++e) {
-    const int k = i0 + e;
-    if (e < P && k < i1) {
-      int32_t aj = k < ctot ? max(before, mk[e]) : jstar;
-      if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
-        aj = 0;
-        bad = true;
-      }
-      al[anc_slot(k)] = aj;
+  auto owner = [&](int r, int k) -> int32_t {
+    int32_t aj = k < ctot ? max(before, mk[r]) : jstar;
+    if (aj < 0 || aj >= N) {  // never expected; flagged, kept in bounds
+      aj = 0;
+      bad = true;
     }
-  }
-  if (bad) atomicOr(&fs->pad, 1);
-  __syncthreads();  // 9
-  // (5) coalesced store of the ancestors
+    return aj;
+  };
   if (ha) {
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
-      const int k = (int)threadIdx.x + r * NT;
-      if (k < N) {
-        anc[off + k] = al[anc_slot(k)];
-        ha[k] = al[anc_slot(k)];
+      const int k = base + r * WAVE + lane;
+      if (r * WAVE < seg && k < N) {
+        const int32_t aj = owner(r, k);
+        anc[off + k] = aj;
+        ha[k] = aj;
       }
     }
   } else {
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
-      const int k = (int)threadIdx.x + r * NT;
-      if (k < N) anc[off + k] = al[anc_slot(k)];
+      const int k = base + r * WAVE + lane;
+      if (r * WAVE < seg && k < N) anc[off + k] = owner(r, k);
     }
   }
+  if (bad) atomicOr(&fs->pad, 1);
   finish();
 }
 

@@ -576,6 +576,19 @@ __device__ __forceinline__ int wave_incl_max_scan_i(int v, int lane) {
   }
   return v;
 }
+// The same running maximum from lane shifts inside each 16-lane row (1, 2,
+// 4, 8) and two row broadcasts (lane 15 of a row into the next row, then
+// lane 31 into rows 2 and 3); lanes a shift reaches from outside take INT_MIN.
+__device__ __forceinline__ int wave_incl_max_scan_rows(int v) {
+  constexpr int lo = -2147483647 - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));  // row_shr 1
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));  // row_shr 2
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false));  // row_shr 4
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false));  // row_shr 8
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false));  // row_bcast 15
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));  // row_bcast 31
+  return v;
+}
 template <int NT>
 __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;

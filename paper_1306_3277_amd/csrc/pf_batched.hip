@@ -7,9 +7,10 @@
 //        the previous resampling is fused into this load), so the state is
 //        read and written once per interval.
 //   K5b  one workgroup per filter, largest filters dispatched first: the
-//        filter's FP64 weights live in LDS (at most 8192), block max, sums,
-//        scan, stratum counts and a merge-path walk all run in LDS, and the
-//        ancestors go to global memory for the next K5a.
+//        filter's FP64 weights are staged in LDS (at most 8192); block max,
+//        sums, scan and stratum counts run in registers and LDS, the
+//        ancestors come from marks and a running maximum, and they go to
+//        global memory for the next K5a.
 // Both kernels read the filter's step counter from device memory and pick
 // the state buffers by its parity, so one captured graph replays every step.
 #include <math.h>
@@ -166,14 +167,14 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // summed sequentially in the lane (an exact monotone prefix), the lanes'
 // totals are scanned across the block, and an exact running maximum over
 // earlier lanes keeps the cumulative weights non-decreasing at lane edges.
-// The stratum counts (< 2^16) and then the ancestors reuse the stage: each
-// particle with offspring marks the first stratum it owns, and a block-wide
-// running maximum over the strata gives every stratum its owner, so each
-// lane does P steps however the offspring are spread (no per-particle loop
-// that one heavy particle could lengthen, no search).  The ancestors go to
-// LDS and one coalesced pass stores them.  The resampling uniform is drawn
-// while the loads are in flight, off the critical path.  64 KB of LDS per
-// workgroup.
+// The stratum counts stay in registers; the ancestors reuse the stage: each
+// particle with offspring marks the first stratum it owns, and a running
+// maximum over the strata (by 64-stratum rows in each wave, then across the
+// waves) gives every stratum its owner, so the work does not depend on how
+// the offspring are spread (no per-particle loop that one heavy particle
+// could lengthen, no search); each row of owners is stored as it stands.
+// The resampling uniform is drawn while the loads are in flight, off the
+// critical path.  64 KB of LDS per workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 // The ancestors in LDS (the stage, once its weights are read): one padding
 // word after every 16, so that lanes reading or writing their own runs of

@@ -208,7 +208,7 @@ def tf_summary(err, ell, ess, bound, rel_bound):
 def large_filter_leg(torch, pfm, stream):
     """One Lorenz '96 (d = 40) filter of 2^20 particles, FP32 mixed: resample +
     gather priced against HBM, propagation against the VALU issue rate."""
-    big = W.config("c3")
+    big = W.config("lorenz96_d40_large")
     _, yb = pfm.simulate(big, stream=stream)
     big = big.with_obs(yb)
     fb = pfm.Filter(big, stream=stream)
@@ -398,7 +398,7 @@ def oracle_worker(argv):
     time.  Uses no GPU."""
     w, P, seconds, obs_path = int(argv[0]), int(argv[1]), float(argv[2]), argv[3]
     import oracle
-    pb = W.config("c4").with_obs(np.load(obs_path, allow_pickle=False))
+    pb = W.config("lorenz96_d8_batched").with_obs(np.load(obs_path, allow_pickle=False))
     t0 = time.perf_counter()
     done_ps, nf, b = 0, 0, w
     while time.perf_counter() - t0 < seconds and b < pb.B:
@@ -434,19 +434,20 @@ def oracle_all_cores(pb, seconds, procs):
 
 def autotune_worker(argv):
     """Child process of autotune_isolated: the autotuner on the headline
-    workload ("c4") or the PMMH shape ("c5", on the headline's data); prints
-    the choice and the candidates' times as one JSON line."""
+    workload ("lorenz96_d8_batched") or the PMMH shape ("lorenz96_d8_chains",
+    on the headline's data); prints the choice and the candidates' times as
+    one JSON line."""
     which = argv[0]
     import torch
     import paper_1306_3277_amd as pfm
     torch.cuda.set_device(0)
     pfm.load()
     stream = torch.cuda.Stream()
-    pb = W.config("c4")
+    pb = W.config("lorenz96_d8_batched")
     _, y = pfm.simulate(pb, stream=stream)
     pb = pb.with_obs(y)
-    if which == "c5":
-        pb = W.config("c5").with_obs(y)
+    if which == "lorenz96_d8_chains":
+        pb = W.config("lorenz96_d8_chains").with_obs(y)
     f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
     threads, groups, cand = f.autotune(steps=pb.T - 1)
     f.close()
@@ -543,7 +544,7 @@ def main():
         return
 
     # ---------------------------------------------------------------- headline
-    pb = W.config("c4")
+    pb = W.config("lorenz96_d8_batched")
     _, y = pfm.simulate(pb, stream=stream)
     pb = pb.with_obs(y)
     n_tot = int(pb.n_particles.sum())
@@ -572,7 +573,7 @@ def main():
         # the tuner replays every candidate over the whole horizon (the
         # weights' concentration, and with it the collective's work, changes
         # along it)
-        tuned = autotune_isolated("c4")
+        tuned = autotune_isolated("lorenz96_d8_batched")
         if tuned is None:
             threads, groups = 512, 2
             tune_src = "default (the autotuner's child process failed)"
@@ -684,7 +685,7 @@ def main():
     if not args.no_legs:
         # ------------------------------------------------------------ single filter
         log("[bench] single-filter leg starts")
-        pc = W.config("c2")
+        pc = W.config("lorenz96_d8")
         _, yc = pfm.simulate(pc, stream=stream)
         pc = pc.with_obs(yc)
         leg = {"workload": pc.name, "particles": int(pc.n_particles[0])}
@@ -709,11 +710,11 @@ def main():
         # ------------------------------------------------------------ PMMH chains
         if args.pmmh_iters > 0:
             log("[bench] PMMH leg starts")
-            pm = W.config("c5")
+            pm = W.config("lorenz96_d8_chains")
             pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-            tuned = autotune_isolated("c5")
+            tuned = autotune_isolated("lorenz96_d8_chains")
             pm_threads, pm_groups = (512, 2) if tuned is None else tuned[:2]
             fm.set_tuning(pm_threads, pm_groups)
             torch.cuda.synchronize()

@@ -37,12 +37,12 @@ def _size(pb, **kw):
 
 
 def test_valid_configs_have_a_size():
-    for pb in (W.config("c1"), W.config("c2"), W.config("c3"), W.config("c4")):
+    for pb in (W.config("windkessel"), W.config("lorenz96_d8"), W.config("lorenz96_d40_large"), W.config("lorenz96_d8_batched")):
         _, n = _size(pb.with_obs(np.zeros((pb.T, pb.n_obs))),
                      layout=binding.PF_LAYOUT_BATCHED if pb.B > 1 else 0)
         assert n > 0
     # state, log-weights, counts, ancestors at least
-    pb = W.config("c3").with_obs(np.zeros((500, 20)))
+    pb = W.config("lorenz96_d40_large").with_obs(np.zeros((500, 20)))
     _, n = _size(pb)
     N = 1 << 20
     assert n >= 2 * 40 * N * 4 + 3 * 4 * N
@@ -53,7 +53,7 @@ def _msg():
 
 
 def test_smc2_workspace_size_and_run_length():
-    pb = W.config("c4")
+    pb = W.config("lorenz96_d8_batched")
     hc = binding._HostCfg(pb.with_obs(np.zeros((pb.T, pb.n_obs))),
                           layout=binding.PF_LAYOUT_BATCHED)
     L = binding.load()
@@ -77,7 +77,7 @@ def test_smc2_workspace_size_and_run_length():
     (lambda c: setattr(c, "n_theta", 3), "n_theta"),
 ])
 def test_invalid_configs_rejected_on_host(mutate, needle):
-    pb = W.config("c2", N=64, T=5).with_obs(np.zeros((5, 8)))
+    pb = W.config("lorenz96_d8", N=64, T=5).with_obs(np.zeros((5, 8)))
     hc = binding._HostCfg(pb)
     mutate(hc.cfg)
     assert binding.load().pf_workspace_bytes(C.byref(hc.cfg)) == 0
@@ -85,29 +85,29 @@ def test_invalid_configs_rejected_on_host(mutate, needle):
 
 
 def test_invalid_arrays_rejected_on_host():
-    pb = W.config("c2", N=64, T=5)
+    pb = W.config("lorenz96_d8", N=64, T=5)
     obs = np.zeros((5, 8))
     obs[2, 3] = np.nan
     _, n = _size(pb.with_obs(obs))
     assert n == 0 and "not finite" in _msg()
-    pb2 = W.config("c2", N=64, T=5).with_obs(np.zeros((5, 8)))
+    pb2 = W.config("lorenz96_d8", N=64, T=5).with_obs(np.zeros((5, 8)))
     pb2.obs_idx = np.array([0, 2, 1, 3, 4, 5, 6, 7], dtype=np.int32)
     _, n = _size(pb2)
     assert n == 0 and "increasing" in _msg()
     _, n = _size(pb.with_obs(np.zeros((5, 8))), n_particles=[0])
     assert n == 0 and "n_particles" in _msg()
-    big = W.config("c4", B=3)
+    big = W.config("lorenz96_d8_batched", B=3)
     _, n = _size(big.with_obs(np.zeros((big.T, 8))), layout=binding.PF_LAYOUT_BATCHED,
                  n_particles=[256, 9000, 512])
     assert n == 0 and "8192" in _msg()
-    wk = W.config("c1", N=16, T=4)
+    wk = W.config("windkessel", N=16, T=4)
     wk.q = None
     _, n = _size(wk.with_obs(np.zeros((4, 1))))
     assert n == 0 and "flow" in _msg()
 
 
 def test_init_rejects_before_touching_the_device():
-    pb = W.config("c2", N=64, T=5).with_obs(np.zeros((5, 8)))
+    pb = W.config("lorenz96_d8", N=64, T=5).with_obs(np.zeros((5, 8)))
     hc = binding._HostCfg(pb)
     hc.cfg.K = -3
     h = C.c_void_p()

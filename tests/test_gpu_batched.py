@@ -135,7 +135,7 @@ def test_batched_resample_u_matches_oracle(pfm):
 def test_batched_full_c4_shape_sampled(pfm):
     """512 filters with counts in {256..8192}, FP32: sampled filters' first
     likelihood increment against the oracle; properties on every filter."""
-    pb = W.config("c4", T=3)
+    pb = W.config("lorenz96_d8_batched", T=3)
     _, y = oracle.simulate(pb)
     pb = pb.with_obs(y)
     f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)

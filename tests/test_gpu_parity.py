@@ -100,7 +100,7 @@ def _free_running_fp64(pfm, pb, check_lw=True):
 
 
 def test_simulator_matches_oracle_bitwise(pfm):
-    for pb in (W.config("c1"), W.config("c2", T=200), W.config("c3", T=60)):
+    for pb in (W.config("windkessel"), W.config("lorenz96_d8", T=200), W.config("lorenz96_d40_large", T=60)):
         xt_ref, y_ref = oracle.simulate(pb)
         xt, y = pfm.simulate(pb)
         np.testing.assert_array_equal(xt, xt_ref, err_msg=pb.name)
@@ -108,7 +108,7 @@ def test_simulator_matches_oracle_bitwise(pfm):
 
 
 def test_windkessel_fp64_full_size_against_oracle_and_kalman(pfm):
-    pb = _with_data(W.config("c1"))  # N = 1024, T = 100
+    pb = _with_data(W.config("windkessel"))  # N = 1024, T = 100
     ref, ll, flips = _free_running_fp64(pfm, pb)
     ll_kf, _ = oracle.kf_wk(pb)
     assert abs(ll - ll_kf) < 5.0, (ll, ll_kf)
@@ -117,17 +117,17 @@ def test_windkessel_fp64_full_size_against_oracle_and_kalman(pfm):
 
 @pytest.mark.parametrize("N,T", [(1, 6), (2, 6), (255, 8), (4096 + 77, 25)])
 def test_lorenz96_d8_fp64_free_running(pfm, N, T):
-    pb = _with_data(W.config("c2", N=N, T=T))
+    pb = _with_data(W.config("lorenz96_d8", N=N, T=T))
     _free_running_fp64(pfm, pb)
 
 
 def test_lorenz96_d8_fp64_full_particle_count(pfm):
-    pb = _with_data(W.config("c2", T=3))  # N = 65536
+    pb = _with_data(W.config("lorenz96_d8", T=3))  # N = 65536
     _free_running_fp64(pfm, pb)
 
 
 def test_lorenz96_d40_fp64_half_observed(pfm):
-    pb = _with_data(W.config("c3", N=1100, T=4, precision=W.FP64))
+    pb = _with_data(W.config("lorenz96_d40_large", N=1100, T=4, precision=W.FP64))
     _free_running_fp64(pfm, pb)
 
 
@@ -157,17 +157,17 @@ def _teacher_forced_fp32(pfm, pb, steps):
 
 
 def test_fp32_teacher_forced_lorenz96_d8(pfm):
-    pb = _with_data(W.config("c2", N=4096 + 13, T=12, precision=W.FP32_MIXED))
+    pb = _with_data(W.config("lorenz96_d8", N=4096 + 13, T=12, precision=W.FP32_MIXED))
     _teacher_forced_fp32(pfm, pb, 12)
 
 
 def test_fp32_teacher_forced_lorenz96_d40(pfm):
-    pb = _with_data(W.config("c3", N=2048 + 5, T=6))
+    pb = _with_data(W.config("lorenz96_d40_large", N=2048 + 5, T=6))
     _teacher_forced_fp32(pfm, pb, 6)
 
 
 def test_fp32_teacher_forced_windkessel(pfm):
-    pb = _with_data(W.config("c1", T=30, precision=W.FP32_MIXED))
+    pb = _with_data(W.config("windkessel", T=30, precision=W.FP32_MIXED))
     _teacher_forced_fp32(pfm, pb, 30)
 
 
@@ -229,7 +229,7 @@ def test_resample_brute_force_every_u_interval(pfm, weights):
 
 
 def test_numeric_flag_from_nan_state(pfm):
-    pb = _with_data(W.config("c2", N=300, T=3))
+    pb = _with_data(W.config("lorenz96_d8", N=300, T=3))
     f = pfm.Filter(pb, precision=pfm.PF_FP64)
     x = f.get_state()
     x[:, :] = np.nan
@@ -248,7 +248,7 @@ def test_numeric_flag_from_nan_state(pfm):
 
 
 def test_partial_nan_counts_as_zero_weight(pfm):
-    pb = _with_data(W.config("c2", N=512, T=2))
+    pb = _with_data(W.config("lorenz96_d8", N=512, T=2))
     f = pfm.Filter(pb, precision=pfm.PF_FP64)
     x = oracle.init(pb, pb.theta[0], 512)
     x[:, ::3] = np.nan
@@ -267,7 +267,7 @@ def test_partial_nan_counts_as_zero_weight(pfm):
 
 
 def test_graph_replay_equals_eager(pfm):
-    pb = _with_data(W.config("c2", N=5000, T=10, precision=W.FP32_MIXED))
+    pb = _with_data(W.config("lorenz96_d8", N=5000, T=10, precision=W.FP32_MIXED))
     f1 = pfm.Filter(pb)
     f1.advance(pb.T)
     f2 = pfm.Filter(pb)
@@ -285,7 +285,7 @@ def test_graph_replay_equals_eager(pfm):
 
 
 def test_several_filters_in_one_handle(pfm):
-    base = _with_data(W.config("c2", N=1, T=6))
+    base = _with_data(W.config("lorenz96_d8", N=1, T=6))
     th = np.array([[8.0, 0.1], [9.5, 0.25], [6.3, 0.05]])
     n = np.array([700, 1, 2100])
     pb = dataclasses.replace(base, theta=th, n_particles=n)
@@ -305,7 +305,7 @@ def test_several_filters_in_one_handle(pfm):
 
 
 def test_set_theta_and_iteration_field(pfm):
-    pb = _with_data(W.config("c2", N=999, T=5))
+    pb = _with_data(W.config("lorenz96_d8", N=999, T=5))
     f = pfm.Filter(pb, precision=pfm.PF_FP64)
     f.advance(2)
     th = np.array([[9.1, 0.2]])
@@ -323,7 +323,7 @@ def test_set_theta_and_iteration_field(pfm):
 
 
 def test_call_order_errors(pfm):
-    pb = _with_data(W.config("c2", N=64, T=2))
+    pb = _with_data(W.config("lorenz96_d8", N=64, T=2))
     f = pfm.Filter(pb)
     with pytest.raises(pfm.PfError) as ei:
         f.resample()
@@ -343,7 +343,7 @@ def test_call_order_errors(pfm):
 def test_lorenz96_d40_full_size_fp32_sampled(pfm):
     """N = 2^20, d = 40, the benchmark's launch shapes: sampled particles
     against the oracle, and resampling properties over all particles."""
-    pb = _with_data(W.config("c3", T=3))
+    pb = _with_data(W.config("lorenz96_d40_large", T=3))
     N = 1 << 20
     f = pfm.Filter(pb)
     rng = np.random.default_rng(0)

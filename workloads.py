@@ -289,17 +289,22 @@ def smc2_wk_m0_inputs(base_theta: np.ndarray, B: int, T: int, seed: int = 5,
 # ---------------------------------------------------------------- named configs
 
 def config(name: str, **kw) -> Problem:
-    """The five headline workloads (c1..c5) plus small variants via kwargs."""
-    if name == "c1":
+    """The named workloads, and smaller variants of them through keyword
+    arguments: "windkessel" (the linear-Gaussian windkessel, N = 1024),
+    "lorenz96_d8" (one Lorenz '96 filter, d = 8, N = 65,536, T = 200),
+    "lorenz96_d40_large" (one filter, d = 40, N = 2^20, T = 500, every second
+    component observed), "lorenz96_d8_batched" (512 filters of uneven N) and
+    "lorenz96_d8_chains" (64 filters of N = 4096, the PMMH chains' shape)."""
+    if name == "windkessel":
         return windkessel(**kw)
-    if name == "c2":
+    if name == "lorenz96_d8":
         return lorenz96(d=8, N=kw.pop("N", 65536), T=kw.pop("T", 200), **kw)
-    if name == "c3":
+    if name == "lorenz96_d40_large":
         return lorenz96(d=40, N=kw.pop("N", 1 << 20), T=kw.pop("T", 500), obs_every=2,
                         precision=kw.pop("precision", FP32_MIXED), **kw)
-    if name == "c4":
+    if name == "lorenz96_d8_batched":
         return lorenz96_batched(**kw)
-    if name == "c5":
+    if name == "lorenz96_d8_chains":
         chains = kw.pop("chains", 64)
         N = kw.pop("N", 4096)
         return lorenz96(d=8, N=N, T=kw.pop("T", 200), B=chains,

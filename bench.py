@@ -449,8 +449,14 @@ def autotune_worker(argv):
     if which == "lorenz96_d8_chains":
         pb = W.config("lorenz96_d8_chains").with_obs(y)
     f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    threads, groups, cand = f.autotune(steps=pb.T - 1)
+    # three passes over the candidates, each candidate's best time kept: the
+    # leading candidates differ by about as much as one pass's noise
+    passes = [f.autotune(steps=pb.T - 1)[2] for _ in range(3)]
     f.close()
+    cand = np.min(np.where(np.stack(passes) > 0, np.stack(passes), np.inf), axis=0)
+    gi, ci = np.unravel_index(int(np.argmin(cand)), cand.shape)
+    threads, groups = (256, 512, 1024)[ci], (1, 2, 4)[gi]
+    cand = np.where(np.isfinite(cand), cand, -1.0)
     print(json.dumps({"threads": threads, "groups": groups, "cand_ms": cand.tolist()}), flush=True)
 
 
@@ -579,7 +585,7 @@ def main():
             tune_src = "default (the autotuner's child process failed)"
             log("[bench] autotune failed; collective workgroup 512, 2 filter groups")
         else:
-            tune_src = "autotuner in a child process, whole horizon per candidate"
+            tune_src = "autotuner in a child process, whole horizon per candidate, best of 3 passes"
             threads, groups, cand_ms = tuned
             log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
                 f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "

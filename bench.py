@@ -504,6 +504,9 @@ def main():
                     help="run only the history / state-sample leg (for kernel traces)")
     ap.add_argument("--profile-smc2", action="store_true",
                     help="run only the SMC^2 leg (for kernel traces)")
+    ap.add_argument("--profile-pmmh", action="store_true",
+                    help="run only PMMH on the chains' shape, 512 lanes / 2 groups "
+                         "(for kernel traces; --pmmh-iters sets its length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline workload only")
     ap.add_argument("--fp64-batched-leg", action="store_true",
@@ -565,6 +568,20 @@ def main():
         return
     if args.profile_smc2:
         print(json.dumps({"profile_smc2": smc2_leg(torch, pfm, pb, stream, args.smc2_T, 512, 2)}),
+              flush=True)
+        return
+    if args.profile_pmmh:
+        pm = W.config("lorenz96_d8_chains").with_obs(y)
+        fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+        fm.set_tuning(512, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fm.pmmh(W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters))
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        fm.close()
+        print(json.dumps({"profile_pmmh": {"iterations": args.pmmh_iters,
+                                           "filters_per_s": pm.B * (args.pmmh_iters + 1) / dtm}}),
               flush=True)
         return
 

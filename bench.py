@@ -453,11 +453,21 @@ def autotune_worker(argv):
     # leading candidates differ by about as much as one pass's noise
     passes = [f.autotune(steps=pb.T - 1)[2] for _ in range(3)]
     f.close()
-    cand = np.min(np.where(np.stack(passes) > 0, np.stack(passes), np.inf), axis=0)
-    gi, ci = np.unravel_index(int(np.argmin(cand)), cand.shape)
-    threads, groups = (256, 512, 1024)[ci], (1, 2, 4)[gi]
-    cand = np.where(np.isfinite(cand), cand, -1.0)
+    threads, groups, cand = pick_tuning(passes)
     print(json.dumps({"threads": threads, "groups": groups, "cand_ms": cand.tolist()}), flush=True)
+
+
+def pick_tuning(passes):
+    """The tuning with the lowest best-of-passes time.  Each pass is the
+    autotuner's [groups (1, 2, 4)] x [workgroup (256, 512, 1024)] array of ms
+    per interval, -1 where a candidate was not run.  Returns (threads,
+    groups, per-candidate best times with -1 kept for candidates never run)."""
+    t = np.stack([np.asarray(p, dtype=np.float64).reshape(3, 3) for p in passes])
+    best = np.min(np.where(t > 0, t, np.inf), axis=0)
+    if not np.isfinite(best).any():
+        raise ValueError("no autotuning candidate was timed")
+    gi, ci = np.unravel_index(int(np.argmin(best)), best.shape)
+    return (256, 512, 1024)[ci], (1, 2, 4)[gi], np.where(np.isfinite(best), best, -1.0)
 
 
 def autotune_isolated(which):

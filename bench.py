@@ -1,20 +1,24 @@
 """Throughput of the MI355X bootstrap particle filter (one JSON line on stdout).
 
-A step is one observation interval of the whole hot path for every particle
-of the workload: propagate (K substeps) + weight + likelihood increment +
-ESS + systematic resampling + ancestor gather.  Inputs (observations,
-parameters, particles) are resident in HBM before timing starts; the data
-are simulated on the GPU from the model.
+A step is one pass of the whole hot path over the headline batch: every
+filter re-initialised (x(t0) drawn), then T observation intervals of
+propagate (K substeps) + weight + likelihood increment + ESS + systematic
+resampling + ancestor gather, replayed from captured graphs, then the
+likelihoods read back (the only host synchronisation).  The rate is in
+particle-steps/s, a particle-step being one particle through one
+observation interval.  Inputs (observations, parameters) are resident in
+HBM before timing starts; the data are simulated on the GPU from the model.
 
 Headline (``value``): the FP32 batched form on the batched workload — 512
 Lorenz '96 (d = 8) filters with F ~ U(6, 10), sigma ~ U(0.05, 0.3) and
-particle counts uniform over {256, ..., 8192}, T = 200 — in particle-steps/s,
-next to the FP64 plain filter (one filter at a time, per-filter kernels) on
-the same workload, and the FP32 error per step measured at full size by
-teacher forcing against the FP64 path.  Secondary legs: the single filter
+particle counts uniform over {256, ..., 8192}, T = 200 — next to the FP64
+plain filter (one filter at a time, per-filter kernels) and the FP64 batched
+form on the same workload, and the FP32 error per step measured at full size
+by teacher forcing against the FP64 path.  Secondary legs: the single filter
 (d = 8, N = 65,536), the large filter (d = 40, N = 2^20: resample + gather
-against HBM, propagation against the VALU issue rate), and marginal
-Metropolis-Hastings chains (64 x N = 4096).
+against HBM, propagation against the FP32 vector peak), and marginal
+Metropolis-Hastings chains (64 x N = 4096), whose acceptance is compared
+with the oracle's chains on the same inputs.
 """
 from __future__ import annotations
 
@@ -34,10 +38,14 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# VALU peak in lane-operations/s: the FP32 vector peak of 157.3 TFLOP/s counts
-# an FMA as 2 FLOP, i.e. 78.6 T lane-operations/s (256 CUs x 2.4 GHz x 128);
-# every VALU instruction is counted as one lane-operation.
+# MI355X's published FP32 vector peak
+FP32_PEAK_TFLOPS = 157.3
+# VALU issue peak in lane-operations/s: the FP32 vector peak counts an FMA as
+# 2 FLOP, i.e. 78.6 T lane-operations/s (256 CUs x 2.4 GHz x 128); every VALU
+# instruction is counted as one lane-operation.
 VALU_PEAK_TOPS = 157.3 / 2
+# the per-step log-likelihood bound of the FP32 form (absolute)
+FP32_ELL_BOUND = 1e-4
 
 
 def log(msg):
@@ -104,6 +112,17 @@ def valu_slots_per_particle_step(model: int, d: int, K: int, n_obs: int, fp32: b
     return K * per_sub + 3 * n_obs + 4
 
 
+def model_flop_per_particle_step(model: int, d: int, K: int, n_obs: int) -> int:
+    """The propagation's algorithmic floating-point work per particle-step,
+    random numbers excluded: Lorenz '96 RK4 about 30 FLOP per component per
+    substep (four drift evaluations of 3 operations plus the stage inputs and
+    the weighted sum), and 4 per observed component for the weight; the
+    windkessel step 5 per substep."""
+    if model == W.MODEL_WK:
+        return 5 * K + 4 * n_obs
+    return 30 * d * K + 4 * n_obs
+
+
 def resample_gather_bytes(d: int, sx: int, slw: int) -> int:
     """Algorithmic HBM bytes per particle of one plain-layout resample +
     gather: read the log-weight (scan), write and read the stratum count,
@@ -141,6 +160,25 @@ def timed(torch, runner, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runner.run(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def filter_passes(f, T, n):
+    """n passes of the whole hot path over the workload: every filter
+    re-initialised, T intervals replayed from the captured graphs, the
+    likelihoods read back (which synchronises the stream)."""
+    for _ in range(n):
+        f.reset(0)
+        f.graph_run(T)
+        f.loglik(allow_numeric=True)
+
+
+def timed_passes(torch, f, T, steps, warmup):
+    filter_passes(f, T, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    filter_passes(f, T, steps)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 
@@ -187,27 +225,41 @@ def teacher_forced_fp32_error(pfm, pb, stream, steps):
     return np.array(err), np.array(ell), np.array(ess)
 
 
-def tf_summary(err, ell, ess, bound, rel_bound):
-    """Distribution of the teacher-forced errors over (interval, filter) pairs;
-    the combined bound is max(bound, rel_bound |ell_t|)."""
-    comb = np.maximum(bound, rel_bound * np.abs(ell))
-    worst = np.argsort(-(err / comb).ravel())[:3]
+def tf_summary(err, ell, ess, bound):
+    """Distribution of the teacher-forced errors over (interval, filter) pairs
+    against the absolute bound, with the pairs that exceed it listed."""
+    over = np.argsort(-err.ravel())
+    n_over = int(np.sum(err > bound))
     ok = ess >= 2.0
-    return {"max_abs": float(err.max()), "p99_abs": float(np.quantile(err, 0.99)),
-            "median_abs": float(np.median(err)),
-            "frac_within_abs_bound": float(np.mean(err <= bound)),
+    return {"bound": bound, "max_abs": float(err.max()),
+            "p99_abs": float(np.quantile(err, 0.99)), "median_abs": float(np.median(err)),
+            "pairs": int(err.size), "pairs_over_bound": n_over,
+            "frac_within_bound": float(np.mean(err <= bound)),
             "max_abs_where_ess_ge_2": float(err[ok].max()) if ok.any() else None,
-            "rel_bound": rel_bound,
-            "frac_within_combined_bound": float(np.mean(err <= comb)),
-            "max_ratio_to_combined_bound": float((err / comb).max()),
+            "pairs_over_bound_where_ess_ge_2": int(np.sum(err[ok] > bound)),
             "worst": [{"err": float(err.ravel()[i]), "ell": float(ell.ravel()[i]),
-                       "ess": float(ess.ravel()[i])} for i in worst],
-            "pairs": int(err.size)}
+                       "ess": float(ess.ravel()[i])} for i in over[:max(3, min(n_over, 12))]]}
+
+
+def resample_gather_hbm(kt, d, n):
+    """Algorithmic-bytes HBM rate of one plain-layout resample + gather
+    (scan + counts, then the merge-path gather) from the kernels' mean
+    durations."""
+    us = kt["scan"] + kt["gather"]
+    byt = resample_gather_bytes(d, 4, 8)
+    gbs = byt * n / (us * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "bytes_per_particle": byt, "us": us,
+            "scan_us": kt["scan"], "gather_us": kt["gather"]}
 
 
 def large_filter_leg(torch, pfm, stream):
     """One Lorenz '96 (d = 40) filter of 2^20 particles, FP32 mixed: resample +
-    gather priced against HBM, propagation against the VALU issue rate."""
+    gather priced against HBM, propagation against the FP32 vector peak.  The
+    resample + gather is also measured with spread weights (an observation sd
+    of 20 on the same data: ESS near N, so the ancestors are nearly the
+    identity and the gather reads every particle's state from HBM rather
+    than a few heavy particles' from cache)."""
     big = W.config("lorenz96_d40_large")
     _, yb = pfm.simulate(big, stream=stream)
     big = big.with_obs(yb)
@@ -216,6 +268,7 @@ def large_filter_leg(torch, pfm, stream):
     rb.run(3)
     kb = kernel_times(rb, 10)
     dtb = timed(torch, rb, 20, 2)
+    _, ess_b, _ = fb.loglik()
     variants = {}
     for name, scheme, msteps in (("stratified", 1, 0), ("multinomial", 3, 0),
                                  ("metropolis_8", 2, 8)):
@@ -224,30 +277,44 @@ def large_filter_leg(torch, pfm, stream):
         kv = kernel_times(rb, 10)
         variants[name] = {"resample_gather_us": kv["scan"] + kv["gather"]}
     fb.close()
+    spread = dataclasses.replace(big, obs_sd=20.0)
+    fs = pfm.Filter(spread, stream=stream)
+    rs = Runner(fs, spread.T)
+    rs.run(3)
+    ks = kernel_times(rs, 10)
+    _, ess_s, _ = fs.loglik()
+    fs.close()
     nb = int(big.n_particles[0])
-    rs_us = kb["scan"] + kb["gather"]
-    byt = resample_gather_bytes(big.d, 4, 8)
-    gbs = byt * nb / (rs_us * 1e-6) / 1e9
+    rg = resample_gather_hbm(kb, big.d, nb)
+    rg["ess_last_step"] = float(ess_b[0])
+    rgs = resample_gather_hbm(ks, big.d, nb)
+    rgs["ess_last_step"] = float(ess_s[0])
+    rgs["obs_sd"] = spread.obs_sd
+    flop_b = model_flop_per_particle_step(big.model, big.d, big.K, big.n_obs)
+    ach_b = flop_b * nb / (kb["propagate"] * 1e-6) / 1e12
     slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
-    ach_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
+    sl_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
     leg = {
         "workload": big.name, "particles": nb, "us_per_step": dtb / 20 * 1e6,
         "particle_steps_per_s": nb * 20 / dtb,
-        "resample_gather": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                            "bytes_per_particle": byt, "us": rs_us,
-                            "scan_us": kb["scan"], "gather_us": kb["gather"]},
-        "propagate": {"bound": "alu", "achieved": ach_b, "peak": VALU_PEAK_TOPS,
-                      "unit": "TOP/s", "frac": ach_b / VALU_PEAK_TOPS,
-                      "us": kb["propagate"], "ops_per_particle_step": slots_b},
+        "resample_gather": rg,
+        "resample_gather_spread_weights": rgs,
+        "propagate": {"bound": "alu", "achieved": ach_b, "peak": FP32_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": ach_b / FP32_PEAK_TFLOPS,
+                      "us": kb["propagate"], "flop_per_particle_step": flop_b,
+                      "issue_slots": {"ops_per_particle_step": slots_b, "achieved": sl_b,
+                                      "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                                      "frac": sl_b / VALU_PEAK_TOPS}},
         "combine_us": kb["combine"],
         "resample_variants": variants,
     }
     log("[bench] large filter resample+gather variants (us): " +
         ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants.items()))
-    log(f"[bench] large filter: resample+gather {rs_us:.1f} us = {gbs:.0f} GB/s "
-        f"({gbs / HBM_PEAK_GBS:.0%}); propagate {kb['propagate']:.1f} us "
-        f"({ach_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
+    log(f"[bench] large filter: resample+gather {rg['us']:.1f} us = {rg['achieved']:.0f} GB/s "
+        f"({rg['frac']:.0%}, ESS {rg['ess_last_step']:.3g}); spread weights {rgs['us']:.1f} us = "
+        f"{rgs['achieved']:.0f} GB/s ({rgs['frac']:.0%}, ESS {rgs['ess_last_step']:.3g}); "
+        f"propagate {kb['propagate']:.1f} us ({ach_b / FP32_PEAK_TFLOPS:.0%} of the FP32 peak, "
+        f"{sl_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
     return leg
 
 
@@ -391,12 +458,29 @@ def smc2_leg(torch, pfm, pb, stream, T, threads, groups):
     return leg
 
 
+def host_cpu():
+    """The host's core count and CPU model (the oracle's timing host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "cores_available": len(os.sched_getaffinity(0)),
+            "model": model}
+
+
 def oracle_worker(argv):
-    """One process of the all-cores oracle figure: filters w, w + P, ... of
-    the headline workload (observations from the file the parent wrote), the
+    """One oracle process, pinned to one core: filters w, w + P, ... of the
+    headline workload (observations from the file the parent wrote), the
     first T / 10 intervals each, for about `seconds`; prints its work and
     time.  Uses no GPU."""
-    w, P, seconds, obs_path = int(argv[0]), int(argv[1]), float(argv[2]), argv[3]
+    w, P, seconds, obs_path, core = (int(argv[0]), int(argv[1]), float(argv[2]), argv[3],
+                                     int(argv[4]))
+    os.sched_setaffinity(0, {core})
     import oracle
     pb = W.config("lorenz96_d8_batched").with_obs(np.load(obs_path, allow_pickle=False))
     t0 = time.perf_counter()
@@ -406,20 +490,25 @@ def oracle_worker(argv):
         done_ps += int(pb.n_particles[b]) * (pb.T // 10)
         nf += 1
         b += P
-    print(json.dumps({"ps": done_ps, "s": time.perf_counter() - t0, "filters": nf}), flush=True)
+    print(json.dumps({"ps": done_ps, "s": time.perf_counter() - t0, "filters": nf,
+                      "first": w, "stride": P, "core": core,
+                      "affinity": sorted(os.sched_getaffinity(0))}), flush=True)
 
 
-def oracle_all_cores(pb, seconds, procs):
-    """The oracle run by `procs` child processes at once on disjoint filters:
-    the aggregate rate of the host's cores."""
+def oracle_procs(pb, seconds, procs):
+    """The oracle in `procs` child processes at once, each pinned to its own
+    core (process w on the w-th core of this process's affinity set), on
+    disjoint filters of the headline workload."""
     import subprocess
     import tempfile
+    cores = sorted(os.sched_getaffinity(0))
     fd, path = tempfile.mkstemp(suffix=".npy")
     os.close(fd)
     try:
         np.save(path, np.ascontiguousarray(pb.obs), allow_pickle=False)
         ps = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
-                                str(w), str(procs), str(seconds), path],
+                                str(w), str(procs), str(seconds), path,
+                                str(cores[w % len(cores)])],
                                stdout=subprocess.PIPE, text=True) for w in range(procs)]
         res = []
         for p in ps:
@@ -430,31 +519,6 @@ def oracle_all_cores(pb, seconds, procs):
     finally:
         os.unlink(path)
     return res
-
-
-def autotune_worker(argv):
-    """Child process of autotune_isolated: the autotuner on the headline
-    workload ("lorenz96_d8_batched") or the PMMH shape ("lorenz96_d8_chains",
-    on the headline's data); prints the choice and the candidates' times as
-    one JSON line."""
-    which = argv[0]
-    import torch
-    import paper_1306_3277_amd as pfm
-    torch.cuda.set_device(0)
-    pfm.load()
-    stream = torch.cuda.Stream()
-    pb = W.config("lorenz96_d8_batched")
-    _, y = pfm.simulate(pb, stream=stream)
-    pb = pb.with_obs(y)
-    if which == "lorenz96_d8_chains":
-        pb = W.config("lorenz96_d8_chains").with_obs(y)
-    f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-    # three passes over the candidates, each candidate's best time kept: the
-    # leading candidates differ by about as much as one pass's noise
-    passes = [f.autotune(steps=pb.T - 1)[2] for _ in range(3)]
-    f.close()
-    threads, groups, cand = pick_tuning(passes)
-    print(json.dumps({"threads": threads, "groups": groups, "cand_ms": cand.tolist()}), flush=True)
 
 
 def pick_tuning(passes):
@@ -470,36 +534,50 @@ def pick_tuning(passes):
     return (256, 512, 1024)[ci], (1, 2, 4)[gi], np.where(np.isfinite(best), best, -1.0)
 
 
-def autotune_isolated(which):
-    """The autotuner run in a child process, so that a failure inside it
-    cannot end the benchmark (the autotuner has ended processes with a host
-    segmentation fault, cause not found).  Returns (threads, groups,
-    candidate times) or None if the child failed."""
-    import subprocess
-    try:
-        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--autotune-worker", which],
-                           capture_output=True, text=True, timeout=600)
-    except subprocess.TimeoutExpired:
-        return None
-    if r.returncode != 0:
-        log(f"[bench] autotune child exited with {r.returncode}: {r.stderr.strip()[-300:]}")
-        return None
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return d["threads"], d["groups"], np.array(d["cand_ms"])
+def autotune(f, steps, passes=3):
+    """The library's autotuner on handle f, `passes` times (each candidate's
+    best pass kept: the leading candidates differ by about one pass's noise);
+    the handle is left on the choice."""
+    threads, groups, cand = pick_tuning([f.autotune(steps=steps)[2] for _ in range(passes)])
+    f.set_tuning(threads, groups)
+    return threads, groups, cand
+
+
+def pmmh_vs_oracle(pfm, y, stream, chains=2, iters=20, T=20):
+    """Acceptance of the FP32 batched PMMH chains against the oracle's FP64
+    chains on the same chain inputs (initial values, proposal normals,
+    acceptance uniforms) and the same generator counters: the chains' shape
+    (N = 4096, d = 8) over the first T observations."""
+    import oracle
+    pm = W.config("lorenz96_d8_chains", chains=chains, T=T).with_obs(y[:T])
+    inp = W.pmmh_inputs(chains=chains, iters=iters)
+    f = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    g = f.pmmh(inp)
+    f.close()
+    t0 = time.perf_counter()
+    r = oracle.pmmh(pm, int(pm.n_particles[0]), inp)
+    dt = time.perf_counter() - t0
+    same = np.mean(np.abs(g["log_f"] - r["log_f"]) == 0.0)
+    return {"chains": chains, "iterations": iters, "T": T, "particles": int(pm.n_particles[0]),
+            "accept_rate_gpu_fp32": float(g["accepts"].sum() / (chains * iters)),
+            "accept_rate_oracle_fp64": float(r["accepts"].sum() / (chains * iters)),
+            "chain_states_identical": float(same),
+            "max_abs_ll_diff_on_identical_states": float(
+                np.max(np.abs(g["ll"] - r["ll"])[np.abs(g["log_f"] - r["log_f"]) == 0.0]))
+            if same > 0 else None,
+            "oracle_seconds": dt}
 
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
         oracle_worker(sys.argv[2:])
         return
-    if len(sys.argv) > 1 and sys.argv[1] == "--autotune-worker":
-        autotune_worker(sys.argv[2:])
-        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=2000,
-                    help="untimed intervals before the timed ones (the device clocks settle)")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed passes of the whole filter over the batch (T intervals each)")
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed passes before the timed ones")
     ap.add_argument("--fp64-steps", type=int, default=40,
                     help="intervals timed for the FP64 plain comparison")
     ap.add_argument("--pmmh-iters", type=int, default=2000)
@@ -519,12 +597,9 @@ def main():
                          "(for kernel traces; --pmmh-iters sets its length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="headline workload only")
-    ap.add_argument("--fp64-batched-leg", action="store_true",
-                    help="also time the FP64 batched layout on the headline workload "
-                         "(off by default: a run with it ended in a host segmentation "
-                         "fault whose cause is not found)")
     ap.add_argument("--profile-headline", action="store_true",
-                    help="run only the timed FP32 batched intervals (for counter runs)")
+                    help="run only the timed FP32 batched passes with a fixed tuning "
+                         "(for counter runs)")
     ap.add_argument("--profile-large", action="store_true",
                     help="run only the large single-filter leg (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -603,42 +678,37 @@ def main():
         tune_src = "fixed (profiling run)"
         f32.set_tuning(threads, groups)
     else:
-        # the tuner replays every candidate over the whole horizon (the
-        # weights' concentration, and with it the collective's work, changes
-        # along it)
-        tuned = autotune_isolated("lorenz96_d8_batched")
-        if tuned is None:
-            threads, groups = 512, 2
-            tune_src = "default (the autotuner's child process failed)"
-            log("[bench] autotune failed; collective workgroup 512, 2 filter groups")
-        else:
-            tune_src = "autotuner in a child process, whole horizon per candidate, best of 3 passes"
-            threads, groups, cand_ms = tuned
-            log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
-                f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
-                f"{np.round(cand_ms * 1e3, 1).tolist()}")
-        f32.set_tuning(threads, groups)
-    r32 = Runner(f32, pb.T)
-    dt32 = timed(torch, r32, args.steps, args.warmup)
+        # every candidate timed over the whole horizon (the weights'
+        # concentration, and with it the collective's work, changes along it)
+        threads, groups, cand_ms = autotune(f32, pb.T - 1)
+        tune_src = "autotuner, whole horizon per candidate, best of 3 passes"
+        log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
+            f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
+            f"{np.round(cand_ms * 1e3, 1).tolist()}")
+    dt32 = timed_passes(torch, f32, pb.T, args.steps, args.warmup)
+    ps_per_step = n_tot * pb.T
     # the same timed region repeated, for the spread of the figure
     reps = [] if args.profile_headline else [
-        timed(torch, r32, args.steps, 0) / args.steps * 1e3 for _ in range(args.repeats)]
-    # per-kernel durations on one stream (no group overlap), for the roofline
-    f32.set_tuning(threads, 1)
-    kt32 = kernel_times(r32, min(args.steps, pb.T))
-    f32.set_tuning(threads, groups)
-    r32.restart()
-    r32.run(pb.T)
-    ll32, _, _ = f32.loglik()
-    f32.close()
-    rate32 = n_tot * args.steps / dt32
-    log(f"[bench] fp32 batched: {dt32 / args.steps * 1e3:.4f} ms/step {rate32:.4e} p-steps/s; "
-        f"propagate {kt32['propagate']:.1f} us, collective {kt32['batched']:.1f} us")
-
+        timed_passes(torch, f32, pb.T, args.steps, 0) / args.steps * 1e3
+        for _ in range(args.repeats)]
     if args.profile_headline:
+        f32.close()
         print(json.dumps({"profile_headline": pb.name, "ms_per_step": dt32 / args.steps * 1e3}),
               flush=True)
         return
+    # per-kernel durations on one stream (no group overlap), for the roofline
+    r32 = Runner(f32, pb.T)
+    f32.set_tuning(threads, 1)
+    kt32 = kernel_times(r32, pb.T)
+    f32.set_tuning(threads, groups)
+    r32.restart()
+    r32.run(pb.T)
+    ll32, _, _ = f32.loglik(allow_numeric=True)
+    f32.close()
+    rate32 = ps_per_step * args.steps / dt32
+    log(f"[bench] fp32 batched: {dt32 / args.steps * 1e3:.3f} ms/step "
+        f"({dt32 / args.steps / pb.T * 1e6:.1f} us/interval) {rate32:.4e} p-steps/s; "
+        f"propagate {kt32['propagate']:.1f} us, collective {kt32['batched']:.1f} us")
 
     log("[bench] FP64 plain leg starts")
     f64 = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_PLAIN, stream=stream)
@@ -646,40 +716,44 @@ def main():
     dt64 = timed(torch, r64, args.fp64_steps, 2)
     r64.restart()
     r64.run(pb.T)
-    ll64, _, _ = f64.loglik()
+    ll64, _, _ = f64.loglik(allow_numeric=True)
     f64.close()
     rate64 = n_tot * args.fp64_steps / dt64
-    log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.4f} ms/step {rate64:.4e} p-steps/s")
+    log(f"[bench] fp64 plain: {dt64 / args.fp64_steps * 1e3:.4f} ms/interval {rate64:.4e} p-steps/s")
 
-    tf = tf_summary(*teacher_forced_fp32_error(pfm, pb, stream, args.tf_steps), 1e-4, 1e-6)
+    tf = tf_summary(*teacher_forced_fp32_error(pfm, pb, stream, args.tf_steps), FP32_ELL_BOUND)
     log(f"[bench] teacher-forced FP32 error over {pb.B} filters x {args.tf_steps} intervals: "
-        f"max {tf['max_abs']:.2e}, p99 {tf['p99_abs']:.2e}, median {tf['median_abs']:.2e}, "
-        f"within 1e-4: {tf['frac_within_abs_bound']:.4f}; within max(1e-4, 1e-6 |ell|): "
-        f"{tf['frac_within_combined_bound']:.4f} (worst ratio {tf['max_ratio_to_combined_bound']:.2f}); "
-        f"max where ESS >= 2: {tf['max_abs_where_ess_ge_2']:.2e}; worst {tf['worst']}")
+        f"max {tf['max_abs']:.2e}, p99 {tf['p99_abs']:.2e}, median {tf['median_abs']:.2e}; "
+        f"{tf['pairs_over_bound']} of {tf['pairs']} pairs over {FP32_ELL_BOUND:g} "
+        f"({tf['pairs_over_bound_where_ess_ge_2']} of them with ESS >= 2; max there "
+        f"{tf['max_abs_where_ess_ge_2']:.2e}); worst {tf['worst'][:3]}")
 
     # FP64 batched (same kernels as the headline, FP64 state and own-math normals)
-    fp64_batched = None
-    if args.fp64_batched_leg:
-        f64b = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-        f64b.autotune(steps=4)
-        r64b = Runner(f64b, pb.T)
-        dt64b = timed(torch, r64b, args.fp64_steps, 4)
-        f64b.close()
-        rate64b = n_tot * args.fp64_steps / dt64b
-        fp64_batched = {"value": rate64b, "unit": "particle-steps/s",
-                        "ms_per_step": dt64b / args.fp64_steps * 1e3, "steps": args.fp64_steps}
-        log(f"[bench] fp64 batched: {dt64b / args.fp64_steps * 1e3:.4f} ms/step "
-            f"{rate64b:.4e} p-steps/s")
+    log("[bench] FP64 batched leg starts")
+    f64b = pfm.Filter(pb, precision=W.FP64, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
+    t64b, g64b, _ = autotune(f64b, 16, passes=1)
+    n64b = max(2, args.steps // 4)
+    dt64b = timed_passes(torch, f64b, pb.T, n64b, 1)
+    f64b.close()
+    rate64b = ps_per_step * n64b / dt64b
+    fp64_batched = {"value": rate64b, "unit": "particle-steps/s",
+                    "ms_per_step": dt64b / n64b * 1e3, "steps": n64b,
+                    "collective_workgroup": t64b, "filter_groups": g64b}
+    log(f"[bench] fp64 batched: {dt64b / n64b * 1e3:.2f} ms/step {rate64b:.4e} p-steps/s")
 
+    flop = model_flop_per_particle_step(pb.model, pb.d, pb.K, pb.n_obs)
     slots = valu_slots_per_particle_step(pb.model, pb.d, pb.K, pb.n_obs, True)
     k5a_s = kt32["propagate"] / 1e6
-    achieved = slots * n_tot / k5a_s / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS,
+    achieved = flop * n_tot / k5a_s / 1e12
+    ach_slots = slots * n_tot / k5a_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                 "traffic": counted_traffic("k_batch_propagate_lorenz96_d8_batched_B512.md"),
                 "kernel": "k_batch_propagate<fp32, d=8>", "kernel_us": kt32["propagate"],
-                "ops_per_particle_step": slots, "particles_per_launch": n_tot}
+                "flop_per_particle_step": flop, "particles_per_launch": n_tot,
+                "issue_slots": {"ops_per_particle_step": slots, "achieved": ach_slots,
+                                "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                                "frac": ach_slots / VALU_PEAK_TOPS}}
 
     out = {
         "metric": "particle-steps/sec (FP32 batched vs FP64 plain) at stated loglik error; "
@@ -698,19 +772,23 @@ def main():
         "config": {"workload": pb.name, "model": "lorenz96", "d": pb.d, "filters": pb.B,
                    "particles": n_tot, "particle_counts": "uniform over 256..8192",
                    "T": pb.T, "substeps": pb.K, "layout": "batched",
+                   "step": f"one pass over the batch: init, {pb.T} intervals, likelihood readout",
+                   "particle_steps_per_step": ps_per_step,
+                   "us_per_interval": dt32 / args.steps / pb.T * 1e6,
                    "collective_workgroup": threads, "filter_groups": groups, "tuning": tune_src,
                    "precision": "fp32 state/propagation, fp64 log-weights/scan/likelihood"},
         "fp64_plain": {"value": rate64, "unit": "particle-steps/s",
-                       "ms_per_step": dt64 / args.fp64_steps * 1e3, "steps": args.fp64_steps},
+                       "ms_per_interval": dt64 / args.fp64_steps * 1e3,
+                       "intervals": args.fp64_steps},
         "fp64_batched": fp64_batched,
         "fp32_batched_over_fp64_plain": rate32 / rate64,
-        "fp32_batched_over_fp64_batched": rate32 / fp64_batched["value"] if fp64_batched else None,
-        "loglik_error": {"fp32_teacher_forced_per_step": tf, "bound": 1e-4,
+        "fp32_batched_over_fp64_batched": rate32 / rate64b,
+        "loglik_error": {"fp32_teacher_forced_per_step": tf, "bound": FP32_ELL_BOUND,
                          "fp64_vs_oracle_rel_bound": 1e-10,
                          "fp32_free_running_median_abs_diff_vs_fp64":
                              float(np.median(np.abs(ll32 - ll64)))},
         "kernels_us": {"fp32_batched": kt32},
-        "repeats_ms_per_step": {"values": [round(x, 5) for x in reps],
+        "repeats_ms_per_step": {"values": [round(x, 4) for x in reps],
                                 "median": float(np.median(reps)) if reps else None},
         "roofline": roofline,
     }
@@ -747,9 +825,7 @@ def main():
             pm = pm.with_obs(y)  # the d = 8 data set of the batched workload
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-            tuned = autotune_isolated("lorenz96_d8_chains")
-            pm_threads, pm_groups = (512, 2) if tuned is None else tuned[:2]
-            fm.set_tuning(pm_threads, pm_groups)
+            pm_threads, pm_groups, _ = autotune(fm, pm.T - 1)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = fm.pmmh(inp)
@@ -766,6 +842,9 @@ def main():
                                                 (pm.B * args.pmmh_iters))}
             log(f"[bench] pmmh: {nfilt / dtm:.1f} filters/s, accept "
                 f"{out['pmmh']['accept_rate']:.3f}")
+            if not args.no_cpu_baseline:
+                out["pmmh"]["vs_oracle"] = pmmh_vs_oracle(pfm, y, stream)
+                log(f"[bench] pmmh vs oracle chains: {out['pmmh']['vs_oracle']}")
 
         # ------------------------------------------------------------ resamplers
         log("[bench] resampler leg starts")
@@ -778,7 +857,7 @@ def main():
         # ------------------------------------------------------------ state sample
         log("[bench] history leg starts")
         out["state_sample"] = path_leg(torch, pfm, pb, stream, threads, groups,
-                                       dt32 / args.steps)
+                                       dt32 / args.steps / pb.T)
 
         # ------------------------------------------------------------ SMC^2
         if args.smc2_T > 0:
@@ -786,34 +865,28 @@ def main():
             out["smc2"] = smc2_leg(torch, pfm, pb, stream, args.smc2_T, threads, groups)
 
     if not args.no_cpu_baseline:
-        log("[bench] CPU oracle sample starts")
-        import oracle
+        host = host_cpu()
+        log(f"[bench] CPU oracle on one pinned core starts (host {host})")
         # bounded sample of the headline workload: whole filters of the batch,
-        # taken in order, all T intervals, until about cpu_seconds of work
-        t0 = time.perf_counter()
-        done_ps = 0
-        nf = 0
-        while time.perf_counter() - t0 < args.cpu_seconds and nf < pb.B:
-            b = nf
-            oracle.pf_run(pb, theta=pb.theta[b], N=int(pb.n_particles[b]), b=b, T=pb.T // 10)
-            done_ps += int(pb.n_particles[b]) * (pb.T // 10)
-            nf += 1
-        dtc = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": done_ps / dtc, "unit": "particle-steps/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{pb.name}: filters 0..{nf - 1} of {pb.B}, first "
-                                         f"{pb.T // 10} of {pb.T} intervals each, FP64, one "
-                                         f"thread ({dtc:.1f} s)"}
+        # taken in order, the first T/10 intervals each, for about cpu_seconds
+        r1 = oracle_procs(pb, args.cpu_seconds, 1)[0]
+        out["cpu_baseline"] = {"value": r1["ps"] / r1["s"], "unit": "particle-steps/s",
+                               "cores": 1, "kind": "oracle", "host": host,
+                               "sample": f"{pb.name}: filters 0..{r1['filters'] - 1} of {pb.B}, "
+                                         f"first {pb.T // 10} of {pb.T} intervals each, FP64, "
+                                         f"one process pinned to core {r1['core']} "
+                                         f"({r1['s']:.1f} s)"}
         if args.cpu_procs > 0:
-            log(f"[bench] CPU oracle on {args.cpu_procs} processes starts")
-            procs = min(args.cpu_procs, pb.B)
-            res = oracle_all_cores(pb, args.cpu_seconds / 2, procs)
+            procs = min(args.cpu_procs, pb.B, host["cores_available"])
+            log(f"[bench] CPU oracle on {procs} pinned processes starts")
+            res = oracle_procs(pb, args.cpu_seconds / 2, procs)
             out["cpu_baseline_all_cores"] = {
                 "value": sum(r["ps"] / r["s"] for r in res), "unit": "particle-steps/s",
-                "cores": procs, "kind": "oracle",
+                "cores": procs, "kind": "oracle", "host": host,
                 "sample": f"{pb.name}: {sum(r['filters'] for r in res)} filters dealt round-robin "
-                          f"to {procs} processes run at once, first {pb.T // 10} of {pb.T} "
-                          f"intervals each, FP64, about {args.cpu_seconds / 2:.1f} s per process"}
+                          f"to {procs} processes run at once, each pinned to its own core, first "
+                          f"{pb.T // 10} of {pb.T} intervals each, FP64, about "
+                          f"{args.cpu_seconds / 2:.1f} s per process"}
     print(json.dumps(out), flush=True)
 
 

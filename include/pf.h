@@ -156,7 +156,12 @@ pf_status pf_get_trace(pf_handle* h, double* ell_out, double* ess_out);
 pf_status pf_destroy(pf_handle* h);
 
 /* Run n_steps observation intervals (pf_step + pf_resample each) by replaying
- * a HIP graph captured on the first call.  Same results as the eager calls. */
+ * HIP graphs captured on the first call (and again after a change of tuning
+ * or resampler).  Each graph is captured on one stream and holds kernel
+ * launches only: the plain layout's holds one interval of every filter; the
+ * batched layout has, per filter group, one graph of one interval and one
+ * of eight, launched on the group's own stream between a fork from and a
+ * join into the handle's stream.  Same results as the eager calls. */
 pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 
 /* Replace every filter's parameters (host [B][n_theta]) and re-initialise
@@ -329,8 +334,12 @@ pf_status pf_smc2(pf_handle* h, pf_handle* proposal, void* d_ws, size_t ws_bytes
  * per-filter collective kernel (256, 512, 1024 lanes) and each number of
  * filter groups (1, 2, 4; groups are balanced by particle count and stepped
  * concurrently on their own streams, so one group's collective overlaps
- * another's propagation), replays `steps` intervals of this handle's own
- * workload, keeps the fastest pair and re-initialises the filters (t = 0).
+ * another's propagation), re-initialises the filters and times `steps`
+ * intervals (at most T - 1, after one untimed interval) of this handle's own
+ * workload on eager launches — no graph is captured or destroyed per
+ * candidate; the next pf_graph_run captures the chosen tuning's graphs —
+ * keeps the fastest pair and re-initialises the filters (t = 0).  On an
+ * error the handle is put back on its previous tuning, re-initialised.
  * ms_out[9] (may be NULL) receives the mean interval time in ms of candidate
  * (groups index g, size index s) at [3g + s] (-1 when groups > B);
  * *threads_out and *groups_out (may be NULL) the choice.  Plain layout:

@@ -223,7 +223,8 @@ struct pf_handle {
   int groups = 1;
   std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt;
   // with G > 1 groups, group g's kernels run on side[g]; ev_a[0] forks the
-  // side streams from the caller's, ev_b[g] joins group g back
+  // side streams from the caller's, ev_b[g] joins group g back.  These
+  // events are only ever recorded and waited on outside stream capture.
   std::vector<hipStream_t> side;
   std::vector<hipEvent_t> ev_a, ev_b;
   // timing
@@ -233,8 +234,9 @@ struct pf_handle {
     int kind;
   };
   std::vector<Ev> events;
-  // graphs: gexecs[0] holds one interval, gexecs[1] (if present) holds
-  // kGraphSteps intervals
+  // graphs, each captured on one stream: plain layout, gexecs[0] holds one
+  // interval of every filter; batched layout, gexecs[2g] holds one interval
+  // of filter group g and gexecs[2g + 1] kGraphSteps of them
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   hipStream_t cap_stream = nullptr;
@@ -465,33 +467,49 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
   return ev_end(H, e0, 4, s);
 }
 
-// n intervals of the batched layout issued from stream s.  With one group
-// both kernels go on s.  With G groups (filters dealt so that every group
-// holds about the same number of particles) group g's intervals run back to
-// back on side[g]: the groups start together after everything issued on s
-// so far, drift against each other, and one group's collective overlaps
-// another's propagation.  s waits for every group at the end.
-pf_status enqueue_batched(pf_handle* H, hipStream_t s, int n) {
+// n intervals of filter group g, back to back on stream s (one stream, no
+// events: this is what a group's graph holds).
+pf_status enqueue_group(pf_handle* H, int g, hipStream_t s, int n) {
   pf_status st;
-  const int G = H->groups;
-  if (G == 1) {
-    for (int i = 0; i < n; ++i)
-      if ((st = enqueue_group_propagate(H, 0, s)) || (st = enqueue_group_collective(H, 0, s)))
-        return st;
-    return PF_OK;
-  }
+  for (int i = 0; i < n; ++i)
+    if ((st = enqueue_group_propagate(H, g, s)) || (st = enqueue_group_collective(H, g, s)))
+      return st;
+  return PF_OK;
+}
+
+// Fork the filter groups' streams from s (they start after everything
+// issued on s so far) and join them back into s.  Never used inside a
+// capture.
+pf_status fork_groups(pf_handle* H, hipStream_t s) {
   HIP_TRY(hipEventRecord(H->ev_a[0], s));
-  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_a[0], 0));
-  for (int g = 0; g < G; ++g)
-    for (int i = 0; i < n; ++i)
-      if ((st = enqueue_group_propagate(H, g, H->side[g])) ||
-          (st = enqueue_group_collective(H, g, H->side[g])))
-        return st;
-  for (int g = 0; g < G; ++g) {
+  for (int g = 0; g < H->groups; ++g) HIP_TRY(hipStreamWaitEvent(H->side[g], H->ev_a[0], 0));
+  return PF_OK;
+}
+pf_status join_groups(pf_handle* H, hipStream_t s) {
+  for (int g = 0; g < H->groups; ++g) {
     HIP_TRY(hipEventRecord(H->ev_b[g], H->side[g]));
     HIP_TRY(hipStreamWaitEvent(s, H->ev_b[g], 0));
   }
   return PF_OK;
+}
+
+// n intervals of the batched layout issued eagerly from stream s.  With one
+// group both kernels go on s.  With G groups (filters dealt so that every
+// group holds about the same number of particles) group g's intervals run
+// back to back on side[g]: the groups start together after everything
+// issued on s so far, drift against each other, and one group's collective
+// overlaps another's propagation; s waits for every group at the end.  The
+// launches are issued interval by interval across the groups, so no group
+// waits for the host to issue another group's whole run.
+pf_status enqueue_batched(pf_handle* H, hipStream_t s, int n) {
+  pf_status st;
+  const int G = H->groups;
+  if (G == 1) return enqueue_group(H, 0, s, n);
+  if ((st = fork_groups(H, s))) return st;
+  for (int i = 0; i < n; ++i)
+    for (int g = 0; g < G; ++g)
+      if ((st = enqueue_group(H, g, H->side[g], 1))) return st;
+  return join_groups(H, s);
 }
 
 pf_status enqueue_step(pf_handle* H, hipStream_t s) {
@@ -708,9 +726,12 @@ pf_status launch_stream(pf_handle* H, hipStream_t* out) {
   return PF_OK;
 }
 
-// gexecs[0]: one whole interval (step + resample); for the batched layout
-// gexecs[1]: kGraphSteps intervals, so the fork and join of the filter
-// groups and the launch of a graph are paid once per kGraphSteps intervals.
+// Captures the graphs pf_graph_run replays.  Every capture is on one
+// stream and holds kernel launches only (no event, copy or memset), so a
+// graph never refers to an event or another stream: plain layout, one
+// interval of every filter; batched layout, for each filter group one
+// interval and kGraphSteps intervals of that group's kernels.  The groups'
+// graphs are launched on their own streams between an eager fork and join.
 pf_status ensure_graphs(pf_handle* H) {
   if (!H->gexecs.empty()) return PF_OK;
   hipStream_t cs;
@@ -719,33 +740,36 @@ pf_status ensure_graphs(pf_handle* H) {
   const bool tm = H->timing;
   H->timing = false;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
+  const int ng = batched ? H->groups : 1;
   const int nv = batched ? 2 : 1;
-  for (int v = 0; v < nv && !st; ++v) {
-    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    if (batched) {
-      st = enqueue_batched(H, cs, v == 0 ? 1 : kGraphSteps);
-    } else {
-      st = enqueue_step(H, cs);
-      if (!st) st = enqueue_resample(H, cs, nullptr);
+  for (int g = 0; g < ng && !st; ++g) {
+    for (int v = 0; v < nv && !st; ++v) {
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      if (batched) {
+        st = enqueue_group(H, g, cs, v == 0 ? 1 : kGraphSteps);
+      } else {
+        st = enqueue_step(H, cs);
+        if (!st) st = enqueue_resample(H, cs, nullptr);
+      }
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        break;
+      }
+      if (e != hipSuccess) {
+        st = fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        break;
+      }
+      H->graphs.push_back(graph);
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        st = fail(PF_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        break;
+      }
+      H->gexecs.push_back(ex);
     }
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &graph);
-    if (st) {
-      if (graph) (void)hipGraphDestroy(graph);
-      break;
-    }
-    if (e != hipSuccess) {
-      st = fail(PF_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
-      break;
-    }
-    H->graphs.push_back(graph);
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      st = fail(PF_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
-      break;
-    }
-    H->gexecs.push_back(ex);
   }
   H->timing = tm;
   if (st) destroy_graphs(H);
@@ -913,10 +937,18 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   if ((st = ensure_graphs(H))) return st;
   hipStream_t ls;
   if ((st = launch_stream(H, &ls))) return st;
+  const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
+  const int G = batched ? H->groups : 1;
+  // group g's graphs go on its own stream (the caller's with one group)
+  auto gs = [&](int g) { return G == 1 ? ls : H->side[g]; };
+  if (G > 1 && (st = fork_groups(H, ls))) return st;
   int left = n_steps;
-  if (H->gexecs.size() > 1)
-    for (; left >= kGraphSteps; left -= kGraphSteps) HIP_TRY(hipGraphLaunch(H->gexecs[1], ls));
-  for (; left > 0; --left) HIP_TRY(hipGraphLaunch(H->gexecs[0], ls));
+  if (batched)
+    for (; left >= kGraphSteps; left -= kGraphSteps)
+      for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g + 1], gs(g)));
+  for (; left > 0; --left)
+    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[batched ? 2 * g : 0], gs(g)));
+  if (G > 1 && (st = join_groups(H, ls))) return st;
   H->t += n_steps;
   return PF_OK;
 }
@@ -1533,29 +1565,36 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
   }
   const int cand_nt[3] = {256, 512, 1024};
   const int cand_g[3] = {1, 2, 4};
+  const int nt0 = H->batch_nt, g0 = H->groups;
   double best = 1e300;
-  int best_nt = H->batch_nt, best_g = H->groups;
-  hipStream_t ls;
-  if ((st = launch_stream(H, &ls))) return st;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  int best_nt = nt0, best_g = g0;
+  // Candidates are timed on eager launches, so no graph is captured,
+  // instantiated or destroyed per candidate: the captured graphs of the
+  // chosen tuning are built once, by the next pf_graph_run.  Each candidate
+  // starts from a fresh initialisation, runs one untimed interval, then n
+  // timed ones (the groups fork once and join once, as in a graph replay).
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) st = fail(PF_E_DEVICE, "hipEventCreate failed: %s", hipGetErrorString(he));
   const int n = steps < H->cfg.T - 1 ? steps : H->cfg.T - 1;
-  for (int gi = 0; gi < 3 && !st; ++gi) {
-    for (int ci = 0; ci < 3 && !st; ++ci) {
+  const bool tm = H->timing;  // no per-kernel timing events for the candidates
+  H->timing = false;
+  for (int gi = 0; gi < 3 && !st && he == hipSuccess; ++gi) {
+    for (int ci = 0; ci < 3 && !st && he == hipSuccess; ++ci) {
       const int idx = gi * 3 + ci;
       if (ms_out) ms_out[idx] = -1.0;
       if (cand_g[gi] > H->cfg.B) continue;
       if ((st = pf_set_tuning(H, cand_nt[ci], cand_g[gi]))) break;
-      if ((st = pf_reset(H, H->iter))) break;
-      if ((st = pf_graph_run(H, 1))) break;  // capture + one untimed interval
+      if ((st = do_init(H, H->stream))) break;
+      if ((st = enqueue_batched(H, H->stream, 1))) break;  // untimed
       if (n < 1) continue;
-      HIP_TRY(hipEventRecord(e0, ls));
-      if ((st = pf_graph_run(H, n))) break;
-      HIP_TRY(hipEventRecord(e1, ls));
-      HIP_TRY(hipEventSynchronize(e1));
+      if ((he = hipEventRecord(e0, H->stream)) != hipSuccess) break;
+      if ((st = enqueue_batched(H, H->stream, n))) break;
+      if ((he = hipEventRecord(e1, H->stream)) != hipSuccess) break;
+      if ((he = hipEventSynchronize(e1)) != hipSuccess) break;
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
       const double per = ms / n;
       if (ms_out) ms_out[idx] = per;
       if (per < best) {
@@ -1565,9 +1604,22 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st) return st;
+  H->timing = tm;
+  if (!st && he != hipSuccess) st = fail(PF_E_DEVICE, "timing failed: %s", hipGetErrorString(he));
+  // every exit waits for the candidates' work before the events go
+  const pf_status st_drain = drain(H);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!st) st = st_drain;
+  if (st) {
+    // keep the error message of the failure; best effort back to the
+    // tuning the handle had, re-initialised
+    const std::string msg = g_err;
+    (void)pf_set_tuning(H, nt0, g0);
+    (void)pf_reset(H, H->iter);
+    g_err = msg;
+    return st;
+  }
   if ((st = pf_set_tuning(H, best_nt, best_g))) return st;
   if (threads_out) *threads_out = best_nt;
   if (groups_out) *groups_out = best_g;

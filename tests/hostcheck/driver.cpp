@@ -147,6 +147,15 @@ static void autotune() {
   double ms[9];
   OK(pf_autotune(h, 3, &th, &gr, ms));
   advance(h, 6);
+  // three passes in a row (as the benchmark runs them), each followed by
+  // graph replays of the chosen tuning
+  for (int pass = 0; pass < 3; ++pass) {
+    OK(pf_autotune(h, 5, &th, &gr, ms));
+    OK(pf_graph_run(h, 2));
+    OK(pf_set_tuning(h, 256, 4));
+    OK(pf_reset(h, 0));
+    OK(pf_graph_run(h, 5));
+  }
   OK(pf_destroy(h));
 }
 

@@ -5,8 +5,14 @@
 // without a GPU.  Device memory is host memory; work runs when issued, or is
 // recorded as a node while its stream is captured.  The stream-capture rules
 // are checked strictly; a violation prints a line starting with
-// "FAKEHIP VIOLATION" and aborts.  Kernel launches come from stub launchers
-// that call fake_kernel(stream).
+// "FAKEHIP VIOLATION" and aborts.  Besides the capture rules it tracks
+// lifetimes: every op issued on a stream counts as unfinished until the
+// host has waited for it (a stream or event synchronisation, followed
+// through the event waits that ordered one stream after another), and a
+// graph exec may only be destroyed, and a stream only destroyed, once every
+// launch on it or op issued to it is finished.  Events are never recorded
+// inside a capture (the library keeps its captured graphs free of events).
+// Kernel launches come from stub launchers that call fake_kernel(stream).
 #include <hip/hip_runtime_api.h>
 
 #include <cstdio>
@@ -28,13 +34,23 @@
 namespace {
 
 struct FGraph;
+struct FStream;
+// a wait issued as op `at` of its stream on an event recorded after `src_ops`
+// ops of stream `src`
+struct FWait {
+  long at;
+  FStream* src;
+  long src_ops;
+};
 struct FStream {
   bool blocking = true;
   bool destroyed = false;
   FGraph* cap = nullptr;  // capture the stream takes part in
   bool origin = false;    // the stream that began that capture
   bool joined = true;     // the origin has waited for this stream's last op
-  long ops = 0;
+  long ops = 0;           // ops issued (kernels, copies, waits, graph launches)
+  long done = 0;          // ops [0, done) known finished by the host
+  std::vector<FWait> waits;
 };
 struct FEvent {
   bool recorded = false, destroyed = false;
@@ -52,6 +68,7 @@ struct FGraph {
 struct FExec {
   bool destroyed = false;
   std::vector<std::function<void()>> nodes;
+  std::vector<std::pair<FStream*, long>> launches;  // (stream, op index)
 };
 
 // objects are never freed, so a use after destruction is caught
@@ -71,6 +88,14 @@ FEvent* E(hipEvent_t e) {
   FEvent* f = (FEvent*)e;
   CHECK(!f->destroyed, "use of a destroyed event");
   return f;
+}
+// The host knows ops [0, upto) of f finished; so did whatever those ops
+// waited for.
+void complete(FStream* f, long upto) {
+  if (upto <= f->done) return;
+  f->done = upto;
+  for (const FWait& w : f->waits)
+    if (w.at < upto) complete(w.src, w.src_ops);
 }
 bool capture_open() {
   for (void* p : g_graphs)
@@ -131,6 +156,7 @@ hipError_t hipStreamDestroy(hipStream_t s) {
   CHECK(s, "destroy of the null stream");
   FStream* f = S(s);
   CHECK(!f->cap, "destroy of a stream taking part in a capture");
+  CHECK(f->done == f->ops, "destroy of a stream with unfinished work");
   f->destroyed = true;
   return hipSuccess;
 }
@@ -138,6 +164,7 @@ hipError_t hipStreamSynchronize(hipStream_t s) {
   FStream* f = S(s);
   CHECK(!f->cap, "synchronize of a capturing stream");
   if (!s) CHECK(!capture_open(), "null-stream synchronize while a capture is open");
+  complete(f, f->ops);
   return hipSuccess;
 }
 hipError_t hipEventCreate(hipEvent_t* e) {
@@ -161,6 +188,7 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
   FEvent* f = E(e);
   FStream* st = S(s);
   if (!s) CHECK(!capture_open(), "event record on the null stream while a capture is open");
+  CHECK(!st->cap, "event recorded inside a capture");
   f->recorded = true;
   f->cap = st->cap;
   f->rec_stream = st;
@@ -187,6 +215,8 @@ hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned int) {
   } else {
     CHECK(!st->cap, "capturing stream waits on an event recorded outside its capture");
     CHECK(!f->cap, "wait on an event recorded inside a capture");
+    st->waits.push_back({st->ops, f->rec_stream, f->rec_ops});
+    st->ops++;
   }
   return hipSuccess;
 }
@@ -194,6 +224,7 @@ hipError_t hipEventSynchronize(hipEvent_t e) {
   FEvent* f = E(e);
   CHECK(f->recorded, "synchronize on an event never recorded");
   CHECK(!f->cap, "synchronize on an event recorded inside a capture");
+  complete(f->rec_stream, f->rec_ops);
   return hipSuccess;
 }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
@@ -203,6 +234,8 @@ hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
   CHECK(!(fa->flags & hipEventDisableTiming) && !(fb->flags & hipEventDisableTiming),
         "elapsed time of an event created without timing");
   CHECK(!fa->cap && !fb->cap, "elapsed time of events recorded inside a capture");
+  CHECK(fa->rec_stream->done >= fa->rec_ops && fb->rec_stream->done >= fb->rec_ops,
+        "elapsed time of events the host has not waited for");
   *ms = (float)(fb->t - fa->t) * 1e-3f + 1e-3f;
   return hipSuccess;
 }
@@ -261,6 +294,7 @@ hipError_t hipGraphLaunch(hipGraphExec_t ex, hipStream_t s) {
   CHECK(!f->cap, "graph launch inside a capture");
   if (!s) CHECK(!capture_open(), "graph launch on the null stream while a capture is open");
   for (auto& n : x->nodes) n();
+  x->launches.push_back({f, f->ops});
   f->ops++;
   return hipSuccess;
 }
@@ -268,6 +302,8 @@ hipError_t hipGraphExecDestroy(hipGraphExec_t ex) {
   CHECK(g_execs.count((void*)ex), "destroy of an unknown graph");
   FExec* x = (FExec*)ex;
   CHECK(!x->destroyed, "graph destroyed twice");
+  for (auto& l : x->launches)
+    CHECK(l.first->done > l.second, "graph exec destroyed while a launch of it may still run");
   x->destroyed = true;
   return hipSuccess;
 }

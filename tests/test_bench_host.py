@@ -40,3 +40,40 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_model_flop_counts():
+    """30 d K + 4 |O| FLOP per particle-step for Lorenz '96: 1,952 at d = 8
+    (all 8 observed, K = 8) and 9,680 at d = 40 (20 observed)."""
+    import workloads as W
+    assert bench.model_flop_per_particle_step(W.MODEL_L96, 8, 8, 8) == 1952
+    assert bench.model_flop_per_particle_step(W.MODEL_L96, 40, 8, 20) == 9680
+
+
+def test_tf_summary_counts_pairs_over_the_bound():
+    err = np.array([[1e-6, 2e-4], [5e-5, 3e-4]])
+    ell = np.array([[-10.0, -250.0], [-12.0, -300.0]])
+    ess = np.array([[900.0, 1.2], [800.0, 1.0]])
+    s = bench.tf_summary(err, ell, ess, 1e-4)
+    assert s["pairs"] == 4 and s["pairs_over_bound"] == 2
+    assert s["frac_within_bound"] == 0.5
+    assert s["max_abs_where_ess_ge_2"] == 5e-5 and s["pairs_over_bound_where_ess_ge_2"] == 0
+    assert s["worst"][0]["err"] == 3e-4 and s["worst"][0]["ess"] == 1.0
+
+
+def test_oracle_worker_is_pinned(tmp_path):
+    """The CPU baseline's oracle process runs on the one core it is given."""
+    import oracle
+    import workloads as W
+    pb = W.config("lorenz96_d8_batched")
+    _, y = oracle.simulate(pb)
+    path = str(tmp_path / "obs.npy")
+    np.save(path, y, allow_pickle=False)
+    core = sorted(os.sched_getaffinity(0))[-1]
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-worker", "0",
+                        "512", "0.01", path, str(core)],
+                       capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    import json
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    assert d["affinity"] == [core] and d["filters"] == 1 and d["ps"] > 0

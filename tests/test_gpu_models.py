@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle_resync import resync
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -121,7 +122,7 @@ def test_lorenz96_other_dimensions_fp64_plain(pfm, d, obs_every, N):
         f.resample()
         if _mismatches_in_band(ref["lw"][t - 1], oracle.resample_u(pb.seed, t), f.ancestors(),
                                ref["anc"][t - 1]):
-            pytest.skip("an ancestor flipped inside the 1e-9 band; later steps diverge")
+            resync(f, pb, [0], t)  # an in-band flip: carry on from the oracle's particles
     ell, _ = f.trace()
     np.testing.assert_array_less(np.abs(ell[0] - ref["ell"]),
                                  REL64 * np.maximum(1.0, np.abs(ref["ell"])))

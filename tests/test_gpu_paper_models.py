@@ -1,7 +1,7 @@
 """GPU parity for the paper's model forms: Lorenz '96 with the noise inside
 the RK4 stages (FP64 bit for bit with the oracle, plain and batched; FP32
 batched equals FP32 plain; FP32 teacher-forced likelihood increments within
-max(1e-4, 1e-6 |ell|) of FP64, d = 8 and d = 40) and the paper's windkessel
+1e-4 of FP64, d = 8 and d = 40) and the paper's windkessel
 example (flow, flow noise, observation sd 2) in FP64."""
 import dataclasses
 
@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle_resync import resync
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -46,6 +47,7 @@ def _fp64_vs_oracle(pfm, pb, layout):
                                           err_msg=f"filter {b}, t = {t}")
         f.resample()
         a = f.ancestors()
+        flipped = []
         for b in range(pb.B):
             ag, ar = a[off[b]:off[b + 1]], refs[b]["anc"][t - 1]
             mism = np.flatnonzero(ag != ar)
@@ -56,7 +58,9 @@ def _fp64_vs_oracle(pfm, pb, layout):
                 u = oracle.resample_u(pb.seed, t, b)
                 for k in mism:
                     assert np.min(np.abs(cw - (u + k) / lwb.size)) < BAND
-                pytest.skip("an ancestor flipped inside the 1e-9 band")
+                flipped.append(b)
+        if flipped:  # in-band flips: carry on from the oracle's particles
+            resync(f, pb, flipped, t)
     ell, _ = f.trace()
     x = f.get_state()
     for b in range(pb.B):
@@ -116,7 +120,7 @@ def test_stage_noise_fp32_teacher_forced(pfm, d, obs_every, N):
         f32.step()
         e64 = f64.trace()[0][0, t]
         e32 = f32.trace()[0][0, t]
-        assert abs(e32 - e64) <= max(1e-4, 1e-6 * abs(e64)), (t, e32, e64)
+        assert abs(e32 - e64) <= 1e-4, (t, e32, e64)
         f64.resample()
         f32.resample()
     f64.close()

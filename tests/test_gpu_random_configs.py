@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle_resync import resync
 import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -76,7 +77,8 @@ def _edge_flip(lw, k, ref_u, band=BAND):
 
 def _ancestors_agree(pb, scheme, lw, ag, ar, t, b):
     """True if equal; False if every difference is a legitimate flip at an
-    edge (the caller stops comparing this configuration); fails otherwise."""
+    edge (the caller then resynchronises this filter on the oracle); fails
+    otherwise."""
     mism = np.flatnonzero(ag != ar)
     if mism.size == 0:
         return True
@@ -102,7 +104,7 @@ def _run_config(pfm, i, layout):
     f = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
     f.set_tuning(nt, groups)
     f.set_resampler(scheme, steps, ess_frac)
-    exact = True
+    flips = 0
     for t in range(1, pb.T + 1):
         f.step()
         lw = f.logweights()
@@ -111,24 +113,30 @@ def _run_config(pfm, i, layout):
                                           err_msg=f"config {i}, filter {b}, t = {t}")
         f.resample()
         a = f.ancestors()
-        for b in range(pb.B):
-            exact &= _ancestors_agree(pb, scheme, refs[b]["lw"][t - 1], a[off[b]:off[b + 1]],
-                                      refs[b]["anc"][t - 1], t, b)
-        if not exact:
-            break
-    if exact:
-        ell, ess = f.trace()
-        x = f.get_state()
-        for b in range(pb.B):
-            r = refs[b]
-            np.testing.assert_array_less(np.abs(ell[b] - r["ell"]),
-                                         REL64 * np.maximum(1.0, np.abs(r["ell"])))
-            np.testing.assert_allclose(ess[b], r["ess"], rtol=1e-9)
-            np.testing.assert_array_equal(x[:, off[b]:off[b + 1]], r["x"])
-    eager = (f.trace()[0], f.get_state(), f.ancestors()) if exact else None
+        flipped = [b for b in range(pb.B)
+                   if not _ancestors_agree(pb, scheme, refs[b]["lw"][t - 1],
+                                           a[off[b]:off[b + 1]], refs[b]["anc"][t - 1], t, b)]
+        if flipped:
+            flips += len(flipped)
+            resync(f, pb, flipped, t, scheme, steps, ess_frac)
+    ell, ess = f.trace()
+    x = f.get_state()
+    for b in range(pb.B):
+        r = refs[b]
+        np.testing.assert_array_less(np.abs(ell[b] - r["ell"]),
+                                     REL64 * np.maximum(1.0, np.abs(r["ell"])))
+        np.testing.assert_allclose(ess[b], r["ess"], rtol=1e-9)
+        np.testing.assert_array_equal(x[:, off[b]:off[b + 1]], r["x"])
     f.close()
-    if not exact:
-        pytest.skip(f"config {i}: an ancestor flipped inside the 1e-9 band")
+    if flips:
+        print(f"config {i}: {flips} in-band ancestor flips, resynchronised on the oracle")
+    # graph replay against eager launches of the same handle type (no resync)
+    e = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
+    e.set_tuning(nt, groups)
+    e.set_resampler(scheme, steps, ess_frac)
+    e.advance(pb.T)
+    eager = (e.trace()[0], e.get_state(), e.ancestors())
+    e.close()
     g = pfm.Filter(pb, precision=pfm.PF_FP64, layout=layout)
     g.set_tuning(nt, groups)
     g.set_resampler(scheme, steps, ess_frac)
@@ -136,6 +144,7 @@ def _run_config(pfm, i, layout):
     for got, want in zip((g.trace()[0], g.get_state(), g.ancestors()), eager):
         np.testing.assert_array_equal(got, want)
     g.close()
+    return flips
 
 
 @pytest.mark.parametrize("i", range(20))

@@ -251,10 +251,12 @@ def test_autotune_keeps_results(pfm):
         assert np.all(ms[ms >= 0] > 0) and np.sum(ms > 0) == 9
         f.advance(pb.T)  # autotune leaves the filters re-initialised
         e1, _ = f.trace()
-        np.testing.assert_array_equal(e1, e0)
+        # another collective width sums the weights in another order: the
+        # increments agree to rounding
+        np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=1e-12)
         f.reset(0)
-        f.graph_run(pb.T)
-        np.testing.assert_array_equal(f.trace()[0], e0)
+        f.graph_run(pb.T)  # graphs of the chosen tuning: the same bits as its eager run
+        np.testing.assert_array_equal(f.trace()[0], e1)
         f.reset(0)
     f.close()
 

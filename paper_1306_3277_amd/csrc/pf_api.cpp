@@ -51,14 +51,12 @@ struct Layout {
   std::vector<int64_t> off;     // [B+1]
   std::vector<int64_t> boff0;   // [B] first block slot
   std::vector<int32_t> nblk;    // [B]
-  std::vector<int64_t> bst0;    // [B] first merge-path boundary slot
-  int64_t bst_total = 0;
-  std::vector<int64_t> bj0;     // [B] first scan-block slot
-  int64_t bj_total = 0;
+  std::vector<int64_t> own0;    // [B] first output-tile owner slot
+  int64_t own_total = 0;
   int64_t nblk_total = 0;
   // byte offsets into the workspace
-  size_t x_cur, x_tmp, lw, counts, anc, part, boff, bstate, bjs, fs, ell, ess, theta, obs, obs_pos, obs_idx,
-      q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, kf_ll, kf_ell, wcum, total;
+  size_t x_cur, x_tmp, lw, marks, anc, part, boff, owner, jc, fs, ell, ess, theta, obs, obs_pos,
+      obs_idx, q, b_off, b_order, b_chunk_f, b_chunk_k, b_u, kf_ll, kf_ell, wcum, total;
   int32_t n_chunks = 0;
 };
 
@@ -134,13 +132,10 @@ Layout make_layout(const pf_config* c) {
   L.off.assign(c->B + 1, 0);
   L.boff0.assign(c->B, 0);
   L.nblk.assign(c->B, 0);
-  L.bst0.assign(c->B, 0);
-  L.bj0.assign(c->B, 0);
+  L.own0.assign(c->B, 0);
   for (int b = 0; b < c->B; ++b) {
-    L.bj0[b] = L.bj_total;
-    L.bj_total += (c->n_particles[b] + pfk::K3_SPAN - 1) / pfk::K3_SPAN;
-    L.bst0[b] = L.bst_total;
-    L.bst_total += (2 * c->n_particles[b] + pfk::K4_DB - 1) / pfk::K4_DB + 1;
+    L.own0[b] = L.own_total;
+    L.own_total += (c->n_particles[b] + pfk::K4_TILE - 1) / pfk::K4_TILE;
     L.off[b + 1] = L.off[b] + c->n_particles[b];
     L.nblk[b] = (int32_t)((c->n_particles[b] + pfk::K1_NT - 1) / pfk::K1_NT);
     L.boff0[b] = L.nblk_total;
@@ -159,15 +154,16 @@ Layout make_layout(const pf_config* c) {
     return at;
   };
   const int64_t N = L.n_total;
-  L.x_cur = take(sx * c->d * N);
-  L.x_tmp = take(sx * c->d * N);
+  // the plain layout's state is kept in whole 64-particle tiles
+  L.x_cur = take(sx * (size_t)pfk::plain_state_values(N, c->d));
+  L.x_tmp = take(sx * (size_t)pfk::plain_state_values(N, c->d));
   L.lw = take(8 * N);  // log-weights are FP64 in both precisions
-  L.counts = take(4 * N);
+  L.marks = take(4 * N);  // -1 between resamplings
   L.anc = take(4 * N);
   L.part = take(24 * L.nblk_total);
   L.boff = take(8 * (L.nblk_total + c->B));  // nblk + 1 offsets per filter
-  L.bstate = take(4 * L.bst_total);
-  L.bjs = take(4 * L.bj_total);
+  L.owner = take(4 * (size_t)(L.own_total > 0 ? L.own_total : 1));  // per output tile
+  L.jc = take(4 * (size_t)(L.own_total > 0 ? L.own_total : 1));     // per scan block
   L.fs = take(sizeof(FilterState) * c->B);
   L.ell = take(8 * (size_t)c->B * c->T);
   L.ess = take(8 * (size_t)c->B * c->T);
@@ -261,8 +257,7 @@ PlainArgs plain_args(const pf_handle* H, int b) {
   a.ld = H->L.n_total;
   a.off = H->L.off[b];
   a.boff0 = H->L.boff0[b];
-  a.bst0 = H->L.bst0[b];
-  a.bj0 = H->L.bj0[b];
+  a.own0 = H->L.own0[b];
   a.nblk = H->L.nblk[b];
   a.K = c.K;
   a.T = c.T;
@@ -524,9 +519,21 @@ pf_status enqueue_step(pf_handle* H, hipStream_t s) {
                                   H->ws + H->L.x_tmp, H->ws + H->L.lw,
                                   H->at<double>(H->L.part), a, s));
     if ((st = ev_end(H, e0, 0, s))) return st;
+    // the collective: likelihood increment, ESS, trigger, and (unless
+    // Metropolis) the cumulative weights' marks or, for multinomial, the
+    // cumulative weights themselves; a large filter's partials are combined
+    // once first
+    if (a.nblk > pfk::FUSE_NB) {
+      if ((st = ev_begin(H, &e0, s))) return st;
+      HIP_TRY(pfk::launch_combine(H->at<double>(H->L.part), H->at<double>(H->L.boff), a, s));
+      if ((st = ev_end(H, e0, 1, s))) return st;
+    }
     if ((st = ev_begin(H, &e0, s))) return st;
-    HIP_TRY(pfk::launch_combine(H->at<double>(H->L.part), H->at<double>(H->L.boff), a, s));
-    if ((st = ev_end(H, e0, 1, s))) return st;
+    a.mode = 0;
+    HIP_TRY(pfk::launch_scan_mark(H->at<double>(H->L.lw), H->at<double>(H->L.part),
+                                  H->at<double>(H->L.boff), H->at<int32_t>(H->L.marks),
+                                  H->at<int32_t>(H->L.owner), H->at<int32_t>(H->L.jc), a, s));
+    if ((st = ev_end(H, e0, 2, s))) return st;
   }
   return PF_OK;
 }
@@ -550,10 +557,22 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
   }
   for (int b = 0; b < c.B; ++b) {
     PlainArgs a = plain_args(H, b);
-    if (u) HIP_TRY(pfk::launch_set_u(a.fs, u[b], s));
     hipEvent_t e0{};
-    pf_status st = ev_begin(H, &e0, s);
-    if (st) return st;
+    pf_status st;
+    if (u) {
+      // redraw the marks (or cumulative weights) from the given uniform; the
+      // step's marks are cleared first
+      HIP_TRY(pfk::launch_set_u(a.fs, u[b], s));
+      if (H->rs.scheme != pfk::RS_METROPOLIS) {
+        HIP_TRY(pfk::launch_fill_i32(H->at<int32_t>(H->L.marks) + a.off, a.N, -1, s));
+        a.mode = 1;
+        HIP_TRY(pfk::launch_scan_mark(H->at<double>(H->L.lw), H->at<double>(H->L.part),
+                                      H->at<double>(H->L.boff), H->at<int32_t>(H->L.marks),
+                                      H->at<int32_t>(H->L.owner), H->at<int32_t>(H->L.jc), a,
+                                      s));
+      }
+    }
+    if ((st = ev_begin(H, &e0, s))) return st;
     if (H->rs.scheme == pfk::RS_METROPOLIS) {
       // no scan, counts or merge: unsorted ancestors and a plain gather
       HIP_TRY(pfk::launch_metropolis_gather(c.precision, H->at<double>(H->L.lw),
@@ -561,26 +580,16 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
                                             H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
     } else if (H->rs.scheme == pfk::RS_MULTINOMIAL) {
-      // the scan leaves the cumulative weights; unsorted ancestors by search
-      HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
-                                     H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
-                                     H->at<int32_t>(H->L.bjs), a, s));
-      if ((st = ev_end(H, e0, 2, s))) return st;
-      if ((st = ev_begin(H, &e0, s))) return st;
-      HIP_TRY(pfk::launch_multinomial_gather(c.precision, a.wcum, H->at<int32_t>(H->L.bjs),
+      // unsorted ancestors by search of the step's cumulative weights
+      HIP_TRY(pfk::launch_multinomial_gather(c.precision, a.wcum, H->at<int32_t>(H->L.jc),
                                              H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
                                              H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
     } else {
-      HIP_TRY(pfk::launch_scan_count(c.precision, H->ws + H->L.lw, H->at<double>(H->L.boff),
-                                     H->at<int32_t>(H->L.counts), H->at<int32_t>(H->L.bstate),
-                                     H->at<int32_t>(H->L.bjs), a, s));
-      if ((st = ev_end(H, e0, 2, s))) return st;
-      if ((st = ev_begin(H, &e0, s))) return st;
-      HIP_TRY(pfk::launch_merge_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.counts),
-                                       H->at<int32_t>(H->L.bstate), H->at<int32_t>(H->L.bjs),
-                                       H->ws + H->L.x_tmp,
-                                       H->ws + H->L.x_cur, H->at<int32_t>(H->L.anc), a, s));
+      HIP_TRY(pfk::launch_tile_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.marks),
+                                      H->at<int32_t>(H->L.owner), H->at<int32_t>(H->L.jc),
+                                      H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
+                                      H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
     }
     if (H->hist)
@@ -822,6 +831,10 @@ pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void
   if (e == hipSuccess) e = cp(L.obs_idx, c.obs_idx, 4 * (size_t)c.n_obs);
   if (e == hipSuccess && c.model == PF_MODEL_WK) e = cp(L.q, c.q, 8 * ((size_t)c.T * c.K + 1));
   if (e == hipSuccess) e = cp(L.b_off, L.off.data(), 8 * (size_t)(c.B + 1));
+  // the plain layout's resampling marks start (and are left by every
+  // resampling) at -1
+  if (e == hipSuccess && c.layout == PF_LAYOUT_PLAIN)
+    e = hipMemsetAsync(H->ws + L.marks, 0xff, 4 * (size_t)L.n_total, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete H;
@@ -995,14 +1008,26 @@ pf_status pf_get_state(pf_handle* H, double* x_out) {
       src = spare;
     }
   }
+  const bool plain = H->cfg.layout == PF_LAYOUT_PLAIN;
+  const int d = H->cfg.d;
+  const int64_t N = H->L.n_total;
+  // the plain layout's state is tiled (pidx); the batched layout's is [d][N]
+  const size_t nv = plain ? (size_t)pfk::plain_state_values(N, d) : n;
+  auto put = [&](auto* v) {
+    for (int i = 0; i < d; ++i)
+      for (int64_t g = 0; g < N; ++g)
+        x_out[(size_t)i * N + g] = (double)v[plain ? pfk::pidx(g, i, d) : (int64_t)i * N + g];
+  };
   if (H->cfg.precision == PF_FP64) {
-    HIP_TRY(hipMemcpyAsync(x_out, H->ws + src, 8 * n, hipMemcpyDeviceToHost, H->stream));
+    std::vector<double> tmp(nv);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), H->ws + src, 8 * nv, hipMemcpyDeviceToHost, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
+    put(tmp.data());
   } else {
-    std::vector<float> tmp(n);
-    HIP_TRY(hipMemcpyAsync(tmp.data(), H->ws + src, 4 * n, hipMemcpyDeviceToHost, H->stream));
+    std::vector<float> tmp(nv);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), H->ws + src, 4 * nv, hipMemcpyDeviceToHost, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
-    for (size_t i = 0; i < n; ++i) x_out[i] = tmp[i];
+    put(tmp.data());
   }
   return PF_OK;
 }
@@ -1015,12 +1040,24 @@ pf_status pf_set_state(pf_handle* H, const double* x_in) {
   const size_t n = (size_t)H->cfg.d * H->L.n_total;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
   const size_t dst = batched ? batched_buf(H, H->t) : H->L.x_cur;
+  const int d = H->cfg.d;
+  const int64_t N = H->L.n_total;
+  // the plain layout's state is tiled (pidx); the batched layout's is [d][N]
+  const size_t nv = batched ? n : (size_t)pfk::plain_state_values(N, d);
+  auto take = [&](auto* v) {
+    for (int i = 0; i < d; ++i)
+      for (int64_t g = 0; g < N; ++g)
+        v[batched ? (int64_t)i * N + g : pfk::pidx(g, i, d)] = x_in[(size_t)i * N + g];
+  };
   if (H->cfg.precision == PF_FP64) {
-    HIP_TRY(hipMemcpyAsync(H->ws + dst, x_in, 8 * n, hipMemcpyHostToDevice, H->stream));
+    std::vector<double> tmp(nv, 0.0);
+    take(tmp.data());
+    HIP_TRY(hipMemcpyAsync(H->ws + dst, tmp.data(), 8 * nv, hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
   } else {
-    std::vector<float> tmp(n);
-    for (size_t i = 0; i < n; ++i) tmp[i] = (float)x_in[i];
-    HIP_TRY(hipMemcpyAsync(H->ws + dst, tmp.data(), 4 * n, hipMemcpyHostToDevice, H->stream));
+    std::vector<float> tmp(nv, 0.0f);
+    take(tmp.data());
+    HIP_TRY(hipMemcpyAsync(H->ws + dst, tmp.data(), 4 * nv, hipMemcpyHostToDevice, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
   }
   if (batched) {  // the next step reads the given particles as they are

@@ -20,6 +20,8 @@ struct FilterState {
   int32_t pad;    // nonzero if the resampler met an inconsistency (never expected)
   double lprev;   // ln sum exp(carried log-weights) when carry is set
   int32_t carry;  // 1 if the last step kept its weights (ESS above the trigger)
+  int32_t tk;     // plain layout: the interval the last propagation processed
+  int32_t cn1;    // plain layout: strata owned by the whole filter (count of its last particle)
   int32_t pad2;
 };
 
@@ -38,14 +40,29 @@ struct KeyArg {
   uint32_t lo, hi;
 };
 
+// Plain layout state: particles in tiles of PT = 64 (one wave).  Tile q
+// holds components 0..d-1 of particles [64q, 64q + 64) as d rows of 64
+// values, so one component of 64 consecutive particles is one contiguous
+// segment and each particle's d components lie in one block of 64 d values
+// (the gather reads an ancestor's components from one region of memory
+// instead of d rows a whole state apart).  g is the particle's index over
+// all filters.
+constexpr int PT = 64;
+__host__ __device__ __forceinline__ int64_t pidx(int64_t g, int i, int d) {
+  return ((g >> 6) * (int64_t)d + i) * PT + (g & (PT - 1));
+}
+// values held by a plain-layout state of n particles (whole tiles)
+__host__ __device__ __forceinline__ int64_t plain_state_values(int64_t n, int d) {
+  return ((n + PT - 1) / PT) * PT * (int64_t)d;
+}
+
 // Arguments of the per-filter (plain layout) kernels.
 struct PlainArgs {
   int64_t N;              // particles of this filter
-  int64_t ld;             // row stride of the structure-of-arrays state (N_total)
+  int64_t ld;             // particles over all filters (N_total)
   int64_t off;            // first particle of this filter
   int64_t boff0;          // first block-partial slot of this filter
-  int64_t bst0;           // first merge-path boundary slot of this filter
-  int64_t bj0;            // first K3-block slot of this filter
+  int64_t own0;           // first output-tile owner / scan-block slot of this filter
   int32_t nblk;           // 256-particle blocks of this filter
   int32_t K, T, d, n_obs;
   uint32_t b;
@@ -61,6 +78,7 @@ struct PlainArgs {
   double* ess_tr;
   ResampleArgs rs;
   double* wcum;           // this filter's cumulative weights [N] (multinomial only)
+  int32_t mode;           // K3: 0 step (likelihood, uniform drawn); 1 ancestors only (given uniform)
 };
 
 // One filter of a batched collective launch: its index, first particle and
@@ -99,13 +117,17 @@ struct BatchArgs {
 };
 
 constexpr int K1_NT = 256;  // particles per propagate / scan block
-constexpr int K2_NT = 512;  // combine kernel threads
-constexpr int K3_NT = 256;  // scan + count threads
+constexpr int K2_NT = 512;  // combine threads (filters of more than FUSE_NB blocks)
+#ifndef PF_FUSE_NB
+#define PF_FUSE_NB 1024
+#endif
+constexpr int FUSE_NB = PF_FUSE_NB;  // up to this many K1 blocks, K3 combines the partials itself
+constexpr int K3_NT = 256;  // scan + mark threads
 constexpr int K3_PER = 4;   // consecutive particles per scan lane
 constexpr int K3_SPAN = K3_NT * K3_PER;  // particles per scan block (4 K1 blocks)
-constexpr int K4_NT = 256;  // merge-path threads
-constexpr int K4_L = 8;     // merge steps per thread
-constexpr int K4_DB = K4_NT * K4_L;  // merge-path diagonals per K4 block
+constexpr int K4_NT = 256;  // tile-gather threads
+constexpr int K4_PER = 4;   // outputs per tile-gather lane
+constexpr int K4_TILE = K4_NT * K4_PER;  // outputs per tile-gather block
 constexpr int BATCH_NT = 256;
 constexpr int BATCH_MAXN = 8192;
 
@@ -115,16 +137,18 @@ hipError_t launch_reset(FilterState* fs, double* ell, double* ess, int B, int T,
                         hipStream_t s);
 hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* xprop, void* lw,
                             double* part, const PlainArgs& a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s);
-hipError_t launch_scan_count(int prec, const void* lw, const double* boff, int32_t* counts,
-                             int32_t* bstate, int32_t* bjs, const PlainArgs& a, hipStream_t s);
-hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts,
-                               const int32_t* bstate, const int32_t* bjs, const void* xprop,
-                               void* xcur, int32_t* anc, const PlainArgs& a, hipStream_t s);
+hipError_t launch_scan_mark(const double* lw, const double* part, const double* boff,
+                            int32_t* marks, int32_t* owner, int32_t* jc, const PlainArgs& a,
+                            hipStream_t s);
+hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const int32_t* owner,
+                              const int32_t* jc, const void* xprop, void* xcur, int32_t* anc,
+                              const PlainArgs& a, hipStream_t s);
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
 hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
                                    int32_t* anc, const PlainArgs& a, hipStream_t s);
-hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* bjs,
+hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* jc,
                                      const void* xprop, void* xcur, int32_t* anc,
                                      const PlainArgs& a, hipStream_t s);
 hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, double obs_sd,

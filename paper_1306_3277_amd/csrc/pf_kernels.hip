@@ -1,15 +1,20 @@
 // Plain-layout kernels of the gfx950 bootstrap particle filter (Alg. 2):
 //   K1 propagate + weight   one particle per lane, K substeps in registers,
 //                           log-weight, per-block (max, sum, sum of squares)
-//   K2 combine              one workgroup: global max, FP64 block offsets,
+//   K2 combine              (filters of more than FUSE_NB blocks) one
+//                           workgroup: global max, FP64 block offsets,
 //                           likelihood increment, ESS, resampling uniform
-//   K3 scan + counts        FP64 block scan of exp(lw - M); for each particle
-//                           the number of strata its cumulative weight covers
-//   K4 merge-path gather    outputs and particles merged along equal-length
-//                           diagonals, so work per lane is independent of the
-//                           weights; ancestors staged in LDS, then coalesced
-//                           gather of the state rows
-// plus initialisation and the synthetic-data simulator.
+//   K3 combine + scan +     (smaller filters combine the block partials in
+//      marks                every K3 block instead of K2) FP64 block scan
+//                           of exp(lw - M); for each particle the number of
+//                           strata its cumulative weight covers, and a mark
+//                           (its index) on the first stratum it owns
+//   K4 tile gather          per tile of 1024 outputs, a running maximum over
+//                           the marks names every output's ancestor (the
+//                           work per lane does not depend on the weights),
+//                           then the ancestors' states are copied
+// plus initialisation and the synthetic-data simulator.  pf_step runs K1
+// (K2) K3, pf_resample K4.  The state is kept in 64-particle tiles (pidx).
 #include <math.h>
 
 #include "pf_device.hpp"
@@ -38,7 +43,7 @@ __global__ __launch_bounds__(K1_NT) void k_init(Real* __restrict__ x, PlainArgs 
       double z[4];
       normals4_f64(draw(key, TAG_INIT, blk, iter, (uint32_t)j, 0, A.b), z);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) x[(int64_t)(4 * blk + m) * A.ld + col] = (Real)z[m];
+      for (int m = 0; m < 4; ++m) x[pidx(col, 4 * blk + m, D)] = (Real)z[m];
     }
   }
 }
@@ -63,130 +68,126 @@ __global__ void k_reset(FilterState* fs, double* ell, double* ess, int B, int T,
     f.pad = 0;
     f.lprev = 0.0;
     f.carry = 0;
+    f.tk = 0;
+    f.cn1 = 0;
     f.pad2 = 0;
     fs[i] = f;
   }
 }
 
-// ---------------------------------------------------------------- K1
-// Observation log-density of one particle, in FP64 from the (FP32 or FP64)
-// state: the residuals are formed after widening the state, so an FP32 path
-// adds no rounding of its own here (a log-weight stored in FP32 would carry
-// ~2^-24 |lw|, above the per-step accuracy once |lw| reaches the hundreds).
-// Components are visited in increasing index, the order of the sorted
-// observation list.
-template <int D, typename Real>
-__device__ __forceinline__ double l96_logdens(const Real (&x)[D], const double* yrow,
-                                              const int32_t* obs_pos, double inv_sd,
-                                              double cst) {
-  double acc = 0.0;
+// ---------------------------------------------------------------- combine
+// The collective over the block partials (max, sum, sum of squares of the
+// 256-particle K1 blocks).  Offsets of the blocks' cumulative weights: K1
+// block i owns [off_i, off_{i+1}), off_nb = S.  They are summed
+// sequentially within each lane's chunk of partials and scanned across the
+// lanes; an exact running maximum then makes them non-decreasing whatever
+// the rounding, so the cumulative weights built on them are monotone.
+//
+// Two forms.  A filter of at most FUSE_NB blocks has every K3 block combine
+// all of its partials itself (the same order, the same code, so every block
+// obtains the same bits with no extra launch and no communication between
+// blocks); the partials are read coalesced and their scaled totals staged
+// in LDS.  A larger filter has one K2 workgroup combine them once and store
+// the offsets, before K3.
+struct Combined {
+  double M, S, S2, lo, hi;
+};
+
+template <int NT, int MAXNB>
+__device__ __forceinline__ Combined combine_block_lds(const double* __restrict__ P, int nb,
+                                                      int k1b, int span) {
+  constexpr int NW = NT / WAVE;
+  __shared__ double sT[MAXNB + MAXNB / 16];  // T_i at i + i/16 (padded against bank conflicts)
+  __shared__ double xm[NW], xs[NW], xs2[NW], xv[NW], xo[2];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  // exchange 1: the global maximum (coalesced reads)
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < nb; i += NT) m = fmax(m, P[3 * i]);
+  m = wave_max(m);
+  if (lane == 0) xm[wv] = m;
+  __syncthreads();
+  double M = xm[0];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const int o = obs_pos[i];
-    if (o >= 0) {
-      const double e = (yrow[o] - (double)x[i]) * inv_sd;
-      acc = acc + e * e;
+  for (int w = 1; w < NW; ++w) M = fmax(M, xm[w]);
+  const bool finite = (M > -INFINITY) && (M < INFINITY);
+  // block totals T_i = s_i exp(m_i - M) to LDS; sum of squares per lane
+  double loc2 = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) {
+    const double mb = P[3 * i];
+    double T = 0.0;
+    if (finite && mb > -INFINITY) {
+      const double sc = exp_nonpos(mb - M);
+      T = P[3 * i + 1] * sc;
+      loc2 += P[3 * i + 2] * (sc * sc);
+    }
+    sT[i + (i >> 4)] = T;
+  }
+  __syncthreads();
+  // each lane's contiguous chunk, summed sequentially
+  const int chunk = (nb + NT - 1) / NT;
+  const int i0 = min(nb, (int)threadIdx.x * chunk), i1 = min(nb, i0 + chunk);
+  double loc = 0.0;
+  for (int i = i0; i < i1; ++i) loc += sT[i + (i >> 4)];
+  // exchange 2: scan of the lanes' sums, total of squares
+  const double incl = wave_incl_scan(loc, lane);
+  const double s2w = wave_sum(loc2);
+  if (lane == WAVE - 1) xs[wv] = incl;
+  if (lane == 0) xs2[wv] = s2w;
+  __syncthreads();
+  double pre = incl - loc, S = 0.0, S2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) pre += xs[w];
+    S += xs[w];
+    S2 += xs2[w];
+  }
+  // this lane's last offset; an exact running maximum over earlier lanes
+  // makes the offsets non-decreasing whatever the rounding of the scan
+  double last = -INFINITY;
+  {
+    double run = pre;
+    for (int i = i0; i < i1; ++i) {
+      last = run;
+      run += sT[i + (i >> 4)];
     }
   }
-  return -0.5 * acc + cst;
-}
-
-template <int MODEL, int D, typename Real>
-__global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restrict__ xcur,
-                                                            Real* __restrict__ xprop,
-                                                            double* __restrict__ lw,
-                                                            double* __restrict__ part,
-                                                            PlainArgs A) {
-  __shared__ double red[K1_NT / WAVE];
-  const int64_t j = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
-  const int t = A.fs->t + 1;
-  const uint32_t iter = A.fs->iter;
-  const Key key = key_of(A.key);
-  double l = -INFINITY;
-  if (j < A.N) {
-    const int64_t col = A.off + j;
-    const double* yrow = A.obs + (int64_t)(t - 1) * A.n_obs;
-    const int n0 = (t - 1) * A.K;
-    if constexpr (MODEL == 1) {
-      if constexpr (sizeof(Real) == 8) {
-        double p = xcur[col];
-        for (int s = 1; s <= A.K; ++s) {
-          const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
-          double z0, z1;
-          bm_pair_f64(w.x, w.y, z0, z1);
-          p = wk_substep_f64(p, A.theta, A.q[n0 + s - 1], z0);
-        }
-        xprop[col] = p;
-        const double e = (yrow[0] - (p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
-        l = -0.5 * (e * e) + A.lw_cst;
-      } else {
-        float p = xcur[col];
-        const float a = (float)(A.theta[0] - 1.0), c = (float)A.theta[1], sp = (float)A.theta[3];
-        for (int s = 1; s <= A.K; ++s) {
-          const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
-          float z0, z1;
-          bm_pair_f32(w.x, w.y, z0, z1);
-          p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
-        }
-        xprop[col] = p;
-        const double e =
-            (yrow[0] - ((double)p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
-        l = -0.5 * (e * e) + A.lw_cst;
-      }
-    } else {
-      Real x[D];
+  const double vin = wave_incl_max_scan(last, lane);
+  const double vup = __shfl_up(vin, 1, WAVE);
+  if (lane == WAVE - 1) xv[wv] = vin;
+  __syncthreads();  // exchange 3
+  double vw = -INFINITY, vall = -INFINITY;
 #pragma unroll
-      for (int i = 0; i < D; ++i) x[i] = xcur[(int64_t)i * A.ld + col];
-      if constexpr (sizeof(Real) == 8) {
-        const double F = A.theta[0], sq = A.theta[1];
-        ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
-        for (int s = 1; s <= A.K; ++s) {
-          if constexpr (MODEL == 3)
-            l96_substep_stage_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
-                                     (uint32_t)(n0 + s), A.b);
-          else
-            l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
-                               (uint32_t)(n0 + s), A.b);
-        }
-      } else {
-        const L96F32 c = l96_f32_consts(A.theta[0], A.theta[1], A.h);
-        for (int s = 1; s <= A.K; ++s) {
-          if constexpr (MODEL == 3)
-            l96_substep_stage_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s),
-                                     A.b);
-          else
-            l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < D; ++i) xprop[(int64_t)i * A.ld + col] = x[i];
-      l = l96_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+  for (int w = 0; w < NW; ++w) {
+    if (w < wv) vw = fmax(vw, xv[w]);
+    vall = fmax(vall, xv[w]);
+  }
+  const double vprev = (lane == 0) ? vw : fmax(vup, vw);
+  const double Sf = fmax(S, vall);
+  // the two offsets this block needs, from the lanes that own them
+  const int k1e = k1b + span;
+  {
+    double run = pre;
+    for (int i = i0; i < i1; ++i) {
+      if (i == k1b) xo[0] = fmax(run, vprev);
+      if (i == k1e) xo[1] = fmax(run, vprev);
+      run += sT[i + (i >> 4)];
     }
-    // weights kept from a step that did not resample carry over
-    if (A.fs->carry) l = lw[col] + l;
-    lw[col] = l;
   }
-  // a NaN log-weight counts as zero weight
-  const double lc = (l == l) ? l : -INFINITY;
-  const double m = block_max<K1_NT>(lc, red);
-  const double e = (m > -INFINITY && m < INFINITY) ? exp_nonpos(lc - m) : 0.0;
-  const double s1 = block_sum<K1_NT>(e, red);
-  const double s2 = block_sum<K1_NT>(e * e, red);
-  if (threadIdx.x == 0) {
-    double* p = part + 3 * (A.boff0 + blockIdx.x);
-    p[0] = m;
-    p[1] = s1;
-    p[2] = s2;
-  }
+  if (threadIdx.x == 0 && k1e >= nb) xo[1] = Sf;
+  __syncthreads();
+  Combined c;
+  c.M = finite ? M : -INFINITY;
+  c.S = Sf;
+  c.S2 = S2;
+  c.lo = xo[0];
+  c.hi = xo[1];
+  return c;
 }
 
-// ---------------------------------------------------------------- K2
-// Offsets of the blocks' cumulative weights.  Block i of a filter owns
-// boff[i] .. boff[i+1]; boff[nb] is the total S.  The offsets are summed
-// sequentially within each thread's chunk and scanned across chunks; a
-// running maximum (exact) then makes them non-decreasing whatever the
-// rounding, so the cumulative weights built on them in K3 are monotone and
-// the stratum counts can be merged.
+// K2 (filters of more than FUSE_NB blocks): one workgroup combines the
+// partials, stores the offsets, and does the filter's bookkeeping
+// (likelihood increment, ESS, trigger, resampling uniform, traces,
+// interval counter).
 __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ part,
                                                    double* __restrict__ boff, PlainArgs A) {
   constexpr int NW = K2_NT / WAVE;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   // the filter's scalars and the resampling uniform, fetched and drawn while
   // the partials load
   FilterState* fst = A.fs;
-  const int t = fst->t + 1;
+  const int t = fst->tk;  // the interval K1 just propagated
   const double loglik0 = fst->loglik;
   const double lprev0 = fst->lprev;
   const int carry0 = fst->carry;
@@ -349,67 +350,239 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   }
 }
 
+
+// ---------------------------------------------------------------- K1
+// Observation log-density of one particle, in FP64 from the (FP32 or FP64)
+// state: the residuals are formed after widening the state, so an FP32 path
+// adds no rounding of its own here (a log-weight stored in FP32 would carry
+// ~2^-24 |lw|, above the per-step accuracy once |lw| reaches the hundreds).
+// Components are visited in increasing index, the order of the sorted
+// observation list.
+template <int D, typename Real>
+__device__ __forceinline__ double l96_logdens(const Real (&x)[D], const double* yrow,
+                                              const int32_t* obs_pos, double inv_sd,
+                                              double cst) {
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int o = obs_pos[i];
+    if (o >= 0) {
+      const double e = (yrow[o] - (double)x[i]) * inv_sd;
+      acc = acc + e * e;
+    }
+  }
+  return -0.5 * acc + cst;
+}
+
+template <int MODEL, int D, typename Real>
+__global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restrict__ xcur,
+                                                            Real* __restrict__ xprop,
+                                                            double* __restrict__ lw,
+                                                            double* __restrict__ part,
+                                                            PlainArgs A) {
+  __shared__ double red[K1_NT / WAVE];
+  const int64_t j = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  const int t = A.fs->t + 1;
+  const uint32_t iter = A.fs->iter;
+  const Key key = key_of(A.key);
+  double l = -INFINITY;
+  if (j < A.N) {
+    const int64_t col = A.off + j;
+    const double* yrow = A.obs + (int64_t)(t - 1) * A.n_obs;
+    const int n0 = (t - 1) * A.K;
+    if constexpr (MODEL == 1) {
+      if constexpr (sizeof(Real) == 8) {
+        double p = xcur[col];
+        for (int s = 1; s <= A.K; ++s) {
+          const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
+          double z0, z1;
+          bm_pair_f64(w.x, w.y, z0, z1);
+          p = wk_substep_f64(p, A.theta, A.q[n0 + s - 1], z0);
+        }
+        xprop[col] = p;
+        const double e = (yrow[0] - (p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+        l = -0.5 * (e * e) + A.lw_cst;
+      } else {
+        float p = xcur[col];
+        const float a = (float)(A.theta[0] - 1.0), c = (float)A.theta[1], sp = (float)A.theta[3];
+        for (int s = 1; s <= A.K; ++s) {
+          const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
+          float z0, z1;
+          bm_pair_f32(w.x, w.y, z0, z1);
+          p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
+        }
+        xprop[col] = p;
+        const double e =
+            (yrow[0] - ((double)p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+        l = -0.5 * (e * e) + A.lw_cst;
+      }
+    } else {
+      Real x[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) x[i] = xcur[pidx(col, i, D)];
+      if constexpr (sizeof(Real) == 8) {
+        const double F = A.theta[0], sq = A.theta[1];
+        ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
+        for (int s = 1; s <= A.K; ++s) {
+          if constexpr (MODEL == 3)
+            l96_substep_stage_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
+                                     (uint32_t)(n0 + s), A.b);
+          else
+            l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
+                               (uint32_t)(n0 + s), A.b);
+        }
+      } else {
+        const L96F32 c = l96_f32_consts(A.theta[0], A.theta[1], A.h);
+        for (int s = 1; s <= A.K; ++s) {
+          if constexpr (MODEL == 3)
+            l96_substep_stage_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s),
+                                     A.b);
+          else
+            l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) xprop[pidx(col, i, D)] = x[i];
+      l = l96_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+    }
+    // weights kept from a step that did not resample carry over
+    if (A.fs->carry) l = lw[col] + l;
+    lw[col] = l;
+  }
+  // a NaN log-weight counts as zero weight
+  const double lc = (l == l) ? l : -INFINITY;
+  const double m = block_max<K1_NT>(lc, red);
+  const double e = (m > -INFINITY && m < INFINITY) ? exp_nonpos(lc - m) : 0.0;
+  const double s1 = block_sum<K1_NT>(e, red);
+  const double s2 = block_sum<K1_NT>(e * e, red);
+  if (threadIdx.x == 0) {
+    double* p = part + 3 * (A.boff0 + blockIdx.x);
+    p[0] = m;
+    p[1] = s1;
+    p[2] = s2;
+    // the interval K3 processes (it must not read the counter it advances)
+    if (blockIdx.x == 0) A.fs->tk = t;
+  }
+}
+
 __global__ void k_set_u(FilterState* fs, double u) {
   if (threadIdx.x == 0 && blockIdx.x == 0) fs->u = u;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------- K3
 // W_j = boff[blk] + (block-local inclusive scan of exp(lw - M)), made
 // non-decreasing by an exact running maximum and capped by boff[blk+1]; then
-// count_j = #{k : (u + k) S < N W_j}, the number of strata owned by particles
-// 0..j.  Systematic resampling is then the merge of the counts with the
-// outputs k = 0..N-1 (K4): at state (j, k), particle j is consumed when
-// c_j <= k, otherwise output k gets ancestor j.  Particle j's states are
-// (j, k) for k in [c_{j-1}, c_j], i.e. the path diagonals j + c_{j-1} ..
-// j + c_j; every lane emits the merge-path state on each K4 block boundary
-// (a multiple of K4_DB) that falls in its range, so K4 needs no search.  At a
-// block edge the states (j, k), k < g = count(boff[blk]), of the block's
-// first particle are emitted by the previous block's last lane, which
-// computes the same g from the same boff value.
-__device__ __forceinline__ void emit_bounds(int32_t* __restrict__ bstate, int64_t j, int64_t d_lo,
-                                            int64_t d_hi) {
-  if (d_hi < d_lo) return;
-  int64_t D = ((d_lo + K4_DB - 1) / K4_DB) * K4_DB;
-  for (; D <= d_hi; D += K4_DB) bstate[D / K4_DB] = (int32_t)j;
-}
-
-__global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__ lw,
-                                                      const double* __restrict__ boff,
-                                                      int32_t* __restrict__ counts,
-                                                      int32_t* __restrict__ bstate_all,
-                                                      int32_t* __restrict__ bjs_all,
-                                                      PlainArgs A) {
-  __shared__ double red[K3_NT / WAVE];
-  __shared__ int64_t wlast[K3_NT / WAVE];
-  __shared__ int redi[K3_NT / WAVE];
+// c_j = #{k : (u + k) S < N W_j}, the number of strata owned by particles
+// 0..j, so particle j owns strata [c_{j-1}, c_j).  Each particle that owns
+// any marks the first of them with its index (one store per particle, no
+// loop over its offspring); the owner of every K4 tile's first stratum is
+// stored by the particle whose strata cover it, so K4 can name every
+// stratum's owner from its tile's marks alone.  At a block edge the strata
+// between the block's last count and g = count(boff[blk+1]) belong to the
+// next block's first particle; the block's last lane records them, because
+// only it knows that count.  Strata past the last particle's count (rounding
+// overflow) go to the last particle of positive weight (jstar).
+template <bool FUSED>
+__global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ lw,
+                                                     const double* __restrict__ part,
+                                                     const double* __restrict__ boff,
+                                                     int32_t* __restrict__ marks_all,
+                                                     int32_t* __restrict__ owner_all,
+                                                     int32_t* __restrict__ jc_all,
+                                                     PlainArgs A) {
+  constexpr int NW = K3_NT / WAVE;
+  __shared__ double xsum[NW], xvmax[NW];
+  __shared__ int64_t xcnt[NW];
+  __shared__ int xcand[NW];
   const int64_t N = A.N;
   const int64_t jb = (int64_t)blockIdx.x * K3_SPAN;
   const int64_t j0 = jb + (int64_t)threadIdx.x * K3_PER;
   const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  const FilterState* f = A.fs;
-  const double M = f->M, S = f->S, u = f->u;
+  // the lane's K3_PER consecutive log-weights, loaded first so that they
+  // arrive while the partials are combined (past the end they reread the
+  // last weight)
+  double lv[K3_PER];
+#pragma unroll
+  for (int e = 0; e < K3_PER; ++e) lv[e] = lw[A.off + min(j0 + e, N - 1)];
+  FilterState* fst = A.fs;
+  const int32_t t_now = fst->tk;  // the interval K1 just propagated
+  const uint32_t it_now = fst->iter;
+  const Key key = key_of(A.key);
+  const int k1b = (int)blockIdx.x * (K3_SPAN / K1_NT);  // first K1 block of this block
+  double M, S, u, lo_off, hi_off;
+  bool pos, carry;
+  if constexpr (FUSED) {
+    // mode 0 draws the resampling uniform (while the partials load); mode 1
+    // redraws the ancestors with the uniform already in the filter's scalars
+    u = A.mode == 0 ? u01_f64(draw(key, TAG_RESAMPLE, 0, it_now, 0, (uint32_t)t_now, A.b).x)
+                    : fst->u;
+    const Combined cb =
+        combine_block_lds<K3_NT, FUSE_NB>(part + 3 * A.boff0, A.nblk, k1b, K3_SPAN / K1_NT);
+    M = cb.M;
+    S = cb.S;
+    lo_off = cb.lo;
+    hi_off = cb.hi;
+    pos = (M > -INFINITY) && (M < INFINITY) && (S > 0.0);
+    const double ess = pos ? (S * S) / cb.S2 : 0.0;
+    // resample when ESS < ess_frac N
+    carry = pos && !(ess < A.rs.ess_frac * (double)N);
+    if (A.mode == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+      // the filter's bookkeeping: likelihood increment (the normaliser is
+      // ln N after a resampling, else the carried weights' ln sum exp), ESS,
+      // trigger, uniform, traces, and the interval counter
+      const double lprev = fst->carry ? fst->lprev : log((double)N);
+      double ell;
+      if (pos) {
+        const double L = M + log(S);
+        ell = L - lprev;
+        fst->lprev = L;
+      } else {
+        ell = -INFINITY;
+        fst->status = 4;
+      }
+      fst->carry = carry;
+      fst->loglik = fst->loglik + ell;
+      fst->M = M;
+      fst->S = S;
+      fst->ell = ell;
+      fst->ess = ess;
+      fst->u = u;
+      A.ell_tr[t_now - 1] = ell;
+      A.ess_tr[t_now - 1] = ess;
+      fst->t = t_now;
+    }
+  } else {
+    // K2 has combined the partials and done the bookkeeping
+    M = fst->M;
+    S = fst->S;
+    u = fst->u;
+    pos = (M > -INFINITY) && (M < INFINITY) && (S > 0.0);
+    carry = fst->carry;
+    const double* bo = boff + A.boff0 + A.b;
+    lo_off = bo[k1b];
+    hi_off = bo[min(k1b + K3_SPAN / K1_NT, A.nblk)];
+  }
+  if (A.rs.scheme == RS_METROPOLIS) return;  // no cumulative weights needed
   // a step that keeps its weights (ESS above the trigger) or has none
   // positive gives every particle one offspring: itself
-  const bool finite = (M > -INFINITY) && (M < INFINITY) && (S > 0.0) && !f->carry;
+  const bool finite = pos && !carry;
   const double invS = 1.0 / S;
   const bool strat = A.rs.scheme == RS_STRATIFIED;
-  const Key key = key_of(A.key);
-  const int32_t t_now = f->t;
-  const uint32_t it_now = f->iter;
   auto count = [&](double W) -> int64_t {
     return strat ? stratum_count_strat(W, S, invS, (int32_t)N, key, t_now, A.b, it_now)
                  : stratum_count(W, S, invS, u, (int32_t)N);
   };
-  const double* bo = boff + A.boff0 + A.b;
-  const int k1b = (int)blockIdx.x * (K3_SPAN / K1_NT);  // first K1 block of this block
-  const double lo_off = bo[k1b];
-  const double hi_off = bo[min(k1b + K3_SPAN / K1_NT, A.nblk)];
-  // in-lane sequential prefix of K3_PER consecutive weights
-  double w[K3_PER], loc[K3_PER], lv[K3_PER];
+  // in-lane sequential prefix of K3_PER consecutive weights, and the lane's
+  // last particle of positive weight (for the rare case where rounding
+  // leaves the final strata without an owner)
+  double w[K3_PER], loc[K3_PER];
   double run = 0.0;
-  // loads issued together (past the end they reread the last weight)
-#pragma unroll
-  for (int e = 0; e < K3_PER; ++e) lv[e] = lw[A.off + min(j0 + e, N - 1)];
+  int cand = -1;
 #pragma unroll
   for (int e = 0; e < K3_PER; ++e) {
     const int64_t j = j0 + e;
@@ -419,22 +592,36 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
       we = (l == l) ? exp_nonpos(l - M) : 0.0;
     }
     w[e] = we;
+    if (we > 0.0) cand = (int)j;
     run += we;
     loc[e] = run;
   }
-  double tot;
-  const double pre = block_incl_scan<K3_NT>(run, red, tot) - run;
+  // exchange 1: the lanes' sums scanned across the block (and the block's
+  // candidate, which only lane 0 needs)
+  const double incl = wave_incl_scan(run, lane);
+  const int cw = wave_max_i(cand);
+  if (lane == WAVE - 1) xsum[wv] = incl;
+  if (lane == 0) xcand[wv] = cw;
+  __syncthreads();
+  double pre = incl - run;
+#pragma unroll
+  for (int q = 0; q < NW; ++q)
+    if (q < wv) pre += xsum[q];
   double V[K3_PER];
 #pragma unroll
   for (int e = 0; e < K3_PER; ++e) V[e] = lo_off + (pre + loc[e]);
-  // exact running maximum over earlier lanes keeps W non-decreasing across
-  // lanes whatever the rounding of the tree scan; capped by the next offset
-  const double vmax = block_incl_max_scan<K3_NT>(V[K3_PER - 1], red);
-  double vprev = __shfl_up(vmax, 1, WAVE);
-  __shared__ double wmax[K3_NT / WAVE];
-  if (lane == WAVE - 1) wmax[wv] = vmax;
+  // exchange 2: an exact running maximum over earlier lanes keeps W
+  // non-decreasing across lanes whatever the rounding of the tree scan;
+  // capped by the next offset
+  const double vin = wave_incl_max_scan(V[K3_PER - 1], lane);
+  const double vup = __shfl_up(vin, 1, WAVE);
+  if (lane == WAVE - 1) xvmax[wv] = vin;
   __syncthreads();
-  if (lane == 0) vprev = wv > 0 ? wmax[wv - 1] : lo_off;
+  double vw = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < NW; ++q)
+    if (q < wv) vw = fmax(vw, xvmax[q]);
+  const double vprev = lane > 0 ? fmax(vup, vw) : (wv > 0 ? vw : lo_off);
   int64_t c[K3_PER];
 #pragma unroll
   for (int e = 0; e < K3_PER; ++e) {
@@ -442,25 +629,26 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
     const double W = fmin(fmax(V[e], vprev), hi_off);
     c[e] = (j < N) ? (finite ? count(W) : j + 1) : 0;
     if (A.rs.scheme == RS_MULTINOMIAL && j < N) A.wcum[j] = W;
-    if (j < N) counts[A.off + j] = (int32_t)c[e];
   }
-  // merge-path states on the K4 block boundaries (see above)
+  // the strata counts at this block's edges (the same function of the same
+  // offset values as the neighbouring blocks compute)
   const int64_t g_lo = finite ? count(lo_off) : jb;
   const int64_t jnext = jb + K3_SPAN;
   const int64_t g_hi = (jnext < N) ? (finite ? count(hi_off) : jnext) : N;
-  int64_t cprev = __shfl_up(c[K3_PER - 1], 1, WAVE);
-  if (lane == WAVE - 1) wlast[wv] = c[K3_PER - 1];
+  // exchange 3: each lane's first particle continues from the previous
+  // lane's last count
+  const int64_t cup = __shfl_up(c[K3_PER - 1], 1, WAVE);
+  if (lane == WAVE - 1) xcnt[wv] = c[K3_PER - 1];
   __syncthreads();
-  if (lane == 0) cprev = wv > 0 ? wlast[wv - 1] : g_lo;
-  int32_t* bstate = bstate_all + A.bst0;
-  // this lane's diagonal ranges: one per particle, plus (for the filter's or
-  // the block's last particle) the overflow outputs and end state, or the
-  // next block's first particle below its edge count
+  int64_t cprev = lane > 0 ? cup : (wv > 0 ? xcnt[wv - 1] : g_lo);
+  // strata [rlo, rhi) owned by particle rj: one range per particle, plus,
+  // for the block's last particle, the strata below the next block's first
+  // count, which belong to the next block's first particle
   int64_t rj[K3_PER + 1], rlo[K3_PER + 1], rhi[K3_PER + 1];
 #pragma unroll
   for (int e = 0; e <= K3_PER; ++e) {
     rj[e] = 0;
-    rlo[e] = 1;
+    rlo[e] = 0;
     rhi[e] = 0;  // empty
   }
 #pragma unroll
@@ -468,134 +656,149 @@ __global__ __launch_bounds__(K3_NT) void k_scan_count(const double* __restrict__
     const int64_t j = j0 + e;
     if (j < N) {
       rj[e] = j;
-      rlo[e] = j + cprev;
-      rhi[e] = j + c[e];
+      rlo[e] = cprev;
+      rhi[e] = c[e];
       if (j == N - 1) {
-        rj[K3_PER] = N;
-        rlo[K3_PER] = N + c[e];
-        rhi[K3_PER] = 2 * N;
+        fst->cn1 = (int32_t)c[e];
       } else if (j == jnext - 1) {
         rj[K3_PER] = j + 1;
-        rlo[K3_PER] = j + 1 + c[e];
-        rhi[K3_PER] = j + g_hi;
+        rlo[K3_PER] = c[e];
+        rhi[K3_PER] = g_hi;
       }
     }
     cprev = c[e];
   }
-  // A range crossing at most two block boundaries is emitted by its lane; a
-  // longer one (a particle owning many strata) by the whole wave, strided
-  // over the lanes, so no lane loops over hundreds of boundaries.
+  if (A.rs.scheme != RS_MULTINOMIAL) {
+    int32_t* marks = marks_all + A.off;
+    int32_t* owner = owner_all + A.own0;
 #pragma unroll
-  for (int e = 0; e <= K3_PER; ++e) {
-    const int64_t first = (rlo[e] + K4_DB - 1) / K4_DB;
-    const int64_t nb = (rhi[e] < rlo[e]) ? 0 : rhi[e] / K4_DB - first + 1;
-    const bool big = nb > 2;
-    if (!big)
-      for (int64_t q = first; q < first + nb; ++q) bstate[q] = (int32_t)rj[e];
-    uint64_t mask = __ballot(big);
-    while (mask) {
-      const int src = __ffsll((unsigned long long)mask) - 1;
-      mask &= mask - 1;
-      const long long bj = __shfl((long long)rj[e], src, WAVE);
-      const long long bq0 = __shfl((long long)first, src, WAVE);
-      const long long bq1 = __shfl((long long)(rhi[e] / K4_DB), src, WAVE);
-      for (long long q = bq0 + lane; q <= bq1; q += WAVE) bstate[q] = (int32_t)bj;
+    for (int e = 0; e <= K3_PER; ++e)
+      if (rlo[e] < rhi[e]) marks[rlo[e]] = (int32_t)rj[e];
+    // Tile q's first stratum q K4_TILE lies in at most one range.  A range
+    // covering at most two tile starts is stored by its lane; a longer one
+    // (a particle owning many strata) by the whole wave, strided over the
+    // lanes, so no lane loops over hundreds of tiles.
+#pragma unroll
+    for (int e = 0; e <= K3_PER; ++e) {
+      const int64_t first = (rlo[e] + K4_TILE - 1) / K4_TILE;
+      const int64_t last = rhi[e] > rlo[e] ? (rhi[e] - 1) / K4_TILE : first - 1;
+      const bool big = last - first + 1 > 2;
+      if (!big)
+        for (int64_t q = first; q <= last; ++q) owner[q] = (int32_t)rj[e];
+      uint64_t mask = __ballot(big);
+      while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const long long bj = __shfl((long long)rj[e], src, WAVE);
+        const long long bq0 = __shfl((long long)first, src, WAVE);
+        const long long bq1 = __shfl((long long)last, src, WAVE);
+        for (long long q = bq0 + lane; q <= bq1; q += WAVE) owner[q] = (int32_t)bj;
+      }
     }
   }
-  // last particle of positive weight in this block, for the rare case where
-  // rounding leaves the final strata without an owner
-  int cand = -1;
+  if (threadIdx.x == 0) {
+    int cb = xcand[0];
 #pragma unroll
-  for (int e = 0; e < K3_PER; ++e)
-    if (j0 + e < N && w[e] > 0.0) cand = (int)(j0 + e);
-  cand = block_max_i<K3_NT>(cand, redi);
-  if (threadIdx.x == 0) bjs_all[A.bj0 + blockIdx.x] = cand;
+    for (int q = 1; q < NW; ++q) cb = max(cb, xcand[q]);
+    jc_all[A.own0 + blockIdx.x] = cb;
+  }
 }
 
 // ---------------------------------------------------------------- K4
-// Block b walks diagonals [b K4_DB, (b+1) K4_DB) of the merge path from the
-// state K3 recorded, with the block's slice of counts staged in LDS and
-// K4_L path steps per lane; the ancestors land in LDS and the state rows
-// are then gathered with coalesced stores (all D components of an output in
-// flight at once).
+// One block per tile of K4_TILE outputs.  Lane t takes outputs
+// k0 + 4t .. k0 + 4t + 3: it reads their marks (and puts the -1 back, so
+// the marks are clear for the next resampling), and a running maximum over
+// the tile, started from the owner of the tile's first stratum, names each
+// output's ancestor (the largest particle that marked a stratum at or
+// before it); outputs past the filter's strata take jstar.  The ancestors go
+// to LDS, and the ancestors' states are then copied with coalesced stores
+// (output k0 + t + 256 q in lane t), D/8 groups of eight components in
+// flight at once.
 template <int D, typename Real>
-__global__ __launch_bounds__(K4_NT) void k_merge_gather(const int32_t* __restrict__ counts,
-                                                        const int32_t* __restrict__ bstate_all,
-                                                        const int32_t* __restrict__ bjs_all,
-                                                        const Real* __restrict__ xprop,
-                                                        Real* __restrict__ xcur,
-                                                        int32_t* __restrict__ anc,
-                                                        PlainArgs A) {
-  __shared__ int32_t sc[K4_DB + 1];
-  __shared__ int32_t sa[K4_DB];
-  __shared__ int32_t s_jstar;
+__global__ __launch_bounds__(K4_NT) void k_tile_gather(int32_t* __restrict__ marks_all,
+                                                       const int32_t* __restrict__ owner_all,
+                                                       const int32_t* __restrict__ jc_all,
+                                                       const Real* __restrict__ xprop,
+                                                       Real* __restrict__ xcur,
+                                                       int32_t* __restrict__ anc,
+                                                       PlainArgs A) {
+  __shared__ int32_t sa[K4_TILE];
+  __shared__ int32_t wtop[K4_NT / WAVE];
   const int64_t N = A.N;
-  const int32_t* c = counts + A.off;
-  const int32_t* bstate = bstate_all + A.bst0;
-  const int64_t d0 = (int64_t)blockIdx.x * K4_DB;
-  const int64_t d1 = min(d0 + K4_DB, 2 * N);
-  const int64_t j0 = bstate[blockIdx.x];
-  const int64_t j1 = (d1 == 2 * N) ? N : (int64_t)bstate[blockIdx.x + 1];
-  const int64_t k0 = d0 - j0, k1 = d1 - j1;
-  bool bad = !(j0 >= 0 && j0 <= j1 && j1 <= N && k0 >= 0 && k0 <= k1 && k1 <= N);
-  for (int i = threadIdx.x; i < K4_DB; i += K4_NT) sa[i] = -1;
-  if (!bad)
-    for (int64_t i = threadIdx.x; i <= j1 - j0 && j0 + i < N; i += K4_NT) sc[i] = c[j0 + i];
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  int32_t* marks = marks_all + A.off;
+  const int64_t k0 = (int64_t)blockIdx.x * K4_TILE;
+  const int64_t kt = k0 + (int64_t)threadIdx.x * K4_PER;
+  const int64_t cn1 = A.fs->cn1;
+  // jstar, from K3's per-block candidates, only for a tile that reaches past
+  // the filter's strata (rounding overflow; rare)
+  __shared__ int32_t s_js;
   if (threadIdx.x < WAVE) {
-    // only a block that reaches past the last particle can need the last
-    // particle of positive weight; find it from the per-block candidates
     int found = -1;
-    if (!bad && j1 == N) {
+    if (k0 + K4_TILE > cn1 && cn1 < N) {
       const int nb3 = (int)((N + K3_SPAN - 1) / K3_SPAN);
       for (int base = nb3 - 1; base >= 0 && found < 0; base -= WAVE) {
         const int i = base - (int)threadIdx.x;
-        found = wave_max_i(i >= 0 ? bjs_all[A.bj0 + i] : -1);
+        found = wave_max_i(i >= 0 ? jc_all[A.own0 + i] : -1);
       }
     }
-    if (threadIdx.x == 0) s_jstar = found;
+    if (threadIdx.x == 0) s_js = found;
   }
-  __syncthreads();
-  const int32_t jstar = s_jstar;
-  const int64_t dt = d0 + (int64_t)threadIdx.x * K4_L;
-  if (!bad && dt < d1) {
-    // first state of this lane: largest j in [lo, hi] with c_{j-1} <= dt - j
-    int64_t lo = max(j0, dt - k1), hi = min(j1, dt - k0);
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if ((int64_t)sc[mid - j0] <= dt - 1 - mid)
-        lo = mid + 1;
-      else
-        hi = mid;
+  int32_t run = k0 < cn1 ? owner_all[A.own0 + blockIdx.x] : -1;
+  int32_t r[K4_PER];
+#pragma unroll
+  for (int e = 0; e < K4_PER; ++e) {
+    const int64_t k = kt + e;
+    int32_t m = -1;
+    if (k < N) {
+      m = marks[k];
+      marks[k] = -1;
     }
-    int64_t jj = lo, k = dt - lo;
-    for (int s = 0; s < K4_L && jj + k < d1; ++s) {
-      if (jj < N && (k >= N || (int64_t)sc[jj - j0] <= k)) {
-        ++jj;
-      } else {
-        if (k >= k0 && k < k1) sa[k - k0] = (int32_t)(jj < N ? jj : jstar);
-        ++k;
-      }
-    }
+    run = max(run, m);
+    r[e] = run;
   }
+  const int32_t incl = wave_incl_max_scan_i(run, lane);
+  int32_t excl = __shfl_up(incl, 1, WAVE);
+  if (lane == 0) excl = -1;
+  if (lane == WAVE - 1) wtop[wv] = incl;
   __syncthreads();
-  if (!bad) {
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += K4_NT) {
-      int32_t aj = sa[k - k0];
-      if (aj < 0 || aj >= N) {  // never expected; flagged, and kept in bounds
+#pragma unroll
+  for (int w = 0; w < K4_NT / WAVE; ++w)
+    if (w < wv) excl = max(excl, wtop[w]);
+  const int32_t js = s_js;
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < K4_PER; ++e) {
+    const int64_t k = kt + e;
+    if (k < N) {
+      int32_t a = k < cn1 ? max(excl, r[e]) : js;
+      if (a < 0 || a >= N) {  // never expected; flagged, and kept in bounds
         bad = true;
-        aj = 0;
+        a = 0;
       }
-      anc[A.off + k] = aj;
-      const Real* src = xprop + A.off + aj;
-      Real* dst = xcur + A.off + k;
+      anc[A.off + k] = a;
+      sa[threadIdx.x * K4_PER + e] = a;
+    }
+  }
+  __syncthreads();
+  constexpr int CG = (D > 0 && D < 8) ? D : 8;
+#pragma unroll
+  for (int q = 0; q < K4_PER; ++q) {
+    const int kk = (int)threadIdx.x + K4_NT * q;
+    const int64_t k = k0 + kk;
+    if (k < N) {
+      const int64_t src = A.off + sa[kk], dst = A.off + k;
       if constexpr (D > 0) {
-        Real v[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) v[i] = src[(int64_t)i * A.ld];
+        for (int g = 0; g < D; g += CG) {
+          Real v[CG];
 #pragma unroll
-        for (int i = 0; i < D; ++i) dst[(int64_t)i * A.ld] = v[i];
+          for (int i = 0; i < CG; ++i) v[i] = xprop[pidx(src, g + i, D)];
+#pragma unroll
+          for (int i = 0; i < CG; ++i) xcur[pidx(dst, g + i, D)] = v[i];
+        }
       } else {
-        for (int i = 0; i < A.d; ++i) dst[(int64_t)i * A.ld] = src[(int64_t)i * A.ld];
+        for (int i = 0; i < A.d; ++i) xcur[pidx(dst, i, A.d)] = xprop[pidx(src, i, A.d)];
       }
     }
   }
@@ -648,11 +851,10 @@ __global__ __launch_bounds__(K1_NT) void k_metropolis(const double* __restrict__
 // Multinomial resampling, as Alg. 2 writes it: output k takes
 // a_k = min{j : W_j > u_k S} for an independent uniform u_k, by binary
 // search of the cumulative weights K3 left (exactly non-decreasing);
-// rounding overflow goes to the last positive weight (from K3's per-block
-// candidates).  A step that keeps its weights, or has none positive, gives
+// rounding overflow goes to the last positive weight (found by K3).  A step that keeps its weights, or has none positive, gives
 // the identity.
 __global__ __launch_bounds__(K1_NT) void k_multinomial(const double* __restrict__ wcum,
-                                                       const int32_t* __restrict__ bjs_all,
+                                                       const int32_t* __restrict__ jc_all,
                                                        int32_t* __restrict__ anc, PlainArgs A) {
   const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
   if (k >= A.N) return;
@@ -672,8 +874,8 @@ __global__ __launch_bounds__(K1_NT) void k_multinomial(const double* __restrict_
       a = lo;
     } else {
       int32_t js = -1;
-      const int nb3 = (int)((A.N + K3_SPAN - 1) / K3_SPAN);
-      for (int i = 0; i < nb3; ++i) js = max(js, bjs_all[A.bj0 + i]);
+      for (int i = (int)((A.N + K3_SPAN - 1) / K3_SPAN) - 1; i >= 0 && js < 0; --i)
+        js = jc_all[A.own0 + i];
       a = js >= 0 ? js : 0;
     }
   }
@@ -689,7 +891,8 @@ __global__ __launch_bounds__(K1_NT) void k_anc_gather(const Real* __restrict__ x
   const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
   if (k >= A.N) return;
   const int64_t src = A.off + anc[A.off + k];
-  for (int i = 0; i < A.d; ++i) xcur[(int64_t)i * A.ld + A.off + k] = xprop[(int64_t)i * A.ld + src];
+  const int64_t dst = A.off + k;
+  for (int i = 0; i < A.d; ++i) xcur[pidx(dst, i, A.d)] = xprop[pidx(src, i, A.d)];
 }
 
 // ---------------------------------------------------------------- simulator
@@ -815,38 +1018,46 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, 1, K2_NT, 0, s, part, boff, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s) {
   hipLaunchKernelGGL(k_set_u, 1, 64, 0, s, fs, u);
   return hipGetLastError();
 }
 
-hipError_t launch_scan_count(int prec, const void* lw, const double* boff, int32_t* counts,
-                             int32_t* bstate, int32_t* bjs, const PlainArgs& a, hipStream_t s) {
-  (void)prec;
-  hipLaunchKernelGGL(k_scan_count, nblocks(a.N, K3_SPAN), K3_NT, 0, s, (const double*)lw, boff,
-                     counts, bstate, bjs, a);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_i32, nblocks(n, 256), 256, 0, s, p, n, v);
   return hipGetLastError();
 }
 
-hipError_t launch_merge_gather(int model, int d, int prec, const int32_t* counts,
-                               const int32_t* bstate, const int32_t* bjs, const void* xprop,
-                               void* xcur, int32_t* anc, const PlainArgs& a, hipStream_t s) {
-  const unsigned g = nblocks(2 * a.N, K4_DB);
+hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, 1, K2_NT, 0, s, part, boff, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_mark(const double* lw, const double* part, const double* boff,
+                            int32_t* marks, int32_t* owner, int32_t* jc, const PlainArgs& a,
+                            hipStream_t s) {
+  const unsigned g = nblocks(a.N, K3_SPAN);
+  if (a.nblk <= FUSE_NB)
+    hipLaunchKernelGGL(k_scan_mark<true>, g, K3_NT, 0, s, lw, part, boff, marks, owner, jc, a);
+  else
+    hipLaunchKernelGGL(k_scan_mark<false>, g, K3_NT, 0, s, lw, part, boff, marks, owner, jc, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const int32_t* owner,
+                              const int32_t* jc, const void* xprop, void* xcur, int32_t* anc,
+                              const PlainArgs& a, hipStream_t s) {
+  const unsigned g = nblocks(a.N, K4_TILE);
   const int dd = model == 1 ? 1 : d;
   switch (dd) {
-#define X(DD)                                                                              \
-  case DD:                                                                                 \
-    if (prec == 0)                                                                         \
-      hipLaunchKernelGGL((k_merge_gather<DD, double>), g, K4_NT, 0, s, counts, bstate, bjs, \
-                         (const double*)xprop, (double*)xcur, anc, a);                     \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_merge_gather<DD, float>), g, K4_NT, 0, s, counts, bstate, bjs,  \
-                         (const float*)xprop, (float*)xcur, anc, a);                       \
+#define X(DD)                                                                               \
+  case DD:                                                                                  \
+    if (prec == 0)                                                                          \
+      hipLaunchKernelGGL((k_tile_gather<DD, double>), g, K4_NT, 0, s, marks, owner, jc,      \
+                         (const double*)xprop, (double*)xcur, anc, a);                      \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_tile_gather<DD, float>), g, K4_NT, 0, s, marks, owner, jc,       \
+                         (const float*)xprop, (float*)xcur, anc, a);                        \
     break;
     X(1) PF_L96_DIMS(X)
 #undef X
@@ -869,11 +1080,11 @@ hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xpro
   return hipGetLastError();
 }
 
-hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* bjs,
+hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* jc,
                                      const void* xprop, void* xcur, int32_t* anc,
                                      const PlainArgs& a, hipStream_t s) {
   const unsigned g = nblocks(a.N, K1_NT);
-  hipLaunchKernelGGL(k_multinomial, g, K1_NT, 0, s, wcum, bjs, anc, a);
+  hipLaunchKernelGGL(k_multinomial, g, K1_NT, 0, s, wcum, jc, anc, a);
   if (prec == 0)
     hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
                        (double*)xcur, (const int32_t*)anc, a);

@@ -16,8 +16,9 @@ namespace pfk {
 constexpr uint32_t TAG_PATH = 9;  // generator tag of the final draw
 
 // Plain layout, one filter: slot t = fs->t gets the particles x (the
-// propagated ones after a step, the initial ones at t = 0) and, for t >= 1,
-// the ancestors drawn at time t.
+// propagated ones after a step, the initial ones at t = 0; read from the
+// state's 64-particle tiles) and, for t >= 1, the ancestors drawn at time t.
+// The history itself keeps one row of N_total values per component.
 template <typename Real>
 __global__ __launch_bounds__(256) void k_record_plain(const Real* __restrict__ x,
                                                       const int32_t* __restrict__ anc,
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void k_record_plain(const Real* __restrict__ x
   if (k >= N) return;
   const int t = fs->t;
   Real* xh = (Real*)H.xh + (int64_t)t * H.d * H.ld;
-  for (int i = 0; i < H.d; ++i) xh[(int64_t)i * H.ld + off + k] = x[(int64_t)i * H.ld + off + k];
+  for (int i = 0; i < H.d; ++i) xh[(int64_t)i * H.ld + off + k] = x[pidx(off + k, i, H.d)];
   if (t >= 1) H.ah[(int64_t)(t - 1) * H.ld + off + k] = anc[off + k];
 }
 

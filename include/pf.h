@@ -32,9 +32,12 @@
  *  - No call falls back to the CPU: without a gfx950 device every call that
  *    needs one returns PF_E_DEVICE.
  *
- * Particle state is structure-of-arrays: component i of particle k of filter
- * b is at x[i * N_total + offset_b + k], with offset_b the sum of the
- * particle counts of filters before b.
+ * Particle state as the host sees it (pf_get_state, pf_set_state) is
+ * structure-of-arrays: component i of particle k of filter b is at
+ * x[i * N_total + offset_b + k], with offset_b the sum of the particle counts
+ * of filters before b.  The device layout inside the workspace is the
+ * library's own (the plain layout keeps 64-particle tiles with each tile's
+ * components contiguous; the batched layout one row per component).
  */
 #ifndef PF_H
 #define PF_H
@@ -368,6 +371,30 @@ pf_status pf_get_ancestors(pf_handle* h, int32_t* a_out);
 /* pf_resample with caller-given uniforms u[B] in [0, 1) instead of the
  * generator's (brute-force checks of the resampler). */
 pf_status pf_resample_u(pf_handle* h, const double* u);
+
+/* ---- stateless systematic resampler ------------------------------------ */
+/* The resampling collective of one filter on its own (Alg. 2's likelihood
+ * and ancestor lines with the systematic resampling of Sec. 3.3), for a
+ * caller that propagates and weights particles itself.  Input: d_lw, n FP64
+ * log-weights in device memory (a NaN counts as weight 0), and the uniform
+ * u in [0, 1).  In FP64: M = max lw, S = sum exp(lw - M),
+ * ell = M + ln S - ln n, ESS = S^2 / sum exp(2(lw - M)), and the ancestors
+ * a_k = min{ j : n W_j > (u + k) S }, k = 0..n-1, with W the prefix sum of
+ * exp(lw - M) (sorted; rounding overflow goes to the last positive weight)
+ * — the same kernels and bits as pf_resample_u on the plain layout.
+ * Outputs, device memory: d_anc[n] (int32), d_stats[2] = (ell, ESS); with
+ * no positive finite weight ell = -infinity, ESS = 0 and the ancestors are
+ * the identity.  Scratch: d_workspace, at least
+ * pf_systematic_workspace_bytes(n) bytes (about 4.2 n), 256-byte aligned,
+ * owned by the caller and reused freely between calls.  Asynchronous on
+ * hip_stream (NULL = the null stream); every operation is a kernel launch,
+ * so the call may be captured into a HIP graph.  Arguments are checked on
+ * the host (PF_E_INVAL: NULL pointer, n outside [1, 2^31 - 1], u outside
+ * [0, 1), workspace too small or misaligned) before any HIP call.  Calls on
+ * one workspace must not overlap. */
+size_t pf_systematic_workspace_bytes(int64_t n);
+pf_status pf_systematic(const double* d_lw, int64_t n, double u, int32_t* d_anc, double* d_stats,
+                        void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---- synthetic data ----------------------------------------------------- */
 /* Simulate the model from theta (host [n_theta]) with generator key

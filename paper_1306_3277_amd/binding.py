@@ -111,6 +111,9 @@ SIGNATURES = {
     "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32]),
     "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
     "pf_timing_get": (C.c_int, [_H, C.POINTER(PfTiming)]),
+    "pf_systematic_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "pf_systematic": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.c_size_t, C.c_void_p]),
     "pf_last_error": (C.c_char_p, []),
     "pf_version": (C.c_char_p, []),
 }
@@ -413,3 +416,29 @@ def simulate(pb, theta=None, data_seed: Optional[int] = None, stream=None, devic
     xt = out[:nx].reshape(pb.T + 1, pb.d)
     y = out[nx:nx + pb.T * len(pb.obs_idx)].reshape(pb.T, len(pb.obs_idx))
     return xt.copy(), y.copy()
+
+
+def systematic(lw, u: float, anc=None, stats=None, workspace=None, stream=None):
+    """pf_systematic on device tensors: lw (float64, n) and the uniform u;
+    returns (ancestors int32 [n], stats float64 [2] = (ell, ESS)) as device
+    tensors, written asynchronously on the stream.  Outputs and workspace are
+    allocated here when not given."""
+    import torch
+    L = load()
+    n = int(lw.numel())
+    assert lw.dtype == torch.float64 and lw.is_contiguous()
+    if anc is None:
+        anc = torch.empty(n, dtype=torch.int32, device=lw.device)
+    if stats is None:
+        stats = torch.empty(2, dtype=torch.float64, device=lw.device)
+    nb = int(L.pf_systematic_workspace_bytes(n))
+    if nb == 0:
+        _check(PF_E_INVAL)
+    if workspace is None:
+        workspace = torch.empty(nb + 256, dtype=torch.uint8, device=lw.device)
+    base = workspace.data_ptr()
+    pad = (-base) % 256
+    _check(L.pf_systematic(C.c_void_p(lw.data_ptr()), n, float(u), C.c_void_p(anc.data_ptr()),
+                           C.c_void_p(stats.data_ptr()), C.c_void_p(base + pad),
+                           C.c_size_t(workspace.numel() - pad), C.c_void_p(_stream_handle(stream))))
+    return anc, stats

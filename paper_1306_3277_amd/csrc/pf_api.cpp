@@ -16,6 +16,7 @@
 #include "pf_kalman.hpp"
 #include "pf_path.hpp"
 #include "pf_smc2.hpp"
+#include "pf_systematic.hpp"
 
 using pfk::FilterState;
 using pfk::PlainArgs;
@@ -23,17 +24,19 @@ using pfk::BatchArgs;
 
 namespace {
 
-thread_local std::string g_err;
+// the last failing call's message on this thread (a fixed buffer: reporting
+// an error allocates nothing)
+thread_local char g_err[512];
 
 pf_status fail(pf_status st, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
   va_end(ap);
-  g_err = buf;
   return st;
 }
+
+void err_clear() { g_err[0] = 0; }
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \
@@ -787,9 +790,53 @@ pf_status ensure_graphs(pf_handle* H) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- stateless systematic resampler
+namespace pfk {
+
+int systematic_check(const double* lw, int64_t n, double u, const int32_t* anc,
+                     const double* stats) {
+  if (!lw || !anc || !stats) return fail(PF_E_INVAL, "NULL device pointer");
+  if (n < 1 || n > (int64_t)0x7fffffff)
+    return fail(PF_E_INVAL, "n = %lld must be in [1, 2^31 - 1]", (long long)n);
+  if (!(u >= 0.0 && u < 1.0)) return fail(PF_E_INVAL, "u = %g must be in [0, 1)", u);
+  return PF_OK;
+}
+
+int systematic_enqueue(const double* lw, int64_t n, double u, int32_t* anc, double* stats,
+                       char* ws, hipStream_t s) {
+  const SysLayout L = sys_layout(n);
+  FilterState* fs = (FilterState*)(ws + L.fs);
+  PlainArgs a{};
+  a.N = n;
+  a.ld = n;
+  a.nblk = (int32_t)((n + K1_NT - 1) / K1_NT);
+  a.T = 1;
+  a.fs = fs;
+  a.ell_tr = stats;
+  a.ess_tr = stats + 1;
+  a.rs.scheme = RS_SYSTEMATIC;
+  a.rs.steps = 0;
+  a.rs.ess_frac = INFINITY;
+  a.mode = 2;  // bookkeeping with the given uniform
+  int32_t* marks = (int32_t*)(ws + L.marks);
+  // every launch is a kernel (no memset, no host copy), so a caller may
+  // capture the sequence in a graph
+  HIP_TRY(launch_reset(fs, stats, stats + 1, 1, 1, 0u, s));
+  HIP_TRY(launch_set_u(fs, u, s));
+  HIP_TRY(launch_fill_i32(marks, n, -1, s));
+  HIP_TRY(launch_lw_partials(lw, (double*)(ws + L.part), a, s));
+  if (a.nblk > FUSE_NB) HIP_TRY(launch_combine((double*)(ws + L.part), (double*)(ws + L.boff), a, s));
+  HIP_TRY(launch_scan_mark(lw, (double*)(ws + L.part), (double*)(ws + L.boff), marks,
+                           (int32_t*)(ws + L.owner), (int32_t*)(ws + L.jc), a, s));
+  HIP_TRY(launch_tile_anc(marks, (int32_t*)(ws + L.owner), (int32_t*)(ws + L.jc), anc, a, s));
+  return PF_OK;
+}
+
+}  // namespace pfk
+
 extern "C" {
 
-const char* pf_last_error(void) { return g_err.c_str(); }
+const char* pf_last_error(void) { return g_err; }
 const char* pf_version(void) { return "pfmi-gfx950 0.1"; }
 
 size_t pf_workspace_bytes(const pf_config* cfg) {
@@ -797,9 +844,31 @@ size_t pf_workspace_bytes(const pf_config* cfg) {
   return make_layout(cfg).total;
 }
 
+size_t pf_systematic_workspace_bytes(int64_t n) {
+  if (n < 1 || n > (int64_t)0x7fffffff) {
+    fail(PF_E_INVAL, "n = %lld must be in [1, 2^31 - 1]", (long long)n);
+    return 0;
+  }
+  return pfk::sys_layout(n).total;
+}
+
+pf_status pf_systematic(const double* d_lw, int64_t n, double u, int32_t* d_anc, double* d_stats,
+                        void* d_workspace, size_t ws_bytes, void* hip_stream) {
+  err_clear();
+  pf_status st = (pf_status)pfk::systematic_check(d_lw, n, u, d_anc, d_stats);
+  if (st) return st;
+  if (!d_workspace) return fail(PF_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(PF_E_INVAL, "workspace not 256-byte aligned");
+  const size_t need = pfk::sys_layout(n).total;
+  if (ws_bytes < need) return fail(PF_E_INVAL, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  return (pf_status)pfk::systematic_enqueue(d_lw, n, u, d_anc, d_stats, (char*)d_workspace,
+                                            (hipStream_t)hip_stream);
+}
+
+
 pf_status pf_init(const pf_config* cfg, void* d_workspace, size_t ws_bytes, void* hip_stream,
                   pf_handle** out) {
-  g_err.clear();
+  err_clear();
   if (!out) return fail(PF_E_INVAL, "out is NULL");
   *out = nullptr;
   pf_status st = validate(cfg);
@@ -1108,7 +1177,7 @@ size_t pf_simulate_doubles(const pf_config* cfg) {
 
 pf_status pf_simulate(const pf_config* cfg, const double* theta, uint64_t data_seed,
                       double* d_out, size_t out_doubles, void* hip_stream) {
-  g_err.clear();
+  err_clear();
   if (!cfg || !theta || !d_out) return fail(PF_E_INVAL, "NULL argument");
   pf_config c = *cfg;
   // the filter-only fields are not needed here
@@ -1214,7 +1283,7 @@ pf_status pf_pmmh(pf_handle* H, int32_t iters, const double* log_f0, const doubl
       ll_trace[(size_t)i * B + b] = ll[b];
     }
   }
-  g_err.clear();
+  err_clear();
   return PF_OK;
 }
 
@@ -1474,7 +1543,7 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
     HIP_TRY(hipStreamSynchronize(s));
   }
   if (numeric) return fail(PF_E_NUMERIC, "some time had no positive theta-weight");
-  g_err.clear();
+  err_clear();
   return PF_OK;
 }
 
@@ -1651,10 +1720,11 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
   if (st) {
     // keep the error message of the failure; best effort back to the
     // tuning the handle had, re-initialised
-    const std::string msg = g_err;
+    char msg[sizeof g_err];
+    std::memcpy(msg, g_err, sizeof msg);
     (void)pf_set_tuning(H, nt0, g0);
     (void)pf_reset(H, H->iter);
-    g_err = msg;
+    std::memcpy(g_err, msg, sizeof msg);
     return st;
   }
   if ((st = pf_set_tuning(H, best_nt, best_g))) return st;

@@ -78,7 +78,8 @@ struct PlainArgs {
   double* ess_tr;
   ResampleArgs rs;
   double* wcum;           // this filter's cumulative weights [N] (multinomial only)
-  int32_t mode;           // K3: 0 step (likelihood, uniform drawn); 1 ancestors only (given uniform)
+  int32_t mode;           // K2/K3: 0 step (bookkeeping, uniform drawn); 1 ancestors only
+                          // (given uniform); 2 bookkeeping with the given uniform
 };
 
 // One filter of a batched collective launch: its index, first particle and
@@ -139,6 +140,9 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
                             double* part, const PlainArgs& a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s);
+hipError_t launch_lw_partials(const double* lw, double* part, const PlainArgs& a, hipStream_t s);
+hipError_t launch_tile_anc(int32_t* marks, const int32_t* owner, const int32_t* jc, int32_t* anc,
+                           const PlainArgs& a, hipStream_t s);
 hipError_t launch_scan_mark(const double* lw, const double* part, const double* boff,
                             int32_t* marks, int32_t* owner, int32_t* jc, const PlainArgs& a,
                             hipStream_t s);

@@ -208,7 +208,8 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
   const int carry0 = fst->carry;
   double u = 0.0;
   if (threadIdx.x == 0)
-    u = u01_f64(draw(key_of(A.key), TAG_RESAMPLE, 0, fst->iter, 0, (uint32_t)t, A.b).x);
+    u = A.mode == 2 ? fst->u
+                    : u01_f64(draw(key_of(A.key), TAG_RESAMPLE, 0, fst->iter, 0, (uint32_t)t, A.b).x);
   // the lane's first KC partials, loaded together (indices past its chunk
   // reread the last block and are masked below)
   double pm[KC], ps[KC], p2[KC];
@@ -465,6 +466,28 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
   }
 }
 
+// Block partials (max, sum, sum of squares of exp(lw - max)) of caller-given
+// FP64 log-weights, the reduction K1 ends with; block 0 publishes the
+// interval index as K1 does.
+__global__ __launch_bounds__(K1_NT) void k_lw_partials(const double* __restrict__ lw,
+                                                       double* __restrict__ part, PlainArgs A) {
+  __shared__ double red[K1_NT / WAVE];
+  const int64_t j = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  const double l = j < A.N ? lw[A.off + j] : -INFINITY;
+  const double lc = (l == l) ? l : -INFINITY;  // a NaN log-weight counts as zero weight
+  const double m = block_max<K1_NT>(lc, red);
+  const double e = (m > -INFINITY && m < INFINITY) ? exp_nonpos(lc - m) : 0.0;
+  const double s1 = block_sum<K1_NT>(e, red);
+  const double s2 = block_sum<K1_NT>(e * e, red);
+  if (threadIdx.x == 0) {
+    double* p = part + 3 * (A.boff0 + blockIdx.x);
+    p[0] = m;
+    p[1] = s1;
+    p[2] = s2;
+    if (blockIdx.x == 0) A.fs->tk = A.fs->t + 1;
+  }
+}
+
 __global__ void k_set_u(FilterState* fs, double u) {
   if (threadIdx.x == 0 && blockIdx.x == 0) fs->u = u;
 }
@@ -517,8 +540,9 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
   double M, S, u, lo_off, hi_off;
   bool pos, carry;
   if constexpr (FUSED) {
-    // mode 0 draws the resampling uniform (while the partials load); mode 1
-    // redraws the ancestors with the uniform already in the filter's scalars
+    // mode 0 draws the resampling uniform (while the partials load); modes 1
+    // and 2 take the uniform already in the filter's scalars (1 redraws only
+    // the ancestors, 2 also does the bookkeeping)
     u = A.mode == 0 ? u01_f64(draw(key, TAG_RESAMPLE, 0, it_now, 0, (uint32_t)t_now, A.b).x)
                     : fst->u;
     const Combined cb =
@@ -531,7 +555,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
     const double ess = pos ? (S * S) / cb.S2 : 0.0;
     // resample when ESS < ess_frac N
     carry = pos && !(ess < A.rs.ess_frac * (double)N);
-    if (A.mode == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (A.mode != 1 && blockIdx.x == 0 && threadIdx.x == 0) {
       // the filter's bookkeeping: likelihood increment (the normaliser is
       // ln N after a resampling, else the carried weights' ln sum exp), ESS,
       // trigger, uniform, traces, and the interval counter
@@ -1025,6 +1049,19 @@ hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s) {
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_fill_i32, nblocks(n, 256), 256, 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_lw_partials(const double* lw, double* part, const PlainArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_lw_partials, nblocks(a.N, K1_NT), K1_NT, 0, s, lw, part, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_anc(int32_t* marks, const int32_t* owner, const int32_t* jc, int32_t* anc,
+                           const PlainArgs& a, hipStream_t s) {
+  // the tile gather with no state components: ancestors only
+  hipLaunchKernelGGL((k_tile_gather<0, float>), nblocks(a.N, K4_TILE), K4_NT, 0, s, marks, owner,
+                     jc, (const float*)nullptr, (float*)nullptr, anc, a);
   return hipGetLastError();
 }
 

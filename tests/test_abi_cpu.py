@@ -122,3 +122,25 @@ def test_init_rejects_before_touching_the_device():
 
 def test_version():
     assert binding.load().pf_version().decode().startswith("pfmi")
+
+
+def test_systematic_arguments_checked_on_the_host():
+    L = binding.load()
+    assert L.pf_systematic_workspace_bytes(0) == 0 and "n = 0" in _msg()
+    n = L.pf_systematic_workspace_bytes(1 << 20)
+    # partials, offsets, one mark per weight, per-tile slots: about 4.2 bytes per weight
+    assert 4 * (1 << 20) < n < 5 * (1 << 20)
+    fake = C.c_void_p(0x10000)  # never dereferenced: every case fails before any HIP call
+    cases = [
+        ((None, 10, 0.5, fake, fake, fake, n), "NULL"),
+        ((fake, 0, 0.5, fake, fake, fake, n), "n = 0"),
+        ((fake, 10, 1.0, fake, fake, fake, n), "u = 1"),
+        ((fake, 10, -0.5, fake, fake, fake, n), "u = -0.5"),
+        ((fake, 10, 0.5, fake, fake, None, n), "workspace is NULL"),
+        ((fake, 10, 0.5, fake, fake, C.c_void_p(0x10010), n), "aligned"),
+        ((fake, 1 << 20, 0.5, fake, fake, fake, 1000), "needs"),
+    ]
+    for args, msg in cases:
+        st = L.pf_systematic(*args, None)
+        assert st == binding.PF_E_INVAL, (args, st)
+        assert msg in _msg(), (msg, _msg())

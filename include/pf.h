@@ -396,6 +396,22 @@ size_t pf_systematic_workspace_bytes(int64_t n);
 pf_status pf_systematic(const double* d_lw, int64_t n, double u, int32_t* d_anc, double* d_stats,
                         void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * pf_systematic with the same inputs, outputs and results, but with no
+ * workspace argument.  Its scratch is a static device array sized for
+ * PF_SYSTEMATIC_NOALLOC_MAX_N weights (about 4.3 MB), one copy per GPU the
+ * library runs on, held until the process ends; the call allocates nothing
+ * (no hipMalloc, no allocating library routine).  n above the maximum is
+ * rejected with PF_E_INVAL.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (on different streams, or from different
+ * threads without ordering) race and must not be issued; calls in stream
+ * order are safe.  The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress) and keeps it. */
+#define PF_SYSTEMATIC_NOALLOC_MAX_N (1 << 20)
+pf_status pf_systematic_noalloc(const double* d_lw, int64_t n, double u, int32_t* d_anc,
+                                double* d_stats, void* hip_stream);
+
 /* ---- synthetic data ----------------------------------------------------- */
 /* Simulate the model from theta (host [n_theta]) with generator key
  * data_seed, in FP64 on the device (the same transition and observation

@@ -114,6 +114,8 @@ SIGNATURES = {
     "pf_systematic_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "pf_systematic": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pf_systematic_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "pf_last_error": (C.c_char_p, []),
     "pf_version": (C.c_char_p, []),
 }
@@ -441,4 +443,19 @@ def systematic(lw, u: float, anc=None, stats=None, workspace=None, stream=None):
     _check(L.pf_systematic(C.c_void_p(lw.data_ptr()), n, float(u), C.c_void_p(anc.data_ptr()),
                            C.c_void_p(stats.data_ptr()), C.c_void_p(base + pad),
                            C.c_size_t(workspace.numel() - pad), C.c_void_p(_stream_handle(stream))))
+    return anc, stats
+
+
+PF_SYSTEMATIC_NOALLOC_MAX_N = 1 << 20
+
+
+def systematic_noalloc(lw, u: float, anc, stats, stream=None):
+    """pf_systematic_noalloc on device tensors: lw (float64, n), u, and the
+    caller's outputs anc (int32, n) and stats (float64, 2), written
+    asynchronously on the stream; the library's static scratch is used."""
+    L = load()
+    n = int(lw.numel())
+    _check(L.pf_systematic_noalloc(C.c_void_p(lw.data_ptr()), n, float(u),
+                                   C.c_void_p(anc.data_ptr()), C.c_void_p(stats.data_ptr()),
+                                   C.c_void_p(_stream_handle(stream))))
     return anc, stats

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpf_mi355x.so")
-SOURCES = ["pf_kernels.hip", "pf_batched.hip", "pf_smc2.hip", "pf_path.hip", "pf_kalman.hip", "pf_api.cpp"]
+SOURCES = ["pf_kernels.hip", "pf_batched.hip", "pf_smc2.hip", "pf_path.hip", "pf_kalman.hip",
+           "pf_noalloc.hip", "pf_api.cpp"]
 ARCH = "gfx950"
 
 

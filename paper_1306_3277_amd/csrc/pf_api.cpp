@@ -793,6 +793,16 @@ pf_status ensure_graphs(pf_handle* H) {
 // ---------------------------------------------------------------- stateless systematic resampler
 namespace pfk {
 
+pf_status set_error(pf_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+void clear_error() { err_clear(); }
+
 int systematic_check(const double* lw, int64_t n, double u, const int32_t* anc,
                      const double* stats) {
   if (!lw || !anc || !stats) return fail(PF_E_INVAL, "NULL device pointer");

@@ -6,9 +6,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/pf.h"
 #include "pf_internal.hpp"
 
 namespace pfk {
+
+// the library's error reporting (pf_api.cpp): set_error sets the message
+// pf_last_error returns and passes the status through; clear_error empties it
+pf_status set_error(pf_status st, const char* fmt, ...);
+void clear_error();
 
 // Byte offsets of the scratch regions for n weights, 256-byte aligned:
 // block partials (3 doubles per 256 weights), block offsets, per-output

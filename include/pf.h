@@ -78,10 +78,18 @@ enum { PF_MODEL_WK = 1, PF_MODEL_L96 = 2, PF_MODEL_L96_STAGE = 3 };
 
 /* Arithmetic of the hot path.
  * PF_FP64: everything in FP64.
- * PF_FP32_MIXED: particle state, propagation and log-weights in FP32; the
+ * PF_FP32_MIXED: particle state, propagation and the observation residuals
+ *   in FP32 (the log-weight is summed in FP64 from the FP32 state); the
  *   max-shifted sums, the weight prefix scan, the likelihood increment, its
- *   running sum and the ESS in FP64. */
-enum { PF_FP64 = 0, PF_FP32_MIXED = 1 };
+ *   running sum and the ESS in FP64.  The state is rounded to FP32 after
+ *   every substep.
+ * PF_FP32_ACCURATE: the particle state is stored in FP32 and the model's
+ *   slopes (the Lorenz '96 drift at the RK4 stages, the windkessel
+ *   increment) and the normals are evaluated in FP32, as in PF_FP32_MIXED;
+ *   within an observation interval the state and each substep's increment
+ *   are carried in FP64, and the log-weight is taken from that state before
+ *   it is rounded for storage.  The collective is as in PF_FP32_MIXED. */
+enum { PF_FP64 = 0, PF_FP32_MIXED = 1, PF_FP32_ACCURATE = 2 };
 
 /* Kernel organisation.
  * PF_LAYOUT_PLAIN: each filter is stepped by its own kernels (propagate +
@@ -96,7 +104,7 @@ enum { PF_LAYOUT_PLAIN = 0, PF_LAYOUT_BATCHED = 1 };
 
 typedef struct pf_config {
   int32_t model;              /* PF_MODEL_* */
-  int32_t precision;          /* PF_FP64 or PF_FP32_MIXED */
+  int32_t precision;          /* PF_FP64, PF_FP32_MIXED or PF_FP32_ACCURATE */
   int32_t layout;             /* PF_LAYOUT_* */
   int32_t d;                  /* state dimension */
   int32_t K;                  /* substeps per observation interval, >= 1 */

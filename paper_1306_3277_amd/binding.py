@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpf_mi355x.so")
 
 PF_OK, PF_E_INVAL, PF_E_DEVICE, PF_E_STATE, PF_E_NUMERIC = 0, 1, 2, 3, 4
 PF_MODEL_WK, PF_MODEL_L96, PF_MODEL_L96_STAGE = 1, 2, 3
-PF_FP64, PF_FP32_MIXED = 0, 1
+PF_FP64, PF_FP32_MIXED, PF_FP32_ACCURATE = 0, 1, 2
 PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
 PF_BATCHED_MAX_PARTICLES = 8192
 PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_STRATIFIED, PF_RESAMPLE_METROPOLIS = 0, 1, 2

@@ -67,7 +67,8 @@ pf_status validate(const pf_config* c) {
   if (!c) return fail(PF_E_INVAL, "cfg is NULL");
   if (c->model != PF_MODEL_WK && c->model != PF_MODEL_L96 && c->model != PF_MODEL_L96_STAGE)
     return fail(PF_E_INVAL, "model %d unknown", c->model);
-  if (c->precision != PF_FP64 && c->precision != PF_FP32_MIXED)
+  if (c->precision != PF_FP64 && c->precision != PF_FP32_MIXED &&
+      c->precision != PF_FP32_ACCURATE)
     return fail(PF_E_INVAL, "precision %d unknown", c->precision);
   if (c->layout != PF_LAYOUT_PLAIN && c->layout != PF_LAYOUT_BATCHED)
     return fail(PF_E_INVAL, "layout %d unknown", c->layout);

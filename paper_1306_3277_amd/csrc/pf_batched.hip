@@ -69,7 +69,7 @@ __device__ __forceinline__ double batch_logdens(const Real (&x)[D], const double
   return -0.5 * acc + cst;
 }
 
-template <int MODEL, int D, typename Real, bool HIST>
+template <int MODEL, int D, typename Real, bool HIST, bool ACC>
 __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__ xa,
                                                               Real* __restrict__ xb,
                                                               double* __restrict__ lw,
@@ -107,16 +107,22 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
       l = -0.5 * (e * e) + A.lw_cst;
     } else {
       float p = xp[src];
+      double pa = p;  // the accurate form carries the pressure in FP64
       const float a = (float)(th[0] - 1.0), c = (float)th[1], sp = (float)th[3];
       for (int s = 1; s <= A.K; ++s) {
         const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)k, (uint32_t)(n0 + s), (uint32_t)f);
         float z0, z1;
         bm_pair_f32(w.x, w.y, z0, z1);
-        p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
+        if constexpr (ACC)
+          pa = pa + (double)wk_increment_f32((float)pa, a, c, sp, (float)A.q[n0 + s - 1], z0);
+        else
+          p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
       }
+      if constexpr (ACC) p = (float)pa;
+      else pa = p;
       xn[dst] = p;
       if constexpr (HIST) ((Real*)A.hx)[(int64_t)t * A.ld + dst] = p;
-      const double e = (yrow[0] - ((double)p + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+      const double e = (yrow[0] - (pa + th[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
       l = -0.5 * (e * e) + A.lw_cst;
     }
   } else {
@@ -133,6 +139,23 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
           l96_substep_f64<D>(x, th[0], th[1], mc, key, TAG_NOISE, iter, (uint32_t)k,
                              (uint32_t)(n0 + s), (uint32_t)f);
       }
+    } else if constexpr (ACC) {
+      double xa[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) xa[i] = (double)x[i];
+      const L96F32A c = l96_f32a_consts(th[0], th[1], A.h);
+      for (int s = 1; s <= A.K; ++s) {
+        if constexpr (MODEL == 3)
+          l96_substep_stage_f32acc<D>(xa, c, key, TAG_NOISE, iter, (uint32_t)k,
+                                      (uint32_t)(n0 + s), (uint32_t)f);
+        else
+          l96_substep_f32acc<D>(xa, c, key, TAG_NOISE, iter, (uint32_t)k, (uint32_t)(n0 + s),
+                                (uint32_t)f);
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) x[i] = (Real)xa[i];
+      // the log-weight from the state before it is rounded for storage
+      l = batch_logdens<D, double>(xa, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
     } else {
       const L96F32 c = l96_f32_consts(th[0], th[1], A.h);
       for (int s = 1; s <= A.K; ++s) {
@@ -151,7 +174,7 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 #pragma unroll
       for (int i = 0; i < D; ++i) xh[(int64_t)i * A.ld + dst] = x[i];
     }
-    l = batch_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+    if constexpr (!ACC || sizeof(Real) == 8) l = batch_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
   }
   // weights kept from a step that did not resample carry over
   if (A.fs[f].carry) l = lw[dst] + l;
@@ -550,16 +573,17 @@ hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc
 }
 
 // K5a with or without the history stores (a separate instantiation, so the
-// kernel without a history carries no trace of them)
-template <int MODEL, int D, typename Real>
+// kernel without a history carries no trace of them); ACC selects the
+// accurate FP32 form
+template <int MODEL, int D, typename Real, bool ACC = false>
 void launch_k5a(unsigned g, hipStream_t s, void* xa, void* xb, double* lw, const int32_t* anc,
                 const BatchArgs& a) {
   if (a.hx)
-    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, true>), g, BATCH_NT, 0, s, (Real*)xa,
-                       (Real*)xb, lw, anc, a);
+    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, true, ACC>), g, BATCH_NT, 0, s,
+                       (Real*)xa, (Real*)xb, lw, anc, a);
   else
-    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, false>), g, BATCH_NT, 0, s, (Real*)xa,
-                       (Real*)xb, lw, anc, a);
+    hipLaunchKernelGGL((k_batch_propagate<MODEL, D, Real, false, ACC>), g, BATCH_NT, 0, s,
+                       (Real*)xa, (Real*)xb, lw, anc, a);
 }
 
 hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
@@ -570,8 +594,10 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
   if (model == 1) {
     if (prec == 0)
       launch_k5a<1, 1, double>(g, s, xa, xb, lw, anc, a);
-    else
+    else if (prec == 1)
       launch_k5a<1, 1, float>(g, s, xa, xb, lw, anc, a);
+    else
+      launch_k5a<1, 1, float, true>(g, s, xa, xb, lw, anc, a);
     return hipGetLastError();
   }
   switch (d * 4 + model) {
@@ -579,14 +605,18 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
   case DD * 4 + 2:                                             \
     if (prec == 0)                                             \
       launch_k5a<2, DD, double>(g, s, xa, xb, lw, anc, a);     \
-    else                                                       \
+    else if (prec == 1)                                        \
       launch_k5a<2, DD, float>(g, s, xa, xb, lw, anc, a);      \
+    else                                                       \
+      launch_k5a<2, DD, float, true>(g, s, xa, xb, lw, anc, a); \
     break;                                                     \
   case DD * 4 + 3:                                             \
     if (prec == 0)                                             \
       launch_k5a<3, DD, double>(g, s, xa, xb, lw, anc, a);     \
-    else                                                       \
+    else if (prec == 1)                                        \
       launch_k5a<3, DD, float>(g, s, xa, xb, lw, anc, a);      \
+    else                                                       \
+      launch_k5a<3, DD, float, true>(g, s, xa, xb, lw, anc, a); \
     break;
     PF_L96_DIMS_B(X)
 #undef X

@@ -186,10 +186,15 @@ __device__ __forceinline__ double wk_substep_f64(double p, const double* th, dou
 }
 
 // FP32 form: the increment (a - 1) p + c q + sp z is formed first and added
-// to the pressure (|p| ~ 90) once.
+// to the pressure (|p| ~ 90) once (the accurate form adds it to an FP64
+// pressure).
+__device__ __forceinline__ float wk_increment_f32(float p, float am1, float c, float sp,
+                                                  float q_prev, float z) {
+  return fmaf(sp, z, fmaf(am1, p, c * q_prev));
+}
 __device__ __forceinline__ float wk_substep_f32(float p, float am1, float c, float sp,
                                                 float q_prev, float z) {
-  return p + fmaf(sp, z, fmaf(am1, p, c * q_prev));
+  return p + wk_increment_f32(p, am1, c, sp, q_prev, z);
 }
 
 // Lorenz '96 drift, written as the oracle writes it:
@@ -340,6 +345,123 @@ __device__ __forceinline__ void l96_substep_f32(float (&x)[D], const L96F32& c, 
     x[i + 2] = x[i + 2] + fmaf(r1, c1, acc[i + 2]);
     x[i + 3] = x[i + 3] + fmaf(r1, s1, acc[i + 3]);
   }
+}
+
+// ---------------------------------------------------------------- FP32 slopes, FP64 accumulation
+// The accurate FP32 form.  The slopes are evaluated in FP32 on FP32 stage
+// inputs, as in the FP32 form, but within an interval the state and each
+// substep's increment are carried in FP64: the stage bases (float)(x + c F)
+// are rounded once from the FP64 state, the slopes are summed in FP32 pairs
+// s14 = g1 + g4 and s23 = g2 + g3 (their rounding weighs h/6 in the
+// increment), and F h + (h/6)(s14 + 2 s23) + sq z is formed and added in
+// FP64.  The FP32 form's rounding of the state after every substep and of
+// its increment are what move its log-weights by up to about 1e-6 of their
+// size; here the state is rounded once, when it is stored, and the
+// log-weight is taken from the unrounded state.
+struct L96F32A {
+  float hh, h, nc2;
+  double Fh, hF, hF2, h6;
+};
+
+__device__ __forceinline__ L96F32A l96_f32a_consts(double F, double sq, double h) {
+  L96F32A c;
+  c.hh = (float)(0.5 * h);
+  c.h = (float)h;
+  c.nc2 = (float)(-1.3862943611198906 * sq * sq);
+  c.Fh = F * h;
+  c.hF = 0.5 * h * F;
+  c.hF2 = h * F;
+  c.h6 = h / 6.0;
+  return c;
+}
+
+// one stage: slopes g of the FP32 stage inputs xt, summed into s (or
+// starting it), and the next stage inputs xc + c_xt g
+template <int D>
+__device__ __forceinline__ void l96_stage_acc(float (&xt)[D], const float (&xc)[D], float (&s)[D],
+                                              float c_xt, bool start, bool last) {
+  const float old0 = xt[0];
+  float pm2 = xt[D - 2], pm1 = xt[D - 1];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const float xi = xt[i];
+    const float xp1 = (i == D - 1) ? old0 : xt[i + 1];
+    const float g = fmaf(xp1 - pm2, pm1, -xi);
+    pm2 = pm1;
+    pm1 = xi;
+    s[i] = start ? g : s[i] + g;
+    if (!last) xt[i] = fmaf(c_xt, g, xc[i]);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void l96_substep_f32acc(double (&x)[D], const L96F32A& c, Key key,
+                                                   uint32_t tag, uint32_t iter, uint32_t j,
+                                                   uint32_t n, uint32_t b) {
+  float xt[D], xc[D], s14[D], s23[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    xt[i] = (float)x[i];
+    xc[i] = (float)(x[i] + c.hF);
+  }
+  l96_stage_acc<D>(xt, xc, s14, c.hh, true, false);
+  l96_stage_acc<D>(xt, xc, s23, c.hh, true, false);
+#pragma unroll
+  for (int i = 0; i < D; ++i) xc[i] = (float)(x[i] + c.hF2);
+  l96_stage_acc<D>(xt, xc, s23, c.h, false, false);
+  l96_stage_acc<D>(xt, xc, s14, 0.0f, false, true);
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    const uint4 w = draw(key, tag, blk, iter, j, n, b);
+    float r0, c0, s0, r1, c1, s1;
+    noise_pair_f32(w.x, w.y, c.nc2, r0, c0, s0);
+    noise_pair_f32(w.z, w.w, c.nc2, r1, c1, s1);
+    const float nz[4] = {r0 * c0, r0 * s0, r1 * c1, r1 * s1};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = 4 * blk + m;
+      const double drift =
+          __builtin_fma(c.h6, __builtin_fma(2.0, (double)s23[i], (double)s14[i]), c.Fh);
+      x[i] = x[i] + (drift + (double)nz[m]);
+    }
+  }
+}
+
+// The same for the paper's form (noise inside the stages): the forcing of
+// component i over the substep is F + nz_i / h, so the stage bases are
+// (float)(x + (c F + (c/h) nz_i)) and the increment starts from F h + nz_i.
+template <int D>
+__device__ __forceinline__ void l96_substep_stage_f32acc(double (&x)[D], const L96F32A& c,
+                                                         Key key, uint32_t tag, uint32_t iter,
+                                                         uint32_t j, uint32_t n, uint32_t b) {
+  float nz[D];
+#pragma unroll
+  for (int blk = 0; blk < D / 4; ++blk) {
+    const uint4 w = draw(key, tag, blk, iter, j, n, b);
+    float r0, c0, s0, r1, c1, s1;
+    noise_pair_f32(w.x, w.y, c.nc2, r0, c0, s0);
+    noise_pair_f32(w.z, w.w, c.nc2, r1, c1, s1);
+    nz[4 * blk] = r0 * c0;
+    nz[4 * blk + 1] = r0 * s0;
+    nz[4 * blk + 2] = r1 * c1;
+    nz[4 * blk + 3] = r1 * s1;
+  }
+  float xt[D], xc[D], s14[D], s23[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    xt[i] = (float)x[i];
+    xc[i] = (float)(x[i] + (c.hF + 0.5 * (double)nz[i]));
+  }
+  l96_stage_acc<D>(xt, xc, s14, c.hh, true, false);
+  l96_stage_acc<D>(xt, xc, s23, c.hh, true, false);
+#pragma unroll
+  for (int i = 0; i < D; ++i) xc[i] = (float)(x[i] + (c.hF2 + (double)nz[i]));
+  l96_stage_acc<D>(xt, xc, s23, c.h, false, false);
+  l96_stage_acc<D>(xt, xc, s14, 0.0f, false, true);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+    x[i] = x[i] + __builtin_fma(c.h6, __builtin_fma(2.0, (double)s23[i], (double)s14[i]),
+                                c.Fh + (double)nz[i]);
 }
 
 // ---------------------------------------------------------------- Lorenz '96, noise in the stages

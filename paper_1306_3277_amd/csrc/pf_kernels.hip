@@ -375,7 +375,7 @@ __device__ __forceinline__ double l96_logdens(const Real (&x)[D], const double* 
   return -0.5 * acc + cst;
 }
 
-template <int MODEL, int D, typename Real>
+template <int MODEL, int D, typename Real, bool ACC = false>
 __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restrict__ xcur,
                                                             Real* __restrict__ xprop,
                                                             double* __restrict__ lw,
@@ -405,16 +405,22 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
         l = -0.5 * (e * e) + A.lw_cst;
       } else {
         float p = xcur[col];
+        double pa = p;  // the accurate form carries the pressure in FP64
         const float a = (float)(A.theta[0] - 1.0), c = (float)A.theta[1], sp = (float)A.theta[3];
         for (int s = 1; s <= A.K; ++s) {
           const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
           float z0, z1;
           bm_pair_f32(w.x, w.y, z0, z1);
-          p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
+          if constexpr (ACC) {
+            pa = pa + (double)wk_increment_f32((float)pa, a, c, sp, (float)A.q[n0 + s - 1], z0);
+          } else {
+            p = wk_substep_f32(p, a, c, sp, (float)A.q[n0 + s - 1], z0);
+          }
         }
+        if constexpr (ACC) p = (float)pa;
+        else pa = p;
         xprop[col] = p;
-        const double e =
-            (yrow[0] - ((double)p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
+        const double e = (yrow[0] - (pa + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
         l = -0.5 * (e * e) + A.lw_cst;
       }
     } else {
@@ -432,6 +438,23 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
             l96_substep_f64<D>(x, F, sq, mc, key, TAG_NOISE, iter, (uint32_t)j,
                                (uint32_t)(n0 + s), A.b);
         }
+      } else if constexpr (ACC) {
+        double xa[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) xa[i] = (double)x[i];
+        const L96F32A c = l96_f32a_consts(A.theta[0], A.theta[1], A.h);
+        for (int s = 1; s <= A.K; ++s) {
+          if constexpr (MODEL == 3)
+            l96_substep_stage_f32acc<D>(xa, c, key, TAG_NOISE, iter, (uint32_t)j,
+                                        (uint32_t)(n0 + s), A.b);
+          else
+            l96_substep_f32acc<D>(xa, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s),
+                                  A.b);
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) xprop[pidx(col, i, D)] = (Real)xa[i];
+        // the log-weight from the state before it is rounded for storage
+        l = l96_logdens<D, double>(xa, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
       } else {
         const L96F32 c = l96_f32_consts(A.theta[0], A.theta[1], A.h);
         for (int s = 1; s <= A.K; ++s) {
@@ -442,9 +465,11 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
             l96_substep_f32<D>(x, c, key, TAG_NOISE, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
         }
       }
+      if constexpr (!ACC || sizeof(Real) == 8) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) xprop[pidx(col, i, D)] = x[i];
-      l = l96_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+        for (int i = 0; i < D; ++i) xprop[pidx(col, i, D)] = x[i];
+        l = l96_logdens<D, Real>(x, yrow, A.obs_pos, A.inv_sd, A.lw_cst);
+      }
     }
     // weights kept from a step that did not resample carry over
     if (A.fs->carry) l = lw[col] + l;
@@ -1011,8 +1036,11 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
     if (prec == 0)
       hipLaunchKernelGGL((k_propagate_weight<1, 1, double>), g, K1_NT, 0, s,
                          (const double*)xcur, (double*)xprop, (double*)lw, part, a);
-    else
+    else if (prec == 1)
       hipLaunchKernelGGL((k_propagate_weight<1, 1, float>), g, K1_NT, 0, s,
+                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);
+    else
+      hipLaunchKernelGGL((k_propagate_weight<1, 1, float, true>), g, K1_NT, 0, s,
                          (const float*)xcur, (float*)xprop, (double*)lw, part, a);
     return hipGetLastError();
   }
@@ -1022,16 +1050,22 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
     if (prec == 0)                                                                        \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, double>), g, K1_NT, 0, s,             \
                          (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
-    else                                                                                  \
+    else if (prec == 1)                                                                   \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, float>), g, K1_NT, 0, s,              \
+                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_propagate_weight<2, DD, float, true>), g, K1_NT, 0, s,        \
                          (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
     break;                                                                                \
   case DD * 4 + 3:                                                                        \
     if (prec == 0)                                                                        \
       hipLaunchKernelGGL((k_propagate_weight<3, DD, double>), g, K1_NT, 0, s,             \
                          (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
-    else                                                                                  \
+    else if (prec == 1)                                                                   \
       hipLaunchKernelGGL((k_propagate_weight<3, DD, float>), g, K1_NT, 0, s,              \
+                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+    else                                                                                  \
+      hipLaunchKernelGGL((k_propagate_weight<3, DD, float, true>), g, K1_NT, 0, s,        \
                          (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
     break;
     PF_L96_DIMS(X)

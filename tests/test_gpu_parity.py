@@ -121,15 +121,19 @@ def test_lorenz96_d40_fp64_half_observed(pfm):
     _free_running_fp64(pfm, pb)
 
 
-def _teacher_forced_fp32(pfm, pb, steps):
+def _teacher_forced_fp32(pfm, pb, steps, form="fast"):
     """Every likelihood increment of the FP32 path, each interval started on
     both sides from the oracle's particles rounded to FP32, against the
     oracle's: within 1e-4 absolute wherever the oracle's effective sample
     size is at least 2.  A filter collapsed onto one particle (ESS < 2) has
     an increment equal to that particle's log-weight, in the hundreds here,
     and its FP32 propagation error alone exceeds 1e-4 there: those steps are
-    printed, not asserted.  Returns (errors, ESS) per step."""
-    f = pfm.Filter(pb, precision=pfm.PF_FP32_MIXED)
+    printed, not asserted.  The accurate FP32 form (state and increments in
+    FP64 within the interval, the log-weight from the unrounded state) is
+    held to 1e-4 on every step, collapsed filters included.  Returns
+    (errors, ESS) per step."""
+    accurate = form == "accurate"
+    f = pfm.Filter(pb, precision=pfm.PF_FP32_ACCURATE if accurate else pfm.PF_FP32_MIXED)
     th = pb.theta[0]
     N = int(pb.n_particles[0])
     x = oracle.init(pb, th, N)
@@ -147,8 +151,8 @@ def _teacher_forced_fp32(pfm, pb, steps):
         err = abs(ell[0, t - 1] - ell_ref)
         errs.append(err)
         esss.append(ess_ref)
-        if ess_ref >= 2.0:
-            assert err <= ABS32, (t, ell[0, t - 1], ell_ref, ess_ref)
+        if ess_ref >= 2.0 or accurate:
+            assert err <= ABS32, (form, t, ell[0, t - 1], ell_ref, ess_ref)
         else:
             print(f"t = {t}: collapsed filter (ESS {ess_ref:.3f}, ell {ell_ref:.2f}), "
                   f"FP32 error {err:.3e}")
@@ -158,29 +162,33 @@ def _teacher_forced_fp32(pfm, pb, steps):
     return np.array(errs), np.array(esss)
 
 
-def test_fp32_teacher_forced_lorenz96_d8(pfm):
+@pytest.mark.parametrize("form", ["fast", "accurate"])
+def test_fp32_teacher_forced_lorenz96_d8(pfm, form):
     pb = _with_data(W.config("lorenz96_d8", N=4096 + 13, T=12, precision=W.FP32_MIXED))
-    _, ess = _teacher_forced_fp32(pfm, pb, 12)
+    _, ess = _teacher_forced_fp32(pfm, pb, 12, form)
     assert np.mean(ess >= 2.0) >= 0.5  # most steps are held to 1e-4
 
 
-def test_fp32_teacher_forced_lorenz96_d40(pfm):
+@pytest.mark.parametrize("form", ["fast", "accurate"])
+def test_fp32_teacher_forced_lorenz96_d40(pfm, form):
     pb = _with_data(W.config("lorenz96_d40_large", N=2048 + 5, T=6))
-    _teacher_forced_fp32(pfm, pb, 6)
+    _teacher_forced_fp32(pfm, pb, 6, form)
 
 
-def test_fp32_teacher_forced_lorenz96_d40_spread_weights(pfm):
+@pytest.mark.parametrize("form", ["fast", "accurate"])
+def test_fp32_teacher_forced_lorenz96_d40_spread_weights(pfm, form):
     """d = 40 with an observation sd of 2 on the same kind of data: the
     weights stay spread (ESS above 2), so the steps are held to 1e-4."""
     pb = _with_data(W.config("lorenz96_d40_large", N=2048 + 5, T=6))
     pb = dataclasses.replace(pb, obs_sd=2.0)
-    _, ess = _teacher_forced_fp32(pfm, pb, 6)
+    _, ess = _teacher_forced_fp32(pfm, pb, 6, form)
     assert np.mean(ess >= 2.0) >= 0.5
 
 
-def test_fp32_teacher_forced_windkessel(pfm):
+@pytest.mark.parametrize("form", ["fast", "accurate"])
+def test_fp32_teacher_forced_windkessel(pfm, form):
     pb = _with_data(W.config("windkessel", T=30, precision=W.FP32_MIXED))
-    _, ess = _teacher_forced_fp32(pfm, pb, 30)
+    _, ess = _teacher_forced_fp32(pfm, pb, 30, form)
     assert np.mean(ess >= 2.0) >= 0.5
 
 

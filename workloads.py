@@ -34,6 +34,7 @@ MODEL_L96 = 2
 MODEL_L96_STAGE = 3  # Lorenz '96 with the noise inside the RK4 stages (the paper's form)
 FP64 = 0
 FP32_MIXED = 1
+FP32_ACCURATE = 2
 
 N_THETA = {MODEL_WK: 6, MODEL_L96: 2, MODEL_L96_STAGE: 2}
 

@@ -614,6 +614,13 @@ def main():
                          "(for counter runs)")
     ap.add_argument("--profile-large", action="store_true",
                     help="run only the large single-filter leg (for counter runs)")
+    ap.add_argument("--profile-groups", type=int, default=1,
+                    help="filter groups of the --profile-headline run")
+    ap.add_argument("--profile-plain", choices=("lorenz96_d8", "lorenz96_d40_large",
+                                                "lorenz96_d40_large_spread"),
+                    help="run only one plain-layout workload, FP32, 40 graph-replayed "
+                         "intervals (for kernel-trace and counter runs); _spread: observation "
+                         "sd 20, so the weights stay spread and the gather reads every state")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 2 GiB device-to-device copy (scales the memory "
                          "counters) and exit")
@@ -647,6 +654,25 @@ def main():
     stream = torch.cuda.Stream()
     if args.profile_large:
         print(json.dumps({"profile_large": large_filter_leg(torch, pfm, stream)}), flush=True)
+        return
+    if args.profile_plain:
+        name = args.profile_plain.replace("_spread", "")
+        pp = W.config(name, precision=W.FP32_MIXED)
+        _, yp = pfm.simulate(pp, stream=stream)
+        pp = pp.with_obs(yp)
+        if args.profile_plain.endswith("_spread"):
+            pp = dataclasses.replace(pp, obs_sd=20.0)
+        fp = pfm.Filter(pp, stream=stream)
+        fp.graph_run(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp.graph_run(40)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        _, essp, _ = fp.loglik(allow_numeric=True)
+        fp.close()
+        print(json.dumps({"profile_plain": args.profile_plain, "us_per_interval": dtp / 40 * 1e6,
+                          "ess_last": float(essp[0])}), flush=True)
         return
 
     # ---------------------------------------------------------------- headline
@@ -686,8 +712,9 @@ def main():
     f32 = pfm.Filter(pb, precision=head_prec, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
     if args.profile_headline:
         # counter runs replay each kernel under the profiler: a fixed tuning
-        # keeps them short
-        threads, groups = 512, 2
+        # keeps them short (one filter group by default, so that every
+        # propagation launch covers the whole batch)
+        threads, groups = 512, args.profile_groups
         tune_src = "fixed (profiling run)"
         f32.set_tuning(threads, groups)
     else:

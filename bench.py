@@ -324,16 +324,16 @@ RESAMPLER_CASES = [("systematic", 0, 0, float("inf")), ("stratified", 1, 0, floa
                    ("systematic_ess0.5", 0, 0, 0.5)]
 
 
-def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=100):
-    """Interval time of the batched workload (FP32 mixed, graph replay) with
-    each resampling variant."""
+def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=200):
+    """Interval time of the batched workload (fast FP32 form, graph replay)
+    with each resampling variant, after a whole warm-up pass."""
     out = {}
     for name, scheme, msteps, frac in RESAMPLER_CASES:
         f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
         f.set_tuning(threads, groups)
         f.set_resampler(scheme, msteps, frac)
         r = Runner(f, pb.T)
-        dt = timed(torch, r, steps, 10)
+        dt = timed(torch, r, steps, pb.T)
         f.close()
         out[name] = {"us_per_interval": dt / steps * 1e6,
                      "particle_steps_per_s": int(pb.n_particles.sum()) * steps / dt}
@@ -916,23 +916,28 @@ def main():
                 out["pmmh"]["vs_oracle"] = pmmh_vs_oracle(pfm, y, stream)
                 log(f"[bench] pmmh vs oracle chains: {out['pmmh']['vs_oracle']}")
 
+        # the legs below run the fast FP32 form: its tuning and interval time
+        if args.headline_form == "fast":
+            ft, fg, fdt = threads, groups, dt32 / args.steps / pb.T
+        else:
+            ft, fg, fdt = to, go, dto / args.steps / pb.T
+
         # ------------------------------------------------------------ resamplers
         log("[bench] resampler leg starts")
-        out["resamplers_batched"] = resampler_leg(torch, pfm, pb, stream, threads, groups)
+        out["resamplers_batched"] = resampler_leg(torch, pfm, pb, stream, ft, fg)
 
         # ------------------------------------------------------------ model forms, Kalman
         log("[bench] models leg starts")
-        out["models"] = models_leg(torch, pfm, pb, stream, threads, groups)
+        out["models"] = models_leg(torch, pfm, pb, stream, ft, fg)
 
         # ------------------------------------------------------------ state sample
         log("[bench] history leg starts")
-        out["state_sample"] = path_leg(torch, pfm, pb, stream, threads, groups,
-                                       dt32 / args.steps / pb.T)
+        out["state_sample"] = path_leg(torch, pfm, pb, stream, ft, fg, fdt)
 
         # ------------------------------------------------------------ SMC^2
         if args.smc2_T > 0:
             log("[bench] SMC^2 leg starts")
-            out["smc2"] = smc2_leg(torch, pfm, pb, stream, args.smc2_T, threads, groups)
+            out["smc2"] = smc2_leg(torch, pfm, pb, stream, args.smc2_T, ft, fg)
 
     if not args.no_cpu_baseline:
         host = host_cpu()

@@ -93,12 +93,14 @@ enum { PF_FP64 = 0, PF_FP32_MIXED = 1, PF_FP32_ACCURATE = 2 };
 
 /* Kernel organisation.
  * PF_LAYOUT_PLAIN: each filter is stepped by its own kernels (propagate +
- *   weight, block combine, scan + stratum counts, merge-path resample +
- *   gather); any particle count up to 2^31 - 1.
- * PF_LAYOUT_BATCHED: all filters are stepped by one persistent kernel per
- *   observation interval (work queue over particle chunks, then one
- *   workgroup per filter for the collective part); every filter's particle
- *   count must be <= PF_BATCHED_MAX_PARTICLES. */
+ *   weight; block combine, weight scan and stratum marks; per-tile ancestor
+ *   expansion + gather); any particle count up to 2^31 - 1.
+ * PF_LAYOUT_BATCHED: all filters are stepped together: one flat propagate +
+ *   weight kernel over every filter's particles, then one workgroup per
+ *   filter for the collective part (likelihood, scan, ancestors; the gather
+ *   is fused into the next propagation), filters split into groups stepped
+ *   concurrently; every filter's particle count must be
+ *   <= PF_BATCHED_MAX_PARTICLES. */
 enum { PF_LAYOUT_PLAIN = 0, PF_LAYOUT_BATCHED = 1 };
 #define PF_BATCHED_MAX_PARTICLES 8192
 

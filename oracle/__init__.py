@@ -45,6 +45,21 @@ class Problem(C.Structure):
     ]
 
 
+class WkMh(C.Structure):
+    _fields_ = [
+        ("prior_shape", C.c_double * 3), ("prior_scale", C.c_double * 3),
+        ("ig_shape", C.c_double), ("ig_scale", C.c_double), ("step_sd", C.c_double * 3),
+        ("ig_prop_shape", C.c_double), ("ig_prop_factor", C.c_double),
+        ("m0", C.c_double), ("s0", C.c_double),
+    ]
+
+
+def _wk_mh(spec) -> WkMh:
+    return WkMh((C.c_double * 3)(*spec.prior_shape), (C.c_double * 3)(*spec.prior_scale),
+                spec.ig_shape, spec.ig_scale, (C.c_double * 3)(*spec.step_sd),
+                spec.ig_prop_shape, spec.ig_prop_factor, spec.m0, spec.s0)
+
+
 _D = C.POINTER(C.c_double)
 _I = C.POINTER(C.c_int32)
 _U = C.POINTER(C.c_uint32)
@@ -112,6 +127,11 @@ def lib():
                                           C.c_int64]),
             "orc_pf_path": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
                                         _D, _D, C.POINTER(C.c_int64)]),
+            "orc_ndtri": (C.c_double, [C.c_double]),
+            "orc_wk_theta": (None, [P, C.POINTER(WkMh), _D, _D]),
+            "orc_wk_log_prior": (C.c_double, [C.POINTER(WkMh), _D]),
+            "orc_kf_pmmh": (C.c_int32, [P, C.POINTER(WkMh), C.c_int32, C.c_int32, _D, _D, _D,
+                                        _D, _D, _I]),
             "orc_smc2": (C.c_int32, [P, C.c_int32, C.POINTER(C.c_int64), C.c_int32, _D,
                                      C.c_int32, _D, _D, _D, _D, _D, _D, _U, _D, _D, _D, _I,
                                      _D, _D, _I, _I, _D, _D, _D]),
@@ -317,6 +337,41 @@ def pmmh(pb, N, inputs, chain0=0, n_chains=None, iters=None):
                    inputs.step_sd, inputs.f_lo, inputs.f_hi, inputs.sigma, _dp(lft), _dp(llt),
                    _ip(acc))
     return dict(log_f=lft, ll=llt, accepts=acc)
+
+
+def ndtri(p: float) -> float:
+    return lib().orc_ndtri(float(p))
+
+
+def wk_theta(pb, spec, rczs) -> np.ndarray:
+    """Model parameters (a, c, Z, sigma_p, m0, s0) from (R, C, Z, sigma^2)."""
+    P = _Prob(pb)
+    x = np.ascontiguousarray(rczs, dtype=np.float64)
+    th = np.zeros(6)
+    lib().orc_wk_theta(P.ref, C.byref(_wk_mh(spec)), _dp(x), _dp(th))
+    return th
+
+
+def wk_log_prior(spec, rczs) -> float:
+    x = np.ascontiguousarray(rczs, dtype=np.float64)
+    return lib().orc_wk_log_prior(C.byref(_wk_mh(spec)), _dp(x))
+
+
+def kf_pmmh(pb, spec, inputs, iters=None):
+    """Reference marginal Metropolis-Hastings chains on the windkessel's
+    (R, C, Z, sigma^2) with the Kalman likelihood (Alg. 3 on Alg. 1)."""
+    P = _Prob(pb)
+    th0 = np.ascontiguousarray(inputs.theta0, dtype=np.float64)
+    n = th0.shape[0]
+    iters = inputs.prop.shape[0] if iters is None else iters
+    prop = np.ascontiguousarray(inputs.prop[:iters], dtype=np.float64)
+    al = np.ascontiguousarray(inputs.alpha[:iters], dtype=np.float64)
+    tht = np.zeros((iters, n, 4))
+    llt = np.zeros((iters, n))
+    acc = np.zeros(n, dtype=np.int32)
+    lib().orc_kf_pmmh(P.ref, C.byref(_wk_mh(spec)), n, iters, _dp(th0), _dp(prop), _dp(al),
+                      _dp(tht), _dp(llt), _ip(acc))
+    return dict(theta=tht, ll=llt, accepts=acc)
 
 
 def copy_index(k, n_src, n_dst, w) -> int:

@@ -1121,3 +1121,143 @@ int32_t orc_smc2_kalman(const orc_problem* P, int32_t B, int32_t n_theta, const 
   free(th);
   return status;
 }
+
+/* ---- marginal Metropolis-Hastings on the windkessel with the Kalman filter
+ * (Sec. 3.2.1, eq. mh, Alg. 3, with the exact likelihood of Alg. 1) ---- */
+
+/* Standard normal distribution function from the complementary error
+ * function: Phi(x) = erfc(-x / sqrt 2) / 2 (accurate in both tails). */
+static double orc_ncdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+/* Phi^{-1}(p) for p in (0, 1).  Above 1/2 by symmetry, -Phi^{-1}(1 - p)
+ * (1 - p is exact there).  At or below 1/2, Newton's method on
+ * ln Phi(z) = ln p from z = 0 (the log form is nearly quadratic in the lower
+ * tail, so it converges fast there), kept inside a bracket [lo, hi] that
+ * every evaluation narrows; a Newton step that leaves the bracket is replaced
+ * by its midpoint.  Stops when the iterate no longer moves. */
+double orc_ndtri(double p) {
+  if (p > 0.5) return -orc_ndtri(1.0 - p);
+  const double inv_sqrt_2pi = 0.39894228040143267794;
+  const double lp = log(p);
+  double lo = -40.0, hi = 0.0, z = 0.0;
+  for (int it = 0; it < 400; ++it) {
+    double P = orc_ncdf(z);
+    double f = log(P) - lp;
+    if (f == 0.0) break;
+    if (f < 0.0) lo = z; else hi = z;
+    double zn = z - f * P / (inv_sqrt_2pi * exp(-0.5 * z * z));
+    if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+    if (zn == z || zn == lo || zn == hi) break;
+    z = zn;
+  }
+  return z;
+}
+
+/* The windkessel's model parameters from (R, C, Z, sigma^2), Sec. 2.1.1:
+ * a = exp(-h / (R C)), c = R (1 - a) (eq. 2-windkessel), the flow noise of
+ * variance sigma^2 scaled by c into the pressure, sd c sigma; the initial
+ * state N(m0, s0^2). */
+void orc_wk_theta(const orc_problem* P, const orc_wk_mh* H, const double* rczs, double* theta) {
+  double a = exp(-P->h / (rczs[0] * rczs[1]));
+  double c = rczs[0] * (1.0 - a);
+  theta[0] = a;
+  theta[1] = c;
+  theta[2] = rczs[2];
+  theta[3] = c * sqrt(rczs[3]);
+  theta[4] = H->m0;
+  theta[5] = H->s0;
+}
+
+/* ln p(R, C, Z, sigma^2) up to a constant: Gamma(k, s) densities
+ * x^{k-1} e^{-x/s} on R, C, Z and the Inverse-Gamma(alpha, beta) density
+ * x^{-alpha-1} e^{-beta/x} on sigma^2 (shape and scale parameters). */
+double orc_wk_log_prior(const orc_wk_mh* H, const double* x) {
+  double lp = 0.0;
+  for (int k = 0; k < 3; ++k)
+    lp += (H->prior_shape[k] - 1.0) * log(x[k]) - x[k] / H->prior_scale[k];
+  lp += -(H->ig_shape + 1.0) * log(x[3]) - H->ig_scale / x[3];
+  return lp;
+}
+
+/* n_chains independent chains over (R, C, Z, sigma^2).  The random numbers
+ * are inputs: prop[i][c][0..2] uniforms in (0, 1) that draw the truncated
+ * Gaussian proposals of R, C and Z by inversion, prop[i][c][3] a
+ * Gamma(ig_prop_shape, 1) variate g, alpha[i][c] in (0, 1].  Iteration i:
+ *   1. proposal: for R, C, Z with sd s > 0, y = x + s z with z drawn from
+ *      N(0, 1) truncated to z > -x/s: with p0 = Phi(-x/s),
+ *      z = Phi^{-1}(p0 + u (1 - p0)) if u <= 1/2, else
+ *      z = -Phi^{-1}((1 - u)(1 - p0)) (the same value, from the upper tail);
+ *      sigma^2' = f sigma^2 / g, an Inverse-Gamma(shape, f sigma^2) draw;
+ *   2. a proposal with a non-positive or non-finite component lies outside
+ *      the prior's support: rejected without a likelihood;
+ *   3. otherwise l' is the Kalman filter's log-likelihood at theta', and the
+ *      move is accepted iff ln alpha <= (l' - l) + ((ln p(theta') -
+ *      ln p(theta)) + ln q(theta | theta') - ln q(theta' | theta)), where the
+ *      proposal term is the sum over moved components of
+ *      ln Phi(x/s) - ln Phi(y/s) (the truncated Gaussians' normalisers) and
+ *      (2 shape + 1) ln r - f (r - 1/r), r = sigma^2'/sigma^2 (the
+ *      Inverse-Gamma proposal's density ratio).
+ * Outputs: theta_trace[i][c][4], ll_trace[i][c] (the chain after iteration
+ * i), accepts[c]. */
+int32_t orc_kf_pmmh(const orc_problem* P, const orc_wk_mh* H, int32_t n_chains, int32_t iters,
+                    const double* theta0, const double* prop, const double* alpha,
+                    double* theta_trace, double* ll_trace, int32_t* accepts) {
+  double* ell = (double*)malloc(sizeof(double) * (size_t)(P->T > 0 ? P->T : 1));
+  for (int32_t c = 0; c < n_chains; ++c) {
+    double x[4], y[4], th[6];
+    for (int k = 0; k < 4; ++k) x[k] = theta0[(int64_t)c * 4 + k];
+    orc_wk_theta(P, H, x, th);
+    double ll = orc_kf_wk(P, th, ell);
+    double lp = orc_wk_log_prior(H, x);
+    int32_t acc = 0;
+    for (int32_t i = 0; i < iters; ++i) {
+      const double* u = prop + ((int64_t)i * n_chains + c) * 4;
+      double lq = 0.0;
+      int inside = 1;
+      for (int k = 0; k < 3; ++k) {
+        double s = H->step_sd[k];
+        if (s > 0.0) {
+          double p0 = orc_ncdf(-x[k] / s);
+          double z = (u[k] <= 0.5) ? orc_ndtri(p0 + u[k] * (1.0 - p0))
+                                   : -orc_ndtri((1.0 - u[k]) * (1.0 - p0));
+          y[k] = x[k] + s * z;
+          if (!(y[k] > 0.0) || !isfinite(y[k])) {
+            inside = 0;
+          } else {
+            lq += log(orc_ncdf(x[k] / s)) - log(orc_ncdf(y[k] / s));
+          }
+        } else {
+          y[k] = x[k];
+        }
+      }
+      if (H->ig_prop_factor > 0.0) {
+        y[3] = H->ig_prop_factor * x[3] / u[3];
+        if (!(y[3] > 0.0) || !isfinite(y[3])) {
+          inside = 0;
+        } else {
+          double r = y[3] / x[3];
+          lq += (2.0 * H->ig_prop_shape + 1.0) * log(r) - H->ig_prop_factor * (r - 1.0 / r);
+        }
+      } else {
+        y[3] = x[3];
+      }
+      if (inside) {
+        orc_wk_theta(P, H, y, th);
+        double llp = orc_kf_wk(P, th, ell);
+        double lpp = orc_wk_log_prior(H, y);
+        double lhs = log(alpha[(int64_t)i * n_chains + c]);
+        if (lhs <= (llp - ll) + ((lpp - lp) + lq)) {
+          for (int k = 0; k < 4; ++k) x[k] = y[k];
+          ll = llp;
+          lp = lpp;
+          ++acc;
+        }
+      }
+      for (int k = 0; k < 4; ++k) theta_trace[((int64_t)i * n_chains + c) * 4 + k] = x[k];
+      ll_trace[(int64_t)i * n_chains + c] = ll;
+    }
+    accepts[c] = acc;
+  }
+  free(ell);
+  return ORC_OK;
+}

@@ -139,6 +139,26 @@ int32_t orc_smc2(const orc_problem* P, int32_t B, const int64_t* n_particles, in
                  double* log_evidence, int32_t* anc_trace, int32_t* acc_trace,
                  double* logw_trace, double* theta_trace, double* x_final);
 
+/* Marginal Metropolis-Hastings on the windkessel parameters (R, C, Z,
+ * sigma^2) with the Kalman filter's exact likelihood (Alg. 3 on Alg. 1);
+ * priors and proposals of Sec. 2.1.1's parameter and proposal blocks. */
+typedef struct orc_wk_mh {
+  double prior_shape[3];  /* Gamma prior shapes of R, C, Z */
+  double prior_scale[3];  /* Gamma prior scales of R, C, Z */
+  double ig_shape;        /* Inverse-Gamma prior of sigma^2: shape */
+  double ig_scale;        /* and scale */
+  double step_sd[3];      /* truncated Gaussian proposal sd of R, C, Z (0: fixed) */
+  double ig_prop_shape;   /* sigma^2' ~ Inv-Gamma(ig_prop_shape, ig_prop_factor sigma^2) */
+  double ig_prop_factor;  /* (0: sigma^2 fixed) */
+  double m0, s0;          /* P_p(t_0) ~ N(m0, s0^2) */
+} orc_wk_mh;
+double orc_ndtri(double p);
+void orc_wk_theta(const orc_problem* P, const orc_wk_mh* H, const double* rczs, double* theta);
+double orc_wk_log_prior(const orc_wk_mh* H, const double* rczs);
+int32_t orc_kf_pmmh(const orc_problem* P, const orc_wk_mh* H, int32_t n_chains, int32_t iters,
+                    const double* theta0, const double* prop, const double* alpha,
+                    double* theta_trace, double* ll_trace, int32_t* accepts);
+
 #ifdef __cplusplus
 }
 #endif

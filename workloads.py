@@ -221,6 +221,65 @@ def pmmh_inputs(chains: int = 64, iters: int = 2000, seed: int = 3, step_sd: flo
 
 
 @dataclasses.dataclass
+class WkMh:
+    """Priors and proposals of marginal Metropolis-Hastings on the
+    windkessel's (R, C, Z, sigma^2) (Sec. 2.1.1, the parameter and proposal
+    blocks), with the initial state N(m0, s0^2).  Gamma and Inverse-Gamma are
+    read as (shape, scale).  A zero step sd (or a zero ``ig_prop_factor``)
+    keeps that parameter fixed."""
+    prior_shape: tuple = (2.0, 2.0, 2.0)
+    prior_scale: tuple = (0.9, 1.5, 0.03)
+    ig_shape: float = 2.0
+    ig_scale: float = 25.0
+    step_sd: tuple = (0.03, 0.1, 0.002)
+    ig_prop_shape: float = 2.0
+    ig_prop_factor: float = 3.0
+    m0: float = 90.0
+    s0: float = 15.0
+
+
+@dataclasses.dataclass
+class WkMhInputs:
+    """Random numbers of the windkessel chains, passed in as inputs:
+    ``theta0`` [chains, 4] the initial (R, C, Z, sigma^2); ``prop``
+    [iters, chains, 4]: uniforms in (0, 1) for R, C, Z and a
+    Gamma(ig_prop_shape, 1) variate for sigma^2; ``alpha`` [iters, chains] in
+    (0, 1)."""
+    theta0: np.ndarray
+    prop: np.ndarray
+    alpha: np.ndarray
+
+
+def _open_uniforms(rng, shape) -> np.ndarray:
+    """Uniforms strictly inside (0, 1): (k + 1/2) 2^-32 for a 32-bit k."""
+    return (rng.integers(0, 2 ** 32, size=shape, dtype=np.uint64).astype(np.float64)
+            + 0.5) * 2.0 ** -32
+
+
+def wk_mh_prior_draws(spec: WkMh, n: int, rng) -> np.ndarray:
+    """n draws of (R, C, Z, sigma^2) from the prior."""
+    out = np.zeros((n, 4))
+    for k in range(3):
+        out[:, k] = rng.gamma(spec.prior_shape[k], spec.prior_scale[k], size=n)
+    out[:, 3] = spec.ig_scale / rng.gamma(spec.ig_shape, 1.0, size=n)
+    return out
+
+
+def wk_mh_inputs(spec: WkMh, chains: int = 64, iters: int = 1000, seed: int = 5,
+                 theta0: Optional[np.ndarray] = None) -> WkMhInputs:
+    """Inputs for ``chains`` chains of ``iters`` iterations; without
+    ``theta0`` the chains start from prior draws."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if theta0 is None:
+        theta0 = wk_mh_prior_draws(spec, chains, rng)
+    theta0 = np.ascontiguousarray(np.broadcast_to(theta0, (chains, 4)), dtype=np.float64)
+    prop = np.zeros((iters, chains, 4))
+    prop[:, :, :3] = _open_uniforms(rng, (iters, chains, 3))
+    prop[:, :, 3] = rng.gamma(spec.ig_prop_shape, 1.0, size=(iters, chains))
+    return WkMhInputs(theta0, prop, _open_uniforms(rng, (iters, chains)))
+
+
+@dataclasses.dataclass
 class Smc2Inputs:
     """Random numbers the SMC^2 parameter layer (Alg. 4) draws, passed in as
     inputs, plus its random walk and prior box.

@@ -378,10 +378,50 @@ def models_leg(torch, pfm, pb, stream, threads, groups, steps=100):
     out["smc_kalman_windkessel_512_theta_T100"] = {
         "seconds": dts, "log_evidence": rk["log_evidence"],
         "accept_rate": float(rk["accepts"].sum() / (512 * wk.T))}
+    out["kalman_mh_windkessel_512_chains"] = kalman_mh_leg(torch, pfm, stream)
     log(f"[bench] models: L96 stage noise {out['lorenz96_stage_noise_batched']['us_per_interval']:.1f} "
         f"us/interval; Kalman 512 x T100 {dtk * 1e3:.3f} ms; SMC with Kalman filters "
-        f"512 x T100 {dts * 1e3:.1f} ms")
+        f"512 x T100 {dts * 1e3:.1f} ms; Kalman MH "
+        f"{out['kalman_mh_windkessel_512_chains']['chain_iterations_per_s']:.3e} iterations/s")
     return out
+
+
+def kalman_mh_leg(torch, pfm, stream, B=512, iters=1000, T=100):
+    """Marginal Metropolis-Hastings on the paper's windkessel (R, C, Z,
+    sigma^2) with the exact Kalman likelihood: B chains x iters iterations
+    on T observations, the paper's priors and proposals, every chain started
+    within 20% of the data's parameters; inputs resident on the device."""
+    wk = W.windkessel_paper(N=1, T=T, B=B)
+    _, y = pfm.simulate(wk, stream=stream)
+    wk = wk.with_obs(y)
+    spec = W.WkMh()
+    truth = np.array([1.0, 1.5, 0.03, 25.0])
+    rng = np.random.default_rng(17)
+    inp = W.wk_mh_inputs(spec, chains=B, iters=iters, seed=18,
+                         theta0=truth * rng.uniform(0.8, 1.2, size=(B, 4)))
+    dev = torch.device("cuda")
+    th0, pr, al = (torch.from_numpy(a).to(dev) for a in (inp.theta0, inp.prop, inp.alpha))
+    f = pfm.Filter(wk, precision=pfm.PF_FP64, stream=stream)
+    res = f.kalman_pmmh(spec, th0, pr, al, iters=20)
+    out = None
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = f.kalman_pmmh(spec, th0, pr, al, out=out)
+        times.append(time.perf_counter() - t0)
+    f.close()
+    dt = min(times)
+    theta = out["theta"][iters // 2:].reshape(-1, 4).cpu().numpy()
+    acc = out["accepts"].cpu().numpy()
+    del res
+    substeps = B * (iters + 1) * T * wk.K
+    return {"chains": B, "iterations": iters, "T": T, "K": wk.K, "seconds": dt,
+            "chain_iterations_per_s": B * iters / dt, "kalman_substeps_per_s": substeps / dt,
+            "accept_rate": float(acc.sum() / (B * iters)),
+            "posterior_mean_second_half": dict(zip(["R", "C", "Z", "sigma2"],
+                                                   theta.mean(0).round(4).tolist())),
+            "truth": dict(zip(["R", "C", "Z", "sigma2"], truth.tolist()))}
 
 
 def path_leg(torch, pfm, pb, stream, threads, groups, dt_plain_interval):

@@ -196,6 +196,56 @@ pf_status pf_reset(pf_handle* h, uint32_t iteration);
  * handle's particles are untouched.  Synchronous. */
 pf_status pf_kalman(pf_handle* h, double* loglik_out, double* ell_out);
 
+/* Marginal Metropolis-Hastings on the windkessel's circuit parameters
+ * (R, C, Z, sigma^2) driven by the Kalman filter's exact likelihood
+ * (Sec. 3.2.1, eq. mh, Alg. 3 with Alg. 1 as the likelihood; the priors and
+ * proposals of Sec. 2.1.1's parameter and proposal blocks, Gamma and
+ * Inverse-Gamma read as (shape, scale)).  The model parameters follow from
+ * (R, C, Z, sigma^2) with the handle's substep h: a = exp(-h/(R C)),
+ * c = R (1 - a) (eq. 2-windkessel), pressure noise sd c sigma (the noise is
+ * on the flow), P_p(t_0) ~ N(m0, s0^2).  Prior: R, C, Z ~ Gamma(shape_k,
+ * scale_k), sigma^2 ~ Inv-Gamma(ig_shape, ig_scale).  Proposal: R, C, Z each
+ * a Gaussian step of sd step_sd[k] truncated to positive values (sd 0: the
+ * parameter stays), sigma^2' ~ Inv-Gamma(ig_prop_shape, ig_prop_factor
+ * sigma^2) (factor 0: it stays); the acceptance ratio carries both
+ * proposals' density ratios. */
+typedef struct pf_wk_mh {
+  double prior_shape[3];  /* Gamma prior shapes of R, C, Z, > 0 */
+  double prior_scale[3];  /* Gamma prior scales of R, C, Z, > 0 */
+  double ig_shape;        /* Inverse-Gamma prior of sigma^2: shape > 0 */
+  double ig_scale;        /* and scale > 0 */
+  double step_sd[3];      /* truncated-Gaussian proposal sd of R, C, Z, >= 0 */
+  double ig_prop_shape;   /* shape of the sigma^2 proposal, > 0 when moved */
+  double ig_prop_factor;  /* its scale is ig_prop_factor sigma^2; >= 0 */
+  double m0, s0;          /* initial pressure mean and sd (s0 >= 0) */
+} pf_wk_mh;
+
+/* B independent chains, one per filter slot of the windkessel handle h (its
+ * flow series, observations, observation sd and h; its particles are
+ * untouched), all iterations of a chain in one lane of one kernel on the
+ * handle's stream (asynchronous).  The random numbers are inputs, device
+ * arrays (FP64, 8-byte aligned, not overlapping the outputs):
+ *   theta0 [B][4]       initial (R, C, Z, sigma^2), each > 0;
+ *   prop   [iters][B][4] u_R, u_C, u_Z uniforms in (0, 1) and g, a
+ *                       Gamma(ig_prop_shape, 1) variate;
+ *   alpha  [iters][B]   uniforms in (0, 1].
+ * Iteration i: for each moved k of R, C, Z with sd s, p0 = Phi(-x_k/s) and
+ * y_k = x_k + s z, z = Phi^{-1}(p0 + u (1 - p0)) if u <= 1/2, else
+ * -Phi^{-1}((1 - u)(1 - p0)) (one truncated draw by inversion, evaluated on
+ * the tail that keeps it accurate); sigma^2' = factor sigma^2 / g.  A
+ * proposal with a component that is not positive and finite is rejected
+ * without a likelihood; otherwise it is accepted iff ln alpha <= (l' - l) +
+ * ((ln p(theta') - ln p(theta)) + ln q(theta | theta') - ln q(theta' |
+ * theta)).  Outputs, device arrays: theta_trace [iters][B][4] and ll_trace
+ * [iters][B] (the chain after each iteration), accepts [B], and, if not
+ * NULL, ll0 [B] (the initial states' log-likelihoods).  Inputs outside the
+ * stated ranges are not reported; they never fault, and their results are
+ * not specified. */
+pf_status pf_kalman_pmmh(pf_handle* h, const pf_wk_mh* spec, int32_t iters,
+                         const double* d_theta0, const double* d_prop, const double* d_alpha,
+                         double* d_theta_trace, double* d_ll_trace, int32_t* d_accepts,
+                         double* d_ll0);
+
 /* ---- resampling variants ------------------------------------------------ */
 /* Which resampler the filters use and when (Sec. 3.3 names multinomial,
  * systematic and stratified resampling and resamplers that avoid the

@@ -53,6 +53,23 @@ class PfTiming(C.Structure):
     ]
 
 
+class PfWkMh(C.Structure):
+    _fields_ = [
+        ("prior_shape", C.c_double * 3), ("prior_scale", C.c_double * 3),
+        ("ig_shape", C.c_double), ("ig_scale", C.c_double), ("step_sd", C.c_double * 3),
+        ("ig_prop_shape", C.c_double), ("ig_prop_factor", C.c_double),
+        ("m0", C.c_double), ("s0", C.c_double),
+    ]
+
+
+def wk_mh_struct(spec) -> PfWkMh:
+    """pf_wk_mh from an object with the same field names."""
+    return PfWkMh((C.c_double * 3)(*spec.prior_shape), (C.c_double * 3)(*spec.prior_scale),
+                  float(spec.ig_shape), float(spec.ig_scale), (C.c_double * 3)(*spec.step_sd),
+                  float(spec.ig_prop_shape), float(spec.ig_prop_factor), float(spec.m0),
+                  float(spec.s0))
+
+
 class PfSmc2In(C.Structure):
     _fields_ = [
         ("T_run", C.c_int32), ("theta0", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
@@ -101,6 +118,8 @@ SIGNATURES = {
                           C.c_double, _D, _D, _I]),
     "pf_set_resampler": (C.c_int, [_H, C.c_int32, C.c_int32, C.c_double]),
     "pf_kalman": (C.c_int, [_H, _D, _D]),
+    "pf_kalman_pmmh": (C.c_int, [_H, C.POINTER(PfWkMh), C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pf_history_bytes": (C.c_size_t, [C.POINTER(PfConfig)]),
     "pf_history_attach": (C.c_int, [_H, C.c_void_p, C.c_size_t]),
     "pf_backtrace": (C.c_int, [_H, _D, _I]),
@@ -303,6 +322,45 @@ class Filter:
         ell = np.zeros((self.B, self.T))
         _check(load().pf_kalman(self.h, _dp(ll), _dp(ell)))
         return ll, ell
+
+    def kalman_pmmh(self, spec, theta0, prop, alpha, iters: Optional[int] = None,
+                    device: str = "cuda", out=None, sync: bool = True):
+        """Marginal Metropolis-Hastings chains on the windkessel's (R, C, Z,
+        sigma^2) with the exact Kalman likelihood, one per filter slot.
+        ``spec`` has pf_wk_mh's fields; theta0 [B, 4], prop [iters, B, 4],
+        alpha [iters, B] are arrays or device tensors (FP64).  Returns device
+        tensors theta [iters, B, 4], ll [iters, B], accepts [B], ll0 [B]
+        (``out``, a dict of those, is reused when given)."""
+        import torch
+        dev = torch.device(device)
+
+        def on_dev(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=dev, dtype=torch.float64).contiguous()
+            return torch.from_numpy(np.array(a, dtype=np.float64)).to(dev)  # a copy
+
+        th0, pr, al = on_dev(theta0), on_dev(prop), on_dev(alpha)
+        iters = int(pr.shape[0]) if iters is None else int(iters)
+        B = self.B
+        if tuple(th0.shape) != (B, 4) or pr.shape[0] < iters or tuple(pr.shape[1:]) != (B, 4) \
+                or al.shape[0] < iters or tuple(al.shape[1:]) != (B,):
+            raise ValueError("theta0 [B, 4], prop [iters, B, 4], alpha [iters, B] expected")
+        if out is None:
+            out = dict(theta=torch.empty((iters, B, 4), dtype=torch.float64, device=dev),
+                       ll=torch.empty((iters, B), dtype=torch.float64, device=dev),
+                       accepts=torch.empty(B, dtype=torch.int32, device=dev),
+                       ll0=torch.empty(B, dtype=torch.float64, device=dev))
+        hs = wk_mh_struct(spec)
+        torch.cuda.synchronize(dev)  # inputs made on torch's stream, the chains run on the handle's
+        _check(load().pf_kalman_pmmh(self.h, C.byref(hs), iters, C.c_void_p(th0.data_ptr()),
+                                     C.c_void_p(pr.data_ptr()), C.c_void_p(al.data_ptr()),
+                                     C.c_void_p(out["theta"].data_ptr()),
+                                     C.c_void_p(out["ll"].data_ptr()),
+                                     C.c_void_p(out["accepts"].data_ptr()),
+                                     C.c_void_p(out["ll0"].data_ptr())))
+        if sync:
+            torch.cuda.synchronize(dev)
+        return out
 
     def smc2(self, proposal: Optional["Filter"], inputs, T: Optional[int] = None,
              traces: bool = True, device: str = "cuda", kalman: bool = False):

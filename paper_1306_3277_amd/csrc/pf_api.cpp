@@ -1582,6 +1582,47 @@ pf_status pf_kalman(pf_handle* H, double* loglik_out, double* ell_out) {
   return PF_OK;
 }
 
+pf_status pf_kalman_pmmh(pf_handle* H, const pf_wk_mh* spec, int32_t iters,
+                         const double* d_theta0, const double* d_prop, const double* d_alpha,
+                         double* d_theta_trace, double* d_ll_trace, int32_t* d_accepts,
+                         double* d_ll0) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  const pf_config& c = H->cfg;
+  if (c.model != PF_MODEL_WK) return fail(PF_E_INVAL, "pf_kalman_pmmh needs the windkessel model");
+  if (!spec) return fail(PF_E_INVAL, "spec is NULL");
+  auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
+  auto nonneg = [](double v) { return std::isfinite(v) && v >= 0.0; };
+  for (int k = 0; k < 3; ++k)
+    if (!pos(spec->prior_shape[k]) || !pos(spec->prior_scale[k]) || !nonneg(spec->step_sd[k]))
+      return fail(PF_E_INVAL, "prior shape/scale of parameter %d must be > 0, step sd >= 0", k);
+  if (!pos(spec->ig_shape) || !pos(spec->ig_scale))
+    return fail(PF_E_INVAL, "Inverse-Gamma prior shape and scale must be > 0");
+  if (!nonneg(spec->ig_prop_factor) || (spec->ig_prop_factor > 0.0 && !pos(spec->ig_prop_shape)))
+    return fail(PF_E_INVAL, "sigma^2 proposal factor must be >= 0 and its shape > 0");
+  if (!std::isfinite(spec->m0) || !nonneg(spec->s0))
+    return fail(PF_E_INVAL, "m0 must be finite and s0 >= 0");
+  if (iters < 0) return fail(PF_E_INVAL, "iters < 0");
+  if (!d_theta0 || !d_accepts) return fail(PF_E_INVAL, "NULL argument");
+  if (iters > 0 && (!d_prop || !d_alpha || !d_theta_trace || !d_ll_trace))
+    return fail(PF_E_INVAL, "NULL argument");
+  const void* ptrs[] = {d_theta0, d_prop, d_alpha, d_theta_trace, d_ll_trace, d_ll0};
+  for (const void* p : ptrs)
+    if (((uintptr_t)p & 7) != 0) return fail(PF_E_INVAL, "arrays must be 8-byte aligned");
+  if (((uintptr_t)d_accepts & 3) != 0) return fail(PF_E_INVAL, "accepts must be 4-byte aligned");
+  pfk::KfArgs K{};
+  K.B = c.B;
+  K.K = c.K;
+  K.T = c.T;
+  K.R = c.obs_sd * c.obs_sd;
+  K.q = H->at<double>(H->L.q);
+  K.obs = H->at<double>(H->L.obs);
+  HIP_TRY(pfk::launch_kf_pmmh(K, *spec, c.h, iters, d_theta0, d_prop, d_alpha, d_theta_trace,
+                              d_ll_trace, d_accepts, d_ll0, H->stream));
+  err_clear();
+  return PF_OK;
+}
+
 size_t pf_history_bytes(const pf_config* cfg) {
   if (validate(cfg) != PF_OK) return 0;
   return hist_layout(cfg, make_layout(cfg).n_total).total;

@@ -144,3 +144,11 @@ def test_systematic_arguments_checked_on_the_host():
         st = L.pf_systematic(*args, None)
         assert st == binding.PF_E_INVAL, (args, st)
         assert msg in _msg(), (msg, _msg())
+
+
+def test_kalman_pmmh_needs_a_handle():
+    L = binding.load()
+    spec = binding.wk_mh_struct(W.WkMh())
+    fake = C.c_void_p(0x10000)  # never dereferenced: the handle check fails first
+    st = L.pf_kalman_pmmh(None, C.byref(spec), 1, fake, fake, fake, fake, fake, fake, None)
+    assert st == binding.PF_E_INVAL, st

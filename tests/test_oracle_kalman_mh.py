@@ -17,8 +17,6 @@ than the chain code itself:
   posterior mean by quadrature of prior x Kalman likelihood;
 * with every step switched off every move is accepted (the ratio is 1).
 """
-import dataclasses
-
 import numpy as np
 import pytest
 import scipy.integrate

@@ -271,6 +271,8 @@ def large_filter_leg(torch, pfm, stream):
     dtb = timed(torch, rb, 20, 2)
     _, ess_b, _ = fb.loglik()
     variants = {}
+    # (rejection resampling is left out here: with an ESS of a few particles
+    # out of 2^20 each output needs ~N w_max / sum w ~ 1e5 attempts)
     for name, scheme, msteps in (("stratified", 1, 0), ("multinomial", 3, 0),
                                  ("metropolis_8", 2, 8)):
         fb.set_resampler(scheme, msteps)
@@ -284,6 +286,13 @@ def large_filter_leg(torch, pfm, stream):
     rs.run(3)
     ks = kernel_times(rs, 10)
     _, ess_s, _ = fs.loglik()
+    variants_spread = {}
+    for name, scheme, msteps in (("stratified", 1, 0), ("multinomial", 3, 0),
+                                 ("metropolis_8", 2, 8), ("rejection", 4, 0)):
+        fs.set_resampler(scheme, msteps)
+        rs.restart()
+        kv = kernel_times(rs, 10)
+        variants_spread[name] = {"resample_gather_us": kv["scan"] + kv["gather"]}
     fs.close()
     nb = int(big.n_particles[0])
     rg = resample_gather_hbm(kb, big.d, nb)
@@ -308,9 +317,12 @@ def large_filter_leg(torch, pfm, stream):
                                       "frac": sl_b / VALU_PEAK_TOPS}},
         "combine_us": kb["combine"],
         "resample_variants": variants,
+        "resample_variants_spread_weights": variants_spread,
     }
     log("[bench] large filter resample+gather variants (us): " +
-        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants.items()))
+        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants.items()) +
+        "; spread weights: " +
+        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants_spread.items()))
     log(f"[bench] large filter: resample+gather {rg['us']:.1f} us = {rg['achieved']:.0f} GB/s "
         f"({rg['frac']:.0%}, ESS {rg['ess_last_step']:.3g}); spread weights {rgs['us']:.1f} us = "
         f"{rgs['achieved']:.0f} GB/s ({rgs['frac']:.0%}, ESS {rgs['ess_last_step']:.3g}); "
@@ -321,22 +333,30 @@ def large_filter_leg(torch, pfm, stream):
 
 RESAMPLER_CASES = [("systematic", 0, 0, float("inf")), ("stratified", 1, 0, float("inf")),
                    ("multinomial", 3, 0, float("inf")), ("metropolis_8", 2, 8, float("inf")),
-                   ("systematic_ess0.5", 0, 0, 0.5)]
+                   ("rejection", 4, 0, float("inf")), ("systematic_ess0.5", 0, 0, 0.5)]
+# rejection resampling costs ~N attempts per output in a collapsed filter
+# (about a quarter of this workload's filters): time only the first
+# intervals after one eight-interval warm-up
+REJECTION_STEPS, REJECTION_WARMUP = 40, 8
 
 
 def resampler_leg(torch, pfm, pb, stream, threads, groups, steps=200):
     """Interval time of the batched workload (fast FP32 form, graph replay)
-    with each resampling variant, after a whole warm-up pass."""
+    with each resampling variant, after a whole warm-up pass (rejection
+    resampling: 40 intervals after 8)."""
     out = {}
     for name, scheme, msteps, frac in RESAMPLER_CASES:
         f = pfm.Filter(pb, precision=W.FP32_MIXED, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
         f.set_tuning(threads, groups)
         f.set_resampler(scheme, msteps, frac)
         r = Runner(f, pb.T)
-        dt = timed(torch, r, steps, pb.T)
+        n, w = (REJECTION_STEPS, REJECTION_WARMUP) if scheme == 4 else (steps, pb.T)
+        dt = timed(torch, r, n, w)
         f.close()
-        out[name] = {"us_per_interval": dt / steps * 1e6,
-                     "particle_steps_per_s": int(pb.n_particles.sum()) * steps / dt}
+        out[name] = {"us_per_interval": dt / n * 1e6,
+                     "particle_steps_per_s": int(pb.n_particles.sum()) * n / dt}
+        if scheme == 4:
+            out[name]["intervals"] = f"{w + 1}-{w + n}"
     log("[bench] resamplers (batched, us/interval): " +
         ", ".join(f"{k} {v['us_per_interval']:.1f}" for k, v in out.items()))
     return out

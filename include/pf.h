@@ -263,6 +263,16 @@ pf_status pf_kalman_pmmh(pf_handle* h, const pf_wk_mh* spec, int32_t iters,
  *     r = (s-1) mod 2, of the generator at (k, t, tag 3 | block
  *     2 + (s-1) div 2 | iteration, b).  No scan or counts; unsorted; tends
  *     to multinomial resampling as steps grows.
+ *   PF_RESAMPLE_REJECTION: needs the largest log-weight M but no scan:
+ *     output k tries candidates j, k first, then floor(w N 2^-32) for fresh
+ *     words w, accepting the first with ln u <= lw_j - M (the same ln);
+ *     attempts 2p and 2p+1 use words (0, 1) and (2, 3) of the generator at
+ *     (k, t + (p div 256) 2^20, tag 11 | block p mod 256 | iteration, b)
+ *     (needs T < 2^20).  Each output is k with probability w_k/w_max +
+ *     (1 - w_k/w_max) W_k, else j with (1 - w_k/w_max) W_j: unbiased
+ *     offspring counts.  The expected number of attempts per output is
+ *     N w_max / sum w (up to N for a collapsed filter); after 2^21 attempts
+ *     the output keeps k.  Unsorted.
  *   PF_RESAMPLE_MULTINOMIAL (Alg. 2's own): independent uniforms u_k (word
  *     k mod 4 of the generator at (k div 4, t, tag 10 | iteration, b)),
  *     a_k = min{j : W_j > u_k S} by binary search of the cumulative weights;
@@ -277,6 +287,7 @@ pf_status pf_kalman_pmmh(pf_handle* h, const pf_wk_mh* spec, int32_t iters,
 #define PF_RESAMPLE_STRATIFIED 1
 #define PF_RESAMPLE_METROPOLIS 2
 #define PF_RESAMPLE_MULTINOMIAL 3
+#define PF_RESAMPLE_REJECTION 4
 #define PF_METROPOLIS_MAX_STEPS 508
 pf_status pf_set_resampler(pf_handle* h, int32_t scheme, int32_t steps, double ess_frac);
 

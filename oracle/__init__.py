@@ -24,6 +24,7 @@ _lib = None
 ORC_OK = 0
 ORC_NUMERIC = 4
 TAG_INIT, TAG_NOISE, TAG_RESAMPLE, TAG_DATA, TAG_OBS, TAG_PATH, TAG_MULTI = 1, 2, 3, 4, 8, 9, 10
+TAG_REJECT = 11
 
 
 def build(force: bool = True) -> str:
@@ -120,6 +121,10 @@ def lib():
                                                  _I]),
             "orc_metropolis_ancestors": (None, [C.c_int64, _D, C.c_int32, C.c_uint64,
                                                 C.c_int32, C.c_uint32, C.c_uint32, _I]),
+            "orc_reject_pair": (None, [C.c_uint64, C.c_int32, C.c_uint32, C.c_uint32, C.c_int64,
+                                       C.c_int64, C.c_int64, C.POINTER(C.c_int64), _D]),
+            "orc_rejection_ancestors": (None, [C.c_int64, _D, C.c_uint64, C.c_int32, C.c_uint32,
+                                               C.c_uint32, _I]),
             "orc_pf_run_ex": (C.c_int32, [P, _D, C.c_int64, C.c_uint32, C.c_uint32, C.c_int32,
                                           C.c_int32, C.c_int32, C.c_double, _D, _D, _D, _I,
                                           _D, _I, _D]),
@@ -431,6 +436,7 @@ def pf_path(pb, theta=None, N=None, b=0, it=0, T=None):
 
 
 RESAMPLE_SYSTEMATIC, RESAMPLE_STRATIFIED, RESAMPLE_METROPOLIS, RESAMPLE_MULTINOMIAL = 0, 1, 2, 3
+RESAMPLE_REJECTION = 4
 
 
 def strat_u(seed, t, b, it, k) -> float:
@@ -459,6 +465,21 @@ def metropolis_ancestors(lw, steps, seed, t, b=0, it=0):
     a = np.zeros(lw.shape[0], dtype=np.int32)
     lib().orc_metropolis_ancestors(lw.shape[0], _dp(lw), int(steps), int(seed), int(t), int(b),
                                    int(it), _ip(a))
+    return a
+
+
+def reject_pair(seed, t, b, it, k, r, N):
+    j, u = C.c_int64(), C.c_double()
+    lib().orc_reject_pair(int(seed), int(t), int(b), int(it), int(k), int(r), int(N),
+                          C.byref(j), C.byref(u))
+    return j.value, u.value
+
+
+def rejection_ancestors(lw, seed, t, b=0, it=0):
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    a = np.zeros(lw.shape[0], dtype=np.int32)
+    lib().orc_rejection_ancestors(lw.shape[0], _dp(lw), int(seed), int(t), int(b), int(it),
+                                  _ip(a))
     return a
 
 

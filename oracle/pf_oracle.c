@@ -885,6 +885,57 @@ void orc_metropolis_ancestors(int64_t N, const double* lw, int32_t steps, uint64
   }
 }
 
+/* The candidate j and uniform u of attempt r (0-based) of output k of the
+ * rejection resampler: attempts 2p and 2p+1 take words (0, 1) and (2, 3)
+ * of the generator at counter (k, t + (p div 256) 2^20, tag REJECT | block
+ * p mod 256 | iteration, b) (t < 2^20); the candidate is floor(w N 2^-32)
+ * of the first word, except at r = 0, where it is k itself; u is the
+ * uniform of the second word. */
+void orc_reject_pair(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k, int64_t r,
+                     int64_t N, int64_t* j, double* u) {
+  const uint64_t p = (uint64_t)r >> 1;
+  uint32_t ctr[4] = {(uint32_t)k, (uint32_t)t + (uint32_t)((p >> 8) << 20),
+                     ((uint32_t)ORC_TAG_REJECT << 28) | ((uint32_t)(p & 255) << 20) | iter, b};
+  uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  const int h = (int)(r & 1);
+  *j = (r == 0) ? k : (int64_t)(((uint64_t)w[2 * h] * (uint64_t)N) >> 32);
+  *u = orc_u01(w[2 * h + 1]);
+}
+
+/* Rejection resampling (a resampler that needs the maximum weight but no
+ * scan; of the family Sec. 3.3 cites as avoiding the collective): output k
+ * tries candidates j (k first, then uniform draws over 0..N-1) until one is
+ * accepted, attempt r accepting iff ln u_r <= lw_j - M with M the largest
+ * log-weight (own ln, so both sides decide alike; a NaN log-weight counts
+ * as -inf).  Every attempt after the first is an independent draw from
+ * the normalised weights conditioned on acceptance, so a_k = k with
+ * probability w_k/w_max + (1 - w_k/w_max) W_k and a_k = j != k with
+ * probability (1 - w_k/w_max) W_j: each output's offspring expectations
+ * are N W_j.  After ORC_REJECT_MAX_ATTEMPTS attempts without acceptance
+ * (probability at most (1 - 1/N)^(2^21)) the output keeps k.  Unsorted. */
+void orc_rejection_ancestors(int64_t N, const double* lw, uint64_t seed, int32_t t, uint32_t b,
+                             uint32_t iter, int32_t* a) {
+  double M = -INFINITY;
+  for (int64_t j = 0; j < N; ++j)
+    if (lw[j] > M) M = lw[j];
+  for (int64_t k = 0; k < N; ++k) {
+    int64_t out = k;
+    for (int64_t r = 0; r < ORC_REJECT_MAX_ATTEMPTS; ++r) {
+      int64_t j;
+      double u;
+      orc_reject_pair(seed, t, b, iter, k, r, N, &j, &u);
+      const double lj = (lw[j] == lw[j]) ? lw[j] : -INFINITY;
+      if (orc_ln(u) <= lj - M) {
+        out = j;
+        break;
+      }
+    }
+    a[k] = (int32_t)out;
+  }
+}
+
 /* Multinomial resampling, as Alg. 2 writes it: N independent uniforms,
  * u_k = the uniform of word k mod 4 of the generator at (k div 4, t, tag
  * MULTI | iteration, b), and a_k = min{ j : W_j > u_k S } (the inverse of
@@ -909,7 +960,7 @@ void orc_multinomial_ancestors(int64_t N, const double* W, double S, int64_t jst
 }
 
 /* Alg. 2 with a choice of resampler (0 systematic, 1 stratified, 2
- * Metropolis with `steps` moves, 3 multinomial) and resampling only when ESS < ess_frac N
+ * Metropolis with `steps` moves, 3 multinomial, 4 rejection) and resampling only when ESS < ess_frac N
  * (ess_frac = +inf: every time).  Without resampling the log-weights carry
  * over: the time-t weights are carry + lw_t, the likelihood factor is
  * ln sum exp(carry + lw_t) - ln sum exp(carry) (ln N after a resampling),
@@ -962,6 +1013,8 @@ int32_t orc_pf_run_ex(const orc_problem* P, const double* theta, int64_t N, uint
           orc_metropolis_ancestors(N, lw, steps, P->seed, t, b, iter, a);
         } else if (resampler == 3) {
           orc_multinomial_ancestors(N, W, S, jstar, P->seed, t, b, iter, a);
+        } else if (resampler == 4) {
+          orc_rejection_ancestors(N, lw, P->seed, t, b, iter, a);
         } else {
           const double u = orc_resample_u(P->seed, t, b, iter), Nd = (double)N;
           int64_t j = 0;

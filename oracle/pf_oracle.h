@@ -30,7 +30,9 @@ extern "C" {
 
 enum { ORC_MODEL_WK = 1, ORC_MODEL_L96 = 2, ORC_MODEL_L96_STAGE = 3 };
 enum { ORC_TAG_INIT = 1, ORC_TAG_NOISE = 2, ORC_TAG_RESAMPLE = 3, ORC_TAG_DATA = 4,
-       ORC_TAG_OBS = 8, ORC_TAG_PATH = 9, ORC_TAG_MULTI = 10 };
+       ORC_TAG_OBS = 8, ORC_TAG_PATH = 9, ORC_TAG_MULTI = 10,
+       ORC_TAG_REJECT = 11 };
+#define ORC_REJECT_MAX_ATTEMPTS (1 << 21)
 enum { ORC_OK = 0, ORC_NUMERIC = 4 };
 
 typedef struct orc_problem {
@@ -102,6 +104,10 @@ void orc_stratified_ancestors(int64_t N, const double* W, double S, int64_t jsta
                               uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int32_t* a);
 void orc_metropolis_ancestors(int64_t N, const double* lw, int32_t steps, uint64_t seed,
                               int32_t t, uint32_t b, uint32_t iter, int32_t* a);
+void orc_reject_pair(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k, int64_t r,
+                     int64_t N, int64_t* j, double* u);
+void orc_rejection_ancestors(int64_t N, const double* lw, uint64_t seed, int32_t t, uint32_t b,
+                             uint32_t iter, int32_t* a);
 double orc_multi_u(uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int64_t k);
 void orc_multinomial_ancestors(int64_t N, const double* W, double S, int64_t jstar,
                                uint64_t seed, int32_t t, uint32_t b, uint32_t iter, int32_t* a);

@@ -22,6 +22,7 @@ PF_LAYOUT_PLAIN, PF_LAYOUT_BATCHED = 0, 1
 PF_BATCHED_MAX_PARTICLES = 8192
 PF_RESAMPLE_SYSTEMATIC, PF_RESAMPLE_STRATIFIED, PF_RESAMPLE_METROPOLIS = 0, 1, 2
 PF_RESAMPLE_MULTINOMIAL = 3
+PF_RESAMPLE_REJECTION = 4
 
 _STATUS = {1: "PF_E_INVAL", 2: "PF_E_DEVICE", 3: "PF_E_STATE", 4: "PF_E_NUMERIC"}
 

@@ -567,7 +567,7 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
       // redraw the marks (or cumulative weights) from the given uniform; the
       // step's marks are cleared first
       HIP_TRY(pfk::launch_set_u(a.fs, u[b], s));
-      if (H->rs.scheme != pfk::RS_METROPOLIS) {
+      if (H->rs.scheme != pfk::RS_METROPOLIS && H->rs.scheme != pfk::RS_REJECTION) {
         HIP_TRY(pfk::launch_fill_i32(H->at<int32_t>(H->L.marks) + a.off, a.N, -1, s));
         a.mode = 1;
         HIP_TRY(pfk::launch_scan_mark(H->at<double>(H->L.lw), H->at<double>(H->L.part),
@@ -582,6 +582,12 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
       HIP_TRY(pfk::launch_metropolis_gather(c.precision, H->at<double>(H->L.lw),
                                             H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
                                             H->at<int32_t>(H->L.anc), a, s));
+      if ((st = ev_end(H, e0, 3, s))) return st;
+    } else if (H->rs.scheme == pfk::RS_REJECTION) {
+      // the step's maximum, no scan: unsorted ancestors and a plain gather
+      HIP_TRY(pfk::launch_rejection_gather(c.precision, H->at<double>(H->L.lw),
+                                           H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
+                                           H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
     } else if (H->rs.scheme == pfk::RS_MULTINOMIAL) {
       // unsorted ancestors by search of the step's cumulative weights
@@ -1684,8 +1690,11 @@ pf_status pf_set_resampler(pf_handle* H, int32_t scheme, int32_t steps, double e
   pf_status st = check_handle(H);
   if (st) return st;
   if (scheme != PF_RESAMPLE_SYSTEMATIC && scheme != PF_RESAMPLE_STRATIFIED &&
-      scheme != PF_RESAMPLE_METROPOLIS && scheme != PF_RESAMPLE_MULTINOMIAL)
+      scheme != PF_RESAMPLE_METROPOLIS && scheme != PF_RESAMPLE_MULTINOMIAL &&
+      scheme != PF_RESAMPLE_REJECTION)
     return fail(PF_E_INVAL, "unknown resampler %d", scheme);
+  if (scheme == PF_RESAMPLE_REJECTION && H->cfg.T >= (1 << 20))
+    return fail(PF_E_INVAL, "rejection resampling needs T < 2^20 (its generator counters)");
   if (steps < 0 || steps > PF_METROPOLIS_MAX_STEPS)
     return fail(PF_E_INVAL, "steps must be in [0, %d]", PF_METROPOLIS_MAX_STEPS);
   if (!(ess_frac >= 0.0)) return fail(PF_E_INVAL, "ess_frac must be >= 0 (or +inf)");

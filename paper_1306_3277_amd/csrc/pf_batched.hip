@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     jstar = max(jstar, xi[w]);
   }
   // the ancestor slots start empty (the stage's weights have all been read;
-  // the Metropolis and multinomial forms still use the stage)
+  // the Metropolis, rejection and multinomial forms still use the stage)
   if constexpr (RS == RS_SYSTEMATIC || RS == RS_STRATIFIED)
     for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
   // exclusive running maximum of the lanes' last cumulative weights
@@ -401,6 +401,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
           }
         }
       }
+      anc[off + k] = j;
+      if (ha) ha[k] = j;
+    }
+    finish();
+    return;
+  }
+  if constexpr (RS == RS_REJECTION) {
+    // rejection resampling from the staged log-weights and their maximum,
+    // no counts or merge: output k tries k, then uniform candidates
+    const Key key = bkey(A.key);
+#pragma unroll 1
+    for (int k = (int)threadIdx.x; k < N; k += NT) {
+      int j = k;
+      if (draw_rs)
+        j = reject_ancestor(key, t, (uint32_t)f, iter, k, N, M,
+                            [&](int32_t i) { return stage[stage_slot(i)]; });
       anc[off + k] = j;
       if (ha) ha[k] = j;
     }
@@ -637,6 +653,7 @@ hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const
     case RS_STRATIFIED: PF_K5B(NTV, RS_STRATIFIED); break;    \
     case RS_METROPOLIS: PF_K5B(NTV, RS_METROPOLIS); break;    \
     case RS_MULTINOMIAL: PF_K5B(NTV, RS_MULTINOMIAL); break;  \
+    case RS_REJECTION: PF_K5B(NTV, RS_REJECTION); break;      \
     default: return hipErrorInvalidValue;                     \
   }
   switch (nt) {

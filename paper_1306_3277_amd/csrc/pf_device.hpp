@@ -13,7 +13,7 @@
 namespace pfk {
 
 enum : uint32_t { TAG_INIT = 1, TAG_NOISE = 2, TAG_RESAMPLE = 3, TAG_DATA = 4, TAG_OBS = 8,
-                  TAG_MULTI = 10 };
+                  TAG_MULTI = 10, TAG_REJECT = 11 };
 constexpr int WAVE = 64;
 
 // ---------------------------------------------------------------- generator
@@ -800,6 +800,38 @@ __device__ __forceinline__ double multi_u(Key key, int32_t t, uint32_t b, uint32
 
 __device__ __forceinline__ int32_t metro_index(uint32_t w, int32_t N) {
   return (int32_t)(((uint64_t)w * (uint64_t)N) >> 32);
+}
+
+// Rejection resampling: attempts 2p and 2p+1 of output k take words (x, y)
+// and (z, w) of the generator at (k, t + (p div 256) 2^20, tag REJECT |
+// block p mod 256 | iteration, b) (t < 2^20): a candidate floor(w N 2^-32)
+// from the first word of each pair (attempt 0's candidate is k itself) and
+// a uniform from the second.  At most REJECT_MAX_ATTEMPTS attempts.
+constexpr int64_t REJECT_MAX_ATTEMPTS = int64_t(1) << 21;
+__device__ __forceinline__ uint4 reject_draw(Key key, int32_t t, uint32_t b, uint32_t iter,
+                                             int32_t k, uint32_t p) {
+  return draw(key, TAG_REJECT, p & 255u, iter, (uint32_t)k, (uint32_t)t + ((p >> 8) << 20), b);
+}
+
+// Output k's ancestor by rejection: candidates until ln u <= lw_j - M (M
+// the largest log-weight); a NaN log-weight counts as -inf.  `lwj(j)` reads
+// log-weight j.  After REJECT_MAX_ATTEMPTS attempts the output keeps k.
+template <class LW>
+__device__ __forceinline__ int32_t reject_ancestor(Key key, int32_t t, uint32_t b, uint32_t iter,
+                                                   int32_t k, int32_t N, double M, LW lwj) {
+#pragma unroll 1
+  for (uint32_t p = 0; p < (uint32_t)(REJECT_MAX_ATTEMPTS >> 1); ++p) {
+    const uint4 w = reject_draw(key, t, b, iter, k, p);
+    int32_t c = p == 0 ? k : metro_index(w.x, N);
+    double lc = lwj(c);
+    lc = (lc == lc) ? lc : -INFINITY;
+    if (ln_f64(u01_f64(w.y)) <= lc - M) return c;
+    c = metro_index(w.z, N);
+    lc = lwj(c);
+    lc = (lc == lc) ? lc : -INFINITY;
+    if (ln_f64(u01_f64(w.w)) <= lc - M) return c;
+  }
+  return k;
 }
 
 }  // namespace pfk

@@ -26,7 +26,8 @@ struct FilterState {
 };
 
 // Resampling variants: the ancestors of a resampling time.
-enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2, RS_MULTINOMIAL = 3 };
+enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2, RS_MULTINOMIAL = 3,
+                 RS_REJECTION = 4 };
 
 // How a filter resamples: the variant, its Metropolis moves, and the ESS
 // trigger (resample when ESS < ess_frac N; +inf: every time).
@@ -152,6 +153,8 @@ hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const 
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
 hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
                                    int32_t* anc, const PlainArgs& a, hipStream_t s);
+hipError_t launch_rejection_gather(int prec, const double* lw, const void* xprop, void* xcur,
+                                  int32_t* anc, const PlainArgs& a, hipStream_t s);
 hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* jc,
                                      const void* xprop, void* xcur, int32_t* anc,
                                      const PlainArgs& a, hipStream_t s);

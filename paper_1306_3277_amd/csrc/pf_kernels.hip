@@ -616,7 +616,8 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
     lo_off = bo[k1b];
     hi_off = bo[min(k1b + K3_SPAN / K1_NT, A.nblk)];
   }
-  if (A.rs.scheme == RS_METROPOLIS) return;  // no cumulative weights needed
+  // no cumulative weights needed
+  if (A.rs.scheme == RS_METROPOLIS || A.rs.scheme == RS_REJECTION) return;
   // a step that keeps its weights (ESS above the trigger) or has none
   // positive gives every particle one offspring: itself
   const bool finite = pos && !carry;
@@ -897,6 +898,26 @@ __global__ __launch_bounds__(K1_NT) void k_metropolis(const double* __restrict__
   anc[A.off + k] = j;
 }
 
+// ---------------------------------------------------------------- rejection resampling
+// Needs the largest log-weight (from the step's reduction) but no scan:
+// output k tries candidates, k first, then uniform draws, until one passes
+// ln u <= lw_j - M.  A step that keeps its weights, or has none positive,
+// gives the identity.
+__global__ __launch_bounds__(K1_NT) void k_rejection(const double* __restrict__ lw,
+                                                     int32_t* __restrict__ anc, PlainArgs A) {
+  const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
+  if (k >= A.N) return;
+  const FilterState* f = A.fs;
+  const double M = f->M;
+  const bool draw_rs = (M > -INFINITY) && (M < INFINITY) && (f->S > 0.0) && !f->carry;
+  const double* l = lw + A.off;
+  int32_t j = (int32_t)k;
+  if (draw_rs)
+    j = reject_ancestor(key_of(A.key), f->t, A.b, f->iter, (int32_t)k, (int32_t)A.N, M,
+                        [&](int32_t i) { return l[i]; });
+  anc[A.off + k] = j;
+}
+
 // Multinomial resampling, as Alg. 2 writes it: output k takes
 // a_k = min{j : W_j > u_k S} for an independent uniform u_k, by binary
 // search of the cumulative weights K3 left (exactly non-decreasing);
@@ -1142,6 +1163,19 @@ hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xpro
                                    int32_t* anc, const PlainArgs& a, hipStream_t s) {
   const unsigned g = nblocks(a.N, K1_NT);
   hipLaunchKernelGGL(k_metropolis, g, K1_NT, 0, s, lw, anc, a);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
+                       (double*)xcur, (const int32_t*)anc, a);
+  else
+    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
+                       (const int32_t*)anc, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rejection_gather(int prec, const double* lw, const void* xprop, void* xcur,
+                                  int32_t* anc, const PlainArgs& a, hipStream_t s) {
+  const unsigned g = nblocks(a.N, K1_NT);
+  hipLaunchKernelGGL(k_rejection, g, K1_NT, 0, s, lw, anc, a);
   if (prec == 0)
     hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
                        (double*)xcur, (const int32_t*)anc, a);

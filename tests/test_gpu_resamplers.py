@@ -2,8 +2,8 @@
 with the oracle, through the C ABI, FP64, plain and batched layouts:
 log-weights (carried ones included) bit for bit at every time, likelihood
 increments within 1e-10 relative, ESS within 1e-9; ancestors bit for bit
-(Metropolis resampling decides on bit-identical log-weights with the same
-logarithm; stratified and multinomial resampling compare FP64 sums taken in
+(Metropolis and rejection resampling decide on bit-identical log-weights
+with the same logarithm; stratified and multinomial resampling compare FP64 sums taken in
 another order, so a flip within 1e-9 of an edge would be legitimate and is
 checked); final particles bit for bit."""
 import dataclasses
@@ -103,7 +103,9 @@ CASES = [(oracle.RESAMPLE_STRATIFIED, 0, float("inf")),
          (oracle.RESAMPLE_STRATIFIED, 0, 0.5),
          (oracle.RESAMPLE_METROPOLIS, 4, 0.5),
          (oracle.RESAMPLE_MULTINOMIAL, 0, float("inf")),
-         (oracle.RESAMPLE_MULTINOMIAL, 0, 0.5)]
+         (oracle.RESAMPLE_MULTINOMIAL, 0, 0.5),
+         (oracle.RESAMPLE_REJECTION, 0, float("inf")),
+         (oracle.RESAMPLE_REJECTION, 0, 0.5)]
 
 
 @pytest.mark.parametrize("scheme,steps,ess_frac", CASES)
@@ -133,12 +135,22 @@ def test_lorenz96_plain_stratified(pfm):
            float("inf"))
 
 
+def test_lorenz96_plain_rejection(pfm):
+    """Rejection resampling on a larger filter whose weights are far from
+    even (many attempts per output)."""
+    base = W.lorenz96(d=8, N=5000, T=5)
+    _, y = oracle.simulate(base)
+    refs = _check(pfm, base.with_obs(y), pfm.PF_LAYOUT_PLAIN, oracle.RESAMPLE_REJECTION, 0,
+                  float("inf"))
+    assert min(refs[0]["ess"]) < 500
+
+
 def test_variant_rules(pfm):
     base = W.lorenz96(d=8, N=64, T=3)
     _, y = oracle.simulate(base)
     pb = base.with_obs(y)
     f = pfm.Filter(pb, precision=pfm.PF_FP64)
-    for bad in [(4, 0, 1.0), (0, -1, 1.0), (2, 509, 1.0), (0, 0, -0.5), (0, 0, float("nan"))]:
+    for bad in [(5, 0, 1.0), (0, -1, 1.0), (2, 509, 1.0), (0, 0, -0.5), (0, 0, float("nan"))]:
         with pytest.raises(pfm.PfError):
             f.set_resampler(*bad)
     f.set_resampler(pfm.PF_RESAMPLE_STRATIFIED)
@@ -151,6 +163,18 @@ def test_variant_rules(pfm):
     for graph in (False, True):
         g = pfm.Filter(pb, precision=pfm.PF_FP64, layout=pfm.PF_LAYOUT_BATCHED)
         g.set_resampler(pfm.PF_RESAMPLE_METROPOLIS, 6, 0.7)
+        if graph:
+            g.graph_run(pb.T)
+        else:
+            g.advance(pb.T)
+        outs.append((g.trace()[0], g.get_state()))
+        g.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    outs = []
+    for graph in (False, True):
+        g = pfm.Filter(pb, precision=pfm.PF_FP64, layout=pfm.PF_LAYOUT_BATCHED)
+        g.set_resampler(pfm.PF_RESAMPLE_REJECTION, 0, float("inf"))
         if graph:
             g.graph_run(pb.T)
         else:

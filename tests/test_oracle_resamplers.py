@@ -14,6 +14,12 @@ collective over the weights) and for resampling triggered by the ESS:
 * Metropolis resampling: no moves is the identity; equal weights give
   uniform ancestors; with many moves the offspring mean approaches N w_j
   (the chain's stationary law), which a reversed acceptance test fails;
+* rejection resampling: equal weights keep every particle in place, one
+  positive weight takes every output; the attempts are the generator's words
+  at their stated counters (also past 512 attempts); each output's law is
+  w_k/w_max on staying plus (1 - w_k/w_max) W_j on every j (a reversed or
+  missing acceptance test fails), NaN weights are never taken, and the
+  filter is unbiased for the Kalman likelihood;
 * ESS-triggered resampling: never resampling is sequential importance
   sampling (likelihood = logsumexp of the accumulated log-weights - ln N,
   identity ancestors, particles never gathered); the resampling flags follow
@@ -201,6 +207,66 @@ def test_multinomial_filter_unbiased_against_kalman(orc):
     ll_kf, _ = orc.kf_wk(pb)
     R = 200
     lls = np.array([orc.pf_run_ex(dataclasses.replace(pb, seed=s), resampler=3)["loglik"]
+                    for s in range(R)])
+    ratio = np.exp(lls - ll_kf)
+    assert abs(ratio.mean() - 1.0) < 4 * ratio.std(ddof=1) / math.sqrt(R) + 1e-3
+
+
+def test_rejection_limits(orc):
+    N = 300
+    np.testing.assert_array_equal(orc.rejection_ancestors(np.full(N, -3.5), 4, 2), np.arange(N))
+    lw = np.full(N, -np.inf)
+    lw[217] = 1.0
+    np.testing.assert_array_equal(orc.rejection_ancestors(lw, 4, 2), np.full(N, 217))
+    lw = np.zeros(N)
+    lw[::3] = np.nan
+    a = orc.rejection_ancestors(lw, 4, 2)
+    assert np.all(a % 3 != 0)
+    keep = np.arange(N) % 3 != 0
+    np.testing.assert_array_equal(a[keep], np.arange(N)[keep])
+
+
+def test_rejection_attempts_are_the_generator_words(orc):
+    seed, t, b, it, N = 7, 13, 5, 3, 1000
+    for k, r in [(0, 0), (4, 1), (9, 2), (9, 3), (31, 511), (31, 512), (2, 600), (77, 70001)]:
+        p = r >> 1
+        w = orc.philox([k, t + ((p >> 8) << 20), (orc.TAG_REJECT << 28) | ((p & 255) << 20) | it, b],
+                       [seed, 0])
+        h = r & 1
+        j, u = orc.reject_pair(seed, t, b, it, k, r, N)
+        assert j == (k if r == 0 else (int(w[2 * h]) * N) >> 32)
+        assert u == orc.u01(int(w[2 * h + 1]))
+
+
+@pytest.mark.parametrize("weights", [[0.3, 0.7], [5, 1, 1, 1, 1, 1], [0.9, 0.01, 0.01, 0.08],
+                                     [1, 0, 0, 3, 0, 2]])
+def test_rejection_output_law(orc, weights):
+    """P(a_k = j) = [j = k] w_k/w_max + (1 - w_k/w_max) W_j, checked per output
+    over many times; the offspring mean is then N W_j."""
+    w = np.asarray(weights, dtype=np.float64)
+    N = w.size
+    with np.errstate(divide="ignore"):
+        lw = np.log(w)
+    R = 6000
+    a = np.array([orc.rejection_ancestors(lw, seed=12, t=t, b=1) for t in range(1, R + 1)])
+    Wn = w / w.sum()
+    for k in range(N):
+        p = (1.0 - w[k] / w.max()) * Wn
+        p[k] += w[k] / w.max()
+        f = np.bincount(a[:, k], minlength=N) / R
+        sd = np.sqrt(p * (1 - p) / R)
+        assert np.all(np.abs(f - p) <= 5 * sd + 1e-12), (k, f, p)
+    cnt = np.array([np.bincount(r, minlength=N) for r in a])
+    assert np.all(np.abs(cnt.mean(0) - N * Wn) <= 5 * cnt.std(0, ddof=1) / math.sqrt(R) + 1e-12)
+
+
+def test_rejection_filter_unbiased_against_kalman(orc):
+    pb = W.windkessel(N=128, T=30)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    ll_kf, _ = orc.kf_wk(pb)
+    R = 200
+    lls = np.array([orc.pf_run_ex(dataclasses.replace(pb, seed=s), resampler=4)["loglik"]
                     for s in range(R)])
     ratio = np.exp(lls - ll_kf)
     assert abs(ratio.mean() - 1.0) < 4 * ratio.std(ddof=1) / math.sqrt(R) + 1e-3

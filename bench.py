@@ -664,6 +664,8 @@ def main():
                     help="run only the history / state-sample leg (for kernel traces)")
     ap.add_argument("--profile-smc2", action="store_true",
                     help="run only the SMC^2 leg (for kernel traces)")
+    ap.add_argument("--pmmh-tuning", default="",
+                    help="collective lanes,groups for --profile-pmmh (default: autotune)")
     ap.add_argument("--profile-pmmh", action="store_true",
                     help="run only PMMH on the chains' shape, 512 lanes / 2 groups "
                          "(for kernel traces; --pmmh-iters sets its length)")
@@ -723,16 +725,21 @@ def main():
         if args.profile_plain.endswith("_spread"):
             pp = dataclasses.replace(pp, obs_sd=20.0)
         fp = pfm.Filter(pp, stream=stream)
-        fp.graph_run(5)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fp.graph_run(40)
-        torch.cuda.synchronize()
-        dtp = time.perf_counter() - t0
+        # five timed passes of 40 intervals after a warm-up pass; the fastest
+        n = min(40, pp.T)
+        fp.graph_run(n)
+        passes = []
+        for _ in range(5):
+            fp.reset(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fp.graph_run(n)
+            torch.cuda.synchronize()
+            passes.append((time.perf_counter() - t0) / n * 1e6)
         _, essp, _ = fp.loglik(allow_numeric=True)
         fp.close()
-        print(json.dumps({"profile_plain": args.profile_plain, "us_per_interval": dtp / 40 * 1e6,
-                          "ess_last": float(essp[0])}), flush=True)
+        print(json.dumps({"profile_plain": args.profile_plain, "us_per_interval": min(passes),
+                          "passes_us": passes, "ess_last": float(essp[0])}), flush=True)
         return
 
     # ---------------------------------------------------------------- headline
@@ -756,16 +763,31 @@ def main():
     if args.profile_pmmh:
         pm = W.config("lorenz96_d8_chains").with_obs(y)
         fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
-        fm.set_tuning(512, 2)
+        if args.pmmh_tuning:
+            th, gr = (int(v) for v in args.pmmh_tuning.split(","))
+            table = None
+        else:
+            th, gr, table = autotune(fm, pm.T - 1)
+        fm.set_tuning(th, gr)
+        # the same filters without the chain layer: whole passes (reset,
+        # T intervals, likelihoods read back) and bare interval replay
+        dtp = timed_passes(torch, fm, pm.T, 10, 2)
+        rp = Runner(fm, pm.T)
+        rp.restart()
+        dti = timed(torch, rp, 400, pm.T)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fm.pmmh(W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters))
         torch.cuda.synchronize()
         dtm = time.perf_counter() - t0
         fm.close()
-        print(json.dumps({"profile_pmmh": {"iterations": args.pmmh_iters,
-                                           "filters_per_s": pm.B * (args.pmmh_iters + 1) / dtm}}),
-              flush=True)
+        print(json.dumps({"profile_pmmh": {
+            "iterations": args.pmmh_iters, "collective_workgroup": th, "filter_groups": gr,
+            "autotune_ms_per_interval": None if table is None else np.asarray(table).tolist(),
+            "filters_per_s": pm.B * (args.pmmh_iters + 1) / dtm,
+            "ms_per_iteration": dtm / (args.pmmh_iters + 1) * 1e3,
+            "ms_per_pass_without_chain": dtp / 10 * 1e3,
+            "us_per_interval_replay": dti / 400 * 1e6}}), flush=True)
         return
 
     head_prec = W.FP32_ACCURATE if args.headline_form == "accurate" else W.FP32_MIXED

@@ -221,7 +221,7 @@ struct pf_handle {
   // the number of filter groups stepped concurrently on their own streams
   int batch_nt = 256;
   int groups = 1;
-  std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt;
+  std::vector<int32_t> grp_chunk0, grp_nchunks, grp_order0, grp_nfilt, grp_maxn;
   // with G > 1 groups, group g's kernels run on side[g]; ev_a[0] forks the
   // side streams from the caller's, ev_b[g] joins group g back.  These
   // events are only ever recorded and waited on outside stream capture.
@@ -462,7 +462,8 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
   pf_status st = ev_begin(H, &e0, s);
   if (st) return st;
   HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                       H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g], s));
+                                       H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g],
+                                       H->grp_maxn[g], s));
   return ev_end(H, e0, 4, s);
 }
 
@@ -552,8 +553,9 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_u, u, 8 * (size_t)c.B, hipMemcpyHostToDevice, s));
     BatchArgs a = batch_args(H);
     a.mode = 1;
+    const int32_t max_n = (int32_t)*std::max_element(H->np.begin(), H->np.end());
     HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                         H->at<int32_t>(H->L.anc), a, c.B, s));
+                                         H->at<int32_t>(H->L.anc), a, c.B, max_n, s));
     pf_status st = record_all(H, 0, s);  // the redrawn ancestors
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));  // u is a host array
@@ -657,6 +659,7 @@ pf_status build_groups(pf_handle* H, int G) {
   H->grp_nchunks.assign(G, 0);
   H->grp_order0.assign(G, 0);
   H->grp_nfilt.assign(G, 0);
+  H->grp_maxn.assign(G, 1);
   // Collective slots: the first one-per-CU slots take the largest filters,
   // and the slots beyond them (which share a CU with those) take the rest
   // smallest first, so the largest filters share their CU with the smallest.
@@ -677,6 +680,7 @@ pf_status build_groups(pf_handle* H, int G) {
       }
     }
     H->grp_nfilt[g] = (int32_t)ord.size() - H->grp_order0[g];
+    if (m > 0) H->grp_maxn[g] = (int32_t)H->np[mg[0]];  // members are largest first
     H->grp_nchunks[g] = (int32_t)chf.size() - H->grp_chunk0[g];
   }
   HIP_TRY(hipMemcpyAsync(H->ws + H->L.b_order, ord.data(), sizeof(pfk::FilterSlot) * ord.size(),

@@ -233,13 +233,16 @@ __device__ __forceinline__ void lane_weights(const double* stage, int N, double 
   }
 }
 
-template <int NT, int RS>
+// MAXP bounds the particles per lane: the launcher picks the smallest of
+// BATCH_MAXN / NT, half and a quarter of it that covers the group's largest
+// filter, so the unrolled per-lane phases do no work for absent particles.
+template <int NT, int RS, int MAXP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 4 : 2, 8))) void k_batch_resample(const double* __restrict__ lw,
                                                        int32_t* __restrict__ anc,
                                                        BatchArgs A) {
-  constexpr int MAXP = BATCH_MAXN / NT;
+  static_assert(MAXP >= 1 && NT * MAXP <= BATCH_MAXN, "stage size");
   constexpr int NW = NT / WAVE;
-  __shared__ double stage[BATCH_MAXN];
+  __shared__ double stage[NT * MAXP];
   __shared__ double xa[NW], xs[NW], xb[NW], xc[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
@@ -643,18 +646,30 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
 }
 
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   int nfilters, hipStream_t s) {
+                                   int nfilters, int max_n, hipStream_t s) {
   if (nfilters <= 0) return hipSuccess;
+  if (max_n < 1 || max_n > BATCH_MAXN) return hipErrorInvalidValue;
   const unsigned g = (unsigned)nfilters;
-#define PF_K5B(NTV, RSV) hipLaunchKernelGGL((k_batch_resample<NTV, RSV>), g, NTV, 0, s, lw, anc, a)
-#define PF_K5B_RS(NTV)                                        \
-  switch (a.rs.scheme) {                                      \
-    case RS_SYSTEMATIC: PF_K5B(NTV, RS_SYSTEMATIC); break;    \
-    case RS_STRATIFIED: PF_K5B(NTV, RS_STRATIFIED); break;    \
-    case RS_METROPOLIS: PF_K5B(NTV, RS_METROPOLIS); break;    \
-    case RS_MULTINOMIAL: PF_K5B(NTV, RS_MULTINOMIAL); break;  \
-    case RS_REJECTION: PF_K5B(NTV, RS_REJECTION); break;      \
-    default: return hipErrorInvalidValue;                     \
+  // the fraction of the full per-lane bound the group's largest filter needs
+  const int full = BATCH_MAXN / nt;
+  const int need = (max_n + nt - 1) / nt;
+  const int q = need * 4 <= full ? 4 : need * 2 <= full ? 2 : 1;
+#define PF_K5B(NTV, RSV, MP) \
+  hipLaunchKernelGGL((k_batch_resample<NTV, RSV, MP>), g, NTV, 0, s, lw, anc, a)
+#define PF_K5B_Q(NTV, RSV)                                  \
+  switch (q) {                                              \
+    case 4: PF_K5B(NTV, RSV, BATCH_MAXN / NTV / 4); break;  \
+    case 2: PF_K5B(NTV, RSV, BATCH_MAXN / NTV / 2); break;  \
+    default: PF_K5B(NTV, RSV, BATCH_MAXN / NTV); break;     \
+  }
+#define PF_K5B_RS(NTV)                                         \
+  switch (a.rs.scheme) {                                       \
+    case RS_SYSTEMATIC: PF_K5B_Q(NTV, RS_SYSTEMATIC); break;   \
+    case RS_STRATIFIED: PF_K5B_Q(NTV, RS_STRATIFIED); break;   \
+    case RS_METROPOLIS: PF_K5B_Q(NTV, RS_METROPOLIS); break;   \
+    case RS_MULTINOMIAL: PF_K5B_Q(NTV, RS_MULTINOMIAL); break; \
+    case RS_REJECTION: PF_K5B_Q(NTV, RS_REJECTION); break;     \
+    default: return hipErrorInvalidValue;                      \
   }
   switch (nt) {
     case 256:
@@ -670,6 +685,7 @@ hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const
       return hipErrorInvalidValue;
   }
 #undef PF_K5B_RS
+#undef PF_K5B_Q
 #undef PF_K5B
   return hipGetLastError();
 }

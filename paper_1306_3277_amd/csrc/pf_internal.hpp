@@ -167,7 +167,7 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
                                     const int32_t* anc, const BatchArgs& a, int nchunks,
                                     hipStream_t s);
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   int nfilters, hipStream_t s);
+                                   int nfilters, int max_n, hipStream_t s);
 hipError_t launch_batched_gather(int prec, const void* xprop, const int32_t* anc, void* xout,
                                  const BatchArgs& a, hipStream_t s);
 

@@ -123,11 +123,18 @@ def model_flop_per_particle_step(model: int, d: int, K: int, n_obs: int) -> int:
     return 30 * d * K + 4 * n_obs
 
 
-def resample_gather_bytes(d: int, sx: int, slw: int) -> int:
-    """Algorithmic HBM bytes per particle of one plain-layout resample +
-    gather: read the log-weight (scan), write and read the stratum count,
-    write the ancestor, read and write the d state components."""
-    return slw + 4 + 4 + 4 + 2 * d * sx
+def plain_propagate_bytes(d: int, sx: int, slw: int) -> int:
+    """Algorithmic HBM bytes per particle of one plain-layout propagation:
+    read the pending ancestor's d state components (the gather of the last
+    resampling) and write the d propagated ones and the log-weight; read
+    and clear the mark, write the ancestor."""
+    return 2 * d * sx + slw + 4 + 4 + 4
+
+
+def plain_scan_bytes(slw: int) -> int:
+    """Algorithmic HBM bytes per particle of the plain-layout scan: read the
+    log-weight, write at most one mark."""
+    return slw + 4
 
 
 class Runner:
@@ -242,34 +249,55 @@ def tf_summary(err, ell, ess, bound):
                        "ess": float(ess.ravel()[i])} for i in over[:max(3, min(n_over, 12))]]}
 
 
-def resample_gather_hbm(kt, d, n):
-    """Algorithmic-bytes HBM rate of one plain-layout resample + gather
-    (scan + counts, then the merge-path gather) from the kernels' mean
-    durations."""
-    us = kt["scan"] + kt["gather"]
-    byt = resample_gather_bytes(d, 4, 8)
+def plain_hbm(us, byt, n):
     gbs = byt * n / (us * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs / HBM_PEAK_GBS, "bytes_per_particle": byt, "us": us,
-            "scan_us": kt["scan"], "gather_us": kt["gather"]}
+            "frac": gbs / HBM_PEAK_GBS, "bytes_per_particle": byt, "us": us}
 
 
 def large_filter_leg(torch, pfm, stream):
-    """One Lorenz '96 (d = 40) filter of 2^20 particles, FP32 mixed: resample +
-    gather priced against HBM, propagation against the FP32 vector peak.  The
-    resample + gather is also measured with spread weights (an observation sd
-    of 20 on the same data: ESS near N, so the ancestors are nearly the
-    identity and the gather reads every particle's state from HBM rather
-    than a few heavy particles' from cache)."""
+    """One Lorenz '96 (d = 40) filter of 2^20 particles, FP32 mixed.  An
+    interval is three kernels: the propagation (which gathers the previous
+    interval's particles through the pending ancestors), the combine of its
+    4,096 block partials, and the scan that marks the new ancestors.  The
+    propagation is priced against the FP32 vector peak and against HBM (it
+    moves the state twice), the scan against HBM.  Also measured with spread
+    weights (an observation sd of 20 on the same data: ESS near N, so the
+    gather reads every particle's row rather than a few heavy particles'
+    from cache)."""
     big = W.config("lorenz96_d40_large")
     _, yb = pfm.simulate(big, stream=stream)
     big = big.with_obs(yb)
-    fb = pfm.Filter(big, stream=stream)
-    rb = Runner(fb, big.T)
-    rb.run(3)
-    kb = kernel_times(rb, 10)
-    dtb = timed(torch, rb, 20, 2)
-    _, ess_b, _ = fb.loglik()
+    nb = int(big.n_particles[0])
+    flop_b = model_flop_per_particle_step(big.model, big.d, big.K, big.n_obs)
+    slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
+
+    def measure(pb):
+        f = pfm.Filter(pb, stream=stream)
+        r = Runner(f, pb.T)
+        r.run(3)
+        kt = kernel_times(r, 10)
+        dt = timed(torch, r, 20, 2)
+        _, ess, _ = f.loglik()
+        ach = flop_b * nb / (kt["propagate"] * 1e-6) / 1e12
+        sl = slots_b * nb / (kt["propagate"] * 1e-6) / 1e12
+        out = {
+            "us_per_step": dt / 20 * 1e6, "particle_steps_per_s": nb * 20 / dt,
+            "ess_last_step": float(ess[0]),
+            "propagate": {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                          "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                          "us": kt["propagate"], "flop_per_particle_step": flop_b,
+                          "issue_slots": {"ops_per_particle_step": slots_b, "achieved": sl,
+                                          "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                                          "frac": sl / VALU_PEAK_TOPS},
+                          "hbm": plain_hbm(kt["propagate"], plain_propagate_bytes(big.d, 4, 8),
+                                           nb)},
+            "combine_us": kt["combine"],
+            "scan": plain_hbm(kt["scan"], plain_scan_bytes(8), nb),
+        }
+        return f, r, out
+
+    fb, rb, leg = measure(big)
     variants = {}
     # (rejection resampling is left out here: with an ESS of a few particles
     # out of 2^20 each output needs ~N w_max / sum w ~ 1e5 attempts)
@@ -278,56 +306,34 @@ def large_filter_leg(torch, pfm, stream):
         fb.set_resampler(scheme, msteps)
         rb.restart()
         kv = kernel_times(rb, 10)
-        variants[name] = {"resample_gather_us": kv["scan"] + kv["gather"]}
+        variants[name] = {"scan_us": kv["scan"], "ancestors_us": kv["gather"],
+                          "propagate_us": kv["propagate"]}
     fb.close()
     spread = dataclasses.replace(big, obs_sd=20.0)
-    fs = pfm.Filter(spread, stream=stream)
-    rs = Runner(fs, spread.T)
-    rs.run(3)
-    ks = kernel_times(rs, 10)
-    _, ess_s, _ = fs.loglik()
+    fs, rs, leg_s = measure(spread)
     variants_spread = {}
     for name, scheme, msteps in (("stratified", 1, 0), ("multinomial", 3, 0),
                                  ("metropolis_8", 2, 8), ("rejection", 4, 0)):
         fs.set_resampler(scheme, msteps)
         rs.restart()
         kv = kernel_times(rs, 10)
-        variants_spread[name] = {"resample_gather_us": kv["scan"] + kv["gather"]}
+        variants_spread[name] = {"scan_us": kv["scan"], "ancestors_us": kv["gather"],
+                                 "propagate_us": kv["propagate"]}
     fs.close()
-    nb = int(big.n_particles[0])
-    rg = resample_gather_hbm(kb, big.d, nb)
-    rg["ess_last_step"] = float(ess_b[0])
-    rgs = resample_gather_hbm(ks, big.d, nb)
-    rgs["ess_last_step"] = float(ess_s[0])
-    rgs["obs_sd"] = spread.obs_sd
-    flop_b = model_flop_per_particle_step(big.model, big.d, big.K, big.n_obs)
-    ach_b = flop_b * nb / (kb["propagate"] * 1e-6) / 1e12
-    slots_b = valu_slots_per_particle_step(big.model, big.d, big.K, big.n_obs, True)
-    sl_b = slots_b * nb / (kb["propagate"] * 1e-6) / 1e12
-    leg = {
-        "workload": big.name, "particles": nb, "us_per_step": dtb / 20 * 1e6,
-        "particle_steps_per_s": nb * 20 / dtb,
-        "resample_gather": rg,
-        "resample_gather_spread_weights": rgs,
-        "propagate": {"bound": "alu", "achieved": ach_b, "peak": FP32_PEAK_TFLOPS,
-                      "unit": "TFLOP/s", "frac": ach_b / FP32_PEAK_TFLOPS,
-                      "us": kb["propagate"], "flop_per_particle_step": flop_b,
-                      "issue_slots": {"ops_per_particle_step": slots_b, "achieved": sl_b,
-                                      "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
-                                      "frac": sl_b / VALU_PEAK_TOPS}},
-        "combine_us": kb["combine"],
-        "resample_variants": variants,
-        "resample_variants_spread_weights": variants_spread,
-    }
-    log("[bench] large filter resample+gather variants (us): " +
-        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants.items()) +
-        "; spread weights: " +
-        ", ".join(f"{k} {v['resample_gather_us']:.1f}" for k, v in variants_spread.items()))
-    log(f"[bench] large filter: resample+gather {rg['us']:.1f} us = {rg['achieved']:.0f} GB/s "
-        f"({rg['frac']:.0%}, ESS {rg['ess_last_step']:.3g}); spread weights {rgs['us']:.1f} us = "
-        f"{rgs['achieved']:.0f} GB/s ({rgs['frac']:.0%}, ESS {rgs['ess_last_step']:.3g}); "
-        f"propagate {kb['propagate']:.1f} us ({ach_b / FP32_PEAK_TFLOPS:.0%} of the FP32 peak, "
-        f"{sl_b / VALU_PEAK_TOPS:.0%} of VALU issue)")
+    leg_s["obs_sd"] = spread.obs_sd
+    leg.update({"workload": big.name, "particles": nb, "spread_weights": leg_s,
+                "resample_variants": variants,
+                "resample_variants_spread_weights": variants_spread})
+    fmt = lambda v: ", ".join(f"{k} {x['scan_us'] + x['ancestors_us']:.1f}"
+                              for k, x in v.items())
+    log("[bench] large filter resampling variants (scan + ancestor kernels, us): " +
+        fmt(variants) + "; spread weights: " + fmt(variants_spread))
+    for name, lg in (("workload", leg), ("spread", leg_s)):
+        p = lg["propagate"]
+        log(f"[bench] large filter ({name} weights, ESS {lg['ess_last_step']:.3g}): "
+            f"{lg['us_per_step']:.1f} us/interval; propagate+gather {p['us']:.1f} us "
+            f"({p['frac']:.0%} of the FP32 peak, {p['hbm']['achieved']:.0f} GB/s), combine "
+            f"{lg['combine_us']:.1f} us, scan {lg['scan']['us']:.1f} us")
     return leg
 
 

@@ -338,9 +338,12 @@ class Filter:
         def on_dev(a):
             if isinstance(a, torch.Tensor):
                 return a.to(device=dev, dtype=torch.float64).contiguous()
-            return torch.from_numpy(np.array(a, dtype=np.float64)).to(dev)  # a copy
+            # a row-major copy (a broadcast view would otherwise keep its strides)
+            return torch.from_numpy(np.array(a, dtype=np.float64, order="C")).to(dev)
 
         th0, pr, al = on_dev(theta0), on_dev(prop), on_dev(alpha)
+        if not (th0.is_contiguous() and pr.is_contiguous() and al.is_contiguous()):
+            raise ValueError("inputs must be row-major")
         iters = int(pr.shape[0]) if iters is None else int(iters)
         B = self.B
         if tuple(th0.shape) != (B, 4) or pr.shape[0] < iters or tuple(pr.shape[1:]) != (B, 4) \

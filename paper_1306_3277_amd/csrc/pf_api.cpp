@@ -384,16 +384,17 @@ pfk::HistArgs hist_args(const pf_handle* H) {
 }
 
 // Copy the current slot (the filters' step counters) into the history: the
-// particles x of every filter (plain layout: x is the given buffer; batched:
-// the buffer of the step's parity) and, past t_0, the ancestors.
-pf_status record_all(pf_handle* H, size_t x_plain, hipStream_t s) {
+// particles of every filter (the buffer of the step's parity) and, past
+// t_0, the ancestors (the plain layout records past t_0 from
+// enqueue_resample, once its ancestors are written out).
+pf_status record_all(pf_handle* H, hipStream_t s) {
   if (!H->hist) return PF_OK;
   const pf_config& c = H->cfg;
   const pfk::HistArgs ha = hist_args(H);
   if (c.layout == PF_LAYOUT_PLAIN) {
     for (int b = 0; b < c.B; ++b)
-      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + x_plain, H->at<int32_t>(H->L.anc), ha,
-                                       H->L.off[b], H->np[b],
+      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + H->L.x_cur, H->ws + H->L.x_tmp,
+                                       H->at<int32_t>(H->L.anc), ha, H->L.off[b], H->np[b],
                                        H->at<FilterState>(H->L.fs) + b, s));
   } else {
     BatchArgs a = batch_args(H);
@@ -409,6 +410,9 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
   HIP_TRY(pfk::launch_reset(H->at<FilterState>(H->L.fs), H->at<double>(H->L.ell),
                             H->at<double>(H->L.ess), c.B, c.T, H->iter, s));
   if (c.layout == PF_LAYOUT_PLAIN) {
+    // marks a previous run left pending are cleared (the pending ancestors
+    // are now the identity)
+    HIP_TRY(pfk::launch_fill_i32(H->at<int32_t>(H->L.marks), H->L.n_total, -1, s));
     for (int b = 0; b < c.B; ++b) {
       PlainArgs a = plain_args(H, b);
       HIP_TRY(pfk::launch_init(c.model, c.d, c.precision, H->ws + H->L.x_cur, a, s));
@@ -418,7 +422,7 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
     HIP_TRY(pfk::launch_batched_init(c.model, c.d, c.precision, H->ws + H->L.x_cur,
                                      H->at<int32_t>(H->L.anc), a, s));
   }
-  pf_status st = record_all(H, H->L.x_cur, s);
+  pf_status st = record_all(H, s);
   if (st) return st;
   H->t = 0;
   H->phase = 0;
@@ -522,7 +526,9 @@ pf_status enqueue_step(pf_handle* H, hipStream_t s) {
     if (st) return st;
     HIP_TRY(pfk::launch_propagate(c.model, c.d, c.precision, H->ws + H->L.x_cur,
                                   H->ws + H->L.x_tmp, H->ws + H->L.lw,
-                                  H->at<double>(H->L.part), a, s));
+                                  H->at<double>(H->L.part), H->at<int32_t>(H->L.marks),
+                                  H->at<int32_t>(H->L.owner), H->at<int32_t>(H->L.jc),
+                                  H->at<int32_t>(H->L.anc), a, s));
     if ((st = ev_end(H, e0, 0, s))) return st;
     // the collective: likelihood increment, ESS, trigger, and (unless
     // Metropolis) the cumulative weights' marks or, for multinomial, the
@@ -543,6 +549,17 @@ pf_status enqueue_step(pf_handle* H, hipStream_t s) {
   return PF_OK;
 }
 
+// Plain layout, filter b: the pending ancestors written out to the ancestor
+// array (from the marks when those are pending), which then become the
+// pending form.
+pf_status plain_anc_out(pf_handle* H, int b, hipStream_t s) {
+  PlainArgs a = plain_args(H, b);
+  HIP_TRY(pfk::launch_tile_anc(H->at<int32_t>(H->L.marks), H->at<int32_t>(H->L.owner),
+                               H->at<int32_t>(H->L.jc), H->at<int32_t>(H->L.anc), a, s));
+  HIP_TRY(pfk::launch_set_amode(a.fs, 1, pfk::AMODE_ARRAY, s));
+  return PF_OK;
+}
+
 pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
   const pf_config& c = H->cfg;
   if (c.layout == PF_LAYOUT_BATCHED) {
@@ -556,7 +573,7 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     const int32_t max_n = (int32_t)*std::max_element(H->np.begin(), H->np.end());
     HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
                                          H->at<int32_t>(H->L.anc), a, c.B, max_n, s));
-    pf_status st = record_all(H, 0, s);  // the redrawn ancestors
+    pf_status st = record_all(H, s);  // the redrawn ancestors
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));  // u is a host array
     return PF_OK;
@@ -578,35 +595,30 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
                                       s));
       }
     }
-    if ((st = ev_begin(H, &e0, s))) return st;
-    if (H->rs.scheme == pfk::RS_METROPOLIS) {
-      // no scan, counts or merge: unsorted ancestors and a plain gather
-      HIP_TRY(pfk::launch_metropolis_gather(c.precision, H->at<double>(H->L.lw),
-                                            H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
+    // The systematic and stratified ancestors stay as the collective's marks,
+    // which the next propagation reads (it gathers through them); the other
+    // resamplers write the ancestor array.  No state is copied here.
+    if (H->rs.scheme == pfk::RS_METROPOLIS || H->rs.scheme == pfk::RS_REJECTION ||
+        H->rs.scheme == pfk::RS_MULTINOMIAL) {
+      if ((st = ev_begin(H, &e0, s))) return st;
+      if (H->rs.scheme == pfk::RS_METROPOLIS)  // no scan, counts or merge
+        HIP_TRY(pfk::launch_metropolis_anc(H->at<double>(H->L.lw), H->at<int32_t>(H->L.anc), a,
+                                           s));
+      else if (H->rs.scheme == pfk::RS_REJECTION)  // the step's maximum, no scan
+        HIP_TRY(pfk::launch_rejection_anc(H->at<double>(H->L.lw), H->at<int32_t>(H->L.anc), a,
+                                          s));
+      else  // search of the step's cumulative weights
+        HIP_TRY(pfk::launch_multinomial_anc(a.wcum, H->at<int32_t>(H->L.jc),
                                             H->at<int32_t>(H->L.anc), a, s));
       if ((st = ev_end(H, e0, 3, s))) return st;
-    } else if (H->rs.scheme == pfk::RS_REJECTION) {
-      // the step's maximum, no scan: unsorted ancestors and a plain gather
-      HIP_TRY(pfk::launch_rejection_gather(c.precision, H->at<double>(H->L.lw),
-                                           H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
-                                           H->at<int32_t>(H->L.anc), a, s));
-      if ((st = ev_end(H, e0, 3, s))) return st;
-    } else if (H->rs.scheme == pfk::RS_MULTINOMIAL) {
-      // unsorted ancestors by search of the step's cumulative weights
-      HIP_TRY(pfk::launch_multinomial_gather(c.precision, a.wcum, H->at<int32_t>(H->L.jc),
-                                             H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
-                                             H->at<int32_t>(H->L.anc), a, s));
-      if ((st = ev_end(H, e0, 3, s))) return st;
-    } else {
-      HIP_TRY(pfk::launch_tile_gather(c.model, c.d, c.precision, H->at<int32_t>(H->L.marks),
-                                      H->at<int32_t>(H->L.owner), H->at<int32_t>(H->L.jc),
-                                      H->ws + H->L.x_tmp, H->ws + H->L.x_cur,
-                                      H->at<int32_t>(H->L.anc), a, s));
-      if ((st = ev_end(H, e0, 3, s))) return st;
+    } else if (H->hist) {
+      // the history keeps the ancestors: written out from the marks
+      if ((st = plain_anc_out(H, b, s))) return st;
     }
     if (H->hist)
-      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + H->L.x_tmp, H->at<int32_t>(H->L.anc),
-                                       hist_args(H), a.off, a.N, a.fs, s));
+      HIP_TRY(pfk::launch_record_plain(c.precision, H->ws + H->L.x_cur, H->ws + H->L.x_tmp,
+                                       H->at<int32_t>(H->L.anc), hist_args(H), a.off, a.N, a.fs,
+                                       s));
   }
   return PF_OK;
 }
@@ -1076,9 +1088,9 @@ pf_status pf_reset(pf_handle* H, uint32_t iteration) {
   return do_init(H, H->stream);
 }
 
-// Buffer holding the propagated state of the last step (batched layout: the
-// step-s state lives in buffer s % 2; buffer 0 holds x(t0)).
-static size_t batched_buf(const pf_handle* H, int32_t t) {
+// Buffer holding the propagated state of step t (both layouts: the step-t
+// state lives in buffer t % 2; buffer 0 holds x(t0)).
+static size_t state_buf(const pf_handle* H, int32_t t) {
   return (t & 1) ? H->L.x_tmp : H->L.x_cur;
 }
 
@@ -1087,16 +1099,26 @@ pf_status pf_get_state(pf_handle* H, double* x_out) {
   if (st) return st;
   if (!x_out) return fail(PF_E_INVAL, "x_out is NULL");
   const size_t n = (size_t)H->cfg.d * H->L.n_total;
-  size_t src = H->phase == 0 ? H->L.x_cur : H->L.x_tmp;
-  if (H->cfg.layout == PF_LAYOUT_BATCHED) {
-    src = batched_buf(H, H->t);
-    if (H->phase == 0) {  // equally weighted set = propagated[ancestors]
-      const size_t spare = batched_buf(H, H->t + 1);
+  // both layouts keep interval t's propagated particles in buffer t % 2
+  size_t src = state_buf(H, H->t);
+  if (H->phase == 0) {  // equally weighted set = propagated[ancestors]
+    const size_t spare = state_buf(H, H->t + 1);
+    if (H->cfg.layout == PF_LAYOUT_BATCHED) {
       BatchArgs a = batch_args(H);
       HIP_TRY(pfk::launch_batched_gather(H->cfg.precision, H->ws + src, H->at<int32_t>(H->L.anc),
                                          H->ws + spare, a, H->stream));
-      src = spare;
+    } else {
+      for (int b = 0; b < H->cfg.B; ++b) {
+        PlainArgs a = plain_args(H, b);
+        HIP_TRY(pfk::launch_tile_gather(H->cfg.model, H->cfg.d, H->cfg.precision,
+                                        H->at<int32_t>(H->L.marks), H->at<int32_t>(H->L.owner),
+                                        H->at<int32_t>(H->L.jc), H->ws + H->L.x_cur,
+                                        H->ws + H->L.x_tmp, H->at<int32_t>(H->L.anc), a,
+                                        H->stream));
+        HIP_TRY(pfk::launch_set_amode(a.fs, 1, pfk::AMODE_ARRAY, H->stream));
+      }
     }
+    src = spare;
   }
   const bool plain = H->cfg.layout == PF_LAYOUT_PLAIN;
   const int d = H->cfg.d;
@@ -1129,7 +1151,7 @@ pf_status pf_set_state(pf_handle* H, const double* x_in) {
   if (H->phase != 0) return fail(PF_E_STATE, "pf_set_state only between intervals");
   const size_t n = (size_t)H->cfg.d * H->L.n_total;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
-  const size_t dst = batched ? batched_buf(H, H->t) : H->L.x_cur;
+  const size_t dst = state_buf(H, H->t);
   const int d = H->cfg.d;
   const int64_t N = H->L.n_total;
   // the plain layout's state is tiled (pidx); the batched layout's is [d][N]
@@ -1150,7 +1172,11 @@ pf_status pf_set_state(pf_handle* H, const double* x_in) {
     HIP_TRY(hipMemcpyAsync(H->ws + dst, tmp.data(), 4 * nv, hipMemcpyHostToDevice, H->stream));
     HIP_TRY(hipStreamSynchronize(H->stream));
   }
-  if (batched) {  // the next step reads the given particles as they are
+  if (!batched) {  // the next step reads the given particles as they are
+    HIP_TRY(pfk::launch_fill_i32(H->at<int32_t>(H->L.marks), H->L.n_total, -1, H->stream));
+    HIP_TRY(pfk::launch_set_amode(H->at<FilterState>(H->L.fs), H->cfg.B, pfk::AMODE_IDENTITY,
+                                  H->stream));
+  } else {  // the next step reads the given particles as they are
     std::vector<int32_t> ident((size_t)H->L.n_total);
     for (int b = 0; b < H->cfg.B; ++b)
       for (int64_t k = 0; k < H->np[b]; ++k) ident[(size_t)(H->L.off[b] + k)] = (int32_t)k;
@@ -1177,6 +1203,9 @@ pf_status pf_get_ancestors(pf_handle* H, int32_t* a_out) {
   pf_status st = check_handle(H);
   if (st) return st;
   if (!a_out) return fail(PF_E_INVAL, "a_out is NULL");
+  if (H->cfg.layout == PF_LAYOUT_PLAIN && H->phase == 0 && H->t > 0)
+    for (int b = 0; b < H->cfg.B; ++b)  // the pending ancestors, written out
+      if ((st = plain_anc_out(H, b, H->stream))) return st;
   HIP_TRY(hipMemcpyAsync(a_out, H->ws + H->L.anc, 4 * (size_t)H->L.n_total,
                          hipMemcpyDeviceToHost, H->stream));
   HIP_TRY(hipStreamSynchronize(H->stream));
@@ -1503,7 +1532,7 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
   double* prop_dev = kalman ? nullptr : P->at<double>(P->L.theta);
 
   for (int32_t i = 1; i <= T && !kalman; ++i) {
-    const size_t cur = batched_buf(H, i - 1), spare = batched_buf(H, i);
+    const size_t cur = state_buf(H, i - 1), spare = state_buf(H, i);
     if (i >= 2) {
       // 1-2. theta-ancestors from v(t_{i-1}), the slots' moves and filter copies
       HIP_TRY(pfk::launch_theta_resample(S, i - 2, in->u[i - 1], 1, anc_tr + (size_t)(i - 1) * B,
@@ -1521,7 +1550,7 @@ pf_status pf_smc2(pf_handle* H, pf_handle* P, void* d_ws, size_t ws_bytes, const
                                     P->at<FilterState>(P->L.fs), acc_tr + (size_t)(i - 1) * B,
                                     s));
     HIP_TRY(pfk::launch_accept_copy(c.precision, H->ws + cur, H->at<int32_t>(H->L.anc),
-                                    P->ws + batched_buf(P, i - 1), P->at<int32_t>(P->L.anc), A, S,
+                                    P->ws + state_buf(P, i - 1), P->at<int32_t>(P->L.anc), A, S,
                                     s));
     // 4. every attached filter advances one interval
     if ((st = pf_graph_run(H, 1))) return st;
@@ -1651,7 +1680,7 @@ pf_status pf_history_attach(pf_handle* H, void* d_hist, size_t bytes) {
   if ((st = drain(H))) return st;
   destroy_graphs(H);  // recaptured with (or without) the recording kernels
   H->hist = (char*)d_hist;
-  if (d_hist && (st = record_all(H, H->L.x_cur, H->stream))) return st;
+  if (d_hist && (st = record_all(H, H->stream))) return st;
   HIP_TRY(hipStreamSynchronize(H->stream));
   return PF_OK;
 }

@@ -22,8 +22,17 @@ struct FilterState {
   int32_t carry;  // 1 if the last step kept its weights (ESS above the trigger)
   int32_t tk;     // plain layout: the interval the last propagation processed
   int32_t cn1;    // plain layout: strata owned by the whole filter (count of its last particle)
-  int32_t pad2;
+  int32_t amode;  // plain layout: where the next propagation finds its ancestors
+                  // (AMODE_IDENTITY, AMODE_MARKS or AMODE_ARRAY)
 };
+
+// Plain layout: the ancestors the next propagation gathers through.  After
+// an initialisation or a state set: none (the identity).  After a
+// systematic or stratified collective: its marks and tile owners, turned
+// into ancestors by the propagation itself (or by the tile-gather kernel
+// when the resampled set is asked for).  After the other resamplers, or once
+// the marks have been turned into ancestors: the ancestor array.
+enum : int32_t { AMODE_IDENTITY = 0, AMODE_MARKS = 1, AMODE_ARRAY = 2 };
 
 // Resampling variants: the ancestors of a resampling time.
 enum : int32_t { RS_SYSTEMATIC = 0, RS_STRATIFIED = 1, RS_METROPOLIS = 2, RS_MULTINOMIAL = 3,
@@ -128,8 +137,9 @@ constexpr int K3_NT = 256;  // scan + mark threads
 constexpr int K3_PER = 4;   // consecutive particles per scan lane
 constexpr int K3_SPAN = K3_NT * K3_PER;  // particles per scan block (4 K1 blocks)
 constexpr int K4_NT = 256;  // tile-gather threads
-constexpr int K4_PER = 4;   // outputs per tile-gather lane
-constexpr int K4_TILE = K4_NT * K4_PER;  // outputs per tile-gather block
+constexpr int K4_PER = 1;   // outputs per tile-gather lane
+constexpr int K4_TILE = K4_NT * K4_PER;  // outputs per tile (one owner each)
+static_assert(K4_TILE == K1_NT, "a propagation block names the ancestors of one tile");
 constexpr int BATCH_NT = 256;
 constexpr int BATCH_MAXN = 8192;
 
@@ -137,8 +147,13 @@ constexpr int BATCH_MAXN = 8192;
 hipError_t launch_init(int model, int d, int prec, void* x, const PlainArgs& a, hipStream_t s);
 hipError_t launch_reset(FilterState* fs, double* ell, double* ess, int B, int T, uint32_t iter,
                         hipStream_t s);
-hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* xprop, void* lw,
-                            double* part, const PlainArgs& a, hipStream_t s);
+// Plain-layout state buffers: the interval-t propagated particles live in
+// buffer t % 2 (xa holds x(t_0)); the propagation of interval t gathers
+// buffer (t - 1) % 2 through the pending ancestors (FilterState::amode).
+hipError_t launch_propagate(int model, int d, int prec, void* xa, void* xb, void* lw,
+                            double* part, int32_t* marks, const int32_t* owner,
+                            const int32_t* jc, int32_t* anc, const PlainArgs& a, hipStream_t s);
+hipError_t launch_set_amode(FilterState* fs, int n, int32_t v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_combine(const double* part, double* boff, const PlainArgs& a, hipStream_t s);
 hipError_t launch_lw_partials(const double* lw, double* part, const PlainArgs& a, hipStream_t s);
@@ -147,17 +162,23 @@ hipError_t launch_tile_anc(int32_t* marks, const int32_t* owner, const int32_t* 
 hipError_t launch_scan_mark(const double* lw, const double* part, const double* boff,
                             int32_t* marks, int32_t* owner, int32_t* jc, const PlainArgs& a,
                             hipStream_t s);
+// The resampled set of the interval the filter stands at (t = fs->t):
+// buffer t % 2 gathered through the pending ancestors into buffer
+// (t + 1) % 2, the ancestors written out (marks cleared).  The pending mode
+// becomes AMODE_ARRAY with launch_set_amode afterwards (the kernel's blocks
+// all read it).  launch_tile_anc: the ancestors only.
 hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const int32_t* owner,
-                              const int32_t* jc, const void* xprop, void* xcur, int32_t* anc,
+                              const int32_t* jc, void* xa, void* xb, int32_t* anc,
                               const PlainArgs& a, hipStream_t s);
 hipError_t launch_set_u(FilterState* fs, double u, hipStream_t s);
-hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
-                                   int32_t* anc, const PlainArgs& a, hipStream_t s);
-hipError_t launch_rejection_gather(int prec, const double* lw, const void* xprop, void* xcur,
-                                  int32_t* anc, const PlainArgs& a, hipStream_t s);
-hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* jc,
-                                     const void* xprop, void* xcur, int32_t* anc,
-                                     const PlainArgs& a, hipStream_t s);
+// Ancestors of the resamplers without marks; the pending mode becomes
+// AMODE_ARRAY.
+hipError_t launch_metropolis_anc(const double* lw, int32_t* anc, const PlainArgs& a,
+                                 hipStream_t s);
+hipError_t launch_rejection_anc(const double* lw, int32_t* anc, const PlainArgs& a,
+                                hipStream_t s);
+hipError_t launch_multinomial_anc(const double* wcum, const int32_t* jc, int32_t* anc,
+                                  const PlainArgs& a, hipStream_t s);
 hipError_t launch_simulate(int model, int d, double* out, const PlainArgs& a, double obs_sd,
                            hipStream_t s);
 // ---- batched (pf_batched.hip) ----

@@ -70,7 +70,7 @@ __global__ void k_reset(FilterState* fs, double* ell, double* ess, int B, int T,
     f.carry = 0;
     f.tk = 0;
     f.cn1 = 0;
-    f.pad2 = 0;
+    f.amode = AMODE_IDENTITY;
     fs[i] = f;
   }
 }
@@ -375,17 +375,82 @@ __device__ __forceinline__ double l96_logdens(const Real (&x)[D], const double* 
   return -0.5 * acc + cst;
 }
 
+// The particle output j continues in this interval (plain layout, every
+// thread of a K1 block calls it: it has a barrier): the identity, the
+// ancestor array, or, after a systematic or stratified collective, the
+// running maximum of the marks over the block's tile (one tile of K4_TILE =
+// K1_NT outputs per block) started from the tile's owner, as the tile
+// gather forms it; those marks are cleared for the next collective and the
+// ancestors written out.  Outputs past the filter's strata (rounding) go to
+// the last particle of positive weight.
+__device__ __forceinline__ int64_t plain_ancestor(int64_t j, int32_t* __restrict__ marks_all,
+                                                  const int32_t* __restrict__ owner_all,
+                                                  const int32_t* __restrict__ jc_all,
+                                                  int32_t* __restrict__ anc,
+                                                  const PlainArgs& A, int32_t* wtop,
+                                                  int32_t* s_js) {
+  const int32_t amode = A.fs->amode;
+  const int64_t N = A.N;
+  if (amode == AMODE_IDENTITY) return j;
+  if (amode == AMODE_ARRAY) return j < N ? (int64_t)anc[A.off + j] : j;
+  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+  const int64_t k0 = (int64_t)blockIdx.x * K1_NT;
+  const int64_t cn1 = A.fs->cn1;
+  if (threadIdx.x < WAVE) {
+    int found = -1;
+    if (k0 + K1_NT > cn1 && cn1 < N) {
+      const int nb3 = (int)((N + K3_SPAN - 1) / K3_SPAN);
+      for (int base = nb3 - 1; base >= 0 && found < 0; base -= WAVE) {
+        const int i = base - (int)threadIdx.x;
+        found = wave_max_i(i >= 0 ? jc_all[A.own0 + i] : -1);
+      }
+    }
+    if (threadIdx.x == 0) *s_js = found;
+  }
+  int32_t* marks = marks_all + A.off;
+  int32_t run = k0 < cn1 ? owner_all[A.own0 + blockIdx.x] : -1;
+  if (j < N) {
+    run = max(run, marks[j]);
+    marks[j] = -1;
+  }
+  const int32_t incl = wave_incl_max_scan_i(run, lane);
+  if (lane == WAVE - 1) wtop[wv] = incl;
+  __syncthreads();
+  int32_t excl = -1;
+#pragma unroll
+  for (int w = 0; w < K1_NT / WAVE; ++w)
+    if (w < wv) excl = max(excl, wtop[w]);
+  if (j >= N) return j;
+  int32_t a = j < cn1 ? max(excl, incl) : *s_js;
+  if (a < 0 || a >= N) {  // never expected; flagged, and kept in bounds
+    atomicOr(&A.fs->pad, 1);
+    a = 0;
+  }
+  anc[A.off + j] = a;
+  return a;
+}
+
 template <int MODEL, int D, typename Real, bool ACC = false>
-__global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restrict__ xcur,
-                                                            Real* __restrict__ xprop,
+__global__ __launch_bounds__(K1_NT) void k_propagate_weight(Real* __restrict__ xa,
+                                                            Real* __restrict__ xb,
                                                             double* __restrict__ lw,
                                                             double* __restrict__ part,
+                                                            int32_t* __restrict__ marks,
+                                                            const int32_t* __restrict__ owner,
+                                                            const int32_t* __restrict__ jc,
+                                                            int32_t* __restrict__ anc,
                                                             PlainArgs A) {
   __shared__ double red[K1_NT / WAVE];
+  __shared__ int32_t wtop[K1_NT / WAVE];
+  __shared__ int32_t s_js;
   const int64_t j = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
   const int t = A.fs->t + 1;
   const uint32_t iter = A.fs->iter;
   const Key key = key_of(A.key);
+  // interval t gathers buffer (t - 1) % 2 and writes buffer t % 2
+  const Real* __restrict__ xcur = ((t - 1) & 1) ? xb : xa;
+  Real* __restrict__ xprop = (t & 1) ? xb : xa;
+  const int64_t src = A.off + plain_ancestor(j, marks, owner, jc, anc, A, wtop, &s_js);
   double l = -INFINITY;
   if (j < A.N) {
     const int64_t col = A.off + j;
@@ -393,7 +458,7 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
     const int n0 = (t - 1) * A.K;
     if constexpr (MODEL == 1) {
       if constexpr (sizeof(Real) == 8) {
-        double p = xcur[col];
+        double p = xcur[src];
         for (int s = 1; s <= A.K; ++s) {
           const uint4 w = draw(key, TAG_NOISE, 0, iter, (uint32_t)j, (uint32_t)(n0 + s), A.b);
           double z0, z1;
@@ -404,7 +469,7 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
         const double e = (yrow[0] - (p + A.theta[2] * A.q[(int64_t)t * A.K])) * A.inv_sd;
         l = -0.5 * (e * e) + A.lw_cst;
       } else {
-        float p = xcur[col];
+        float p = xcur[src];
         double pa = p;  // the accurate form carries the pressure in FP64
         const float a = (float)(A.theta[0] - 1.0), c = (float)A.theta[1], sp = (float)A.theta[3];
         for (int s = 1; s <= A.K; ++s) {
@@ -426,7 +491,7 @@ __global__ __launch_bounds__(K1_NT) void k_propagate_weight(const Real* __restri
     } else {
       Real x[D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) x[i] = xcur[pidx(col, i, D)];
+      for (int i = 0; i < D; ++i) x[i] = xcur[pidx(src, i, D)];
       if constexpr (sizeof(Real) == 8) {
         const double F = A.theta[0], sq = A.theta[1];
         ModelConsts mc{A.h, A.hh, A.h6, A.inv_sd, A.lw_cst};
@@ -721,6 +786,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
   if (A.rs.scheme != RS_MULTINOMIAL) {
     int32_t* marks = marks_all + A.off;
     int32_t* owner = owner_all + A.own0;
+    if (threadIdx.x == 0) fst->amode = AMODE_MARKS;  // the next propagation reads them
 #pragma unroll
     for (int e = 0; e <= K3_PER; ++e)
       if (rlo[e] < rhi[e]) marks[rlo[e]] = (int32_t)rj[e];
@@ -755,104 +821,46 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- K4
-// One block per tile of K4_TILE outputs.  Lane t takes outputs
-// k0 + 4t .. k0 + 4t + 3: it reads their marks (and puts the -1 back, so
-// the marks are clear for the next resampling), and a running maximum over
-// the tile, started from the owner of the tile's first stratum, names each
-// output's ancestor (the largest particle that marked a stratum at or
-// before it); outputs past the filter's strata take jstar.  The ancestors go
-// to LDS, and the ancestors' states are then copied with coalesced stores
-// (output k0 + t + 256 q in lane t), D/8 groups of eight components in
-// flight at once.
+// The resampled set, on demand (the stepping path never runs this: the next
+// propagation gathers through the pending ancestors itself).  One block per
+// tile of K4_TILE outputs: with marks pending, a running maximum over the
+// tile's marks (which it clears), started from the owner of the tile's
+// first stratum, names each output's ancestor (outputs past the strata take
+// the last particle of positive weight); with the identity or the ancestor
+// array pending, those.  The ancestors are written out, and with buffers
+// given, buffer t % 2 (t = fs->t) is gathered through them into buffer
+// (t + 1) % 2.
 template <int D, typename Real>
 __global__ __launch_bounds__(K4_NT) void k_tile_gather(int32_t* __restrict__ marks_all,
                                                        const int32_t* __restrict__ owner_all,
                                                        const int32_t* __restrict__ jc_all,
-                                                       const Real* __restrict__ xprop,
-                                                       Real* __restrict__ xcur,
+                                                       Real* __restrict__ xa,
+                                                       Real* __restrict__ xb,
                                                        int32_t* __restrict__ anc,
                                                        PlainArgs A) {
-  __shared__ int32_t sa[K4_TILE];
+  static_assert(K4_PER == 1 && K4_NT == K1_NT, "one output per lane, one tile per block");
   __shared__ int32_t wtop[K4_NT / WAVE];
-  const int64_t N = A.N;
-  const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-  int32_t* marks = marks_all + A.off;
-  const int64_t k0 = (int64_t)blockIdx.x * K4_TILE;
-  const int64_t kt = k0 + (int64_t)threadIdx.x * K4_PER;
-  const int64_t cn1 = A.fs->cn1;
-  // jstar, from K3's per-block candidates, only for a tile that reaches past
-  // the filter's strata (rounding overflow; rare)
   __shared__ int32_t s_js;
-  if (threadIdx.x < WAVE) {
-    int found = -1;
-    if (k0 + K4_TILE > cn1 && cn1 < N) {
-      const int nb3 = (int)((N + K3_SPAN - 1) / K3_SPAN);
-      for (int base = nb3 - 1; base >= 0 && found < 0; base -= WAVE) {
-        const int i = base - (int)threadIdx.x;
-        found = wave_max_i(i >= 0 ? jc_all[A.own0 + i] : -1);
-      }
-    }
-    if (threadIdx.x == 0) s_js = found;
+  const int64_t k = (int64_t)blockIdx.x * K4_TILE + threadIdx.x;
+  const int64_t a = plain_ancestor(k, marks_all, owner_all, jc_all, anc, A, wtop, &s_js);
+  if (k >= A.N) return;
+  anc[A.off + k] = (int32_t)a;
+  if (xa == nullptr) return;
+  const int t = A.fs->t;
+  const Real* __restrict__ xprop = (t & 1) ? xb : xa;
+  Real* __restrict__ xout = (t & 1) ? xa : xb;
+  const int64_t src = A.off + a, dst = A.off + k;
+  if constexpr (D > 0) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) xout[pidx(dst, i, D)] = xprop[pidx(src, i, D)];
+  } else {
+    for (int i = 0; i < A.d; ++i) xout[pidx(dst, i, A.d)] = xprop[pidx(src, i, A.d)];
   }
-  int32_t run = k0 < cn1 ? owner_all[A.own0 + blockIdx.x] : -1;
-  int32_t r[K4_PER];
-#pragma unroll
-  for (int e = 0; e < K4_PER; ++e) {
-    const int64_t k = kt + e;
-    int32_t m = -1;
-    if (k < N) {
-      m = marks[k];
-      marks[k] = -1;
-    }
-    run = max(run, m);
-    r[e] = run;
-  }
-  const int32_t incl = wave_incl_max_scan_i(run, lane);
-  int32_t excl = __shfl_up(incl, 1, WAVE);
-  if (lane == 0) excl = -1;
-  if (lane == WAVE - 1) wtop[wv] = incl;
-  __syncthreads();
-#pragma unroll
-  for (int w = 0; w < K4_NT / WAVE; ++w)
-    if (w < wv) excl = max(excl, wtop[w]);
-  const int32_t js = s_js;
-  bool bad = false;
-#pragma unroll
-  for (int e = 0; e < K4_PER; ++e) {
-    const int64_t k = kt + e;
-    if (k < N) {
-      int32_t a = k < cn1 ? max(excl, r[e]) : js;
-      if (a < 0 || a >= N) {  // never expected; flagged, and kept in bounds
-        bad = true;
-        a = 0;
-      }
-      anc[A.off + k] = a;
-      sa[threadIdx.x * K4_PER + e] = a;
-    }
-  }
-  __syncthreads();
-  constexpr int CG = (D > 0 && D < 8) ? D : 8;
-#pragma unroll
-  for (int q = 0; q < K4_PER; ++q) {
-    const int kk = (int)threadIdx.x + K4_NT * q;
-    const int64_t k = k0 + kk;
-    if (k < N) {
-      const int64_t src = A.off + sa[kk], dst = A.off + k;
-      if constexpr (D > 0) {
-#pragma unroll
-        for (int g = 0; g < D; g += CG) {
-          Real v[CG];
-#pragma unroll
-          for (int i = 0; i < CG; ++i) v[i] = xprop[pidx(src, g + i, D)];
-#pragma unroll
-          for (int i = 0; i < CG; ++i) xcur[pidx(dst, g + i, D)] = v[i];
-        }
-      } else {
-        for (int i = 0; i < A.d; ++i) xcur[pidx(dst, i, A.d)] = xprop[pidx(src, i, A.d)];
-      }
-    }
-  }
-  if (bad) atomicOr(&A.fs->pad, 1);
+}
+
+__global__ void k_set_amode(FilterState* fs, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) fs[i].amode = v;
 }
 
 // ---------------------------------------------------------------- Metropolis resampling
@@ -896,6 +904,7 @@ __global__ __launch_bounds__(K1_NT) void k_metropolis(const double* __restrict__
     }
   }
   anc[A.off + k] = j;
+  if (k == 0) A.fs->amode = AMODE_ARRAY;
 }
 
 // ---------------------------------------------------------------- rejection resampling
@@ -916,6 +925,7 @@ __global__ __launch_bounds__(K1_NT) void k_rejection(const double* __restrict__ 
     j = reject_ancestor(key_of(A.key), f->t, A.b, f->iter, (int32_t)k, (int32_t)A.N, M,
                         [&](int32_t i) { return l[i]; });
   anc[A.off + k] = j;
+  if (k == 0) A.fs->amode = AMODE_ARRAY;
 }
 
 // Multinomial resampling, as Alg. 2 writes it: output k takes
@@ -950,19 +960,7 @@ __global__ __launch_bounds__(K1_NT) void k_multinomial(const double* __restrict_
     }
   }
   anc[A.off + k] = (int32_t)a;
-}
-
-// x_cur[k] = x_prop[a_k] for unsorted ancestors.
-template <typename Real>
-__global__ __launch_bounds__(K1_NT) void k_anc_gather(const Real* __restrict__ xprop,
-                                                      Real* __restrict__ xcur,
-                                                      const int32_t* __restrict__ anc,
-                                                      PlainArgs A) {
-  const int64_t k = (int64_t)blockIdx.x * K1_NT + threadIdx.x;
-  if (k >= A.N) return;
-  const int64_t src = A.off + anc[A.off + k];
-  const int64_t dst = A.off + k;
-  for (int i = 0; i < A.d; ++i) xcur[pidx(dst, i, A.d)] = xprop[pidx(src, i, A.d)];
+  if (k == 0) A.fs->amode = AMODE_ARRAY;
 }
 
 // ---------------------------------------------------------------- simulator
@@ -1050,19 +1048,20 @@ hipError_t launch_reset(FilterState* fs, double* ell, double* ess, int B, int T,
   return hipGetLastError();
 }
 
-hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* xprop, void* lw,
-                            double* part, const PlainArgs& a, hipStream_t s) {
+hipError_t launch_propagate(int model, int d, int prec, void* xa, void* xb, void* lw,
+                            double* part, int32_t* marks, const int32_t* owner,
+                            const int32_t* jc, int32_t* anc, const PlainArgs& a, hipStream_t s) {
   const unsigned g = (unsigned)a.nblk;
   if (model == 1) {
     if (prec == 0)
       hipLaunchKernelGGL((k_propagate_weight<1, 1, double>), g, K1_NT, 0, s,
-                         (const double*)xcur, (double*)xprop, (double*)lw, part, a);
+                         (double*)xa, (double*)xb, (double*)lw, part, marks, owner, jc, anc, a);
     else if (prec == 1)
       hipLaunchKernelGGL((k_propagate_weight<1, 1, float>), g, K1_NT, 0, s,
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);
     else
       hipLaunchKernelGGL((k_propagate_weight<1, 1, float, true>), g, K1_NT, 0, s,
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);
     return hipGetLastError();
   }
   switch (d * 4 + model) {
@@ -1070,24 +1069,24 @@ hipError_t launch_propagate(int model, int d, int prec, const void* xcur, void* 
   case DD * 4 + 2:                                                                        \
     if (prec == 0)                                                                        \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, double>), g, K1_NT, 0, s,             \
-                         (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
+                         (double*)xa, (double*)xb, (double*)lw, part, marks, owner, jc, anc, a);      \
     else if (prec == 1)                                                                   \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, float>), g, K1_NT, 0, s,              \
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);        \
     else                                                                                  \
       hipLaunchKernelGGL((k_propagate_weight<2, DD, float, true>), g, K1_NT, 0, s,        \
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);        \
     break;                                                                                \
   case DD * 4 + 3:                                                                        \
     if (prec == 0)                                                                        \
       hipLaunchKernelGGL((k_propagate_weight<3, DD, double>), g, K1_NT, 0, s,             \
-                         (const double*)xcur, (double*)xprop, (double*)lw, part, a);      \
+                         (double*)xa, (double*)xb, (double*)lw, part, marks, owner, jc, anc, a);      \
     else if (prec == 1)                                                                   \
       hipLaunchKernelGGL((k_propagate_weight<3, DD, float>), g, K1_NT, 0, s,              \
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);        \
     else                                                                                  \
       hipLaunchKernelGGL((k_propagate_weight<3, DD, float, true>), g, K1_NT, 0, s,        \
-                         (const float*)xcur, (float*)xprop, (double*)lw, part, a);        \
+                         (float*)xa, (float*)xb, (double*)lw, part, marks, owner, jc, anc, a);        \
     break;
     PF_L96_DIMS(X)
 #undef X
@@ -1114,9 +1113,14 @@ hipError_t launch_lw_partials(const double* lw, double* part, const PlainArgs& a
 
 hipError_t launch_tile_anc(int32_t* marks, const int32_t* owner, const int32_t* jc, int32_t* anc,
                            const PlainArgs& a, hipStream_t s) {
-  // the tile gather with no state components: ancestors only
   hipLaunchKernelGGL((k_tile_gather<0, float>), nblocks(a.N, K4_TILE), K4_NT, 0, s, marks, owner,
-                     jc, (const float*)nullptr, (float*)nullptr, anc, a);
+                     jc, (float*)nullptr, (float*)nullptr, anc, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_amode(FilterState* fs, int n, int32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_amode, (unsigned)((n + 255) / 256), 256, 0, s, fs, n, v);
   return hipGetLastError();
 }
 
@@ -1137,7 +1141,7 @@ hipError_t launch_scan_mark(const double* lw, const double* part, const double* 
 }
 
 hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const int32_t* owner,
-                              const int32_t* jc, const void* xprop, void* xcur, int32_t* anc,
+                              const int32_t* jc, void* xa, void* xb, int32_t* anc,
                               const PlainArgs& a, hipStream_t s) {
   const unsigned g = nblocks(a.N, K4_TILE);
   const int dd = model == 1 ? 1 : d;
@@ -1146,10 +1150,10 @@ hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const 
   case DD:                                                                                  \
     if (prec == 0)                                                                          \
       hipLaunchKernelGGL((k_tile_gather<DD, double>), g, K4_NT, 0, s, marks, owner, jc,      \
-                         (const double*)xprop, (double*)xcur, anc, a);                      \
+                         (double*)xa, (double*)xb, anc, a);                                 \
     else                                                                                    \
       hipLaunchKernelGGL((k_tile_gather<DD, float>), g, K4_NT, 0, s, marks, owner, jc,       \
-                         (const float*)xprop, (float*)xcur, anc, a);                        \
+                         (float*)xa, (float*)xb, anc, a);                                   \
     break;
     X(1) PF_L96_DIMS(X)
 #undef X
@@ -1159,43 +1163,21 @@ hipError_t launch_tile_gather(int model, int d, int prec, int32_t* marks, const 
   return hipGetLastError();
 }
 
-hipError_t launch_metropolis_gather(int prec, const double* lw, const void* xprop, void* xcur,
-                                   int32_t* anc, const PlainArgs& a, hipStream_t s) {
-  const unsigned g = nblocks(a.N, K1_NT);
-  hipLaunchKernelGGL(k_metropolis, g, K1_NT, 0, s, lw, anc, a);
-  if (prec == 0)
-    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
-                       (double*)xcur, (const int32_t*)anc, a);
-  else
-    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
-                       (const int32_t*)anc, a);
+hipError_t launch_metropolis_anc(const double* lw, int32_t* anc, const PlainArgs& a,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_metropolis, nblocks(a.N, K1_NT), K1_NT, 0, s, lw, anc, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rejection_gather(int prec, const double* lw, const void* xprop, void* xcur,
-                                  int32_t* anc, const PlainArgs& a, hipStream_t s) {
-  const unsigned g = nblocks(a.N, K1_NT);
-  hipLaunchKernelGGL(k_rejection, g, K1_NT, 0, s, lw, anc, a);
-  if (prec == 0)
-    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
-                       (double*)xcur, (const int32_t*)anc, a);
-  else
-    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
-                       (const int32_t*)anc, a);
+hipError_t launch_rejection_anc(const double* lw, int32_t* anc, const PlainArgs& a,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_rejection, nblocks(a.N, K1_NT), K1_NT, 0, s, lw, anc, a);
   return hipGetLastError();
 }
 
-hipError_t launch_multinomial_gather(int prec, const double* wcum, const int32_t* jc,
-                                     const void* xprop, void* xcur, int32_t* anc,
-                                     const PlainArgs& a, hipStream_t s) {
-  const unsigned g = nblocks(a.N, K1_NT);
-  hipLaunchKernelGGL(k_multinomial, g, K1_NT, 0, s, wcum, jc, anc, a);
-  if (prec == 0)
-    hipLaunchKernelGGL(k_anc_gather<double>, g, K1_NT, 0, s, (const double*)xprop,
-                       (double*)xcur, (const int32_t*)anc, a);
-  else
-    hipLaunchKernelGGL(k_anc_gather<float>, g, K1_NT, 0, s, (const float*)xprop, (float*)xcur,
-                       (const int32_t*)anc, a);
+hipError_t launch_multinomial_anc(const double* wcum, const int32_t* jc, int32_t* anc,
+                                  const PlainArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_multinomial, nblocks(a.N, K1_NT), K1_NT, 0, s, wcum, jc, anc, a);
   return hipGetLastError();
 }
 

@@ -15,18 +15,21 @@ namespace pfk {
 
 constexpr uint32_t TAG_PATH = 9;  // generator tag of the final draw
 
-// Plain layout, one filter: slot t = fs->t gets the particles x (the
-// propagated ones after a step, the initial ones at t = 0; read from the
-// state's 64-particle tiles) and, for t >= 1, the ancestors drawn at time t.
+// Plain layout, one filter: slot t = fs->t gets the particles of buffer
+// t % 2 (the propagated ones after a step, the initial ones at t = 0; read
+// from the state's 64-particle tiles) and, for t >= 1, the ancestors drawn
+// at time t (written out before this runs).
 // The history itself keeps one row of N_total values per component.
 template <typename Real>
-__global__ __launch_bounds__(256) void k_record_plain(const Real* __restrict__ x,
+__global__ __launch_bounds__(256) void k_record_plain(const Real* __restrict__ xa,
+                                                      const Real* __restrict__ xb,
                                                       const int32_t* __restrict__ anc,
                                                       HistArgs H, int64_t off, int64_t N,
                                                       const FilterState* __restrict__ fs) {
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= N) return;
   const int t = fs->t;
+  const Real* __restrict__ x = (t & 1) ? xb : xa;  // the interval-t particles
   Real* xh = (Real*)H.xh + (int64_t)t * H.d * H.ld;
   for (int i = 0; i < H.d; ++i) xh[(int64_t)i * H.ld + off + k] = x[pidx(off + k, i, H.d)];
   if (t >= 1) H.ah[(int64_t)(t - 1) * H.ld + off + k] = anc[off + k];
@@ -94,15 +97,17 @@ __global__ __launch_bounds__(64) void k_backtrace(HistArgs H, const int64_t* __r
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_record_plain(int prec, const void* x, const int32_t* anc, const HistArgs& H,
-                               int64_t off, int64_t N, const FilterState* fs, hipStream_t s) {
+hipError_t launch_record_plain(int prec, const void* xa, const void* xb, const int32_t* anc,
+                               const HistArgs& H, int64_t off, int64_t N, const FilterState* fs,
+                               hipStream_t s) {
   const unsigned g = (unsigned)((N + 255) / 256);
   if (g == 0) return hipSuccess;
   if (prec == 0)
-    hipLaunchKernelGGL(k_record_plain<double>, g, 256, 0, s, (const double*)x, anc, H, off, N,
-                       fs);
+    hipLaunchKernelGGL(k_record_plain<double>, g, 256, 0, s, (const double*)xa,
+                       (const double*)xb, anc, H, off, N, fs);
   else
-    hipLaunchKernelGGL(k_record_plain<float>, g, 256, 0, s, (const float*)x, anc, H, off, N, fs);
+    hipLaunchKernelGGL(k_record_plain<float>, g, 256, 0, s, (const float*)xa, (const float*)xb,
+                       anc, H, off, N, fs);
   return hipGetLastError();
 }
 

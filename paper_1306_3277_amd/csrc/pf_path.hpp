@@ -14,8 +14,9 @@ struct HistArgs {
   int32_t d, T;
 };
 
-hipError_t launch_record_plain(int prec, const void* x, const int32_t* anc, const HistArgs& H,
-                               int64_t off, int64_t N, const FilterState* fs, hipStream_t s);
+hipError_t launch_record_plain(int prec, const void* xa, const void* xb, const int32_t* anc,
+                               const HistArgs& H, int64_t off, int64_t N, const FilterState* fs,
+                               hipStream_t s);
 hipError_t launch_record_batched(int prec, const void* xa, const void* xb, const int32_t* anc,
                                  const HistArgs& H, const BatchArgs& A, int nchunks,
                                  hipStream_t s);

@@ -272,7 +272,7 @@ def wk_mh_inputs(spec: WkMh, chains: int = 64, iters: int = 1000, seed: int = 5,
     rng = np.random.Generator(np.random.PCG64(seed))
     if theta0 is None:
         theta0 = wk_mh_prior_draws(spec, chains, rng)
-    theta0 = np.array(np.broadcast_to(theta0, (chains, 4)), dtype=np.float64)  # a copy
+    theta0 = np.array(np.broadcast_to(theta0, (chains, 4)), dtype=np.float64, order="C")
     prop = np.zeros((iters, chains, 4))
     prop[:, :, :3] = _open_uniforms(rng, (iters, chains, 3))
     prop[:, :, 3] = rng.gamma(spec.ig_prop_shape, 1.0, size=(iters, chains))

@@ -234,9 +234,9 @@ struct pf_handle {
     int kind;
   };
   std::vector<Ev> events;
-  // graphs, each captured on one stream: plain layout, gexecs[0] holds one
-  // interval of every filter; batched layout, gexecs[2g] holds one interval
-  // of filter group g and gexecs[2g + 1] kGraphSteps of them
+  // graphs, each captured on one stream: gexecs[2g] holds one interval and
+  // gexecs[2g + 1] kGraphSteps intervals (plain layout: g = 0, every filter;
+  // batched layout: filter group g)
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   hipStream_t cap_stream = nullptr;
@@ -763,10 +763,10 @@ pf_status launch_stream(pf_handle* H, hipStream_t* out) {
 
 // Captures the graphs pf_graph_run replays.  Every capture is on one
 // stream and holds kernel launches only (no event, copy or memset), so a
-// graph never refers to an event or another stream: plain layout, one
-// interval of every filter; batched layout, for each filter group one
-// interval and kGraphSteps intervals of that group's kernels.  The groups'
-// graphs are launched on their own streams between an eager fork and join.
+// graph never refers to an event or another stream: one interval and
+// kGraphSteps intervals, of every filter (plain layout) or of each filter
+// group (batched layout).  The groups' graphs are launched on their own
+// streams between an eager fork and join.
 pf_status ensure_graphs(pf_handle* H) {
   if (!H->gexecs.empty()) return PF_OK;
   hipStream_t cs;
@@ -776,15 +776,16 @@ pf_status ensure_graphs(pf_handle* H) {
   H->timing = false;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
   const int ng = batched ? H->groups : 1;
-  const int nv = batched ? 2 : 1;
   for (int g = 0; g < ng && !st; ++g) {
-    for (int v = 0; v < nv && !st; ++v) {
+    for (int v = 0; v < 2 && !st; ++v) {
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       if (batched) {
         st = enqueue_group(H, g, cs, v == 0 ? 1 : kGraphSteps);
       } else {
-        st = enqueue_step(H, cs);
-        if (!st) st = enqueue_resample(H, cs, nullptr);
+        for (int i = 0; i < (v == 0 ? 1 : kGraphSteps) && !st; ++i) {
+          st = enqueue_step(H, cs);
+          if (!st) st = enqueue_resample(H, cs, nullptr);
+        }
       }
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(cs, &graph);
@@ -1058,11 +1059,10 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   auto gs = [&](int g) { return G == 1 ? ls : H->side[g]; };
   if (G > 1 && (st = fork_groups(H, ls))) return st;
   int left = n_steps;
-  if (batched)
-    for (; left >= kGraphSteps; left -= kGraphSteps)
-      for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g + 1], gs(g)));
+  for (; left >= kGraphSteps; left -= kGraphSteps)
+    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g + 1], gs(g)));
   for (; left > 0; --left)
-    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[batched ? 2 * g : 0], gs(g)));
+    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g], gs(g)));
   if (G > 1 && (st = join_groups(H, ls))) return st;
   H->t += n_steps;
   return PF_OK;

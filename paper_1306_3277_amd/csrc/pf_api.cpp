@@ -467,7 +467,7 @@ pf_status enqueue_group_collective(pf_handle* H, int g, hipStream_t s) {
   if (st) return st;
   HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
                                        H->at<int32_t>(H->L.anc), a, H->grp_nfilt[g],
-                                       H->grp_maxn[g], s));
+                                       H->grp_maxn[g], H->grp_nchunks[g], s));
   return ev_end(H, e0, 4, s);
 }
 
@@ -572,7 +572,8 @@ pf_status enqueue_resample(pf_handle* H, hipStream_t s, const double* u) {
     a.mode = 1;
     const int32_t max_n = (int32_t)*std::max_element(H->np.begin(), H->np.end());
     HIP_TRY(pfk::launch_batched_resample(H->batch_nt, H->at<double>(H->L.lw),
-                                         H->at<int32_t>(H->L.anc), a, c.B, max_n, s));
+                                         H->at<int32_t>(H->L.anc), a, c.B, max_n,
+                                         H->L.n_chunks, s));
     pf_status st = record_all(H, s);  // the redrawn ancestors
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));  // u is a host array

@@ -411,18 +411,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     return;
   }
   if constexpr (RS == RS_REJECTION) {
-    // rejection resampling from the staged log-weights and their maximum,
-    // no counts or merge: output k tries k, then uniform candidates
-    const Key key = bkey(A.key);
-#pragma unroll 1
-    for (int k = (int)threadIdx.x; k < N; k += NT) {
-      int j = k;
-      if (draw_rs)
-        j = reject_ancestor(key, t, (uint32_t)f, iter, k, N, M,
-                            [&](int32_t i) { return stage[stage_slot(i)]; });
-      anc[off + k] = j;
-      if (ha) ha[k] = j;
-    }
+    // rejection resampling draws its ancestors in k_batch_reject, one lane
+    // per output over the whole group (a collapsed filter's outputs take
+    // about N attempts each, too many for one workgroup); here only the
+    // filter's bookkeeping
     finish();
     return;
   }
@@ -544,6 +536,32 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   finish();
 }
 
+// Rejection resampling (RS_REJECTION), after the collective's bookkeeping:
+// one lane per output over the group's chunks, reading the filter's
+// log-weights and largest log-weight M from memory.  A step that keeps its
+// weights, or has none positive, gives the identity.
+__global__ __launch_bounds__(BATCH_NT) void k_batch_reject(const double* __restrict__ lw,
+                                                           int32_t* __restrict__ anc,
+                                                           BatchArgs A) {
+  const int f = A.chunk_f[A.chunk0 + blockIdx.x];
+  const int64_t off = A.off[f];
+  const int N = (int)(A.off[f + 1] - off);
+  const int k = A.chunk_k[A.chunk0 + blockIdx.x] + (int)threadIdx.x;
+  if (k >= N) return;
+  const FilterState* fs = A.fs + f;
+  const double M = fs->M;
+  const int t = fs->t;
+  const bool draw_rs = (M > -INFINITY) && (M < INFINITY) && (fs->S > 0.0) && !fs->carry;
+  int j = k;
+  if (draw_rs) {
+    const double* l = lw + off;
+    j = reject_ancestor(bkey(A.key), t, (uint32_t)f, fs->iter, k, N, M,
+                        [&](int32_t i) { return l[i]; });
+  }
+  anc[off + k] = j;
+  if (A.ha) A.ha[(int64_t)(t - 1) * A.ld + off + k] = j;
+}
+
 // x_out = x_prop[ancestors]: materialises the equally weighted set for
 // inspection (the stepping kernels never need it).
 template <typename Real>
@@ -646,7 +664,7 @@ hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* 
 }
 
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   int nfilters, int max_n, hipStream_t s) {
+                                   int nfilters, int max_n, int nchunks, hipStream_t s) {
   if (nfilters <= 0) return hipSuccess;
   if (max_n < 1 || max_n > BATCH_MAXN) return hipErrorInvalidValue;
   const unsigned g = (unsigned)nfilters;
@@ -687,6 +705,8 @@ hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const
 #undef PF_K5B_RS
 #undef PF_K5B_Q
 #undef PF_K5B
+  if (a.rs.scheme == RS_REJECTION && nchunks > 0)
+    hipLaunchKernelGGL(k_batch_reject, (unsigned)nchunks, BATCH_NT, 0, s, lw, anc, a);
   return hipGetLastError();
 }
 

@@ -187,8 +187,10 @@ hipError_t launch_batched_init(int model, int d, int prec, void* x, int32_t* anc
 hipError_t launch_batched_propagate(int model, int d, int prec, void* xa, void* xb, double* lw,
                                     const int32_t* anc, const BatchArgs& a, int nchunks,
                                     hipStream_t s);
+// The collective of nfilters filters (the launch's slots in `order`); with
+// rejection resampling also the ancestors of the launch's nchunks chunks.
 hipError_t launch_batched_resample(int nt, const double* lw, int32_t* anc, const BatchArgs& a,
-                                   int nfilters, int max_n, hipStream_t s);
+                                   int nfilters, int max_n, int nchunks, hipStream_t s);
 hipError_t launch_batched_gather(int prec, const void* xprop, const int32_t* anc, void* xout,
                                  const BatchArgs& a, hipStream_t s);
 

@@ -92,9 +92,9 @@ enum { PF_MODEL_WK = 1, PF_MODEL_L96 = 2, PF_MODEL_L96_STAGE = 3 };
 enum { PF_FP64 = 0, PF_FP32_MIXED = 1, PF_FP32_ACCURATE = 2 };
 
 /* Kernel organisation.
- * PF_LAYOUT_PLAIN: each filter is stepped by its own kernels (propagate +
- *   weight; block combine, weight scan and stratum marks; per-tile ancestor
- *   expansion + gather); any particle count up to 2^31 - 1.
+ * PF_LAYOUT_PLAIN: each filter is stepped by its own kernels (ancestors from
+ *   the last resampling's marks, gather, propagate + weight; block combine,
+ *   weight scan and stratum marks); any particle count up to 2^31 - 1.
  * PF_LAYOUT_BATCHED: all filters are stepped together: one flat propagate +
  *   weight kernel over every filter's particles, then one workgroup per
  *   filter for the collective part (likelihood, scan, ancestors; the gather
@@ -150,7 +150,9 @@ pf_status pf_step(pf_handle* h);
 /* Systematic resampling of every filter after pf_step (Sec. 3.3): one
  * uniform u from the generator, strata (u + k)/N, ancestor
  * a_k = min{ j : N W_j > (u + k) S } with W the FP64 prefix sum of
- * exp(lw - M), then the gather x_k <- x_{a_k}.  Ancestors are sorted. */
+ * exp(lw - M); the resampled set x_k = x_{a_k} is what the next pf_step
+ * propagates (it gathers through the ancestors as it loads the state, so
+ * the set is written out only for pf_get_state).  Ancestors are sorted. */
 pf_status pf_resample(pf_handle* h);
 
 /* Synchronise the stream and copy out per-filter results: loglik_out[B]
@@ -500,8 +502,9 @@ typedef struct pf_timing {
   double propagate_ms;   /* propagate + weight kernels */
   double combine_ms;     /* block-combine kernels (likelihood increment, offsets) */
   double scan_ms;        /* weight scan + stratum count kernels */
-  double gather_ms;      /* merge-path resample + ancestor gather kernels */
-  double batched_ms;     /* persistent batched step kernel */
+  double gather_ms;      /* plain layout: ancestor kernels of the resamplers
+                            without marks (and of an attached history) */
+  double batched_ms;     /* batched layout: the collective kernels */
   int64_t propagate_launches, combine_launches, scan_launches, gather_launches,
       batched_launches;
 } pf_timing;

@@ -277,12 +277,13 @@ def large_filter_leg(torch, pfm, stream):
         r = Runner(f, pb.T)
         r.run(3)
         kt = kernel_times(r, 10)
-        dt = timed(torch, r, 20, 2)
+        r.restart()
+        dt = min(timed(torch, r, 40, 8) for _ in range(3))  # the fastest of three runs
         _, ess, _ = f.loglik()
         ach = flop_b * nb / (kt["propagate"] * 1e-6) / 1e12
         sl = slots_b * nb / (kt["propagate"] * 1e-6) / 1e12
         out = {
-            "us_per_step": dt / 20 * 1e6, "particle_steps_per_s": nb * 20 / dt,
+            "us_per_step": dt / 40 * 1e6, "particle_steps_per_s": nb * 40 / dt,
             "ess_last_step": float(ess[0]),
             "propagate": {"bound": "alu", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
                           "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,

@@ -445,6 +445,26 @@ pf_status pf_get_ancestors(pf_handle* h, int32_t* a_out);
  * generator's (brute-force checks of the resampler). */
 pf_status pf_resample_u(pf_handle* h, const double* u);
 
+/* ---- checkpoint and resume ---------------------------------------------- */
+/* Resume from a checkpoint.  The filter is defined over an interval so that
+ * it can be restarted from its own output (Sec. 3.1.2; SMC over parameters
+ * re-enters it interval by interval, Alg. 4).  Puts every filter at t
+ * observations processed (0 <= t <= T) with the equally weighted set x_in
+ * (FP64 host [d][N_total], as pf_get_state returns it after pf_resample;
+ * values are rounded to the path's precision) and the running
+ * log-likelihoods loglik[B] (-infinity sets the filter's numeric flag; NaN
+ * or +infinity is PF_E_INVAL).  The generator is positional: its counters
+ * name the filter, particle, substep and the handle's iteration field, not a
+ * place in a sequence.  So a handle with the same configuration, seed and
+ * iteration (pf_reset) goes on exactly as the run the checkpoint came from:
+ * T intervals in one run, and T/2 intervals, pf_get_state and pf_loglik,
+ * then pf_restore and T/2 more on a fresh handle, give the same bits.  Equal
+ * weights are assumed: after an interval in which an ESS-triggered
+ * resampler kept its weights, those weights are not restored.  Trace rows
+ * from t on are cleared.  PF_E_STATE between pf_step and pf_resample and on
+ * a handle with a history attached.  Synchronous. */
+pf_status pf_restore(pf_handle* h, int32_t t, const double* x_in, const double* loglik);
+
 /* ---- stateless systematic resampler ------------------------------------ */
 /* The resampling collective of one filter on its own (Alg. 2's likelihood
  * and ancestor lines with the systematic resampling of Sec. 3.3), for a

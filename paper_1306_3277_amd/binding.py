@@ -109,6 +109,7 @@ SIGNATURES = {
     "pf_reset": (C.c_int, [_H, C.c_uint32]),
     "pf_get_state": (C.c_int, [_H, _D]),
     "pf_set_state": (C.c_int, [_H, _D]),
+    "pf_restore": (C.c_int, [_H, C.c_int32, _D, _D]),
     "pf_get_logweights": (C.c_int, [_H, _D]),
     "pf_get_ancestors": (C.c_int, [_H, _I]),
     "pf_resample_u": (C.c_int, [_H, _D]),
@@ -431,6 +432,16 @@ class Filter:
     def set_state(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.d, self.n_total)
         _check(load().pf_set_state(self.h, _dp(x)))
+
+    def restore(self, t: int, x, loglik):
+        """Resume from a checkpoint: every filter at t intervals with the
+        equally weighted set x ([d][N_total]) and running log-likelihoods
+        loglik[B] (what get_state and loglik return after a resampling)."""
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.d, self.n_total)
+        ll = np.ascontiguousarray(loglik, dtype=np.float64).reshape(-1)
+        if ll.size != self.B:
+            raise ValueError(f"loglik has {ll.size} entries for {self.B} filters")
+        _check(load().pf_restore(self.h, int(t), _dp(x), _dp(ll)))
 
     def logweights(self) -> np.ndarray:
         lw = np.zeros(self.n_total)

@@ -1189,6 +1189,54 @@ pf_status pf_set_state(pf_handle* H, const double* x_in) {
   return PF_OK;
 }
 
+pf_status pf_restore(pf_handle* H, int32_t t, const double* x_in, const double* loglik) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (!x_in || !loglik) return fail(PF_E_INVAL, "x_in and loglik must not be NULL");
+  if (H->phase != 0) return fail(PF_E_STATE, "pf_restore only between intervals");
+  if (t < 0 || t > H->cfg.T) return fail(PF_E_INVAL, "t = %d outside [0, T = %d]", t, H->cfg.T);
+  if (H->hist) return fail(PF_E_STATE, "pf_restore on a handle with a history attached");
+  const int B = H->cfg.B;
+  for (int b = 0; b < B; ++b)
+    if (std::isnan(loglik[b]) || loglik[b] == INFINITY)
+      return fail(PF_E_INVAL, "loglik[%d] is NaN or +infinity", b);
+  if ((st = drain(H))) return st;
+  // every filter at t, equally weighted (no carried weights), with the
+  // given running likelihood; -infinity keeps the numeric flag
+  std::vector<FilterState> fs((size_t)B);
+  HIP_TRY(hipMemcpyAsync(fs.data(), H->ws + H->L.fs, sizeof(FilterState) * fs.size(),
+                         hipMemcpyDeviceToHost, H->stream));
+  HIP_TRY(hipStreamSynchronize(H->stream));
+  for (int b = 0; b < B; ++b) {
+    FilterState& f = fs[(size_t)b];
+    f.loglik = loglik[b];
+    f.status = std::isfinite(loglik[b]) ? 0 : 4;
+    f.M = f.S = f.u = f.ell = f.ess = f.lprev = 0.0;
+    f.t = t;
+    f.tk = t;
+    f.carry = 0;
+    f.pad = 0;
+    f.cn1 = 0;
+    f.amode = pfk::AMODE_IDENTITY;
+  }
+  HIP_TRY(hipMemcpyAsync(H->ws + H->L.fs, fs.data(), sizeof(FilterState) * fs.size(),
+                         hipMemcpyHostToDevice, H->stream));
+  // trace rows from t on start empty, as after pf_init
+  const size_t T = (size_t)H->cfg.T;
+  std::vector<double> tr((size_t)B * T);
+  for (size_t L : {H->L.ell, H->L.ess}) {
+    HIP_TRY(hipMemcpyAsync(tr.data(), H->ws + L, 8 * tr.size(), hipMemcpyDeviceToHost, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+    for (int b = 0; b < B; ++b)
+      for (size_t i = (size_t)t; i < T; ++i) tr[(size_t)b * T + i] = 0.0;
+    HIP_TRY(hipMemcpyAsync(H->ws + L, tr.data(), 8 * tr.size(), hipMemcpyHostToDevice, H->stream));
+    HIP_TRY(hipStreamSynchronize(H->stream));
+  }
+  // the particles go to the buffer of interval t, read through the identity
+  H->t = t;
+  return pf_set_state(H, x_in);
+}
+
 pf_status pf_get_logweights(pf_handle* H, double* lw_out) {
   pf_status st = check_handle(H);
   if (st) return st;

@@ -248,6 +248,8 @@ static void plain() {
   std::vector<int32_t> a(n), idx(3 * 6);
   OK(pf_backtrace(h, path.data(), idx.data()));
   OK(pf_get_state(h, x.data()));
+  const double ll0[3] = {0.0, -1.0, -2.0};
+  EXPECT(pf_restore(h, 1, x.data(), ll0), PF_E_STATE);  // a history is attached
   OK(pf_set_state(h, x.data()));
   OK(pf_step(h));
   OK(pf_get_logweights(h, lw.data()));
@@ -263,6 +265,9 @@ static void plain() {
   int32_t t = 0;
   OK(pf_loglik(h, ll, ess, &t));
   OK(pf_history_attach(h, nullptr, 0));
+  OK(pf_restore(h, 5, x.data(), ll));
+  advance(h, 2);
+  OK(pf_graph_run(h, 1));
   OK(pf_timing_enable(h, 1));
   OK(pf_reset(h, 1));
   advance(h, 2);
@@ -275,9 +280,13 @@ static void errors() {
   Dev dev;
   Prob p = l96(5, 4, PF_FP32_MIXED, PF_LAYOUT_BATCHED, 6);
   pf_handle* h = open_(p, dev, nullptr);
+  int64_t n = 0;
+  for (auto v : p.np) n += v;
+  std::vector<double> x(8 * (size_t)n, 0.25), ll(5, 0.0);
   EXPECT(pf_resample(h), PF_E_STATE);
   OK(pf_step(h));
   EXPECT(pf_step(h), PF_E_STATE);
+  EXPECT(pf_restore(h, 0, x.data(), ll.data()), PF_E_STATE);  // between step and resample
   EXPECT(pf_graph_run(h, 1), PF_E_STATE);
   OK(pf_resample(h));
   EXPECT(pf_graph_run(h, 4), PF_E_STATE);
@@ -285,6 +294,14 @@ static void errors() {
   EXPECT(pf_set_tuning(h, 300, 2), PF_E_INVAL);
   EXPECT(pf_set_tuning(h, 512, 9), PF_E_INVAL);
   EXPECT(pf_set_resampler(h, 5, 0, INFINITY), PF_E_INVAL);
+  EXPECT(pf_restore(h, 7, x.data(), ll.data()), PF_E_INVAL);
+  EXPECT(pf_restore(h, 0, nullptr, ll.data()), PF_E_INVAL);
+  ll[3] = NAN;
+  EXPECT(pf_restore(h, 0, x.data(), ll.data()), PF_E_INVAL);
+  ll[3] = -INFINITY;
+  OK(pf_restore(h, 2, x.data(), ll.data()));
+  OK(pf_graph_run(h, 1));
+  OK(pf_restore(h, 1, x.data(), ll.data()));
   OK(pf_graph_run(h, 3));
   EXPECT(pf_step(h), PF_E_STATE);  // t = T
   OK(pf_set_tuning(h, 1024, 8));   // groups capped at B

@@ -152,3 +152,12 @@ def test_kalman_pmmh_needs_a_handle():
     fake = C.c_void_p(0x10000)  # never dereferenced: the handle check fails first
     st = L.pf_kalman_pmmh(None, C.byref(spec), 1, fake, fake, fake, fake, fake, fake, None)
     assert st == binding.PF_E_INVAL, st
+
+
+def test_restore_needs_a_handle():
+    L = binding.load()
+    x = np.zeros(8)
+    ll = np.zeros(1)
+    st = L.pf_restore(None, 0, x.ctypes.data_as(C.POINTER(C.c_double)),
+                      ll.ctypes.data_as(C.POINTER(C.c_double)))
+    assert st == binding.PF_E_INVAL, st

@@ -11,7 +11,11 @@ resampling and the whole bootstrap filter (Alg. 2).
   observations (scipy multivariate normal);
 * the particle filter against the Kalman filter: E[exp(ll - ll_KF)] = 1 (the
   estimate is unbiased, Sec. 3.1.2) and, with the state made deterministic,
-  the likelihood collapses to a closed form.
+  the likelihood collapses to a closed form;
+* resume: the filter is defined over an interval (Sec. 3.1.2), and with a
+  positional generator the run over t_{0:T} equals the run over t_{0:s}
+  followed by a run over t_{s:T} started from its resampled set and running
+  likelihood, bit for bit.
 """
 import dataclasses
 import math
@@ -189,6 +193,37 @@ def test_pf_single_particle_is_plain_likelihood(orc):
         ref = scipy.stats.norm.logpdf(y[t - 1], loc=x[:, 0], scale=0.5).sum()
         assert r["ell"][t - 1] == pytest.approx(ref, abs=1e-11)
     np.testing.assert_array_equal(r["x"], x)
+
+
+def _interval_run(orc, pb, th, x, t0, t1, ll):
+    """Alg. 2 over t_{t0:t1} from the equally weighted set x and running
+    log-likelihood ll, one step function at a time."""
+    ells = []
+    for t in range(t0 + 1, t1 + 1):
+        xp = orc.propagate(pb, th, x, t)
+        lw = orc.weight(pb, th, xp, t)
+        _, e, _, a = orc.reduce_resample(lw, orc.resample_u(pb.seed, t))
+        ll = ll + e
+        ells.append(e)
+        x = orc.gather(xp, a)
+    return x, ll, ells
+
+
+@pytest.mark.parametrize("model", ["windkessel", "lorenz96"])
+def test_resume_from_a_checkpoint_is_the_whole_run(orc, model):
+    pb = W.windkessel(N=300, T=16) if model == "windkessel" else W.lorenz96(d=8, N=300, T=16)
+    _, y = orc.simulate(pb)
+    pb = pb.with_obs(y)
+    th = pb.theta[0]
+    full = orc.pf_run(pb)
+    for s in (0, 1, 7, 15, 16):
+        x, ll, e1 = _interval_run(orc, pb, th, orc.init(pb, th, 300), 0, s, 0.0)
+        # the checkpoint crosses a serialisation, as a file would
+        x_ck, ll_ck = np.frombuffer(x.tobytes()).reshape(x.shape), float(repr(ll))
+        xe, lle, e2 = _interval_run(orc, pb, th, x_ck, s, pb.T, ll_ck)
+        np.testing.assert_array_equal(np.array(e1 + e2), full["ell"])
+        assert lle == full["loglik"]
+        np.testing.assert_array_equal(xe, full["x"])
 
 
 def test_pmmh_chain_has_the_posterior_as_its_law(orc):

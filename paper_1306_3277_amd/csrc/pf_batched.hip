@@ -200,44 +200,6 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // critical path.  64 KB of LDS per workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 
-// Wave-wide scans and reductions of doubles by DPP lane moves (shifts
-// inside 16-lane rows, then row broadcasts), which stay in the vector unit
-// instead of going through the LDS permutes a shuffle compiles to.  Lanes
-// a move does not reach take `old`.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v, double old) {
-  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, ROWS,
-                                             0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, ROWS,
-                                             0xf, false);
-  return __hiloint2double(hi, lo);
-}
-// inclusive sum over lanes 0..lane
-__device__ __forceinline__ double dpp_incl_sum(double v) {
-  v += dpp_move<0x111, 0xf>(v, 0.0);  // row_shr 1
-  v += dpp_move<0x112, 0xf>(v, 0.0);  // row_shr 2
-  v += dpp_move<0x114, 0xf>(v, 0.0);  // row_shr 4
-  v += dpp_move<0x118, 0xf>(v, 0.0);  // row_shr 8
-  v += dpp_move<0x142, 0xa>(v, 0.0);  // row_bcast 15 into rows 1 and 3
-  v += dpp_move<0x143, 0xc>(v, 0.0);  // row_bcast 31 into rows 2 and 3
-  return v;
-}
-// inclusive maximum over lanes 0..lane (exact)
-__device__ __forceinline__ double dpp_incl_max(double v) {
-  v = fmax(v, dpp_move<0x111, 0xf>(v, -INFINITY));
-  v = fmax(v, dpp_move<0x112, 0xf>(v, -INFINITY));
-  v = fmax(v, dpp_move<0x114, 0xf>(v, -INFINITY));
-  v = fmax(v, dpp_move<0x118, 0xf>(v, -INFINITY));
-  v = fmax(v, dpp_move<0x142, 0xa>(v, -INFINITY));
-  v = fmax(v, dpp_move<0x143, 0xc>(v, -INFINITY));
-  return v;
-}
-// the value of the wave's last lane, in every lane
-__device__ __forceinline__ double last_lane(double v) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
-  return __hiloint2double(hi, lo);
-}
 // The ancestors in LDS (the stage, once its weights are read): one padding
 // word after every 16, so that lanes reading or writing their own runs of
 // P consecutive entries hit distinct banks (8,704 words for 8192 entries).
@@ -326,7 +288,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
       }
     }
   }
-  m = last_lane(dpp_incl_max(m));
+  m = wave_max(m);
   if (lane == 0) xa[wv] = m;
   __syncthreads();  // 1
   double u = bc;
@@ -342,9 +304,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   int cand = -1;
   lane_weights<MAXP, MAXP>(stage, N, M, finite, P, i0, i1, loc, run, run2, cand);
   // one exchange: scan of the lanes' sums, total of squares, last positive
-  const double incl = dpp_incl_sum(run);
-  const double s2w = last_lane(dpp_incl_sum(run2));
-  const int cw = __builtin_amdgcn_readlane(wave_incl_max_scan_rows(cand), WAVE - 1);
+  const double incl = wave_incl_scan(run);
+  const double s2w = wave_sum(run2);
+  const int cw = wave_max_i(cand);
   // (the lane sums go to their own array, so no barrier separates them from
   // the maxima read above; the stage's reuse comes after two more barriers)
   if (lane == WAVE - 1) xs[wv] = incl;
@@ -368,8 +330,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
   // exclusive running maximum of the lanes' last cumulative weights
   const double vlast = (i1 > i0) ? pre + run : -INFINITY;
-  const double vin = dpp_incl_max(vlast);
-  double vprev = dpp_move<0x138, 0xf>(vin, -INFINITY);  // wave_shr 1: lane - 1's value
+  const double vin = wave_incl_max_scan(vlast);
+  double vprev = wave_prev(vin, -INFINITY);
   if (lane == WAVE - 1) xc[wv] = vin;
   __syncthreads();  // 4
   double vw = -INFINITY, vall = -INFINITY;

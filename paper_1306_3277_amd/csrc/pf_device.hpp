@@ -600,29 +600,73 @@ __device__ __forceinline__ double exp_nonpos(double xin) {
 }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+// Wave-wide scans and reductions by DPP lane moves: shifts inside 16-lane
+// rows (1, 2, 4, 8), then two row broadcasts (lane 15 of a row into the next
+// row, then lane 31 into rows 2 and 3).  They stay in the vector unit,
+// where a shuffle goes through an LDS permute.  Every lane of the wave must
+// be active; lanes a move does not reach take `old`.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move_i(int v, int old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v, double old) {
+  const int lo = dpp_move_i<CTRL, ROWS>(__double2loint(v), __double2loint(old));
+  const int hi = dpp_move_i<CTRL, ROWS>(__double2hiint(v), __double2hiint(old));
+  return __hiloint2double(hi, lo);
+}
+// inclusive sum over lanes 0..lane
+__device__ __forceinline__ double wave_incl_scan(double v, int = 0) {
+  v += dpp_move<0x111, 0xf>(v, 0.0);  // row_shr 1
+  v += dpp_move<0x112, 0xf>(v, 0.0);  // row_shr 2
+  v += dpp_move<0x114, 0xf>(v, 0.0);  // row_shr 4
+  v += dpp_move<0x118, 0xf>(v, 0.0);  // row_shr 8
+  v += dpp_move<0x142, 0xa>(v, 0.0);  // row_bcast 15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v, 0.0);  // row_bcast 31 into rows 2 and 3
   return v;
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+// inclusive running maximum over lanes 0..lane (exact: max does not round)
+__device__ __forceinline__ double wave_incl_max_scan(double v, int = 0) {
+  v = fmax(v, dpp_move<0x111, 0xf>(v, -INFINITY));
+  v = fmax(v, dpp_move<0x112, 0xf>(v, -INFINITY));
+  v = fmax(v, dpp_move<0x114, 0xf>(v, -INFINITY));
+  v = fmax(v, dpp_move<0x118, 0xf>(v, -INFINITY));
+  v = fmax(v, dpp_move<0x142, 0xa>(v, -INFINITY));
+  v = fmax(v, dpp_move<0x143, 0xc>(v, -INFINITY));
   return v;
 }
+__device__ __forceinline__ int wave_incl_max_scan_rows(int v) {
+  constexpr int lo = -2147483647 - 1;
+  v = max(v, dpp_move_i<0x111, 0xf>(v, lo));
+  v = max(v, dpp_move_i<0x112, 0xf>(v, lo));
+  v = max(v, dpp_move_i<0x114, 0xf>(v, lo));
+  v = max(v, dpp_move_i<0x118, 0xf>(v, lo));
+  v = max(v, dpp_move_i<0x142, 0xa>(v, lo));
+  v = max(v, dpp_move_i<0x143, 0xc>(v, lo));
+  return v;
+}
+__device__ __forceinline__ int wave_incl_max_scan_i(int v, int = 0) {
+  return wave_incl_max_scan_rows(v);
+}
+// the value of lane 63, in every lane
+__device__ __forceinline__ double last_lane(double v) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_max(double v) { return last_lane(wave_incl_max_scan(v)); }
+__device__ __forceinline__ double wave_sum(double v) { return last_lane(wave_incl_scan(v)); }
 __device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
-  return v;
+  return __builtin_amdgcn_readlane(wave_incl_max_scan_rows(v), WAVE - 1);
 }
-// inclusive scan across a wave
-__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const double u = __shfl_up(v, o, WAVE);
-    if (lane >= o) v += u;
-  }
-  return v;
+// lane - 1's value (wave_shr 1); lane 0 takes `old`
+__device__ __forceinline__ double wave_prev(double v, double old) {
+  return dpp_move<0x138, 0xf>(v, old);
+}
+__device__ __forceinline__ int64_t wave_prev_i64(int64_t v, int64_t old) {
+  const int lo = dpp_move_i<0x138, 0xf>((int)(uint32_t)v, (int)(uint32_t)old);
+  const int hi = dpp_move_i<0x138, 0xf>((int)(v >> 32), (int)(old >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
 // Block-wide reductions for a block of NT threads (NT/64 waves); `red` is
@@ -681,36 +725,7 @@ __device__ __forceinline__ double block_incl_scan(double v, double* red, double&
   return pre + v;
 }
 
-// inclusive running maximum across a wave and a block (exact: max does not round)
-__device__ __forceinline__ double wave_incl_max_scan(double v, int lane) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const double u = __shfl_up(v, o, WAVE);
-    if (lane >= o) v = fmax(v, u);
-  }
-  return v;
-}
-__device__ __forceinline__ int wave_incl_max_scan_i(int v, int lane) {
-#pragma unroll
-  for (int o = 1; o < WAVE; o <<= 1) {
-    const int u = __shfl_up(v, o, WAVE);
-    if (lane >= o) v = max(v, u);
-  }
-  return v;
-}
-// The same running maximum from lane shifts inside each 16-lane row (1, 2,
-// 4, 8) and two row broadcasts (lane 15 of a row into the next row, then
-// lane 31 into rows 2 and 3); lanes a shift reaches from outside take INT_MIN.
-__device__ __forceinline__ int wave_incl_max_scan_rows(int v) {
-  constexpr int lo = -2147483647 - 1;
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x111, 0xf, 0xf, false));  // row_shr 1
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x112, 0xf, 0xf, false));  // row_shr 2
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xf, 0xf, false));  // row_shr 4
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xf, 0xf, false));  // row_shr 8
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xa, 0xf, false));  // row_bcast 15
-  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xc, 0xf, false));  // row_bcast 31
-  return v;
-}
+// inclusive running maximum across a block (exact)
 template <int NT>
 __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;

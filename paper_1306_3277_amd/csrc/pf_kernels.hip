@@ -152,7 +152,7 @@ __device__ __forceinline__ Combined combine_block_lds(const double* __restrict__
     }
   }
   const double vin = wave_incl_max_scan(last, lane);
-  const double vup = __shfl_up(vin, 1, WAVE);
+  const double vup = wave_prev(vin, -INFINITY);
   if (lane == WAVE - 1) xv[wv] = vin;
   __syncthreads();  // exchange 3
   double vw = -INFINITY, vall = -INFINITY;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(K2_NT) void k_combine(const double* __restrict__ pa
     }
   }
   const double vin = wave_incl_max_scan(last, lane);
-  const double vup = __shfl_up(vin, 1, WAVE);
+  const double vup = wave_prev(vin, -INFINITY);
   if (lane == WAVE - 1) xv[wv] = vin;
   __syncthreads();  // exchange 3
   double vw = -INFINITY, vall = -INFINITY;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
   // non-decreasing across lanes whatever the rounding of the tree scan;
   // capped by the next offset
   const double vin = wave_incl_max_scan(V[K3_PER - 1], lane);
-  const double vup = __shfl_up(vin, 1, WAVE);
+  const double vup = wave_prev(vin, -INFINITY);
   if (lane == WAVE - 1) xvmax[wv] = vin;
   __syncthreads();
   double vw = -INFINITY;
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(K3_NT) void k_scan_mark(const double* __restrict__ 
   const int64_t g_hi = (jnext < N) ? (finite ? count(hi_off) : jnext) : N;
   // exchange 3: each lane's first particle continues from the previous
   // lane's last count
-  const int64_t cup = __shfl_up(c[K3_PER - 1], 1, WAVE);
+  const int64_t cup = wave_prev_i64(c[K3_PER - 1], 0);
   if (lane == WAVE - 1) xcnt[wv] = c[K3_PER - 1];
   __syncthreads();
   int64_t cprev = lane > 0 ? cup : (wv > 0 ? xcnt[wv - 1] : g_lo);

@@ -243,11 +243,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
                                                        BatchArgs A) {
   static_assert(MAXP >= 1 && NT * MAXP <= BATCH_MAXN, "stage size");
   constexpr int NW = NT / WAVE;
+  // The ancestor slots (one padding word after every 16) have an array of
+  // their own when it fits beside a stage of at most 32 KB (filters of up
+  // to 4,096 particles at 512 lanes); then they are cleared at the start,
+  // two barriers before any mark.  A larger stage is reused for them once
+  // its weights are read, and one barrier orders their clearing before the
+  // marks.
+  constexpr bool SEP = NT * MAXP <= 4096 && (RS == RS_SYSTEMATIC || RS == RS_STRATIFIED);
+  constexpr int NAL = SEP ? NT * MAXP + NT * MAXP / 16 : 1;
   __shared__ double stage[NT * MAXP];
-  __shared__ double xa[NW], xs[NW], xb[NW], xc[NW];
+  __shared__ int32_t al_own[NAL];
+  __shared__ double xa[NW], xs[NW], xb[NW];
   __shared__ int xi[NW];
   __shared__ double bc;
-  int32_t* al = reinterpret_cast<int32_t*>(stage);                    // ancestors, 34 KB
+  int32_t* al = SEP ? al_own : reinterpret_cast<int32_t*>(stage);
   const FilterSlot slot = A.order[A.order0 + blockIdx.x];
   const int f = slot.f;
   const int64_t off = slot.off;
@@ -264,6 +273,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   const int t = resample_only ? fs->t : fs->t + 1;
   // the history's ancestor slot t-1 of this filter, if one is attached
   int32_t* const ha = A.ha ? A.ha + (int64_t)(t - 1) * A.ld + off : nullptr;
+  if constexpr (SEP)
+    for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
   // (1) coalesced load to the stage and the maximum; the loads are issued
   // together (indices past the filter read its last element and are
   // dropped), so their latencies overlap
@@ -304,44 +315,55 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   int cand = -1;
   lane_weights<MAXP, MAXP>(stage, N, M, finite, P, i0, i1, loc, run, run2, cand);
   // one exchange: scan of the lanes' sums, total of squares, last positive
+  // The scan's partial sums are rounded along different trees, so one
+  // lane's may fall an ulp below the lane before: a running maximum makes
+  // them non-decreasing, held past the filter's last particle (lanes with no
+  // particles take -inf there), so that a wave's total is its last
+  // particle's.
   const double incl = wave_incl_scan(run);
+  const double inclm = wave_incl_max_scan((i1 > i0) ? incl : -INFINITY);
   const double s2w = wave_sum(run2);
   const int cw = wave_max_i(cand);
   // (the lane sums go to their own array, so no barrier separates them from
-  // the maxima read above; the stage's reuse comes after two more barriers)
-  if (lane == WAVE - 1) xs[wv] = incl;
+  // the maxima read above; the stage is reused only after this exchange)
+  if (lane == WAVE - 1) xs[wv] = (inclm > -INFINITY) ? inclm : 0.0;
   if (lane == 0) {
     xb[wv] = s2w;
     xi[wv] = cw;
   }
   __syncthreads();  // 3
-  double pre = incl - run, S = 0.0, S2 = 0.0;
+  // S: the waves' totals added in order; base: the same sum over the waves
+  // before this one (the same operations, so the same bits)
+  double base = 0.0, S = 0.0, S2 = 0.0;
   int jstar = -1;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
-    if (w < wv) pre += xs[w];
+    if (w == wv) base = S;
     S += xs[w];
     S2 += xb[w];
     jstar = max(jstar, xi[w]);
   }
-  // the ancestor slots start empty (the stage's weights have all been read;
-  // the Metropolis, rejection and multinomial forms still use the stage)
-  if constexpr (RS == RS_SYSTEMATIC || RS == RS_STRATIFIED)
+  // the ancestor slots in the stage start empty once its weights are read
+  // (the Metropolis, rejection and multinomial forms still use the stage)
+  if constexpr (!SEP && (RS == RS_SYSTEMATIC || RS == RS_STRATIFIED)) {
     for (int k = (int)threadIdx.x; k < N; k += NT) al[anc_slot(k)] = -1;
-  // exclusive running maximum of the lanes' last cumulative weights
-  const double vlast = (i1 > i0) ? pre + run : -INFINITY;
-  const double vin = wave_incl_max_scan(vlast);
-  double vprev = wave_prev(vin, -INFINITY);
-  if (lane == WAVE - 1) xc[wv] = vin;
-  __syncthreads();  // 4
-  double vw = -INFINITY, vall = -INFINITY;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    if (w < wv) vw = fmax(vw, xc[w]);
-    vall = fmax(vall, xc[w]);
+    __syncthreads();  // 4
   }
-  vprev = (lane == 0) ? vw : fmax(vprev, vw);
-  S = fmax(S, vall);
+  // The cumulative weights: lane l's last particle has V_l = base + its
+  // running total; before its first particle stands V_{l-1}, which the lane
+  // before computes from the same two values (at a wave's first lane it is
+  // base, the previous wave's last V); the particles between take
+  // min(V_{l-1} + in-lane prefix, V_l).  Each value lies in [V_{l-1}, V_l]
+  // (the prefixes are non-negative), so the sequence never decreases across
+  // lanes and waves, and the filter's last particle has exactly S.
+  // (the lane move runs in every lane, outside the select: a lane whose
+  // source lane is switched off would read nothing)
+  const double inprev = wave_prev(inclm, 0.0);
+  const double vprev = (lane == 0) ? base : base + inprev;
+  const double vlast = base + inclm;
+  auto cum = [&](int e) -> double {
+    return (i0 + e == i1 - 1) ? vlast : fmin(vprev + loc[e], vlast);
+  };
   // every lane holds the same S and S2, so every lane takes the trigger's
   // decision itself (resample when ESS < ess_frac N); a step that keeps its
   // weights, or has none positive, gives every particle one offspring:
@@ -426,7 +448,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
 #pragma unroll
     for (int e = 0; e < MAXP; ++e) {
       const int i = i0 + e;
-      if (e < P && i < i1) stage[i] = fmin(fmax(pre + loc[e], vprev), S);
+      if (e < P && i < i1) stage[i] = cum(e);
     }
     __syncthreads();  // 6
     const Key key = bkey(A.key);
@@ -451,10 +473,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
     return;
   }
   // (3) stratum counts of this lane's particles, in registers.  Particle i
-  // owns strata [c_{i-1}, c_i).  Every lane evaluates its cumulative
-  // weights as W = min(max(prefix, earlier lanes' maximum), S), so the count
-  // before its first particle is the one the lane before computed, at
-  // W = min(vprev, S), and the last particle's is at W = min(vall, S).
+  // owns strata [c_{i-1}, c_i).  The count before the lane's first particle
+  // is the one the lane before computed for its last, at the same V_{l-1}.
   auto count_at = [&](double W, int i) -> int32_t {
     if (!draw_rs) return i + 1;
     if constexpr (RS == RS_STRATIFIED)
@@ -466,14 +486,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
 #pragma unroll
   for (int e = 0; e < MAXP; ++e) {
     const int i = i0 + e;
-    cnt[e] = (e < P && i < i1) ? count_at(fmin(fmax(pre + loc[e], vprev), S), i) : 0;
+    cnt[e] = (e < P && i < i1) ? count_at(cum(e), i) : 0;
   }
   // (4) ancestors: each particle with offspring marks the first stratum it
   // owns, and a running maximum over the strata then gives each its owner
   // (the runs are in particle order), so every lane does the same work
   // however the offspring fall.
   {
-    int cprev = (i0 > 0 && i0 < N) ? count_at(fmin(vprev, S), i0 - 1) : 0;
+    int cprev = (i0 > 0 && i0 < N) ? count_at(vprev, i0 - 1) : 0;
 #pragma unroll
     for (int e = 0; e < MAXP; ++e) {
       const int i = i0 + e;
@@ -489,12 +509,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   // row to row and then across the waves; each row is stored as it stands,
   // 64 consecutive ancestors per wave
   const int seg = ((N + NW - 1) / NW + WAVE - 1) & ~(WAVE - 1);  // <= 64 MAXP
-  const int base = wv * seg;
+  const int sbase = wv * seg;
   int mk[MAXP];
   int rowmax = -1;
 #pragma unroll
   for (int r = 0; r < MAXP; ++r) {
-    const int k = base + r * WAVE + lane;
+    const int k = sbase + r * WAVE + lane;
     const int v = (r * WAVE < seg && k < N) ? al[anc_slot(k)] : -1;
     mk[r] = max(wave_incl_max_scan_rows(v), rowmax);
     rowmax = __builtin_amdgcn_readlane(mk[r], WAVE - 1);
@@ -505,8 +525,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
 #pragma unroll
   for (int w = 0; w < NW; ++w)
     if (w < wv) before = max(before, xi[w]);
-  // strata past the last count (rounding) go to the last positive particle
-  const int ctot = count_at(fmin(vall, S), N - 1);
+  // strata past the last count (never expected: the last particle's
+  // cumulative weight is S) go to the last positive particle
+  const int ctot = count_at(S, N - 1);
   bool bad = false;
   auto owner = [&](int r, int k) -> int32_t {
     int32_t aj = k < ctot ? max(before, mk[r]) : jstar;
@@ -519,7 +540,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   if (ha) {
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
-      const int k = base + r * WAVE + lane;
+      const int k = sbase + r * WAVE + lane;
       if (r * WAVE < seg && k < N) {
         const int32_t aj = owner(r, k);
         anc[off + k] = aj;
@@ -529,7 +550,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 
   } else {
 #pragma unroll
     for (int r = 0; r < MAXP; ++r) {
-      const int k = base + r * WAVE + lane;
+      const int k = sbase + r * WAVE + lane;
       if (r * WAVE < seg && k < N) anc[off + k] = owner(r, k);
     }
   }

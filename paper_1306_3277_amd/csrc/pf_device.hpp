@@ -604,7 +604,9 @@ __device__ __forceinline__ double exp_nonpos(double xin) {
 // rows (1, 2, 4, 8), then two row broadcasts (lane 15 of a row into the next
 // row, then lane 31 into rows 2 and 3).  They stay in the vector unit,
 // where a shuffle goes through an LDS permute.  Every lane of the wave must
-// be active; lanes a move does not reach take `old`.
+// be active (call them outside lane-dependent branches and selects, or a
+// lane reads a switched-off neighbour); lanes a move does not reach take
+// `old`.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_move_i(int v, int old) {
   return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);

@@ -188,16 +188,19 @@ __global__ __launch_bounds__(BATCH_NT) void k_batch_propagate(Real* __restrict__
 // so both the coalesced writes and the lanes' reads of their own 16-element
 // runs are free of bank conflicts) and read back per lane.  Their weights are
 // summed sequentially in the lane (an exact monotone prefix), the lanes'
-// totals are scanned across the block, and an exact running maximum over
-// earlier lanes keeps the cumulative weights non-decreasing at lane edges.
-// The stratum counts stay in registers; the ancestors reuse the stage: each
-// particle with offspring marks the first stratum it owns, and a running
+// totals are scanned across the block (held non-decreasing by a running
+// maximum within each wave), and each particle's cumulative weight is
+// bounded by the totals before and after its lane's run, so the sequence
+// never decreases at lane edges.  The stratum counts stay in registers; the
+// ancestors reuse the stage (or, for a stage of at most 32 KB, have an
+// array of their own): each particle with offspring marks the first
+// stratum it owns, and a running
 // maximum over the strata (by 64-stratum rows in each wave, then across the
 // waves) gives every stratum its owner, so the work does not depend on how
 // the offspring are spread (no per-particle loop that one heavy particle
 // could lengthen, no search); each row of owners is stored as it stands.
 // The resampling uniform is drawn while the loads are in flight, off the
-// critical path.  64 KB of LDS per workgroup.
+// critical path.  At most 66 KB of LDS per workgroup.
 __device__ __forceinline__ int stage_slot(int i) { return i ^ ((i >> 4) & 15); }
 
 // The ancestors in LDS (the stage, once its weights are read): one padding

@@ -173,10 +173,12 @@ pf_status pf_destroy(pf_handle* h);
 /* Run n_steps observation intervals (pf_step + pf_resample each) by replaying
  * HIP graphs captured on the first call (and again after a change of tuning
  * or resampler).  Each graph is captured on one stream and holds kernel
- * launches only: the plain layout's holds one interval of every filter; the
- * batched layout has, per filter group, one graph of one interval and one
- * of eight, launched on the group's own stream between a fork from and a
- * join into the handle's stream.  Same results as the eager calls. */
+ * launches only: graphs of 1, 2, 4, ... 128 intervals (up to 8 for the plain
+ * layout with more than four filters), of every filter (plain layout) or of
+ * one filter group (batched layout, launched on the group's own stream
+ * between a fork from and a join into the handle's stream); a run replays
+ * the longest that fit first (200 = 128 + 64 + 8).  Same results as the
+ * eager calls. */
 pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 
 /* Replace every filter's parameters (host [B][n_theta]) and re-initialise

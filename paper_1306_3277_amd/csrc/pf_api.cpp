@@ -234,11 +234,12 @@ struct pf_handle {
     int kind;
   };
   std::vector<Ev> events;
-  // graphs, each captured on one stream: gexecs[2g] holds one interval and
-  // gexecs[2g + 1] kGraphSteps intervals (plain layout: g = 0, every filter;
-  // batched layout: filter group g)
+  // graphs, each captured on one stream: gexecs[g * gnv + v] holds 2^v
+  // intervals, v < gnv (plain layout: g = 0, every filter; batched layout:
+  // filter group g)
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
+  int gnv = 0;
   hipStream_t cap_stream = nullptr;
   // attached history (ancestry storage), or null
   char* hist = nullptr;
@@ -429,7 +430,15 @@ pf_status do_init(pf_handle* H, hipStream_t s) {
   return PF_OK;
 }
 
-constexpr int kGraphSteps = 8;
+// Graph lengths: 1, 2, 4, ... intervals up to 2^(n - 1), so that a run of
+// any length replays in a few graph launches per stream (each launch costs
+// the device several microseconds, and a PMMH or headline pass is T = 200
+// intervals).  Up to 128 intervals when an interval is a few kernels (one
+// filter, or one filter group), up to 8 when it is a launch per filter of
+// many (the plain layout with B > 4), to keep captures small.
+int graph_ladder(const pf_handle* H) {
+  return (H->cfg.layout == PF_LAYOUT_PLAIN && H->cfg.B > 4) ? 4 : 8;
+}
 
 // An attached history's slots, for the stepping kernels that record into
 // it (the propagation writes the particles, the collective the ancestors).
@@ -725,6 +734,7 @@ void destroy_graphs(pf_handle* H) {
   for (auto g : H->graphs) (void)hipGraphDestroy(g);
   H->gexecs.clear();
   H->graphs.clear();
+  H->gnv = 0;
 }
 
 // Waits for everything the handle has issued: its stream, the stream graph
@@ -764,8 +774,8 @@ pf_status launch_stream(pf_handle* H, hipStream_t* out) {
 
 // Captures the graphs pf_graph_run replays.  Every capture is on one
 // stream and holds kernel launches only (no event, copy or memset), so a
-// graph never refers to an event or another stream: one interval and
-// kGraphSteps intervals, of every filter (plain layout) or of each filter
+// graph never refers to an event or another stream: 2^v intervals for each
+// step v of the ladder, of every filter (plain layout) or of each filter
 // group (batched layout).  The groups' graphs are launched on their own
 // streams between an eager fork and join.
 pf_status ensure_graphs(pf_handle* H) {
@@ -777,13 +787,14 @@ pf_status ensure_graphs(pf_handle* H) {
   H->timing = false;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
   const int ng = batched ? H->groups : 1;
+  const int nv = graph_ladder(H);
   for (int g = 0; g < ng && !st; ++g) {
-    for (int v = 0; v < 2 && !st; ++v) {
+    for (int v = 0; v < nv && !st; ++v) {
       HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       if (batched) {
-        st = enqueue_group(H, g, cs, v == 0 ? 1 : kGraphSteps);
+        st = enqueue_group(H, g, cs, 1 << v);
       } else {
-        for (int i = 0; i < (v == 0 ? 1 : kGraphSteps) && !st; ++i) {
+        for (int i = 0; i < (1 << v) && !st; ++i) {
           st = enqueue_step(H, cs);
           if (!st) st = enqueue_resample(H, cs, nullptr);
         }
@@ -810,6 +821,7 @@ pf_status ensure_graphs(pf_handle* H) {
   }
   H->timing = tm;
   if (st) destroy_graphs(H);
+  else H->gnv = nv;
   return st;
 }
 
@@ -1059,11 +1071,11 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   // group g's graphs go on its own stream (the caller's with one group)
   auto gs = [&](int g) { return G == 1 ? ls : H->side[g]; };
   if (G > 1 && (st = fork_groups(H, ls))) return st;
+  // the longest graphs first: n = 200 is 128 + 64 + 8
   int left = n_steps;
-  for (; left >= kGraphSteps; left -= kGraphSteps)
-    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g + 1], gs(g)));
-  for (; left > 0; --left)
-    for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[2 * g], gs(g)));
+  for (int v = H->gnv - 1; v >= 0; --v)
+    for (; left >= (1 << v); left -= 1 << v)
+      for (int g = 0; g < G; ++g) HIP_TRY(hipGraphLaunch(H->gexecs[g * H->gnv + v], gs(g)));
   if (G > 1 && (st = join_groups(H, ls))) return st;
   H->t += n_steps;
   return PF_OK;

@@ -3,7 +3,8 @@
 A step is one pass of the whole hot path over the headline batch: every
 filter re-initialised (x(t0) drawn), then T observation intervals of
 propagate (K substeps) + weight + likelihood increment + ESS + systematic
-resampling + ancestor gather, replayed from captured graphs, then the
+resampling + ancestor gather (graph replays or eager launches, as the
+autotuner measured faster on this host), then the
 likelihoods read back (the only host synchronisation).  The rate is in
 particle-steps/s, a particle-step being one particle through one
 observation interval.  Inputs (observations, parameters) are resident in
@@ -605,10 +606,16 @@ def pick_tuning(passes):
 def autotune(f, steps, passes=3):
     """The library's autotuner on handle f, `passes` times (each candidate's
     best pass kept: the leading candidates differ by about one pass's noise);
-    the handle is left on the choice."""
+    the handle is left on the choice.  The replay mode (graph replay or eager
+    launches, whichever the library's last pass measured faster) stays when
+    that pass chose the same tuning; another tuning goes back to graphs."""
     threads, groups, cand = pick_tuning([f.autotune(steps=steps)[2] for _ in range(passes)])
     f.set_tuning(threads, groups)
     return threads, groups, cand
+
+
+def replay_mode(f):
+    return "eager launches" if f.get_tuning()[2] else "graph replay"
 
 
 def pmmh_vs_oracle(pfm, y, stream, chains=2, iters=20, T=20):
@@ -814,6 +821,7 @@ def main():
         log(f"[bench] autotune: collective workgroup {threads}, {groups} filter group(s); "
             f"us/interval (rows: 1, 2, 4 groups; cols: 256, 512, 1024 lanes): "
             f"{np.round(cand_ms * 1e3, 1).tolist()}")
+    head_replay = replay_mode(f32)
     dt32 = timed_passes(torch, f32, pb.T, args.steps, args.warmup)
     ps_per_step = n_tot * pb.T
     # the same timed region repeated, for the spread of the figure
@@ -929,6 +937,7 @@ def main():
                    "particle_steps_per_step": ps_per_step,
                    "us_per_interval": dt32 / args.steps / pb.T * 1e6,
                    "collective_workgroup": threads, "filter_groups": groups, "tuning": tune_src,
+                   "replay": head_replay,
                    "precision": ("fp32 accurate form: fp32 state in memory, fp32 slopes and "
                                  "normals, fp64 state and increments within each interval, fp64 "
                                  "log-weights/scan/likelihood" if args.headline_form == "accurate"
@@ -985,6 +994,7 @@ def main():
             inp = W.pmmh_inputs(chains=pm.B, iters=args.pmmh_iters)
             fm = pfm.Filter(pm, layout=pfm.PF_LAYOUT_BATCHED, stream=stream)
             pm_threads, pm_groups, _ = autotune(fm, pm.T - 1)
+            pm_replay = replay_mode(fm)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = fm.pmmh(inp)
@@ -994,6 +1004,7 @@ def main():
             nfilt = pm.B * (args.pmmh_iters + 1)
             out["pmmh"] = {"chains": pm.B, "iterations": args.pmmh_iters,
                            "collective_workgroup": pm_threads, "filter_groups": pm_groups,
+                           "replay": pm_replay,
                            "particles": int(pm.n_particles[0]), "T": pm.T,
                            "filters_per_s": nfilt / dtm,
                            "particle_steps_per_s": nfilt * int(pm.n_particles[0]) * pm.T / dtm,

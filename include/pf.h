@@ -177,8 +177,10 @@ pf_status pf_destroy(pf_handle* h);
  * layout with more than four filters), of every filter (plain layout) or of
  * one filter group (batched layout, launched on the group's own stream
  * between a fork from and a join into the handle's stream); a run replays
- * the longest that fit first (200 = 128 + 64 + 8).  Same results as the
- * eager calls. */
+ * the longest that fit first (200 = 128 + 64 + 8).  A batched handle set to
+ * eager replay (pf_set_replay, or pf_autotune when it measured eager
+ * launches faster on this host) issues the same kernels as eager launches
+ * instead.  Same results as the eager calls either way. */
 pf_status pf_graph_run(pf_handle* h, int32_t n_steps);
 
 /* Replace every filter's parameters (host [B][n_theta]) and re-initialise
@@ -415,9 +417,12 @@ pf_status pf_smc2(pf_handle* h, pf_handle* proposal, void* d_ws, size_t ws_bytes
  * another's propagation), re-initialises the filters and times `steps`
  * intervals (at most T - 1, after one untimed interval) of this handle's own
  * workload on eager launches — no graph is captured or destroyed per
- * candidate; the next pf_graph_run captures the chosen tuning's graphs —
- * keeps the fastest pair and re-initialises the filters (t = 0).  On an
- * error the handle is put back on its previous tuning, re-initialised.
+ * candidate — and keeps the fastest pair.  It then captures the chosen
+ * tuning's graphs once, times their replay over the same intervals, sets
+ * the replay mode of pf_graph_run to whichever of the two was faster
+ * (pf_get_tuning reports it), and re-initialises the filters (t = 0).  On
+ * an error while trying the candidates the handle is put back on its
+ * previous tuning; on any error it is re-initialised.
  * ms_out[9] (may be NULL) receives the mean interval time in ms of candidate
  * (groups index g, size index s) at [3g + s] (-1 when groups > B);
  * *threads_out and *groups_out (may be NULL) the choice.  Plain layout:
@@ -427,9 +432,23 @@ pf_status pf_autotune(pf_handle* h, int32_t steps, int32_t* threads_out, int32_t
 
 /* Set the batched layout's tuning directly: collective_threads in
  * {256, 512, 1024}, groups in [1, 8] (capped at B).  Takes effect from the
- * next interval; the plain layout ignores it.  Synchronous: waits for the
- * work already issued before the captured graphs are rebuilt. */
+ * next interval; the plain layout ignores it.  A different tuning waits for
+ * the work already issued, drops the captured graphs (rebuilt by the next
+ * pf_graph_run) and goes back to graph replay; the tuning the handle has
+ * already changes nothing. */
 pf_status pf_set_tuning(pf_handle* h, int32_t collective_threads, int32_t groups);
+
+/* How pf_graph_run issues a batched handle's intervals: eager = 1, as eager
+ * launches (the host issues them at the device's pace); eager = 0, by graph
+ * replay (the default).  The plain layout always replays graphs.
+ * PF_E_INVAL for another value. */
+pf_status pf_set_replay(pf_handle* h, int32_t eager);
+
+/* The batched layout's tuning and replay mode (host outputs, each may be
+ * NULL): collective width, filter groups, and 1 for eager replay; zeros for
+ * the plain layout. */
+pf_status pf_get_tuning(pf_handle* h, int32_t* collective_threads, int32_t* groups,
+                        int32_t* eager_replay);
 
 /* ---- inspection and teacher forcing (synchronous; same kernels) -------- */
 /* Current particle set, FP64 host [d][N_total]: after pf_resample (or init)

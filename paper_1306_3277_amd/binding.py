@@ -130,6 +130,9 @@ SIGNATURES = {
                           C.POINTER(PfSmc2Out)]),
     "pf_autotune": (C.c_int, [_H, C.c_int32, _I, _I, _D]),
     "pf_set_tuning": (C.c_int, [_H, C.c_int32, C.c_int32]),
+    "pf_set_replay": (C.c_int, [_H, C.c_int32]),
+    "pf_get_tuning": (C.c_int, [_H, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_int32)]),
     "pf_timing_enable": (C.c_int, [_H, C.c_int32]),
     "pf_timing_get": (C.c_int, [_H, C.POINTER(PfTiming)]),
     "pf_systematic_workspace_bytes": (C.c_size_t, [C.c_int64]),
@@ -422,6 +425,16 @@ class Filter:
 
     def set_tuning(self, threads: int, groups: int):
         _check(load().pf_set_tuning(self.h, int(threads), int(groups)))
+
+    def set_replay(self, eager: bool):
+        """graph_run by eager launches (True) or graph replay (False)."""
+        _check(load().pf_set_replay(self.h, 1 if eager else 0))
+
+    def get_tuning(self):
+        """(collective threads, groups, eager replay) of a batched handle."""
+        th, gr, eg = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().pf_get_tuning(self.h, C.byref(th), C.byref(gr), C.byref(eg)))
+        return th.value, gr.value, bool(eg.value)
 
     # -- inspection / teacher forcing
     def get_state(self) -> np.ndarray:

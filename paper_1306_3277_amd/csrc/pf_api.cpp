@@ -240,6 +240,9 @@ struct pf_handle {
   std::vector<hipGraph_t> graphs;
   std::vector<hipGraphExec_t> gexecs;
   int gnv = 0;
+  // batched layout: pf_graph_run issues its intervals as eager launches
+  // (the autotuner found them faster than the graph replay on this host)
+  bool eager_replay = false;
   hipStream_t cap_stream = nullptr;
   // attached history (ancestry storage), or null
   char* hist = nullptr;
@@ -1063,9 +1066,14 @@ pf_status pf_graph_run(pf_handle* H, int32_t n_steps) {
   if (H->t + n_steps > H->cfg.T)
     return fail(PF_E_STATE, "%d steps from t = %d exceed T = %d", n_steps, H->t, H->cfg.T);
   if (n_steps == 0) return PF_OK;
-  if ((st = ensure_graphs(H))) return st;
   hipStream_t ls;
   if ((st = launch_stream(H, &ls))) return st;
+  if (H->eager_replay && H->cfg.layout == PF_LAYOUT_BATCHED) {
+    if ((st = enqueue_batched(H, ls, n_steps))) return st;
+    H->t += n_steps;
+    return PF_OK;
+  }
+  if ((st = ensure_graphs(H))) return st;
   const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
   const int G = batched ? H->groups : 1;
   // group g's graphs go on its own stream (the caller's with one group)
@@ -1807,12 +1815,67 @@ pf_status pf_set_tuning(pf_handle* H, int32_t collective_threads, int32_t groups
     return fail(PF_E_INVAL, "collective_threads must be 256, 512 or 1024");
   if (groups < 1 || groups > 8) return fail(PF_E_INVAL, "groups must be in [1, 8]");
   if (H->cfg.layout != PF_LAYOUT_BATCHED) return PF_OK;  // nothing to tune
+  // the tuning the handle has already: nothing changes (its graphs and the
+  // replay choice stay)
+  if (collective_threads == H->batch_nt && std::min(groups, H->cfg.B) == H->groups) return PF_OK;
   if ((st = drain(H))) return st;
   destroy_graphs(H);
+  H->eager_replay = false;  // graph replay until a tuner run compares the two
   H->batch_nt = collective_threads;
   if (groups != H->groups) return build_groups(H, groups);
   return PF_OK;
 }
+
+pf_status pf_set_replay(pf_handle* H, int32_t eager) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  if (eager != 0 && eager != 1) return fail(PF_E_INVAL, "eager must be 0 or 1");
+  if (H->cfg.layout != PF_LAYOUT_BATCHED) return PF_OK;  // the plain layout always replays graphs
+  H->eager_replay = eager == 1;
+  return PF_OK;
+}
+
+pf_status pf_get_tuning(pf_handle* H, int32_t* collective_threads, int32_t* groups,
+                        int32_t* eager_replay) {
+  pf_status st = check_handle(H);
+  if (st) return st;
+  const bool batched = H->cfg.layout == PF_LAYOUT_BATCHED;
+  if (collective_threads) *collective_threads = batched ? H->batch_nt : 0;
+  if (groups) *groups = batched ? H->groups : 0;
+  if (eager_replay) *eager_replay = (batched && H->eager_replay) ? 1 : 0;
+  return PF_OK;
+}
+
+namespace {
+// Mean interval time (ms) of n intervals replayed from the handle's graphs
+// after a fresh initialisation and one untimed graph interval (t + 1 + n
+// must not exceed T).
+pf_status time_graph_replay(pf_handle* H, int n, double* ms_out) {
+  pf_status st = do_init(H, H->stream);
+  if (st) return st;
+  H->eager_replay = false;
+  if ((st = pf_graph_run(H, 1))) return st;  // captures the graphs
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  hipStream_t ls = nullptr;
+  if (he == hipSuccess) st = launch_stream(H, &ls);
+  if (he == hipSuccess && !st) he = hipEventRecord(e0, ls);
+  if (he == hipSuccess && !st) st = pf_graph_run(H, n);
+  if (he == hipSuccess && !st) he = hipEventRecord(e1, ls);
+  if (he == hipSuccess && !st) he = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (he == hipSuccess && !st) he = hipEventElapsedTime(&ms, e0, e1);
+  if (!st && he != hipSuccess) st = fail(PF_E_DEVICE, "graph timing failed: %s", hipGetErrorString(he));
+  // the events go only after the replays they bracket have finished
+  const pf_status st_drain = drain(H);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (!st) st = st_drain;
+  *ms_out = ms / n;
+  return st;
+}
+}  // namespace
 
 pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t* groups_out,
                       double* ms_out) {
@@ -1885,6 +1948,21 @@ pf_status pf_autotune(pf_handle* H, int32_t steps, int32_t* threads_out, int32_t
   if ((st = pf_set_tuning(H, best_nt, best_g))) return st;
   if (threads_out) *threads_out = best_nt;
   if (groups_out) *groups_out = best_g;
+  // the chosen tuning replayed from its graphs (captured once, here) over
+  // the same horizon, against its eager time: pf_graph_run then takes the
+  // faster (the eager launches win where the host issues them faster than
+  // the device runs them)
+  if (n >= 1 && best < 1e300) {
+    double graph_ms = 0.0;
+    if ((st = time_graph_replay(H, n, &graph_ms))) {
+      char msg[sizeof g_err];  // keep the failure's message; re-initialise
+      std::memcpy(msg, g_err, sizeof msg);
+      (void)pf_reset(H, H->iter);
+      std::memcpy(g_err, msg, sizeof msg);
+      return st;
+    }
+    H->eager_replay = best < graph_ms;
+  }
   return pf_reset(H, H->iter);
 }
 

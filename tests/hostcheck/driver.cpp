@@ -155,10 +155,15 @@ static void autotune() {
   for (int pass = 0; pass < 3; ++pass) {
     OK(pf_autotune(h, 5, &th, &gr, ms));
     OK(pf_graph_run(h, 2));
+    int32_t t2 = 0, g2 = 0, eg = 0;
+    OK(pf_get_tuning(h, &t2, &g2, &eg));
+    OK(pf_set_replay(h, 1 - eg));  // the other replay mode
+    OK(pf_graph_run(h, 3));
     OK(pf_set_tuning(h, 256, 4));
     OK(pf_reset(h, 0));
     OK(pf_graph_run(h, 5));
   }
+  EXPECT(pf_set_replay(h, 3), PF_E_INVAL);
   OK(pf_destroy(h));
 }
 

@@ -161,3 +161,10 @@ def test_restore_needs_a_handle():
     st = L.pf_restore(None, 0, x.ctypes.data_as(C.POINTER(C.c_double)),
                       ll.ctypes.data_as(C.POINTER(C.c_double)))
     assert st == binding.PF_E_INVAL, st
+
+
+def test_tuning_calls_need_a_handle():
+    L = binding.load()
+    assert L.pf_set_replay(None, 1) == binding.PF_E_INVAL
+    t = C.c_int32()
+    assert L.pf_get_tuning(None, C.byref(t), None, None) == binding.PF_E_INVAL

@@ -262,11 +262,52 @@ def test_autotune_keeps_results(pfm):
         # another collective width sums the weights in another order: the
         # increments agree to rounding
         np.testing.assert_allclose(e1, e0, rtol=1e-12, atol=1e-12)
+        assert f.get_tuning()[:2] == (threads, groups)
         f.reset(0)
-        f.graph_run(pb.T)  # graphs of the chosen tuning: the same bits as its eager run
+        f.graph_run(pb.T)  # the chosen tuning replayed: the same bits as its eager run
         np.testing.assert_array_equal(f.trace()[0], e1)
         f.reset(0)
+        # both replay modes, whichever the tuner chose
+        for eager in (False, True):
+            f.set_replay(eager)
+            assert f.get_tuning()[2] == eager
+            f.graph_run(pb.T)
+            np.testing.assert_array_equal(f.trace()[0], e1)
+            f.reset(0)
     f.close()
+
+
+def test_replay_modes_and_tuning_queries(pfm):
+    """pf_set_replay switches a batched handle's graph_run between graph
+    replay and eager launches (the same bits, with a history attached too);
+    a change of tuning goes back to graph replay, the same tuning changes
+    nothing; the plain layout reports zeros."""
+    th, n = W.batched_thetas(9, seed=13)
+    pb = _problem(n, th, T=9)
+    outs = []
+    for eager in (False, True):
+        f = pfm.Filter(pb, layout=pfm.PF_LAYOUT_BATCHED)
+        f.set_tuning(512, 2)
+        f.set_replay(eager)
+        f.attach_history()
+        f.graph_run(3)
+        f.advance(1)
+        f.graph_run(pb.T - 4)
+        outs.append((f.trace()[0], f.get_state(), f.ancestors(), f.backtrace()[0]))
+        assert f.get_tuning() == (512, 2, eager)
+        f.set_tuning(512, 2)
+        assert f.get_tuning() == (512, 2, eager)
+        f.set_tuning(256, 2)
+        assert f.get_tuning() == (256, 2, False)
+        from paper_1306_3277_amd import binding
+        assert binding.load().pf_set_replay(f.h, 2) == binding.PF_E_INVAL
+        f.close()
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    p = pfm.Filter(W.lorenz96(d=8, N=64, T=3), precision=pfm.PF_FP64)
+    p.set_replay(True)
+    assert p.get_tuning() == (0, 0, False)
+    p.close()
 
 
 def test_filter_groups_do_not_change_results(pfm):

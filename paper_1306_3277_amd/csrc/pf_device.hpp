@@ -744,10 +744,14 @@ __device__ __forceinline__ double block_incl_max_scan(double v, double* red) {
 
 // Number of strata k in [0, N) with (u + k) S < N W, i.e. the particles up
 // to and including this one own strata 0 .. count-1.  The estimate from one
-// multiplication by invS = 1/S is checked with the exact product comparison
-// on both sides; only when a check fails (the estimate rounded across a
-// stratum edge) does a lane step to the exact count, so the result does not
-// depend on how the estimate rounds.  N < 2^31.
+// multiplication by invS = 1/S lies within about N 2^-51 of NW/S - u, and a
+// stratum's rounded product comparison can differ from the real one only
+// within about N 2^-52 of it; so an estimate farther than N 2^-44 from an
+// integer is the exact count.  Otherwise (about N 2^-43 of the time) it is
+// checked with the exact product comparison on both sides, and a lane whose
+// check fails (the estimate rounded across a stratum edge) steps to the
+// exact count, so the result does not depend on how the estimate rounds.
+// N < 2^31.
 __device__ __forceinline__ int32_t stratum_count(double W, double S, double invS, double u,
                                                  int32_t N) {
   const double Nd = (double)N;
@@ -755,6 +759,9 @@ __device__ __forceinline__ int32_t stratum_count(double W, double S, double invS
   const double xv = NW * invS - u;
   // fmax maps a NaN estimate to 0; the exact checks below then decide
   int32_t est = (int32_t)__builtin_ceil(fmin(fmax(xv, 0.0), Nd));
+  const double fr = xv - __builtin_floor(xv);  // NaN for a NaN estimate
+  const double thr = Nd * 0x1p-44;
+  if (fr > thr && fr < 1.0 - thr) return est;
   const bool down = est > 0 && !((u + (double)(est - 1)) * S < NW);
   const bool up = est < N && (u + (double)est) * S < NW;
   if (down) {

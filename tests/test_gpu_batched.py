@@ -227,6 +227,13 @@ def test_pmmh_fp64_chains_match_oracle(pfm):
     np.testing.assert_array_equal(got["log_f"], ref["log_f"])
     np.testing.assert_array_equal(got["accepts"], ref["accepts"])
     np.testing.assert_allclose(got["ll"], ref["ll"], rtol=REL64)
+    # the same chains with the filters' intervals issued as eager launches
+    # (the replay mode the autotuner may choose) and with two filter groups
+    f.set_tuning(512, 2)
+    f.set_replay(True)
+    got2 = f.pmmh(inp)
+    for k in ("log_f", "accepts", "ll"):
+        np.testing.assert_array_equal(got2[k], got[k])
     f.close()
 
 
